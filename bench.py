@@ -1,0 +1,197 @@
+"""Throughput of the alchemical-window hot path on one MI355X.
+
+Workload: the 20-window solvent leg (2,500 seeded-orientation 3-site waters in
+a 42 A box plus a 40-atom ligand; cutoff 10 A, skin 1 A, PME 48^3 order 4;
+8 electrostatic then 12 vdW windows), all windows batched in every launch.
+
+One bench step = one pass of the whole hot path over the batch: `--md` Langevin
+-middle steps of 2 fs for every window (list check/rebuild, real-space pair
+kernel, PME, bonded terms, integrator with SETTLE), then the reduced
+potentials u_kn of every window's current frame at all 20 states.  After the
+timed steps, MBAR solves the collected u_kn (inside the timed region).
+
+Prints one JSON line: aggregate ns.windows/day, the pair kernel's roofline
+(FP32 ALU bound; algorithmic flops from in-cutoff pairs; duration from HIP
+events recorded around the kernel inside the timed region), the FP64 oracle
+timed on the host as the CPU baseline, and the unbatched per-window form of
+the same leg for comparison.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "aggregate ns·windows/day at |ΔΔG|≤0.01 kcal/mol; p50/p99 leg latency"
+KB = 0.0019872043
+DT = 0.002                      # ps
+PEAK_FP32 = 157.3               # TFLOP/s, MI355X FP32 vector (published)
+FLOP_PER_PAIR = 75              # FP32 flops per in-cutoff pair (FMA = 2)
+TRAFFIC_FILE = os.path.join(ROOT, 'profiles', 'pairs_traffic_solvent20.json')
+
+
+def _src_digest():
+    h = hashlib.sha256()
+    for f in ('nonbonded.hip', 'erfc_coeffs.h', 'felis_internal.h'):
+        h.update(open(os.path.join(ROOT, 'paper_2603_22274_amd', 'csrc', f), 'rb').read())
+    return h.hexdigest()[:16]
+
+
+def _traffic():
+    try:
+        t = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    if t.get('kernel_digest') != _src_digest():
+        return None
+    return t.get('bytes_per_launch')
+
+
+def cpu_baseline(sysd):
+    """One window-step of the FP64 oracle (forces by brute force + PME, one
+    Langevin-middle step) on the host; scaled to ns.windows/day."""
+    from oracle import energy as oenergy, integrate as ointeg
+    from oracle.ewald import PME
+    pme = PME(sysd.box, sysd.grid, sysd.ewald_alpha)
+    lam = sysd.lambdas[9]
+    x = sysd.pos.astype(np.float64)
+    v = np.zeros_like(x)
+    force = lambda y: oenergy.window_energy(sysd, y, lam, pme=pme)[1]
+    t0 = time.perf_counter()
+    ointeg.langevin_middle_step(sysd, x, v, force, DT, 300.0, 0.5, 1, 9, 0)
+    t = time.perf_counter() - t0
+    return {"value": DT * 1e-3 / t * 86400.0, "unit": "ns·windows/day", "cores": 1, "kind": "oracle",
+            "sample": f"one window-step (window 9) of the {sysd.n_atoms}-atom leg: brute-force FP64 pair sums, "
+                      f"FP64 PME 48^3, one Langevin-middle step with SHAKE; {t:.1f} s single-threaded numpy "
+                      f"on {os.cpu_count()} available host cores"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument('--gpus', type=int, default=1)
+    ap.add_argument('--steps', type=int, default=20)
+    ap.add_argument('--warmup', type=int, default=3)
+    ap.add_argument('--md', type=int, default=50, help='MD steps per bench step (u_kn sample interval)')
+    ap.add_argument('--no-cpu-baseline', action='store_true')
+    ap.add_argument('--no-per-window', action='store_true')
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get('WORLD_SIZE', '1')) > 1:
+        print("bench.py measures one GPU: the path needs no collective and nothing here runs on a second GPU; "
+              "legs and window segments shard across GPUs without exchange (see DESIGN.md).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2603_22274_amd import felis, gen
+
+    sysd = gen.config1()
+    ctx = felis.Context(0)
+    leg = felis.Leg(ctx, sysd, seed=22274)
+    W = leg.n_windows
+    beta = 1.0 / (KB * 300.0)
+    felis.build_nlist(ctx, [leg], force=True)
+    # settle the lattice start before anything is measured
+    felis.step(ctx, [leg], 200, DT, 300.0, 5.0)
+    ctx.device_check()
+    # algorithmic work: unique pairs within r_c per window (FP64 distances)
+    felis.build_nlist(ctx, [leg])
+    npairs_cut = sum(len(felis.nlist_export_pairs(ctx, leg, w, sysd.r_cut)) for w in range(W))
+
+    n_samples = args.steps
+    u = torch.empty((W, W * n_samples), dtype=torch.float64, device='cuda')
+
+    def bench_step(k, timed):
+        felis.step(ctx, [leg], args.md, DT, 300.0, 0.5)
+        col = u[:, k * W:(k + 1) * W] if timed else None
+        felis.ukn(ctx, leg, sysd.lambdas, leg.x, leg.y, leg.z, beta, out=col)
+
+    for k in range(args.warmup):
+        bench_step(0, False)
+    torch.cuda.synchronize()
+    ctx.device_check()
+    felis.profile(ctx, True)
+    for which in range(5):
+        felis.profile_read(ctx, which)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        bench_step(k, True)
+    N_k = np.full(W, n_samples)
+    mbar_ok = True
+    try:
+        f, iters = felis.mbar(ctx, u, N_k, tol=1e-10, max_iter=20000)
+    except felis.FelisError as e:
+        if e.code != felis.E_NOCONV:
+            raise
+        mbar_ok, f, iters = False, None, 20000
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    felis.profile(ctx, False)
+    prof = {name: felis.profile_read(ctx, i) for i, name in enumerate(('pairs', 'pme', 'nlist', 'integrate', 'ukn'))}
+    ctx.device_check()
+    wall = t1 - t0
+    md_steps = args.steps * args.md
+    ns_windows = md_steps * DT * W / 1000.0
+    value = ns_windows / (wall / 86400.0)
+    pairs_ms, pairs_n = prof['pairs']
+    avg_pairs_s = pairs_ms / max(pairs_n, 1) / 1000.0
+    flops = npairs_cut * FLOP_PER_PAIR
+    achieved = flops / avg_pairs_s / 1e12
+    traffic = _traffic()
+    dg = float((f[-1] - f[0]) / beta) if f is not None else None
+
+    per_window = None
+    if not args.no_per_window:
+        # the same leg as 20 one-window legs, each launched on its own
+        legs1 = [felis.Leg(ctx, sysd, windows=[w], seed=22274, positions=leg.positions()[w].cpu().numpy())
+                 for w in range(W)]
+        for l in legs1:
+            felis.build_nlist(ctx, [l], force=True)
+        nrep = max(1, args.md // 2)
+        for l in legs1:
+            felis.step(ctx, [l], 5, DT, 300.0, 0.5)
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        for l in legs1:
+            felis.step(ctx, [l], nrep, DT, 300.0, 0.5)
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        per_window = {"value": nrep * DT * W / 1000.0 / ((tb - ta) / 86400.0), "unit": "ns·windows/day",
+                      "form": "one window per leg and launch chain (same kernels), MD only",
+                      "md_steps_per_window": nrep}
+
+    cpu = None if args.no_cpu_baseline else cpu_baseline(sysd)
+    out = {
+        "metric": METRIC, "value": value, "unit": "ns·windows/day", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": wall / args.steps * 1000.0, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "fp32", "data": "synthetic",
+        "config": {"workload": "solvent leg, 20 windows, 7540 atoms (2500 TIP3P-geometry waters + 40-atom "
+                               "ligand), 42 A box, r_c 10 A, skin 1 A, PME 48^3 order 4, 2 fs, 300 K",
+                   "md_steps_per_step": args.md, "windows": W, "atoms": sysd.n_atoms,
+                   "ukn_states": W, "mbar_samples": int(W * n_samples)},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP32, "traffic": traffic,
+                     "kernel": "k_pairs (real-space pair kernel, all 20 windows per launch)",
+                     "pairs_in_cutoff_per_launch": int(npairs_cut), "flop_per_pair": FLOP_PER_PAIR,
+                     "avg_launch_ms": avg_pairs_s * 1000.0, "launches": pairs_n},
+        "cpu_baseline": cpu,
+        "per_window_form": per_window,
+        "stage_ms_per_md_step": {k: v[0] / max(v[1], 1) for k, v in prof.items() if k != 'ukn'},
+        "ukn_ms_per_call": prof['ukn'][0] / max(prof['ukn'][1], 1),
+        "mbar": {"converged": mbar_ok, "iterations": iters, "dG_kcal_per_mol": dg},
+        "leg_latency_s": {"p50": wall, "p99": wall, "legs": 1,
+                          "note": "one leg in this workload; the served mixed batch reports its own"},
+    }
+    print(json.dumps(out))
+
+
+if __name__ == '__main__':
+    main()

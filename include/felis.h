@@ -1,0 +1,229 @@
+/* felis.h -- C ABI of the MI355X (gfx950) alchemical-window hot path.
+ *
+ * For every lambda window of an absolute-binding decoupling leg the library
+ * evaluates alchemically scaled nonbonded forces and energies, PME reciprocal
+ * space, Langevin-middle dynamics with rigid water, the cross-lambda reduced
+ * potential matrix u_kn and its MBAR solve.  The method is the one of the
+ * paper's sections "Double annihilation protocol" (ligand charges scaled
+ * linearly to zero, Beutler softcore 12-6 LJ with lambda_ij = min(lambda_i,
+ * lambda_j), alpha = 0.5, p = 1, Lorentz-Berthelot mixing), "Restraints"
+ * (Boresch distance/angle/dihedral set), "Simulation protocol" (Langevin
+ * middle integrator, 2 fs, rigid TIP3P, MBAR) and appendix B (1 nm PME and
+ * vdW cutoffs, universal lambda schedules).
+ *
+ * Units: angstrom, ps, amu, e, kcal/mol, K.
+ * Precision: pair, PME and integrator arithmetic in FP32; forces accumulate in
+ * int64 fixed point (FELIS_FORCE_SCALE units per kcal/mol/A), so results are
+ * bitwise reproducible; energies, u_kn and MBAR in FP64 (energy partial sums
+ * are combined in int64 fixed point at 2^-30 kcal/mol).
+ * Memory: every device buffer is allocated and owned by the caller (e.g. a
+ * PyTorch tensor's data pointer).  The library never frees caller memory and
+ * allocates device memory only in felis_create (a few KB of tables and an
+ * error word).  Per-leg scratch lives in caller memory sized by
+ * felis_leg_work_size.
+ * Streams: every call is enqueued on the HIP stream given to felis_create and
+ * returns without waiting, except felis_leg_init, felis_check,
+ * felis_nlist_export_pairs and felis_mbar (they synchronise that stream).
+ * Errors: every function returns FELIS_OK (0) or a negative FELIS_E_* code; no
+ * exception crosses the ABI and nothing aborts.  Device-side faults (list
+ * capacity, fixed-point overflow, non-finite forces) are latched in a device
+ * error word and reported by the next felis_check.  felis_last_error gives a
+ * message for the last failing call on the context.
+ * Threads: one context per host thread and stream; no global state.
+ */
+#ifndef FELIS_H
+#define FELIS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FELIS_OK 0
+#define FELIS_E_INVAL (-1)       /* bad argument, size or pointer */
+#define FELIS_E_DEVICE (-2)      /* HIP runtime error */
+#define FELIS_E_BOX (-3)         /* r_cut + skin >= half the shortest box edge */
+#define FELIS_E_CAPACITY (-4)    /* neighbour list capacity exceeded (see felis_check) */
+#define FELIS_E_OVERFLOW (-5)    /* fixed-point range exceeded or non-finite value */
+#define FELIS_E_NOCONV (-6)      /* MBAR reached max_iter */
+#define FELIS_E_UNSUPPORTED (-7) /* spline order != 4, softcore p != 1, grid > 128 ... */
+
+#define FELIS_FORCE_SCALE 4294967296.0   /* int64 force units per kcal/mol/A (2^32) */
+
+/* energy vector of one window, kcal/mol */
+#define FELIS_NE 8
+enum {
+  FELIS_E_COUL_REAL = 0, /* real-space erfc Coulomb over non-excluded pairs < r_cut */
+  FELIS_E_LJ = 1,        /* softcore / plain 12-6 LJ over non-excluded pairs < r_cut */
+  FELIS_E_EXCL = 2,      /* -KE q_i q_j erf(alpha r)/r over excluded pairs */
+  FELIS_E_SELF = 3,      /* Ewald self term + neutralising-background term */
+  FELIS_E_RECIP = 4,     /* PME reciprocal energy */
+  FELIS_E_BOND = 5,      /* harmonic bonds (k/2)(r - r0)^2 */
+  FELIS_E_RESTRAINT = 6, /* lambda_restraint x Boresch energy */
+  FELIS_E_TOTAL = 7
+};
+
+/* flags for felis_nonbonded / felis_pme / felis_bonded */
+#define FELIS_ENERGY 1   /* also compute the call's energy components */
+
+typedef struct felis_ctx felis_ctx;
+
+/* One decoupling leg: a periodic orthorhombic system and its windows.
+ * Pointers marked (dev) are device pointers owned by the caller and must stay
+ * valid while the leg is used; (host) pointers are read during the call only. */
+typedef struct felis_leg {
+  int32_t n_atoms;
+  double box[3];                 /* edges, A */
+  double r_cut;                  /* real-space Coulomb and LJ cutoff, A */
+  double skin;                   /* neighbour-list buffer: list radius = r_cut + skin */
+  double ewald_alpha;            /* Ewald splitting parameter, 1/A */
+  double sc_alpha;               /* softcore alpha (paper: 0.5) */
+  int32_t sc_p;                  /* softcore power (paper: 1; only 1 is supported) */
+  int32_t grid[3];               /* PME grid, each 2^a 3^b 5^c and <= 128 */
+  int32_t spline_order;          /* PME B-spline order (only 4 is supported) */
+  const float* charge;           /* (dev) [n_atoms] e, unscaled */
+  const float* sigma;            /* (dev) [n_atoms] LJ sigma, A */
+  const float* epsilon;          /* (dev) [n_atoms] LJ epsilon, kcal/mol */
+  const float* mass;             /* (dev) [n_atoms] amu */
+  const uint8_t* is_ligand;      /* (dev) [n_atoms] 1 = alchemical ligand atom */
+  int32_t n_excl;                /* excluded pairs (rigid-water and bonded 1-2 / 1-3) */
+  const int32_t* excl_ij;        /* (dev) [n_excl][2], i < j */
+  const int32_t* excl_ptr;       /* (dev) [n_atoms + 1] CSR of the same set, symmetric */
+  const int32_t* excl_idx;       /* (dev) [2 n_excl] */
+  int32_t n_bonds;
+  const int32_t* bond_ij;        /* (dev) [n_bonds][2] */
+  const float* bond_k;           /* (dev) [n_bonds] kcal/mol/A^2, energy (k/2)(r - r0)^2 */
+  const float* bond_r0;          /* (dev) [n_bonds] A */
+  int32_t n_waters;
+  const int32_t* water_ohh;      /* (dev) [n_waters][3] O, H1, H2 (rigid, SETTLE) */
+  double d_oh, d_hh;             /* rigid water geometry, A */
+  int32_t has_restraint;         /* 1: Boresch restraint on the anchors below */
+  int32_t restraint_atoms[6];    /* P1 P2 P3 L1 L2 L3 */
+  double restraint_g0[6];        /* r0 (A), thetaA0, thetaB0, phiA0, phiB0, phiC0 (rad) */
+  double restraint_k[6];         /* k_r (kcal/mol/A^2), k_theta x2 (kcal/mol/rad^2), k_phi x3 (kcal/mol) */
+  int32_t n_windows;
+  const double* lambdas;         /* (host) [n_windows][3] lambda_elec, lambda_vdw, lambda_restraint */
+  float *x, *y, *z;              /* (dev) [n_windows][n_atoms] positions, A (never wrapped) */
+  float *vx, *vy, *vz;           /* (dev) [n_windows][n_atoms] velocities, A/ps */
+  int64_t *fx, *fy, *fz;         /* (dev) [n_windows][n_atoms] forces, FELIS_FORCE_SCALE units */
+  double* energy;                /* (dev) [n_windows][FELIS_NE] */
+  uint64_t seed;                 /* noise key of this leg */
+  int64_t step;                  /* index of the next MD step (advanced by felis_step) */
+  int32_t list_cap;              /* list entries per 8-atom cluster; 0 = sized from density */
+  void* work;                    /* (dev) library scratch of work_bytes */
+  size_t work_bytes;
+} felis_leg;
+
+/* Create a context on HIP device `device` that enqueues on `hip_stream`
+ * (a hipStream_t, NULL = default stream).  FELIS_E_DEVICE if the device or
+ * its allocation of the context's tables fails. */
+int felis_create(felis_ctx** out, int device, void* hip_stream);
+void felis_destroy(felis_ctx* ctx);
+const char* felis_last_error(const felis_ctx* ctx);
+
+/* Synchronise the stream and report the device error word:
+ * FELIS_E_CAPACITY (list overflow; *needed_cap, if non-NULL, receives the
+ * longest cluster list seen), FELIS_E_OVERFLOW, FELIS_E_INVAL, or FELIS_OK.
+ * Clears the word. */
+int felis_check(felis_ctx* ctx, int32_t* needed_cap);
+
+/* Bytes of device scratch a leg needs (lists, sorted copies, PME grids,
+ * accumulators).  Validates the leg's sizes: FELIS_E_BOX, FELIS_E_UNSUPPORTED,
+ * FELIS_E_INVAL. */
+int felis_leg_work_size(const felis_leg* leg, size_t* bytes);
+
+/* Fill the leg's scratch (lambda table, FFT tables, water/ligand index
+ * tables) and mark every window for a list build.  Call once after the
+ * topology and initial positions are in place, and again after positions are
+ * replaced from outside.  Synchronises the stream. */
+int felis_leg_init(felis_ctx* ctx, felis_leg* leg);
+
+/* Neighbour lists (appendix B cutoffs; list radius r_cut + skin).  Per window,
+ * atoms are sorted along a Morton curve of fine cells and grouped into
+ * 8-atom clusters; each cluster lists every atom j with, for each of its atoms
+ * i, a bit: |d_ij| < r_cut + skin in FP64 minimum image, j != i, (i, j) not
+ * excluded.  With force = 0 only windows whose atoms moved more than skin/2
+ * since their last build are rebuilt; force = 1 rebuilds all. */
+int felis_build_nlist(felis_ctx* ctx, felis_leg* legs, int n_legs, int force);
+
+/* Test/diagnostic export of window `window`'s list: every pair (i < j) whose
+ * list bit is set and whose FP64 minimum-image distance is < r (pass
+ * r >= r_cut + skin for the whole list) is written to pairs[2 k], pairs[2 k + 1]
+ * (dev, capacity `cap` pairs, unordered); *n_pairs receives the count (also
+ * when it exceeds cap, then FELIS_E_CAPACITY).  Synchronises. */
+int felis_nlist_export_pairs(felis_ctx* ctx, const felis_leg* leg, int window, double r,
+                             int32_t* pairs, int64_t cap, int64_t* n_pairs);
+
+/* Real-space part for every window of every leg ("Double annihilation
+ * protocol"): erfc Coulomb with ligand charges x lambda_elec, softcore LJ
+ * (lambda_ij = lambda_vdw when i or j is ligand, else plain LJ), both cut at
+ * r_cut, plus the excluded-pair, self and background Ewald terms.  Forces are
+ * OVERWRITTEN (this call starts a force evaluation); with FELIS_ENERGY the
+ * components COUL_REAL, LJ, EXCL, SELF and TOTAL are written. */
+int felis_nonbonded(felis_ctx* ctx, felis_leg* legs, int n_legs, int flags);
+
+/* PME reciprocal space (order-4 B-spline spreading, 3D FFT, influence function,
+ * gather); forces are ADDED; with FELIS_ENERGY writes RECIP and TOTAL. */
+int felis_pme(felis_ctx* ctx, felis_leg* legs, int n_legs, int flags);
+
+/* Harmonic bonds and lambda_restraint-scaled Boresch restraint (section
+ * "Restraints"); forces are ADDED; with FELIS_ENERGY writes BOND, RESTRAINT
+ * and TOTAL. */
+int felis_bonded(felis_ctx* ctx, felis_leg* legs, int n_legs, int flags);
+
+/* n_steps Langevin-middle steps ("Simulation protocol") for every window:
+ * list check/rebuild, forces (nonbonded + PME + bonded), then
+ * v += dt F/m; x += dt/2 v; v = a v + sqrt((1-a^2) kT/m) xi; x += dt/2 v;
+ * SETTLE on rigid waters; v += (x_constrained - x_unconstrained)/dt, with
+ * a = exp(-gamma dt) and xi from Philox4x32-10 keyed by (leg seed) and
+ * counted by (atom, window, step), so a window's trajectory does not depend
+ * on the batch it runs in.  Each leg's `step` advances by n_steps. */
+int felis_step(felis_ctx* ctx, felis_leg* legs, int n_legs, int n_steps, double dt,
+               double temperature, double gamma);
+
+/* Reduced potentials of n_frames frames of one leg at K lambda states:
+ * u[k * u_stride + f] = beta [lam_e E_LE + lam_e^2 E_LL + E_sc(lam_v) + lam_r U_B]
+ * (lambda-independent terms dropped; MBAR is invariant to them).  Frame f's
+ * coordinates are fx/fy/fz + f * frame_stride (dev, float, n_atoms each).
+ * lambdas (host) [K][3].  Uses the leg's scratch (call felis_leg_init first);
+ * at most 64 distinct lambda_vdw values and 256 ligand atoms. */
+int felis_ukn(felis_ctx* ctx, felis_leg* leg, const double* lambdas, int K, const float* fx,
+              const float* fy, const float* fz, int64_t frame_stride, int64_t n_frames,
+              double beta, double* u, int64_t u_stride);
+
+/* Kernel timing with HIP events recorded on the context's stream around the
+ * launches of one stage inside felis_step / felis_ukn (the events bracket
+ * exactly the stage's kernels, so their elapsed time is the stage's device
+ * time).  felis_profile(ctx, 1) starts recording; felis_profile_read
+ * synchronises, returns the summed milliseconds and the number of bracketed
+ * launches for stage `which` since the last read, and resets it. */
+enum {
+  FELIS_PROF_PAIRS = 0,     /* the real-space pair kernel */
+  FELIS_PROF_PME = 1,       /* spreading, five FFT passes, gather */
+  FELIS_PROF_NLIST = 2,     /* displacement check and list rebuild */
+  FELIS_PROF_INTEGRATE = 3, /* Langevin-middle update with SETTLE */
+  FELIS_PROF_UKN = 4,       /* one felis_ukn call */
+  FELIS_PROF_N = 5
+};
+int felis_profile(felis_ctx* ctx, int enable);
+int felis_profile_read(felis_ctx* ctx, int which, double* total_ms, int64_t* launches);
+
+/* Scratch bytes for felis_mbar. */
+int felis_mbar_work_size(int K, int64_t n_total, size_t* bytes);
+
+/* MBAR (Shirts & Chodera 2008; "Simulation protocol"): self-consistent
+ * iteration in log-sum-exp form on u (dev, FP64, [K][n_total] row-major),
+ * N_k (host, samples per state in column order), gauge f_0 = 0, until
+ * max|f_new - f| <= rel_tol * max(1, max|f|).  f_out (host) [K] dimensionless
+ * free energies; *iters the iterations used.  FELIS_E_NOCONV at max_iter.
+ * Synchronises. */
+int felis_mbar(felis_ctx* ctx, const double* u, const int32_t* N_k, int K, int64_t n_total,
+               double rel_tol, int max_iter, double* f_out, int* iters, void* work,
+               size_t work_bytes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FELIS_H */

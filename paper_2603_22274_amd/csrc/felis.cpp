@@ -1,0 +1,590 @@
+// C ABI of the alchemical-window hot path (declarations and documentation in
+// include/felis.h).  Host side: argument validation, the per-leg scratch
+// layout, device descriptor upload and the launch sequences.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "felis_internal.h"
+
+using namespace felis;
+
+namespace {
+
+struct Layout {
+  size_t lam, free_atoms, lig_idx, xr, yr, zr, flag, perm, cellcode, cellstart, cursor, xyzq, prm, bblo,
+      bbhi, lcount, lent, grid64, cgrid, tw[3], bmod[3], eacc, uacc, ucst, total;
+};
+
+struct Plan {
+  LegHost h;
+  Layout lay;
+  int nbits;
+  int nrad[3], rad[3][kMaxRadix];
+};
+
+struct Meta {          // facts read from the topology at felis_leg_init
+  int nfree, nlig;
+  size_t work_bytes;
+};
+
+// HIP events bracketing one kind of launch on the context's stream
+struct Timer {
+  std::vector<hipEvent_t> ev;     // start, stop, start, stop ...
+  size_t used = 0;
+};
+
+}  // namespace
+
+struct felis_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  LegDev* d_legs = nullptr;          // device table of kMaxLegs descriptors
+  LegDev* h_stage = nullptr;         // pinned staging
+  std::vector<LegDev> cache;         // last uploaded table
+  int* d_err = nullptr;              // [0] error bits, [1] largest list length
+  unsigned long long* d_count = nullptr;
+  std::unordered_map<const void*, Meta> meta;
+  std::string last_error;
+  bool prof = false;
+  Timer timers[FELIS_PROF_N];
+};
+
+namespace {
+
+int fail(felis_ctx* c, int code, const char* msg) {
+  if (c) c->last_error = msg;
+  return code;
+}
+
+size_t al(size_t v) { return (v + 255) & ~size_t(255); }
+
+bool factor_plan(int K, int* rad, int* nrad) {
+  int m = K, n = 0;
+  while (m % 4 == 0 && n < kMaxRadix) { rad[n++] = 4; m /= 4; }
+  while (m % 2 == 0 && n < kMaxRadix) { rad[n++] = 2; m /= 2; }
+  while (m % 3 == 0 && n < kMaxRadix) { rad[n++] = 3; m /= 3; }
+  while (m % 5 == 0 && n < kMaxRadix) { rad[n++] = 5; m /= 5; }
+  *nrad = n;
+  return m == 1;
+}
+
+int make_plan(felis_ctx* c, const felis_leg* L, Plan& P) {
+  if (!L) return fail(c, FELIS_E_INVAL, "null leg");
+  if (L->n_atoms <= 0 || L->n_windows <= 0) return fail(c, FELIS_E_INVAL, "n_atoms and n_windows must be positive");
+  if (L->n_atoms >= (1 << 24)) return fail(c, FELIS_E_UNSUPPORTED, "more than 2^24 atoms");
+  for (int d = 0; d < 3; ++d)
+    if (!(L->box[d] > 0)) return fail(c, FELIS_E_INVAL, "box edges must be positive");
+  if (!(L->r_cut > 0) || !(L->skin >= 0) || !(L->ewald_alpha > 0))
+    return fail(c, FELIS_E_INVAL, "r_cut, skin, ewald_alpha");
+  const double lmin = std::min(L->box[0], std::min(L->box[1], L->box[2]));
+  if (!(L->r_cut + L->skin < 0.5 * lmin)) return fail(c, FELIS_E_BOX, "r_cut + skin must be below half the box");
+  if (L->sc_p != 1) return fail(c, FELIS_E_UNSUPPORTED, "softcore p must be 1");
+  if (L->spline_order != 4) return fail(c, FELIS_E_UNSUPPORTED, "PME spline order must be 4");
+  if (!(L->sc_alpha >= 0)) return fail(c, FELIS_E_INVAL, "sc_alpha");
+  if (!L->charge || !L->sigma || !L->epsilon || !L->mass || !L->is_ligand)
+    return fail(c, FELIS_E_INVAL, "null parameter array");
+  if (!L->x || !L->y || !L->z || !L->vx || !L->vy || !L->vz || !L->fx || !L->fy || !L->fz || !L->energy)
+    return fail(c, FELIS_E_INVAL, "null state array");
+  if (!L->lambdas) return fail(c, FELIS_E_INVAL, "null lambdas");
+  if (L->n_excl < 0 || (L->n_excl > 0 && (!L->excl_ij || !L->excl_ptr || !L->excl_idx)))
+    return fail(c, FELIS_E_INVAL, "exclusions");
+  if (!L->excl_ptr) return fail(c, FELIS_E_INVAL, "excl_ptr is required");
+  if (L->n_bonds < 0 || (L->n_bonds > 0 && (!L->bond_ij || !L->bond_k || !L->bond_r0)))
+    return fail(c, FELIS_E_INVAL, "bonds");
+  if (L->n_waters < 0 || 3LL * L->n_waters > L->n_atoms || (L->n_waters > 0 && !L->water_ohh))
+    return fail(c, FELIS_E_INVAL, "waters");
+  if (L->has_restraint)
+    for (int t = 0; t < 6; ++t)
+      if (L->restraint_atoms[t] < 0 || L->restraint_atoms[t] >= L->n_atoms)
+        return fail(c, FELIS_E_INVAL, "restraint atom out of range");
+  Plan& p = P;
+  LegHost& h = p.h;
+  std::memset(&p, 0, sizeof(p));
+  h.n = L->n_atoms;
+  h.W = L->n_windows;
+  h.npad = (h.n + 7) & ~7;
+  h.nclus = h.npad / 8;
+  const double V = L->box[0] * L->box[1] * L->box[2];
+  const double rl = L->r_cut + L->skin;
+  int cap = L->list_cap;
+  if (cap <= 0) {
+    const double rho = h.n / V;
+    // union of r_list spheres around a cluster's atoms, with room for clusters
+    // that straddle a jump of the Morton order (up to ~2x the compact size)
+    cap = (int)std::ceil(3.0 * rho * 4.0 / 3.0 * M_PI * std::pow(rl + 1.5, 3) + 64.0);
+  }
+  cap = std::min((cap + 7) & ~7, h.npad);
+  h.cap = std::max(cap, 8);
+  h.nexcl = L->n_excl;
+  h.nbonds = L->n_bonds;
+  h.nwat = L->n_waters;
+  h.nfree = h.n - 3 * h.nwat;
+  h.has_rest = L->has_restraint ? 1 : 0;
+  for (int d = 0; d < 3; ++d) {
+    const int K = L->grid[d];
+    if (K < 4 || K > kMaxFFT || !factor_plan(K, p.rad[d], &p.nrad[d]))
+      return fail(c, FELIS_E_UNSUPPORTED, "PME grid dimensions must be 2^a 3^b 5^c in [4, 128]");
+    h.K[d] = K;
+  }
+  h.Ktot = h.K[0] * h.K[1] * h.K[2];
+  h.npair = (h.W + 1) / 2;
+  int nbits = (int)std::floor(std::log2(lmin / 2.4));
+  nbits = std::max(1, std::min(7, nbits));
+  p.nbits = nbits;
+  h.ncell = 1 << (3 * nbits);
+  Layout& y = p.lay;
+  size_t o = 0;
+  auto put = [&](size_t bytes) { size_t r = o; o += al(bytes); return r; };
+  const size_t W = h.W, n = h.n, npad = h.npad, nc = h.nclus;
+  y.lam = put(W * 4 * sizeof(float));
+  y.free_atoms = put(n * 4);
+  y.lig_idx = put(n * 4);
+  y.xr = put(W * n * 4); y.yr = put(W * n * 4); y.zr = put(W * n * 4);
+  y.flag = put(W * 4);
+  y.perm = put(W * npad * 4);
+  y.cellcode = put(W * n * 4);
+  y.cellstart = put(W * (h.ncell + 1) * 4);
+  y.cursor = put(W * h.ncell * 4);
+  y.xyzq = put(W * npad * 16);
+  y.prm = put(W * npad * 16);
+  y.bblo = put(W * nc * 16);
+  y.bbhi = put(W * nc * 16);
+  y.lcount = put(W * nc * 4);
+  y.lent = put(W * nc * (size_t)h.cap * 4);
+  y.grid64 = put(2 * (size_t)h.npair * h.Ktot * 8);
+  y.cgrid = put((size_t)h.npair * h.Ktot * 8);
+  for (int d = 0; d < 3; ++d) { y.tw[d] = put(h.K[d] * 8); y.bmod[d] = put(h.K[d] * 4); }
+  y.eacc = put(W * FELIS_NE * 8);
+  y.uacc = put((size_t)h.npair * (3 + kMaxLamV) * 8);
+  y.ucst = put(8 * sizeof(double));
+  y.total = o;
+  return FELIS_OK;
+}
+
+LegDev make_dev(const felis_ctx* c, const felis_leg* L, const Plan& p, const Meta& m) {
+  LegDev g;
+  std::memset(&g, 0, sizeof(g));
+  const LegHost& h = p.h;
+  g.n = h.n; g.W = h.W; g.npad = h.npad; g.nclus = h.nclus; g.cap = h.cap;
+  g.nexcl = h.nexcl; g.nbonds = h.nbonds; g.nwat = h.nwat; g.nfree = m.nfree; g.nlig = m.nlig;
+  for (int d = 0; d < 3; ++d) g.K[d] = h.K[d];
+  g.Ktot = h.Ktot; g.npair = h.npair;
+  g.nbits = p.nbits; g.ncoarse = 1 << (p.nbits - 1); g.ncell = h.ncell;
+  for (int d = 0; d < 3; ++d) {
+    g.nrad[d] = p.nrad[d];
+    for (int k = 0; k < kMaxRadix; ++k) g.rad[d][k] = p.rad[d][k];
+  }
+  g.has_rest = h.has_rest;
+  for (int t = 0; t < 6; ++t) {
+    g.ranch[t] = L->restraint_atoms[t];
+    g.rg0[t] = (float)L->restraint_g0[t];
+    g.rk[t] = (float)L->restraint_k[t];
+  }
+  for (int d = 0; d < 3; ++d) {
+    g.L[d] = L->box[d];
+    g.invL[d] = 1.0 / L->box[d];
+    g.Lf[d] = (float)L->box[d];
+    g.invLf[d] = (float)(1.0 / L->box[d]);
+  }
+  g.rc2 = (float)(L->r_cut * L->r_cut);
+  g.alpha = (float)L->ewald_alpha;
+  g.sc_alpha = (float)L->sc_alpha;
+  g.skin_half2 = (float)(0.25 * L->skin * L->skin);
+  g.rlist = L->r_cut + L->skin;
+  g.rlist2 = g.rlist * g.rlist;
+  g.d_oh = (float)L->d_oh;
+  g.d_hh = (float)L->d_hh;
+  const double V = L->box[0] * L->box[1] * L->box[2];
+  g.pme_pref = (float)(kKE / (M_PI * V));
+  g.self_pref = (float)(kKE * L->ewald_alpha / std::sqrt(M_PI));
+  g.bg_pref = kKE * M_PI / (2.0 * V * L->ewald_alpha * L->ewald_alpha);
+  g.q = L->charge; g.sig = L->sigma; g.eps = L->epsilon; g.mass = L->mass; g.lig = L->is_ligand;
+  g.excl_ij = L->excl_ij; g.excl_ptr = L->excl_ptr; g.excl_idx = L->excl_idx;
+  g.bond_ij = L->bond_ij; g.bond_k = L->bond_k; g.bond_r0 = L->bond_r0;
+  g.water = L->water_ohh;
+  g.x = L->x; g.y = L->y; g.z = L->z; g.vx = L->vx; g.vy = L->vy; g.vz = L->vz;
+  g.fx = (long long*)L->fx; g.fy = (long long*)L->fy; g.fz = (long long*)L->fz;
+  g.energy = L->energy;
+  char* w = (char*)L->work;
+  const Layout& y = p.lay;
+  g.lam = (float*)(w + y.lam);
+  g.free_atoms = (int*)(w + y.free_atoms);
+  g.lig_idx = (int*)(w + y.lig_idx);
+  g.xr = (float*)(w + y.xr); g.yr = (float*)(w + y.yr); g.zr = (float*)(w + y.zr);
+  g.flag = (int*)(w + y.flag);
+  g.perm = (int*)(w + y.perm);
+  g.cellcode = (int*)(w + y.cellcode);
+  g.cellstart = (int*)(w + y.cellstart);
+  g.cursor = (int*)(w + y.cursor);
+  g.xyzq = (float4*)(w + y.xyzq);
+  g.prm = (float4*)(w + y.prm);
+  g.bblo = (float4*)(w + y.bblo);
+  g.bbhi = (float4*)(w + y.bbhi);
+  g.lcount = (int*)(w + y.lcount);
+  g.lent = (unsigned*)(w + y.lent);
+  g.grid64 = (long long*)(w + y.grid64);
+  g.cgrid = (float2*)(w + y.cgrid);
+  for (int d = 0; d < 3; ++d) { g.tw[d] = (float2*)(w + y.tw[d]); g.bmod[d] = (float*)(w + y.bmod[d]); }
+  g.eacc = (long long*)(w + y.eacc);
+  g.uacc = (long long*)(w + y.uacc);
+  g.err = c->d_err;
+  g.need = c->d_err + 1;
+  return g;
+}
+
+// Build descriptors for a batch; uploads the table when it changed.
+int prepare(felis_ctx* c, const felis_leg* legs, int n_legs, std::vector<LegHost>& hs) {
+  if (!c) return FELIS_E_INVAL;
+  if (n_legs < 1 || n_legs > kMaxLegs || !legs) return fail(c, FELIS_E_INVAL, "n_legs must be in [1, 64]");
+  std::vector<LegDev> devs(n_legs);
+  hs.resize(n_legs);
+  for (int i = 0; i < n_legs; ++i) {
+    Plan p;
+    int rc = make_plan(c, &legs[i], p);
+    if (rc) return rc;
+    auto it = c->meta.find(legs[i].work);
+    if (it == c->meta.end()) return fail(c, FELIS_E_INVAL, "leg not initialised (felis_leg_init)");
+    if (!legs[i].work || legs[i].work_bytes < p.lay.total) return fail(c, FELIS_E_INVAL, "leg work buffer too small");
+    p.h.nfree = it->second.nfree;
+    p.h.nlig = it->second.nlig;
+    hs[i] = p.h;
+    devs[i] = make_dev(c, &legs[i], p, it->second);
+  }
+  if ((int)c->cache.size() == n_legs && std::memcmp(c->cache.data(), devs.data(), sizeof(LegDev) * n_legs) == 0)
+    return FELIS_OK;
+  std::memcpy(c->h_stage, devs.data(), sizeof(LegDev) * n_legs);
+  if (hipMemcpyAsync(c->d_legs, c->h_stage, sizeof(LegDev) * n_legs, hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+      hipStreamSynchronize(c->stream) != hipSuccess)
+    return fail(c, FELIS_E_DEVICE, "descriptor upload failed");
+  c->cache = devs;
+  return FELIS_OK;
+}
+
+// Records an event for timer t when profiling is on (start when stop == false).
+void mark(felis_ctx* c, int t, bool stop) {
+  if (!c->prof) return;
+  Timer& T = c->timers[t];
+  if (!stop && T.used + 2 > T.ev.size()) {
+    for (int k = 0; k < 2; ++k) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return;
+      T.ev.push_back(e);
+    }
+  }
+  if (!stop && T.used + 2 > T.ev.size()) return;
+  (void)hipEventRecord(T.ev[T.used], c->stream);
+  ++T.used;
+}
+
+int launched(felis_ctx* c) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(c, FELIS_E_DEVICE, hipGetErrorString(e));
+  return FELIS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int felis_create(felis_ctx** out, int device, void* hip_stream) {
+  if (!out) return FELIS_E_INVAL;
+  *out = nullptr;
+  if (hipSetDevice(device) != hipSuccess) return FELIS_E_DEVICE;
+  felis_ctx* c = new felis_ctx();
+  c->device = device;
+  c->stream = (hipStream_t)hip_stream;
+  if (hipMalloc((void**)&c->d_legs, sizeof(LegDev) * kMaxLegs) != hipSuccess ||
+      hipHostMalloc((void**)&c->h_stage, sizeof(LegDev) * kMaxLegs, hipHostMallocDefault) != hipSuccess ||
+      hipMalloc((void**)&c->d_err, 4 * sizeof(int)) != hipSuccess ||
+      hipMalloc((void**)&c->d_count, sizeof(unsigned long long)) != hipSuccess ||
+      hipMemset(c->d_err, 0, 4 * sizeof(int)) != hipSuccess) {
+    felis_destroy(c);
+    return FELIS_E_DEVICE;
+  }
+  *out = c;
+  return FELIS_OK;
+}
+
+void felis_destroy(felis_ctx* c) {
+  if (!c) return;
+  if (c->stream) (void)hipStreamSynchronize(c->stream); else (void)hipDeviceSynchronize();
+  if (c->d_legs) (void)hipFree(c->d_legs);
+  if (c->h_stage) (void)hipHostFree(c->h_stage);
+  if (c->d_err) (void)hipFree(c->d_err);
+  if (c->d_count) (void)hipFree(c->d_count);
+  for (auto& T : c->timers)
+    for (hipEvent_t e : T.ev) (void)hipEventDestroy(e);
+  delete c;
+}
+
+const char* felis_last_error(const felis_ctx* c) { return c ? c->last_error.c_str() : "null context"; }
+
+int felis_check(felis_ctx* c, int32_t* needed_cap) {
+  if (!c) return FELIS_E_INVAL;
+  int e[4] = {0, 0, 0, 0};
+  if (hipStreamSynchronize(c->stream) != hipSuccess ||
+      hipMemcpy(e, c->d_err, sizeof(e), hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemset(c->d_err, 0, 4 * sizeof(int)) != hipSuccess)
+    return fail(c, FELIS_E_DEVICE, "device error word unreadable");
+  if (needed_cap) *needed_cap = e[1];
+  if (e[0] & kErrListCap) return fail(c, FELIS_E_CAPACITY, "neighbour list capacity exceeded (raise list_cap)");
+  if (e[0] & kErrOverflow) {
+    static const char* sites[] = {"?", "pair forces", "pair energies", "excluded pairs", "bonded/restraint",
+                                  "PME gather", "PME energy", "u_kn", "self", "energy sum"};
+    char msg[200];
+    const int st = (e[2] >= 0 && e[2] <= 9) ? e[2] : 0;
+    std::snprintf(msg, sizeof msg, "fixed-point overflow or non-finite value (first at %s, window %d, atom %d)",
+                  sites[st], e[3] >> 20, e[3] & 0xfffff);
+    return fail(c, FELIS_E_OVERFLOW, msg);
+  }
+  if (e[0] & kErrExcl) return fail(c, FELIS_E_UNSUPPORTED, "an atom has more than 8 exclusions");
+  if (e[0]) return fail(c, FELIS_E_INVAL, "device reported an invalid configuration");
+  return FELIS_OK;
+}
+
+int felis_leg_work_size(const felis_leg* leg, size_t* bytes) {
+  if (!bytes) return FELIS_E_INVAL;
+  Plan p;
+  int rc = make_plan(nullptr, leg, p);
+  if (rc) return rc;
+  *bytes = p.lay.total;
+  return FELIS_OK;
+}
+
+int felis_leg_init(felis_ctx* c, felis_leg* L) {
+  if (!c) return FELIS_E_INVAL;
+  Plan p;
+  int rc = make_plan(c, L, p);
+  if (rc) return rc;
+  if (!L->work || L->work_bytes < p.lay.total) return fail(c, FELIS_E_INVAL, "leg work buffer too small");
+  const LegHost& h = p.h;
+  char* w = (char*)L->work;
+  const Layout& y = p.lay;
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return fail(c, FELIS_E_DEVICE, "stream sync failed");
+  // topology facts
+  std::vector<uint8_t> lig(h.n);
+  std::vector<int> wat(3 * (size_t)h.nwat);
+  if (hipMemcpy(lig.data(), L->is_ligand, h.n, hipMemcpyDeviceToHost) != hipSuccess)
+    return fail(c, FELIS_E_DEVICE, "is_ligand copy failed");
+  if (h.nwat && hipMemcpy(wat.data(), L->water_ohh, wat.size() * 4, hipMemcpyDeviceToHost) != hipSuccess)
+    return fail(c, FELIS_E_DEVICE, "water copy failed");
+  std::vector<char> inwat(h.n, 0);
+  for (int v : wat) {
+    if (v < 0 || v >= h.n || inwat[v]) return fail(c, FELIS_E_INVAL, "water atom out of range or repeated");
+    inwat[v] = 1;
+  }
+  std::vector<int> freeat, ligi;
+  for (int a = 0; a < h.n; ++a) {
+    if (!inwat[a]) freeat.push_back(a);
+    if (lig[a]) ligi.push_back(a);
+  }
+  // lambda table: elec, vdw, restraint, sc_alpha (1 - vdw)
+  std::vector<float> lam(4 * (size_t)h.W);
+  for (int k = 0; k < h.W; ++k) {
+    const double le = L->lambdas[3 * k], lv = L->lambdas[3 * k + 1], lr = L->lambdas[3 * k + 2];
+    if (!(le >= 0 && le <= 1 && lv >= 0 && lv <= 1 && lr >= 0 && lr <= 1))
+      return fail(c, FELIS_E_INVAL, "lambdas must lie in [0, 1]");
+    lam[4 * k] = (float)le; lam[4 * k + 1] = (float)lv; lam[4 * k + 2] = (float)lr;
+    lam[4 * k + 3] = (float)(L->sc_alpha * (1.0 - lv));
+  }
+  bool ok = hipMemcpy(w + y.lam, lam.data(), lam.size() * 4, hipMemcpyHostToDevice) == hipSuccess;
+  if (!freeat.empty()) ok &= hipMemcpy(w + y.free_atoms, freeat.data(), freeat.size() * 4, hipMemcpyHostToDevice) == hipSuccess;
+  if (!ligi.empty()) ok &= hipMemcpy(w + y.lig_idx, ligi.data(), ligi.size() * 4, hipMemcpyHostToDevice) == hipSuccess;
+  for (int d = 0; d < 3; ++d) {
+    const int K = h.K[d];
+    std::vector<float> tw(2 * (size_t)K), bm(K);
+    for (int k = 0; k < K; ++k) {
+      const double a = 2.0 * M_PI * k / K;
+      tw[2 * k] = (float)std::cos(a);
+      tw[2 * k + 1] = (float)-std::sin(a);
+      const double den = (2.0 + std::cos(a)) / 3.0;     // order-4 Euler spline denominator
+      bm[k] = (float)(1.0 / (den * den));
+    }
+    ok &= hipMemcpy(w + y.tw[d], tw.data(), tw.size() * 4, hipMemcpyHostToDevice) == hipSuccess;
+    ok &= hipMemcpy(w + y.bmod[d], bm.data(), bm.size() * 4, hipMemcpyHostToDevice) == hipSuccess;
+  }
+  // zeroed accumulators and grids, forced list build
+  const float far = 1.0e18f;
+  unsigned farbits;
+  std::memcpy(&farbits, &far, 4);
+  ok &= hipMemsetD32Async((hipDeviceptr_t)(w + y.xr), farbits, 3 * ((y.yr - y.xr) / 4), c->stream) == hipSuccess;
+  ok &= hipMemsetD32Async((hipDeviceptr_t)(w + y.flag), 1, h.W, c->stream) == hipSuccess;
+  ok &= hipMemsetAsync(w + y.lcount, 0, (size_t)h.W * h.nclus * 4, c->stream) == hipSuccess;
+  ok &= hipMemsetAsync(w + y.grid64, 0, y.cgrid - y.grid64, c->stream) == hipSuccess;
+  ok &= hipMemsetAsync(w + y.eacc, 0, y.ucst - y.eacc, c->stream) == hipSuccess;
+  ok &= hipStreamSynchronize(c->stream) == hipSuccess;
+  if (!ok) return fail(c, FELIS_E_DEVICE, "leg initialisation copies failed");
+  Meta m;
+  m.nfree = (int)freeat.size();
+  m.nlig = (int)ligi.size();
+  m.work_bytes = L->work_bytes;
+  c->meta[L->work] = m;
+  c->cache.clear();
+  return FELIS_OK;
+}
+
+int felis_build_nlist(felis_ctx* c, felis_leg* legs, int n_legs, int force) {
+  std::vector<LegHost> hs;
+  int rc = prepare(c, legs, n_legs, hs);
+  if (rc) return rc;
+  launch_check(c->stream, c->d_legs, hs.data(), n_legs, force ? 1 : 0);
+  launch_build(c->stream, c->d_legs, hs.data(), n_legs);
+  return launched(c);
+}
+
+int felis_nlist_export_pairs(felis_ctx* c, const felis_leg* leg, int window, double r, int32_t* pairs,
+                             int64_t cap, int64_t* n_pairs) {
+  std::vector<LegHost> hs;
+  int rc = prepare(c, leg, 1, hs);
+  if (rc) return rc;
+  if (window < 0 || window >= leg->n_windows || !n_pairs || (cap > 0 && !pairs))
+    return fail(c, FELIS_E_INVAL, "export arguments");
+  unsigned long long cnt = 0;
+  if (hipMemsetAsync(c->d_count, 0, sizeof(cnt), c->stream) != hipSuccess) return fail(c, FELIS_E_DEVICE, "memset");
+  launch_export(c->stream, c->d_legs, hs[0], window, r, pairs, cap, c->d_count);
+  if ((rc = launched(c))) return rc;
+  if (hipMemcpyAsync(&cnt, c->d_count, sizeof(cnt), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+      hipStreamSynchronize(c->stream) != hipSuccess)
+    return fail(c, FELIS_E_DEVICE, "export count copy failed");
+  *n_pairs = (int64_t)cnt;
+  return (int64_t)cnt > cap ? fail(c, FELIS_E_CAPACITY, "export buffer too small") : FELIS_OK;
+}
+
+int felis_nonbonded(felis_ctx* c, felis_leg* legs, int n_legs, int flags) {
+  std::vector<LegHost> hs;
+  int rc = prepare(c, legs, n_legs, hs);
+  if (rc) return rc;
+  const bool en = flags & FELIS_ENERGY;
+  if (en) launch_zero_energy(c->stream, c->d_legs, hs.data(), n_legs, FELIS_E_COUL_REAL, FELIS_E_SELF + 1);
+  launch_pack(c->stream, c->d_legs, hs.data(), n_legs);
+  launch_pairs(c->stream, c->d_legs, hs.data(), n_legs, en);
+  launch_corrections(c->stream, c->d_legs, hs.data(), n_legs, en);
+  if (en) launch_finish_energy(c->stream, c->d_legs, hs.data(), n_legs, FELIS_E_COUL_REAL, FELIS_E_SELF + 1);
+  return launched(c);
+}
+
+int felis_pme(felis_ctx* c, felis_leg* legs, int n_legs, int flags) {
+  std::vector<LegHost> hs;
+  int rc = prepare(c, legs, n_legs, hs);
+  if (rc) return rc;
+  const bool en = flags & FELIS_ENERGY;
+  if (en) launch_zero_energy(c->stream, c->d_legs, hs.data(), n_legs, FELIS_E_RECIP, FELIS_E_RECIP + 1);
+  launch_pme(c->stream, c->d_legs, hs.data(), n_legs, en);
+  if (en) launch_finish_energy(c->stream, c->d_legs, hs.data(), n_legs, FELIS_E_RECIP, FELIS_E_RECIP + 1);
+  return launched(c);
+}
+
+int felis_bonded(felis_ctx* c, felis_leg* legs, int n_legs, int flags) {
+  std::vector<LegHost> hs;
+  int rc = prepare(c, legs, n_legs, hs);
+  if (rc) return rc;
+  const bool en = flags & FELIS_ENERGY;
+  if (en) launch_zero_energy(c->stream, c->d_legs, hs.data(), n_legs, FELIS_E_BOND, FELIS_E_RESTRAINT + 1);
+  launch_bonded(c->stream, c->d_legs, hs.data(), n_legs, en);
+  if (en) launch_finish_energy(c->stream, c->d_legs, hs.data(), n_legs, FELIS_E_BOND, FELIS_E_RESTRAINT + 1);
+  return launched(c);
+}
+
+int felis_step(felis_ctx* c, felis_leg* legs, int n_legs, int n_steps, double dt, double temperature,
+               double gamma) {
+  std::vector<LegHost> hs;
+  int rc = prepare(c, legs, n_legs, hs);
+  if (rc) return rc;
+  if (n_steps < 0 || !(dt > 0) || !(temperature >= 0) || !(gamma >= 0))
+    return fail(c, FELIS_E_INVAL, "n_steps, dt, temperature, gamma");
+  std::vector<long long> step(n_legs);
+  std::vector<unsigned long long> seed(n_legs);
+  for (int s = 0; s < n_steps; ++s) {
+    for (int i = 0; i < n_legs; ++i) { step[i] = legs[i].step + s; seed[i] = legs[i].seed; }
+    mark(c, FELIS_PROF_NLIST, false);
+    launch_check(c->stream, c->d_legs, hs.data(), n_legs, 0);
+    launch_build(c->stream, c->d_legs, hs.data(), n_legs);
+    mark(c, FELIS_PROF_NLIST, true);
+    launch_pack(c->stream, c->d_legs, hs.data(), n_legs);
+    mark(c, FELIS_PROF_PAIRS, false);
+    launch_pairs(c->stream, c->d_legs, hs.data(), n_legs, false);
+    mark(c, FELIS_PROF_PAIRS, true);
+    launch_corrections(c->stream, c->d_legs, hs.data(), n_legs, false);
+    launch_bonded(c->stream, c->d_legs, hs.data(), n_legs, false);
+    mark(c, FELIS_PROF_PME, false);
+    launch_pme(c->stream, c->d_legs, hs.data(), n_legs, false);
+    mark(c, FELIS_PROF_PME, true);
+    mark(c, FELIS_PROF_INTEGRATE, false);
+    launch_integrate(c->stream, c->d_legs, hs.data(), n_legs, step.data(), seed.data(), (float)dt,
+                     (float)temperature, (float)gamma);
+    mark(c, FELIS_PROF_INTEGRATE, true);
+  }
+  for (int i = 0; i < n_legs; ++i) legs[i].step += n_steps;
+  return launched(c);
+}
+
+int felis_ukn(felis_ctx* c, felis_leg* leg, const double* lambdas, int K, const float* fx, const float* fy,
+              const float* fz, int64_t frame_stride, int64_t n_frames, double beta, double* u, int64_t u_stride) {
+  std::vector<LegHost> hs;
+  int rc = prepare(c, leg, 1, hs);
+  if (rc) return rc;
+  if (!lambdas || !fx || !fy || !fz || !u || K < 1 || n_frames < 0 || frame_stride < leg->n_atoms ||
+      u_stride < n_frames)
+    return fail(c, FELIS_E_INVAL, "u_kn arguments");
+  for (int k = 0; k < K; ++k)
+    for (int t = 0; t < 3; ++t)
+      if (!(lambdas[3 * k + t] >= 0 && lambdas[3 * k + t] <= 1)) return fail(c, FELIS_E_INVAL, "lambdas in [0, 1]");
+  Plan p;
+  make_plan(c, leg, p);
+  char* w = (char*)leg->work;
+  mark(c, FELIS_PROF_UKN, false);
+  rc = launch_ukn(c->stream, c->d_legs, hs[0], leg->sc_alpha, lambdas, K, fx, fy, fz, frame_stride, n_frames, beta,
+                  u, u_stride, (long long*)(w + p.lay.uacc), (double*)(w + p.lay.ucst));
+  mark(c, FELIS_PROF_UKN, true);
+  if (rc) return fail(c, rc, "u_kn: more than 128 states, 64 distinct lambda_vdw or 256 ligand atoms");
+  return launched(c);
+}
+
+int felis_profile(felis_ctx* c, int enable) {
+  if (!c) return FELIS_E_INVAL;
+  c->prof = enable != 0;
+  return FELIS_OK;
+}
+
+int felis_profile_read(felis_ctx* c, int which, double* total_ms, int64_t* launches) {
+  if (!c || which < 0 || which >= FELIS_PROF_N || !total_ms || !launches) return FELIS_E_INVAL;
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return fail(c, FELIS_E_DEVICE, "stream sync failed");
+  Timer& T = c->timers[which];
+  double tot = 0.0;
+  int64_t n = 0;
+  for (size_t k = 0; k + 1 < T.used; k += 2) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, T.ev[k], T.ev[k + 1]) != hipSuccess) return fail(c, FELIS_E_DEVICE, "event timing");
+    tot += ms;
+    ++n;
+  }
+  T.used = 0;
+  *total_ms = tot;
+  *launches = n;
+  return FELIS_OK;
+}
+
+int felis_mbar_work_size(int K, int64_t n_total, size_t* bytes) {
+  if (!bytes || K < 2 || n_total < 1) return FELIS_E_INVAL;
+  *bytes = mbar_work_bytes(K, n_total);
+  return FELIS_OK;
+}
+
+int felis_mbar(felis_ctx* c, const double* u, const int32_t* N_k, int K, int64_t n_total, double rel_tol,
+               int max_iter, double* f_out, int* iters, void* work, size_t work_bytes) {
+  if (!c) return FELIS_E_INVAL;
+  int rc = launch_mbar(c->stream, u, N_k, K, n_total, rel_tol, max_iter, f_out, iters, work, work_bytes);
+  if (rc == FELIS_E_INVAL) return fail(c, rc, "MBAR arguments (K in [2, 512], sum N_k = n_total, work size)");
+  if (rc == FELIS_E_NOCONV) return fail(c, rc, "MBAR did not converge within max_iter");
+  if (rc) return fail(c, rc, "MBAR device error");
+  return launched(c);
+}
+
+}  // extern "C"

@@ -1,0 +1,176 @@
+// Internal definitions shared by the HIP kernels and the C-ABI host code.
+// Not part of the public interface (see include/felis.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include "../../include/felis.h"
+
+namespace felis {
+
+constexpr int kMaxLegs = 64;        // legs per batched launch
+constexpr int kMaxExcl = 8;         // exclusions per atom handled by the list build
+constexpr int kMaxLigand = 256;     // ligand atoms handled by the u_kn kernels
+constexpr int kMaxLamV = 64;        // distinct lambda_vdw values per u_kn call
+constexpr int kMaxStates = 128;     // lambda states per u_kn call
+constexpr int kMaxRadix = 8;        // FFT stages per axis
+constexpr int kMaxFFT = 128;        // largest PME grid dimension
+constexpr int kClus = 8;            // atoms per i-cluster (pair kernel)
+
+constexpr double kKE = 332.06371;                 // kcal A / (mol e^2)
+constexpr double kKB = 0.0019872043;              // kcal / (mol K)
+constexpr double kAccel = 418.4;                  // (kcal/mol/A/amu) -> A/ps^2
+constexpr double kForceScale = 4294967296.0;      // 2^32 int64 units per kcal/mol/A
+constexpr double kGridScale = 1099511627776.0;    // 2^40 int64 units per e
+constexpr double kEnergyScale = 1073741824.0;     // 2^30 int64 units per kcal/mol
+
+// error bits in the context's device error word
+enum : int {
+  kErrListCap = 1,       // a cluster's neighbour list exceeded its capacity
+  kErrOverflow = 2,      // fixed-point range exceeded or non-finite force/energy
+  kErrExcl = 4,          // an atom has more than kMaxExcl exclusions
+  kErrBox = 8,           // cutoff or list radius inconsistent with the box
+};
+
+// Per-leg device descriptor: sizes, parameters, and pointers into the
+// caller's state and the leg's private workspace.
+struct LegDev {
+  int n, W, npad, nclus, cap;           // atoms, windows, padded atoms, clusters, list cap
+  int nexcl, nbonds, nwat, nfree, nlig;
+  int K[3], Ktot, npair;
+  int nbits, ncoarse, ncell;            // fine cells = 2^nbits per axis (Morton order)
+  int nrad[3], rad[3][kMaxRadix];       // FFT radix plan per axis
+  int has_rest, ranch[6];
+  float rg0[6], rk[6];
+  double L[3], invL[3];
+  float Lf[3], invLf[3];
+  float rc2, alpha, sc_alpha, skin_half2;
+  double rlist, rlist2;
+  float d_oh, d_hh;
+  float pme_pref;                       // KE / (pi V)
+  float self_pref;                      // KE alpha / sqrt(pi)
+  double bg_pref;                       // KE pi / (2 V alpha^2)
+  // topology (caller-owned)
+  const float *q, *sig, *eps, *mass;
+  const uint8_t* lig;
+  const int *excl_ij, *excl_ptr, *excl_idx;
+  const int* bond_ij;
+  const float *bond_k, *bond_r0;
+  const int* water;
+  // state (caller-owned) [W][n]
+  float *x, *y, *z, *vx, *vy, *vz;
+  long long *fx, *fy, *fz;
+  double* energy;                       // [W][FELIS_NE]
+  // workspace (library-owned layout)
+  float* lam;                           // [W][4] elec, vdw, restraint, sc_alpha*(1-vdw)
+  int* free_atoms;                      // [nfree] atoms not in a rigid water
+  int* lig_idx;                         // [nlig] ligand atoms
+  float *xr, *yr, *zr;                  // [W][n] positions at the last list build
+  int* flag;                            // [W] rebuild flags
+  int* perm;                            // [W][npad] sorted slot -> atom (-1 = padding)
+  int* cellcode;                        // [W][n]
+  int* cellstart;                       // [W][ncell + 1]
+  int* cursor;                          // [W][ncell]
+  float4* xyzq;                         // [W][npad] x, y, z, q_scaled * sqrt(KE)
+  float4* prm;                          // [W][npad] sigma/2, 2 sqrt(eps), ligand flag, q
+  float4* bblo;                         // [W][nclus] cluster bounding boxes (wrapped)
+  float4* bbhi;
+  int* lcount;                          // [W][nclus]
+  unsigned* lent;                       // [W][nclus][cap] (slot << 8 | 8-bit i mask)
+  long long* grid64;                    // [W][Ktot] fixed-point charge grids
+  float2* cgrid;                        // [npair][Ktot] complex grids
+  float2* tw[3];                        // [K] exp(-2 pi i k / K) per axis
+  float* bmod[3];                       // [K] B-spline moduli factor per axis
+  long long* eacc;                      // [W][FELIS_NE] fixed-point energies
+  long long* uacc;                      // [npair][3 + kMaxLamV] u_kn accumulators
+  int* err;                             // context error word
+  int* need;                            // context: largest list length seen
+};
+
+// Maps a flat block index to (leg, block within leg) for batched launches.
+struct BlockMap {
+  int n_legs;
+  int start[kMaxLegs + 1];
+};
+
+__device__ __forceinline__ int find_leg(const BlockMap& m, int b) {
+  int lo = 0, hi = m.n_legs - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (m.start[mid] <= b) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Sites that convert to fixed point; the first overflow records its site and
+// the window/atom (or item) it happened at in err[2], err[3].
+enum : int {
+  kSitePairs = 1, kSitePairsE = 2, kSiteExcl = 3, kSiteBonded = 4, kSiteGather = 5, kSiteGatherE = 6,
+  kSiteUkn = 7, kSiteSelf = 8, kSiteEnergy = 9
+};
+
+__device__ __forceinline__ long long to_fixed(double v, double scale, int* err, int site = 0, int where = -1) {
+  double s = v * scale;
+  if (!(fabs(s) < 9.0e18)) {
+    atomicOr(err, kErrOverflow);
+    if (atomicCAS(&err[2], 0, site ? site : -1) == 0) err[3] = where;
+    return 0;
+  }
+  return __double2ll_rn(s);
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ __forceinline__ float wrapf(float x, float L, float invL) {
+  return x - L * floorf(x * invL);
+}
+
+// Block-map construction on the host: blocks_of(leg) blocks for each leg.
+template <typename F>
+inline int make_map(BlockMap& m, int n_legs, F blocks_of) {
+  m.n_legs = n_legs;
+  int s = 0;
+  for (int i = 0; i < n_legs; ++i) { m.start[i] = s; s += blocks_of(i); }
+  m.start[n_legs] = s;
+  for (int i = n_legs + 1; i <= kMaxLegs; ++i) m.start[i] = s;
+  return s;
+}
+
+// Host-side mirror of the sizes each launcher needs.
+struct LegHost {
+  int n, W, npad, nclus, cap, nexcl, nbonds, nwat, nfree, nlig, K[3], Ktot, npair, ncell;
+  int has_rest;
+};
+
+// ---- launchers (one per translation unit) ----
+void launch_check(hipStream_t s, const LegDev* d, const LegHost* h, int nl, int force);
+void launch_build(hipStream_t s, const LegDev* d, const LegHost* h, int nl);
+void launch_export(hipStream_t s, const LegDev* d, const LegHost& h, int window, double r,
+                   int* pairs, long long cap, unsigned long long* count);
+void launch_pack(hipStream_t s, const LegDev* d, const LegHost* h, int nl);
+void launch_pairs(hipStream_t s, const LegDev* d, const LegHost* h, int nl, bool energy);
+void launch_corrections(hipStream_t s, const LegDev* d, const LegHost* h, int nl, bool energy);
+void launch_bonded(hipStream_t s, const LegDev* d, const LegHost* h, int nl, bool energy);
+void launch_pme(hipStream_t s, const LegDev* d, const LegHost* h, int nl, bool energy);
+void launch_integrate(hipStream_t s, const LegDev* d, const LegHost* h, int nl,
+                      const long long* step, const unsigned long long* seed, float dt,
+                      float temperature, float gamma);
+void launch_zero_energy(hipStream_t s, const LegDev* d, const LegHost* h, int nl, int c0, int c1);
+void launch_finish_energy(hipStream_t s, const LegDev* d, const LegHost* h, int nl, int c0, int c1);
+void launch_fill_i64(hipStream_t s, long long* p, size_t n);
+void launch_pme_fft(hipStream_t s, const LegDev* d, const LegHost* h, int nl);
+int launch_ukn(hipStream_t s, const LegDev* d, const LegHost& h, double sc_alpha, const double* lambdas,
+               int K, const float* fx, const float* fy, const float* fz, long long frame_stride,
+               long long n_frames, double beta, double* u, long long u_stride, long long* uacc,
+               double* cst);
+int launch_mbar(hipStream_t s, const double* u, const int* N_k, int K, long long Ntot, double tol,
+                int max_iter, double* f_out, int* iters, void* work, size_t work_bytes);
+size_t mbar_work_bytes(int K, long long Ntot);
+
+}  // namespace felis

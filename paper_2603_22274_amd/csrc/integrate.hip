@@ -1,0 +1,132 @@
+// Langevin-middle step with SETTLE rigid water (section "Simulation protocol":
+// LangevinMiddleIntegrator, rigid TIP3P).  Per window and atom, FP32:
+//   v += dt F/m;  dx = dt/2 v;  v = a v + sqrt((1 - a^2) kT/m) xi;  dx += dt/2 v;
+//   waters: SETTLE on (old, old + dx);  v += (dx_constrained - dx)/dt;  x += dx.
+// Displacements are kept relative to the old positions, so the constraint
+// solve runs on O(1 A) numbers at full FP32 precision.
+// xi: Philox4x32-10 (Salmon et al. 2011) on counter (atom, window, step_lo,
+// step_hi) and key (seed_lo, seed_hi); words -> u = ((w >> 8) + 1/2) 2^-24 ->
+// Box-Muller: (sqrt(-2 ln u0) cos 2pi u1, sqrt(-2 ln u0) sin 2pi u1,
+// sqrt(-2 ln u2) cos 2pi u3).
+#include "felis_internal.h"
+#include "settle.h"
+
+namespace felis {
+namespace {
+
+__device__ __forceinline__ void philox(unsigned c[4], unsigned k0, unsigned k1) {
+  const unsigned M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const unsigned hi0 = __umulhi(M0, c[0]), lo0 = M0 * c[0];
+    const unsigned hi1 = __umulhi(M1, c[2]), lo1 = M1 * c[2];
+    const unsigned n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+    c[0] = n0; c[1] = lo1; c[2] = n2; c[3] = lo0;
+    k0 += 0x9E3779B9u; k1 += 0xBB67AE85u;
+  }
+}
+
+__device__ __forceinline__ v3 noise3(unsigned long long seed, int window, long long step, int atom) {
+  unsigned c[4] = {(unsigned)atom, (unsigned)window, (unsigned)(step & 0xffffffffll),
+                   (unsigned)((unsigned long long)step >> 32)};
+  philox(c, (unsigned)(seed & 0xffffffffull), (unsigned)(seed >> 32));
+  float u[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) u[k] = ((float)(c[k] >> 8) + 0.5f) * 5.9604644775390625e-8f;
+  const float r1 = sqrtf(-2.0f * logf(u[0]));
+  const float r2 = sqrtf(-2.0f * logf(u[2]));
+  float s1, c1, s2, c2;
+  sincospif(2.0f * u[1], &s1, &c1);
+  sincospif(2.0f * u[3], &s2, &c2);
+  return mk(r1 * c1, r1 * s1, r2 * c2);
+}
+
+struct StepArgs {
+  long long step[kMaxLegs];
+  unsigned long long seed[kMaxLegs];
+  float dt, kT, gamma;
+};
+
+// kick, half drift, O step, half drift for one atom: returns the total
+// displacement and the post-O velocity
+__device__ __forceinline__ void advance(const LegDev& g, const StepArgs& S, int leg, int w, int a,
+                                        v3& dx, v3& vel) {
+  const size_t o = (size_t)w * g.n + a;
+  const float m = g.mass[a];
+  const float dt = S.dt;
+  const float acc = (float)kAccel / m;
+  const float F[3] = {(float)((double)g.fx[o] * (1.0 / kForceScale)),
+                      (float)((double)g.fy[o] * (1.0 / kForceScale)),
+                      (float)((double)g.fz[o] * (1.0 / kForceScale))};
+  v3 v = mk(g.vx[o] + dt * F[0] * acc, g.vy[o] + dt * F[1] * acc, g.vz[o] + dt * F[2] * acc);
+  const float hd = 0.5f * dt;
+  dx = vmul(v, hd);
+  const float ea = expf(-S.gamma * dt);
+  const float sd = sqrtf((1.0f - ea * ea) * S.kT * acc);
+  const v3 xi = noise3(S.seed[leg], w, S.step[leg], a);
+  v = vadd(vmul(v, ea), vmul(xi, sd));
+  dx = vadd(dx, vmul(v, hd));
+  vel = v;
+}
+
+__device__ __forceinline__ void store(const LegDev& g, int w, int a, v3 dx, v3 v) {
+  const size_t o = (size_t)w * g.n + a;
+  g.x[o] += dx.x; g.y[o] += dx.y; g.z[o] += dx.z;
+  g.vx[o] = v.x; g.vy[o] = v.y; g.vz[o] = v.z;
+}
+
+// items: window x unit (rigid waters first, then every other atom)
+__global__ __launch_bounds__(256) void k_integrate(const LegDev* legs, BlockMap map, StepArgs S) {
+  const int leg = find_leg(map, blockIdx.x);
+  const LegDev& g = legs[leg];
+  const long long i = (long long)(blockIdx.x - map.start[leg]) * blockDim.x + threadIdx.x;
+  const int units = g.nwat + g.nfree;
+  if (i >= (long long)g.W * units) return;
+  const int w = (int)(i / units);
+  const int u = (int)(i - (long long)w * units);
+  if (u >= g.nwat) {
+    const int a = g.free_atoms[u - g.nwat];
+    v3 dx, v;
+    advance(g, S, leg, w, a, dx, v);
+    store(g, w, a, dx, v);
+    return;
+  }
+  const int ao = g.water[3 * u], ah1 = g.water[3 * u + 1], ah2 = g.water[3 * u + 2];
+  v3 dO, dH1, dH2, vO, vH1, vH2;
+  advance(g, S, leg, w, ao, dO, vO);
+  advance(g, S, leg, w, ah1, dH1, vH1);
+  advance(g, S, leg, w, ah2, dH2, vH2);
+  const size_t base = (size_t)w * g.n;
+  const v3 xo = mk(g.x[base + ao], g.y[base + ao], g.z[base + ao]);
+  const v3 b0 = vsub(mk(g.x[base + ah1], g.y[base + ah1], g.z[base + ah1]), xo);
+  const v3 c0 = vsub(mk(g.x[base + ah2], g.y[base + ah2], g.z[base + ah2]), xo);
+  v3 a1 = dO, b1 = vadd(b0, dH1), c1 = vadd(c0, dH2);
+  const v3 a1u = a1, b1u = b1, c1u = c1;
+  settle(b0, c0, a1, b1, c1, g.mass[ao], g.mass[ah1], g.d_oh, g.d_hh);
+  const float idt = 1.0f / S.dt;
+  vO = vadd(vO, vmul(vsub(a1, a1u), idt));
+  vH1 = vadd(vH1, vmul(vsub(b1, b1u), idt));
+  vH2 = vadd(vH2, vmul(vsub(c1, c1u), idt));
+  store(g, w, ao, a1, vO);
+  store(g, w, ah1, vsub(b1, b0), vH1);
+  store(g, w, ah2, vsub(c1, c0), vH2);
+}
+
+}  // namespace
+
+void launch_integrate(hipStream_t s, const LegDev* d, const LegHost* h, int nl, const long long* step,
+                      const unsigned long long* seed, float dt, float temperature, float gamma) {
+  BlockMap m;
+  const int nb = make_map(m, nl, [&](int i) {
+    return (int)(((long long)h[i].W * (h[i].nwat + h[i].nfree) + 255) / 256);
+  });
+  if (!nb) return;
+  StepArgs S;
+  for (int i = 0; i < nl; ++i) { S.step[i] = step[i]; S.seed[i] = seed[i]; }
+  S.dt = dt;
+  S.kT = (float)(kKB * temperature);
+  S.gamma = gamma;
+  hipLaunchKernelGGL(k_integrate, dim3(nb), dim3(256), 0, s, d, m, S);
+}
+
+}  // namespace felis

@@ -1,0 +1,384 @@
+// Real-space alchemical pair kernel, Ewald corrections, bonds and the Boresch
+// restraint.
+//
+// Pair terms follow section "Double annihilation protocol": ligand charges
+// scaled by lambda_elec; Beutler softcore U = lam 4 eps (s6^2/s^2 - s6/s),
+// s = alpha (1 - lam) s6 + r^6 (p = 1), lam = lambda_vdw for any pair touching
+// the ligand and 1 otherwise; Lorentz-Berthelot mixing; everything cut at r_c
+// (appendix B).  Real-space Coulomb is the Ewald direct term erfc(a r)/r.
+//
+// Pair kernel layout (gfx950, wave64): one wave per 8-atom i-cluster; lane
+// l = ii + 8 jj holds i-atom ii and, per iteration, the jj-th of 8 listed
+// j-atoms.  Each cluster lists all its partners (both directions), so every
+// atom's pair force is summed by one wave in a fixed order and written once:
+// no atomics and no cross-wave ordering.  FP32 arithmetic; energies summed in
+// FP64 per lane and combined in int64 fixed point.
+#include "felis_internal.h"
+#include "erfc_coeffs.h"
+#include "restraint.h"
+
+namespace felis {
+namespace {
+
+__device__ __forceinline__ float erfc_fit(float x, float* ex) {
+  const float t = __builtin_amdgcn_rcpf(fmaf(FELIS_ERFC_P, x, 1.0f));
+  float p = felis_erfc_c[0];
+#pragma unroll
+  for (int k = 1; k < FELIS_ERFC_NC; ++k) p = fmaf(p, t, felis_erfc_c[k]);
+  const float e = __expf(-x * x);
+  *ex = e;
+  return p * t * e;
+}
+
+// items: window x slot -- current coordinates and scaled charges in sorted order
+__global__ __launch_bounds__(256) void k_pack(const LegDev* legs, BlockMap map) {
+  const int leg = find_leg(map, blockIdx.x);
+  const LegDev& g = legs[leg];
+  const long long i = (long long)(blockIdx.x - map.start[leg]) * blockDim.x + threadIdx.x;
+  if (i >= (long long)g.W * g.npad) return;
+  const int w = (int)(i / g.npad);
+  const int a = g.perm[i];
+  float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+  if (a >= 0) {
+    const size_t o = (size_t)w * g.n + a;
+    const float q = g.q[a] * (g.lig[a] ? g.lam[4 * w] : 1.0f);
+    v = make_float4(g.x[o], g.y[o], g.z[o], q * (float)sqrt(kKE));
+  }
+  g.xyzq[i] = v;
+}
+
+template <bool ENERGY>
+__global__ __launch_bounds__(256) void k_pairs(const LegDev* legs, BlockMap map) {
+  const int leg = find_leg(map, blockIdx.x);
+  const LegDev& g = legs[leg];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const long long item = (long long)(blockIdx.x - map.start[leg]) * 4 + wave;
+  if (item >= (long long)g.W * g.nclus) return;
+  const int w = (int)(item / g.nclus);
+  const int c = (int)(item - (long long)w * g.nclus);
+  const int ii = lane & 7, jj = lane >> 3;
+  const float4* __restrict__ xq = g.xyzq + (size_t)w * g.npad;
+  const float4* __restrict__ pr = g.prm + (size_t)w * g.npad;
+  const float4 xi = xq[c * kClus + ii];
+  const float4 pi = pr[c * kClus + ii];
+  const float lam_v = g.lam[4 * w + 1];
+  const float a_sc = g.lam[4 * w + 3];
+  const bool soft_window = lam_v < 1.0f;
+  const float Lx = g.Lf[0], Ly = g.Lf[1], Lz = g.Lf[2];
+  const float iLx = g.invLf[0], iLy = g.invLf[1], iLz = g.invLf[2];
+  const float rc2 = g.rc2, alpha = g.alpha;
+  const float c2a = 2.0f * alpha * 0.56418958354775628f;   // 2 alpha / sqrt(pi)
+  const unsigned* __restrict__ ent = g.lent + (size_t)item * g.cap;
+  const int cnt = g.lcount[item];
+  float fx = 0.f, fy = 0.f, fz = 0.f;
+  double ec = 0.0, el = 0.0;
+  for (int it = 0; it < cnt; it += 8) {
+    const unsigned e = ent[it + jj];
+    const int s = (int)(e >> 8);
+    const bool m = (e >> ii) & 1u;
+    const float4 xj = xq[s];
+    const float4 pj = pr[s];
+    float dx = xj.x - xi.x, dy = xj.y - xi.y, dz = xj.z - xi.z;
+    dx = fmaf(-Lx, rintf(dx * iLx), dx);
+    dy = fmaf(-Ly, rintf(dy * iLy), dy);
+    dz = fmaf(-Lz, rintf(dz * iLz), dz);
+    const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+    const bool in = m && (r2 < rc2);
+    const float r2s = in ? r2 : 1.0f;
+    const float rinv = __builtin_amdgcn_rsqf(r2s);
+    const float rinv2 = rinv * rinv;
+    const float r = r2s * rinv;
+    float ex;
+    const float erfcv = erfc_fit(alpha * r, &ex);
+    const float qq = xi.w * xj.w;
+    const float fc = qq * fmaf(erfcv, rinv, c2a * ex) * rinv2;
+    const float sig = pi.x + pj.x;
+    const float eps4 = pi.y * pj.y;
+    const bool ligp = (pi.z + pj.z) > 0.0f;
+    float flj, elj = 0.0f;
+    if (soft_window && __ballot(in && ligp) != 0ull) {
+      const float lam = ligp ? lam_v : 1.0f;
+      const float a = ligp ? a_sc : 0.0f;
+      const float s2 = sig * sig;
+      const float s6 = s2 * s2 * s2;
+      const float r4 = r2s * r2s;
+      const float den = fmaf(a, s6, r4 * r2s);
+      const float inv = __builtin_amdgcn_rcpf(den);
+      const float u = s6 * inv;
+      const float le = lam * eps4;
+      flj = 6.0f * le * fmaf(2.0f, u, -1.0f) * u * inv * r4;
+      if (ENERGY) elj = le * fmaf(u, u, -u);
+    } else {
+      const float s2 = sig * sig * rinv2;
+      const float s6 = s2 * s2 * s2;
+      flj = eps4 * fmaf(12.0f, s6, -6.0f) * s6 * rinv2;
+      if (ENERGY) elj = eps4 * fmaf(s6, s6, -s6);
+    }
+    const float fs = in ? (fc + flj) : 0.0f;
+    fx = fmaf(-fs, dx, fx);
+    fy = fmaf(-fs, dy, fy);
+    fz = fmaf(-fs, dz, fz);
+    if (ENERGY && in) {
+      ec += (double)(qq * erfcv * rinv);
+      el += (double)elj;
+    }
+  }
+  for (int o = 8; o < 64; o <<= 1) {
+    fx += __shfl_xor(fx, o, 64);
+    fy += __shfl_xor(fy, o, 64);
+    fz += __shfl_xor(fz, o, 64);
+  }
+  if (jj == 0) {
+    const int a = g.perm[(size_t)w * g.npad + c * kClus + ii];
+    if (a >= 0) {
+      const size_t o = (size_t)w * g.n + a;
+      const int where = (w << 20) | a;
+      g.fx[o] = to_fixed((double)fx, kForceScale, g.err, kSitePairs, where);
+      g.fy[o] = to_fixed((double)fy, kForceScale, g.err, kSitePairs, where);
+      g.fz[o] = to_fixed((double)fz, kForceScale, g.err, kSitePairs, where);
+    }
+  }
+  if (ENERGY) {
+    ec = wave_sum(ec);
+    el = wave_sum(el);
+    if (lane == 0) {
+      long long* acc = g.eacc + (size_t)w * FELIS_NE;
+      atomicAdd((unsigned long long*)&acc[FELIS_E_COUL_REAL],
+                (unsigned long long)to_fixed(0.5 * ec, kEnergyScale, g.err, kSitePairsE, w));
+      atomicAdd((unsigned long long*)&acc[FELIS_E_LJ],
+                (unsigned long long)to_fixed(0.5 * el, kEnergyScale, g.err, kSitePairsE, w));
+    }
+  }
+}
+
+__device__ __forceinline__ void add_force(const LegDev& g, size_t o, float fx, float fy, float fz, int site) {
+  const int where = (int)o;
+  atomicAdd((unsigned long long*)&g.fx[o], (unsigned long long)to_fixed((double)fx, kForceScale, g.err, site, where));
+  atomicAdd((unsigned long long*)&g.fy[o], (unsigned long long)to_fixed((double)fy, kForceScale, g.err, site, where));
+  atomicAdd((unsigned long long*)&g.fz[o], (unsigned long long)to_fixed((double)fz, kForceScale, g.err, site, where));
+}
+
+__device__ __forceinline__ void add_energy(const LegDev& g, int w, int comp, double e, int lane) {
+  e = wave_sum(e);
+  if (lane == 0)
+    atomicAdd((unsigned long long*)&g.eacc[(size_t)w * FELIS_NE + comp],
+              (unsigned long long)to_fixed(e, kEnergyScale, g.err, kSiteEnergy, comp));
+}
+
+__device__ __forceinline__ float3 min_img(const LegDev& g, float dx, float dy, float dz) {
+  dx = fmaf(-g.Lf[0], rintf(dx * g.invLf[0]), dx);
+  dy = fmaf(-g.Lf[1], rintf(dy * g.invLf[1]), dy);
+  dz = fmaf(-g.Lf[2], rintf(dz * g.invLf[2]), dz);
+  return make_float3(dx, dy, dz);
+}
+
+// items: window x excluded pair -- remove the reciprocal interaction of
+// excluded pairs: E = -KE q_i q_j erf(alpha r)/r.
+template <bool ENERGY>
+__global__ __launch_bounds__(256) void k_excl(const LegDev* legs, BlockMap map) {
+  const int leg = find_leg(map, blockIdx.x);
+  const LegDev& g = legs[leg];
+  const long long i = (long long)(blockIdx.x - map.start[leg]) * blockDim.x + threadIdx.x;
+  const long long tot = (long long)g.W * g.nexcl;
+  const int lane = threadIdx.x & 63;
+  double e = 0.0;
+  int w = (int)(min(i, tot - 1) / max(g.nexcl, 1));
+  if (i < tot) {
+    const int p = (int)(i - (long long)w * g.nexcl);
+    const int a = g.excl_ij[2 * p], b = g.excl_ij[2 * p + 1];
+    const float le = g.lam[4 * w];
+    const float qa = g.q[a] * (g.lig[a] ? le : 1.f), qb = g.q[b] * (g.lig[b] ? le : 1.f);
+    const size_t oa = (size_t)w * g.n + a, ob = (size_t)w * g.n + b;
+    const float3 d = min_img(g, g.x[ob] - g.x[oa], g.y[ob] - g.y[oa], g.z[ob] - g.z[oa]);
+    const float r2 = d.x * d.x + d.y * d.y + d.z * d.z;
+    const float qq = (float)kKE * qa * qb;
+    const float c2a = 2.0f * g.alpha * 0.56418958354775628f;
+    float fs, en;
+    if (r2 > 1e-8f) {
+      const float r = sqrtf(r2), rinv = 1.0f / r;
+      const float erfv = erff(g.alpha * r);
+      en = -qq * erfv * rinv;
+      fs = qq * (c2a * __expf(-g.alpha * g.alpha * r2) - erfv * rinv) * rinv * rinv;
+    } else {
+      en = -qq * c2a;
+      fs = 0.f;
+    }
+    // F_a = fs (r_a - r_b) = -fs d
+    add_force(g, oa, -fs * d.x, -fs * d.y, -fs * d.z, kSiteExcl);
+    add_force(g, ob, fs * d.x, fs * d.y, fs * d.z, kSiteExcl);
+    e = en;
+  }
+  if (ENERGY) {
+    // waves may straddle windows: reduce per window present in the wave
+    const int w0 = __shfl(w, 0, 64);
+    const bool same = __ballot(i < tot && w != w0) == 0ull;
+    if (same) add_energy(g, w0, FELIS_E_EXCL, e, lane);
+    else if (i < tot) atomicAdd((unsigned long long*)&g.eacc[(size_t)w * FELIS_NE + FELIS_E_EXCL],
+                                (unsigned long long)to_fixed(e, kEnergyScale, g.err));
+  }
+}
+
+// one block per window: Ewald self term and neutralising background
+__global__ __launch_bounds__(256) void k_self(const LegDev* legs, BlockMap map) {
+  const int leg = find_leg(map, blockIdx.x);
+  const LegDev& g = legs[leg];
+  const int w = blockIdx.x - map.start[leg];
+  const double le = (double)g.lam[4 * w];
+  double s1 = 0.0, s2 = 0.0;
+  for (int a = threadIdx.x; a < g.n; a += blockDim.x) {
+    const double q = (double)g.q[a] * (g.lig[a] ? le : 1.0);
+    s1 += q; s2 += q * q;
+  }
+  __shared__ double r1[256], r2[256];
+  r1[threadIdx.x] = s1; r2[threadIdx.x] = s2;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) { r1[threadIdx.x] += r1[threadIdx.x + s]; r2[threadIdx.x] += r2[threadIdx.x + s]; }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double e = -(double)g.self_pref * r2[0] - g.bg_pref * r1[0] * r1[0];
+    atomicAdd((unsigned long long*)&g.eacc[(size_t)w * FELIS_NE + FELIS_E_SELF],
+              (unsigned long long)to_fixed(e, kEnergyScale, g.err));
+  }
+}
+
+__device__ __forceinline__ float3 vec(const LegDev& g, size_t ofrom, size_t oto) {
+  return min_img(g, g.x[oto] - g.x[ofrom], g.y[oto] - g.y[ofrom], g.z[oto] - g.z[ofrom]);
+}
+
+// items: window x (bonds + 1): harmonic bonds; the last item of a window is
+// the lambda_restraint-scaled Boresch restraint (section "Restraints").
+template <bool ENERGY>
+__global__ __launch_bounds__(256) void k_bonded(const LegDev* legs, BlockMap map) {
+  const int leg = find_leg(map, blockIdx.x);
+  const LegDev& g = legs[leg];
+  const long long i = (long long)(blockIdx.x - map.start[leg]) * blockDim.x + threadIdx.x;
+  const int per = g.nbonds + 1;
+  const long long tot = (long long)g.W * per;
+  const int lane = threadIdx.x & 63;
+  double eb = 0.0, er = 0.0;
+  const int w = (int)(min(i, tot - 1) / per);
+  if (i < tot) {
+    const int k = (int)(i - (long long)w * per);
+    const size_t base = (size_t)w * g.n;
+    if (k < g.nbonds) {
+      const int a = g.bond_ij[2 * k], b = g.bond_ij[2 * k + 1];
+      const float3 d = vec(g, base + b, base + a);          // r_a - r_b
+      const float r = sqrtf(d.x * d.x + d.y * d.y + d.z * d.z);
+      const float dr = r - g.bond_r0[k];
+      const float fs = -g.bond_k[k] * dr / r;                // F_a = fs (r_a - r_b)
+      add_force(g, base + a, fs * d.x, fs * d.y, fs * d.z, kSiteBonded);
+      add_force(g, base + b, -fs * d.x, -fs * d.y, -fs * d.z, kSiteBonded);
+      eb = 0.5 * (double)g.bond_k[k] * (double)dr * (double)dr;
+    } else if (g.has_rest && g.lam[4 * w + 2] != 0.0f) {
+      const float lr = g.lam[4 * w + 2];
+      v3 p[6], F[6];
+      const size_t o1 = base + g.ranch[0];
+      for (int t = 0; t < 6; ++t) {
+        const size_t ot = base + g.ranch[t];
+        const float3 d = min_img(g, g.x[ot] - g.x[o1], g.y[ot] - g.y[o1], g.z[ot] - g.z[o1]);
+        p[t] = mk(d.x, d.y, d.z);
+      }
+      er = (double)lr * boresch_eval(p, g.rg0, g.rk, F);
+      for (int t = 0; t < 6; ++t)
+        add_force(g, base + g.ranch[t], lr * F[t].x, lr * F[t].y, lr * F[t].z, kSiteBonded);
+    }
+  }
+  if (ENERGY) {
+    const int w0 = __shfl(w, 0, 64);
+    const bool same = __ballot(i < tot && w != w0) == 0ull;
+    if (same) {
+      add_energy(g, w0, FELIS_E_BOND, eb, lane);
+      add_energy(g, w0, FELIS_E_RESTRAINT, er, lane);
+    } else if (i < tot) {
+      long long* acc = g.eacc + (size_t)w * FELIS_NE;
+      atomicAdd((unsigned long long*)&acc[FELIS_E_BOND], (unsigned long long)to_fixed(eb, kEnergyScale, g.err));
+      atomicAdd((unsigned long long*)&acc[FELIS_E_RESTRAINT], (unsigned long long)to_fixed(er, kEnergyScale, g.err));
+    }
+  }
+}
+
+// items: window -- zero energy accumulators [c0, c1)
+__global__ void k_ezero(const LegDev* legs, BlockMap map, int c0, int c1) {
+  const int leg = find_leg(map, blockIdx.x);
+  const LegDev& g = legs[leg];
+  const int w = (blockIdx.x - map.start[leg]) * blockDim.x + threadIdx.x;
+  if (w >= g.W) return;
+  for (int c = c0; c < c1; ++c) g.eacc[(size_t)w * FELIS_NE + c] = 0;
+}
+
+// items: window -- publish components [c0, c1) and the total
+__global__ void k_efinish(const LegDev* legs, BlockMap map, int c0, int c1) {
+  const int leg = find_leg(map, blockIdx.x);
+  const LegDev& g = legs[leg];
+  const int w = (blockIdx.x - map.start[leg]) * blockDim.x + threadIdx.x;
+  if (w >= g.W) return;
+  double* e = g.energy + (size_t)w * FELIS_NE;
+  for (int c = c0; c < c1; ++c) e[c] = (double)g.eacc[(size_t)w * FELIS_NE + c] * (1.0 / kEnergyScale);
+  double t = 0.0;
+  for (int c = 0; c < FELIS_E_TOTAL; ++c) t += e[c];
+  e[FELIS_E_TOTAL] = t;
+}
+
+__global__ void k_fill_i64(long long* p, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+inline int blocks_for(long long items, int per) { return (int)((items + per - 1) / per); }
+
+}  // namespace
+
+void launch_pack(hipStream_t s, const LegDev* d, const LegHost* h, int nl) {
+  BlockMap m;
+  const int nb = make_map(m, nl, [&](int i) { return blocks_for((long long)h[i].W * h[i].npad, 256); });
+  if (nb) hipLaunchKernelGGL(k_pack, dim3(nb), dim3(256), 0, s, d, m);
+}
+
+void launch_pairs(hipStream_t s, const LegDev* d, const LegHost* h, int nl, bool energy) {
+  BlockMap m;
+  const int nb = make_map(m, nl, [&](int i) { return blocks_for((long long)h[i].W * h[i].nclus, 4); });
+  if (!nb) return;
+  if (energy) hipLaunchKernelGGL(k_pairs<true>, dim3(nb), dim3(256), 0, s, d, m);
+  else hipLaunchKernelGGL(k_pairs<false>, dim3(nb), dim3(256), 0, s, d, m);
+}
+
+void launch_corrections(hipStream_t s, const LegDev* d, const LegHost* h, int nl, bool energy) {
+  BlockMap m;
+  int nb = make_map(m, nl, [&](int i) { return blocks_for((long long)h[i].W * h[i].nexcl, 256); });
+  if (nb) {
+    if (energy) hipLaunchKernelGGL(k_excl<true>, dim3(nb), dim3(256), 0, s, d, m);
+    else hipLaunchKernelGGL(k_excl<false>, dim3(nb), dim3(256), 0, s, d, m);
+  }
+  if (energy) {
+    nb = make_map(m, nl, [&](int i) { return h[i].W; });
+    if (nb) hipLaunchKernelGGL(k_self, dim3(nb), dim3(256), 0, s, d, m);
+  }
+}
+
+void launch_bonded(hipStream_t s, const LegDev* d, const LegHost* h, int nl, bool energy) {
+  BlockMap m;
+  const int nb = make_map(m, nl, [&](int i) { return blocks_for((long long)h[i].W * (h[i].nbonds + 1), 256); });
+  if (!nb) return;
+  if (energy) hipLaunchKernelGGL(k_bonded<true>, dim3(nb), dim3(256), 0, s, d, m);
+  else hipLaunchKernelGGL(k_bonded<false>, dim3(nb), dim3(256), 0, s, d, m);
+}
+
+void launch_zero_energy(hipStream_t s, const LegDev* d, const LegHost* h, int nl, int c0, int c1) {
+  BlockMap m;
+  const int nb = make_map(m, nl, [&](int i) { return blocks_for(h[i].W, 64); });
+  if (nb) hipLaunchKernelGGL(k_ezero, dim3(nb), dim3(64), 0, s, d, m, c0, c1);
+}
+
+void launch_finish_energy(hipStream_t s, const LegDev* d, const LegHost* h, int nl, int c0, int c1) {
+  BlockMap m;
+  const int nb = make_map(m, nl, [&](int i) { return blocks_for(h[i].W, 64); });
+  if (nb) hipLaunchKernelGGL(k_efinish, dim3(nb), dim3(64), 0, s, d, m, c0, c1);
+}
+
+void launch_fill_i64(hipStream_t s, long long* p, size_t n) {
+  if (n) hipLaunchKernelGGL(k_fill_i64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n);
+}
+
+}  // namespace felis

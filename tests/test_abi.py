@@ -1,0 +1,136 @@
+"""Host-side checks of the C ABI (no GPU needed).
+
+* libfelis.so loads and exports every function include/felis.h declares.
+* The ctypes mirror of felis_leg has the C layout (size and offsets).
+* Work-size validation rejects unsupported configurations without a device.
+* The SETTLE constraint solve (csrc/settle.h, compiled for the host) equals
+  the oracle's converged SHAKE on perturbed rigid waters.
+"""
+import ctypes as C
+import os
+import re
+import subprocess
+import tempfile
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, 'include', 'felis.h')
+
+
+def _lib():
+    from paper_2603_22274_amd import build, felis
+    if not os.path.exists(felis.LIB_PATH):
+        build.build()
+    return felis.lib()
+
+
+def test_exports_every_declared_symbol():
+    names = set(re.findall(r'\b(felis_[a-z_0-9]+)\s*\(', open(HEADER).read()))
+    assert len(names) >= 14
+    L = _lib()
+    missing = [n for n in sorted(names) if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_leg_struct_layout_matches_header():
+    from paper_2603_22274_amd.felis import FelisLeg
+    src = r'''
+#include <stddef.h>
+#include <stdio.h>
+#include "felis.h"
+int main(void) {
+  printf("%zu %zu %zu %zu %zu %zu\n", sizeof(felis_leg), offsetof(felis_leg, charge),
+         offsetof(felis_leg, restraint_k), offsetof(felis_leg, lambdas), offsetof(felis_leg, seed),
+         offsetof(felis_leg, work_bytes));
+  return 0;
+}
+'''
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, 'l.c')
+        open(c, 'w').write(src)
+        exe = os.path.join(d, 'l')
+        subprocess.run(['gcc', '-I', os.path.join(ROOT, 'include'), c, '-o', exe], check=True)
+        out = [int(v) for v in subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split()]
+    py = [C.sizeof(FelisLeg)] + [getattr(FelisLeg, f).offset for f in
+                                 ('charge', 'restraint_k', 'lambdas', 'seed', 'work_bytes')]
+    assert out == py
+
+
+def test_work_size_validation():
+    from paper_2603_22274_amd import felis, gen
+    L = _lib()
+    s = gen.config0()
+    leg = felis.FelisLeg()
+    leg.n_atoms = s.n_atoms
+    leg.box = (C.c_double * 3)(*s.box)
+    leg.r_cut, leg.skin, leg.ewald_alpha, leg.sc_alpha, leg.sc_p = 9.0, 0.25, s.ewald_alpha, 0.5, 1
+    leg.grid = (C.c_int32 * 3)(20, 20, 20)
+    leg.spline_order = 4
+    dummy = C.c_void_p(16)
+    for f in ('charge', 'sigma', 'epsilon', 'mass', 'is_ligand', 'x', 'y', 'z', 'vx', 'vy', 'vz', 'fx', 'fy',
+              'fz', 'energy', 'lambdas', 'excl_ptr'):
+        setattr(leg, f, dummy)
+    leg.n_windows = 12
+    n = C.c_size_t(0)
+    assert L.felis_leg_work_size(C.byref(leg), C.byref(n)) == 0 and n.value > 0
+    leg.skin = 0.4          # 9.4 > 18.6 / 2
+    assert L.felis_leg_work_size(C.byref(leg), C.byref(n)) == felis.E_BOX
+    leg.skin = 0.25
+    leg.spline_order = 6
+    assert L.felis_leg_work_size(C.byref(leg), C.byref(n)) == felis.E_UNSUPPORTED
+    leg.spline_order = 4
+    leg.grid = (C.c_int32 * 3)(20, 21 * 7, 20)
+    assert L.felis_leg_work_size(C.byref(leg), C.byref(n)) == felis.E_UNSUPPORTED
+
+
+def test_settle_matches_oracle_shake():
+    from oracle.integrate import shake_waters
+    from paper_2603_22274_amd import gen
+    shim = r'''
+#include "settle.h"
+extern "C" void settle_many(int n, const float* old, float* nw, float mO, float mH, float doh, float dhh) {
+  for (int i = 0; i < n; ++i) {
+    const float* o = old + 9 * i; float* p = nw + 9 * i;
+    felis::v3 b0 = felis::mk(o[3] - o[0], o[4] - o[1], o[5] - o[2]);
+    felis::v3 c0 = felis::mk(o[6] - o[0], o[7] - o[1], o[8] - o[2]);
+    felis::v3 a1 = felis::mk(p[0] - o[0], p[1] - o[1], p[2] - o[2]);
+    felis::v3 b1 = felis::mk(p[3] - o[0], p[4] - o[1], p[5] - o[2]);
+    felis::v3 c1 = felis::mk(p[6] - o[0], p[7] - o[1], p[8] - o[2]);
+    felis::settle(b0, c0, a1, b1, c1, mO, mH, doh, dhh);
+    p[0] = a1.x + o[0]; p[1] = a1.y + o[1]; p[2] = a1.z + o[2];
+    p[3] = b1.x + o[0]; p[4] = b1.y + o[1]; p[5] = b1.z + o[2];
+    p[6] = c1.x + o[0]; p[7] = c1.y + o[1]; p[8] = c1.z + o[2];
+  }
+}
+'''
+    s = gen.config0()
+    rng = np.random.default_rng(0)
+    W = s.waters[:64]
+    old = s.pos[W].astype(np.float64)                        # (64, 3, 3) rigid
+    new = old + rng.normal(0, 0.02, old.shape)               # unconstrained step
+    with tempfile.TemporaryDirectory() as d:
+        cpp = os.path.join(d, 's.cpp')
+        open(cpp, 'w').write(shim)
+        so = os.path.join(d, 's.so')
+        subprocess.run(['g++', '-O2', '-shared', '-fPIC', '-I',
+                        os.path.join(ROOT, 'paper_2603_22274_amd', 'csrc'), cpp, '-o', so], check=True)
+        lib = C.CDLL(so)
+        o32 = np.ascontiguousarray(old, np.float32)
+        n32 = np.ascontiguousarray(new, np.float32)
+        lib.settle_many(len(W), o32.ctypes.data_as(C.c_void_p), n32.ctypes.data_as(C.c_void_p),
+                        C.c_float(s.mass[W[0, 0]]), C.c_float(s.mass[W[0, 1]]), C.c_float(s.d_oh),
+                        C.c_float(s.d_hh))
+    # oracle: SHAKE over the same waters (indices relabelled 0..191)
+    x_old = old.reshape(-1, 3)
+    x_new = np.asarray(o32, np.float64).reshape(-1, 3) * 0 + new.reshape(-1, 3)
+    wat = np.arange(3 * len(W)).reshape(-1, 3)
+    mass = np.tile(s.mass[W[0]], len(W))
+    ref = shake_waters(np.asarray(o32, np.float64).reshape(-1, 3), np.asarray(new.astype(np.float32), np.float64).reshape(-1, 3),
+                       wat, mass, s.d_oh, s.d_hh, np.array([1e4] * 3))
+    got = n32.reshape(-1, 3).astype(np.float64)
+    assert np.max(np.abs(got - ref)) < 2e-5
+    # constraints met in FP32
+    r = np.linalg.norm(got[0::3] - got[1::3], axis=1)
+    assert np.max(np.abs(r - s.d_oh)) < 1e-5
