@@ -19,7 +19,7 @@ namespace {
 
 struct Layout {
   size_t lam, free_atoms, lig_idx, xr, yr, zr, flag, perm, cellcode, cellstart, cursor, xyzq, prm, bblo,
-      bbhi, lcount, lent, grid64, cgrid, tw[3], bmod[3], eacc, uacc, ucst, total;
+      bbhi, lcount, lent, grid64, cgrid, tw[3], bmod[3], eacc, uacc, upart, lpart, ucst, total;
 };
 
 struct Plan {
@@ -163,6 +163,8 @@ int make_plan(felis_ctx* c, const felis_leg* L, Plan& P) {
   for (int d = 0; d < 3; ++d) { y.tw[d] = put(h.K[d] * 8); y.bmod[d] = put(h.K[d] * 4); }
   y.eacc = put(W * FELIS_NE * 8);
   y.uacc = put((size_t)h.npair * (3 + kMaxLamV) * 8);
+  y.upart = put((size_t)h.npair * ((h.n + 255) / 256) * 4 * (1 + kMaxLamV) * 8);
+  y.lpart = put((size_t)h.npair * 4 * (1 + kMaxLamV) * 8);
   y.ucst = put(8 * sizeof(double));
   y.total = o;
   return FELIS_OK;
@@ -234,6 +236,8 @@ LegDev make_dev(const felis_ctx* c, const felis_leg* L, const Plan& p, const Met
   for (int d = 0; d < 3; ++d) { g.tw[d] = (float2*)(w + y.tw[d]); g.bmod[d] = (float*)(w + y.bmod[d]); }
   g.eacc = (long long*)(w + y.eacc);
   g.uacc = (long long*)(w + y.uacc);
+  g.upart = (double*)(w + y.upart);
+  g.lpart = (double*)(w + y.lpart);
   g.err = c->d_err;
   g.need = c->d_err + 1;
   return g;
@@ -506,8 +510,7 @@ int felis_step(felis_ctx* c, felis_leg* legs, int n_legs, int n_steps, double dt
     mark(c, FELIS_PROF_NLIST, false);
     launch_check(c->stream, c->d_legs, hs.data(), n_legs, 0);
     launch_build(c->stream, c->d_legs, hs.data(), n_legs);
-    mark(c, FELIS_PROF_NLIST, true);
-    launch_pack(c->stream, c->d_legs, hs.data(), n_legs);
+    mark(c, FELIS_PROF_NLIST, true);       // the build stage also packs the sorted coordinates
     mark(c, FELIS_PROF_PAIRS, false);
     launch_pairs(c->stream, c->d_legs, hs.data(), n_legs, false);
     mark(c, FELIS_PROF_PAIRS, true);

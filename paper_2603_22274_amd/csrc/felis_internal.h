@@ -84,7 +84,9 @@ struct LegDev {
   float2* tw[3];                        // [K] exp(-2 pi i k / K) per axis
   float* bmod[3];                       // [K] B-spline moduli factor per axis
   long long* eacc;                      // [W][FELIS_NE] fixed-point energies
-  long long* uacc;                      // [npair][3 + kMaxLamV] u_kn accumulators
+  long long* uacc;                      // [npair][3 + kMaxLamV] u_kn fixed-point sums (PME, restraint)
+  double* upart;                        // [npair][ceil(n/256)][4][1 + kMaxLamV] u_kn pair partials
+  double* lpart;                        // [npair][4][1 + kMaxLamV] ligand-ligand partials
   int* err;                             // context error word
   int* need;                            // context: largest list length seen
 };

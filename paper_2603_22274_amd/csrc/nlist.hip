@@ -1,10 +1,14 @@
 // Neighbour lists: displacement check, Morton cell sort, 8-atom clusters and
-// per-cluster j-lists with FP64 exact inclusion bits (appendix B cutoffs).
+// per-cluster j-lists (appendix B cutoffs).
 //
-// Built with -ffp-contract=off: the FP64 inclusion test d^2 < r_list^2 uses
-// d = x_j - x_i, d -= L * rint(d / L) (separate multiply and subtract) and
-// d^2 = (dx^2 + dy^2) + dz^2, so the set of listed pairs is a deterministic
-// function of the float coordinates.
+// A cluster lists every atom j that lies within r_list + 0.01 A (FP32
+// minimum image) of at least one of its atoms i, with one bit per i; the
+// margin is far above the FP32 error of d^2, so the listed pairs are a
+// superset of the pairs within r_list.  The canonical list -- pairs with
+// FP64 d^2 < r_list^2, d = x_j - x_i, d -= L * rint(d / L) as separate
+// multiply and subtract, d^2 = (dx^2 + dy^2) + dz^2 -- is what the export
+// applies to that superset; this unit is built with -ffp-contract=off so
+// that sequence is exact as written.
 #include "felis_internal.h"
 
 namespace felis {
@@ -169,13 +173,13 @@ __global__ __launch_bounds__(256) void k_bbox(const LegDev* legs, BlockMap map) 
   if (!g.flag[w]) return;
   const int c = (int)(i - (long long)w * g.nclus);
   const int* p = g.perm + (size_t)w * g.npad + c * kClus;
-  const size_t o = (size_t)w * g.n;
+  const float4* xq = g.xyzq + (size_t)w * g.npad + c * kClus;
   float lo[3] = {3.0e38f, 3.0e38f, 3.0e38f}, hi[3] = {-3.0e38f, -3.0e38f, -3.0e38f};
   for (int k = 0; k < kClus; ++k) {
-    const int a = p[k];
-    if (a < 0) continue;
-    const float v[3] = {wrapf(g.x[o + a], g.Lf[0], g.invLf[0]), wrapf(g.y[o + a], g.Lf[1], g.invLf[1]),
-                        wrapf(g.z[o + a], g.Lf[2], g.invLf[2])};
+    if (p[k] < 0) continue;
+    const float4 r = xq[k];
+    const float v[3] = {wrapf(r.x, g.Lf[0], g.invLf[0]), wrapf(r.y, g.Lf[1], g.invLf[1]),
+                        wrapf(r.z, g.Lf[2], g.invLf[2])};
     for (int d = 0; d < 3; ++d) { lo[d] = fminf(lo[d], v[d]); hi[d] = fmaxf(hi[d], v[d]); }
   }
   g.bblo[i] = make_float4(lo[0], lo[1], lo[2], 0.f);
@@ -223,70 +227,124 @@ __global__ __launch_bounds__(256) void k_build(const LegDev* legs, BlockMap map)
   const float lo[3] = {lo4.x, lo4.y, lo4.z}, hi[3] = {hi4.x, hi4.y, hi4.z};
   float cen[3], half[3];
   int r0[3], r1[3];
-  const int nco = g.ncoarse;
+  const int nf = g.ncoarse;          // search blocks: aligned 2x2x2 groups of fine cells
+  bool all_cells = false;
   for (int d = 0; d < 3; ++d) {
     cen[d] = 0.5f * (lo[d] + hi[d]);
     half[d] = 0.5f * (hi[d] - lo[d]);
-    const float cs = g.Lf[d] / (float)nco;
-    r0[d] = (int)floorf((lo[d] - (float)g.rlist) / cs) - 1;
-    r1[d] = (int)floorf((hi[d] + (float)g.rlist) / cs) + 1;
-    if (r1[d] - r0[d] + 1 >= nco) { r0[d] = 0; r1[d] = nco - 1; }
+    const float cs = g.Lf[d] / (float)nf;
+    r0[d] = (int)floorf((lo[d] - (float)g.rlist - 0.05f) / cs);
+    r1[d] = (int)floorf((hi[d] + (float)g.rlist + 0.05f) / cs);
+    if (r1[d] - r0[d] + 1 >= nf) { r0[d] = 0; r1[d] = nf - 1; all_cells = true; }
   }
+  const float4* __restrict__ xq = g.xyzq + (size_t)w * g.npad;
   const float pre = (float)g.rlist + 0.05f;
   const float pre2 = pre * pre;
+  const float incl = (float)g.rlist + 0.01f;
+  const float inc2 = incl * incl;
+  float xi[kClus][3];
+  int ai[kClus];
+#pragma unroll
+  for (int ii = 0; ii < kClus; ++ii) {
+    ai[ii] = __builtin_amdgcn_readfirstlane(s_ai[wave][ii]);        // wave-uniform: SGPRs
+    for (int d = 0; d < 3; ++d)
+      xi[ii][d] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int((float)s_xi[wave][ii][d])));
+  }
   const int* cst = g.cellstart + (size_t)w * (g.ncell + 1);
   unsigned* out = g.lent + (size_t)item * g.cap;
   int count = 0;
   const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  const int nX = r1[0] - r0[0] + 1, nY = r1[1] - r0[1] + 1, nZ = r1[2] - r0[2] + 1;
+  const int ncells = nX * nY * nZ;
+  __shared__ int s_start[4][64];     // first sorted slot of each cell in the chunk
+  __shared__ int s_pre[4][64];       // exclusive prefix of candidate counts
 
-  for (int X = r0[0]; X <= r1[0]; ++X)
-    for (int Y = r0[1]; Y <= r1[1]; ++Y)
-      for (int Z = r0[2]; Z <= r1[2]; ++Z) {
-        const unsigned cc = morton3((unsigned)((X % nco + nco) % nco), (unsigned)((Y % nco + nco) % nco),
-                                    (unsigned)((Z % nco + nco) % nco), g.nbits - 1);
-        const int s0 = cst[8 * cc], s1 = cst[8 * cc + 8];
-        for (int sb = s0; sb < s1; sb += 64) {
-          const int s = sb + lane;
-          unsigned mask = 0;
-          if (s < s1) {
-            const int a = perm[s];
-            const float xj[3] = {g.x[o + a], g.y[o + a], g.z[o + a]};
-            float dd = 0.f;
-            for (int d = 0; d < 3; ++d) {
-              float v = wrapf(xj[d], g.Lf[d], g.invLf[d]) - cen[d];
-              v -= g.Lf[d] * rintf(v * g.invLf[d]);
-              float e = fabsf(v) - half[d];
-              if (half[d] > 0.25f * g.Lf[d]) e = 0.f;
-              e = fmaxf(e, 0.f);
-              dd += e * e;
-            }
-            if (dd < pre2) {
-              const double X0 = (double)xj[0], X1 = (double)xj[1], X2 = (double)xj[2];
-              for (int ii = 0; ii < kClus; ++ii) {
-                const int ai = s_ai[wave][ii];
-                if (ai < 0 || ai == a) continue;
-                double dx = X0 - s_xi[wave][ii][0];
-                double dy = X1 - s_xi[wave][ii][1];
-                double dz = X2 - s_xi[wave][ii][2];
-                dx = dx - g.L[0] * rint(dx * g.invL[0]);
-                dy = dy - g.L[1] * rint(dy * g.invL[1]);
-                dz = dz - g.L[2] * rint(dz * g.invL[2]);
-                const double d2 = (dx * dx + dy * dy) + dz * dz;
-                if (!(d2 < g.rlist2)) continue;
-                bool ex = false;
-                for (int k = 0; k < s_nex[wave][ii]; ++k) ex |= (s_ex[wave][ii][k] == a);
-                if (!ex) mask |= 1u << ii;
-              }
+  // Cells are taken 64 at a time: lanes fetch their cell's slot range in
+  // parallel, a wave scan lays the candidates of the chunk end to end, and the
+  // wave sweeps that flat range 64 candidates per iteration (cell order, then
+  // sorted order within a cell: deterministic).
+  for (int cb = 0; cb < ncells; cb += 64) {
+    const int ci = cb + lane;
+    int s0 = 0, cnt = 0;
+    if (ci < ncells) {
+      const int C[3] = {r0[0] + ci / (nY * nZ), r0[1] + (ci / nZ) % nY, r0[2] + ci % nZ};
+      // distance from the cell (unwrapped frame of the cluster box) to the box;
+      // when the range wraps onto itself every cell is kept
+      float gap2 = 0.f;
+      for (int d = 0; d < 3; ++d) {
+        const float cs = g.Lf[d] / (float)nf;
+        const float gp = fmaxf(0.f, fmaxf((float)C[d] * cs - hi[d], lo[d] - (float)(C[d] + 1) * cs));
+        gap2 += gp * gp;
+      }
+      if (all_cells || gap2 < pre2) {
+        const unsigned cc = morton3((unsigned)((C[0] % nf + nf) % nf), (unsigned)((C[1] % nf + nf) % nf),
+                                    (unsigned)((C[2] % nf + nf) % nf), g.nbits - 1);
+        s0 = cst[8 * cc];                // fine cells 8cc .. 8cc+7 are contiguous
+        cnt = cst[8 * cc + 8] - s0;
+      }
+    }
+    int inc = cnt;
+    for (int o = 1; o < 64; o <<= 1) {
+      const int v = __shfl_up(inc, o, 64);
+      if (lane >= o) inc += v;
+    }
+    const int total = __shfl(inc, 63, 64);
+    s_start[wave][lane] = s0;
+    s_pre[wave][lane] = inc - cnt;
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    for (int t0 = 0; t0 < total; t0 += 64) {
+      const int t = t0 + lane;
+      unsigned mask = 0;
+      int s = 0;
+      if (t < total) {
+        int lo = 0, hi = 63;                     // last cell with prefix <= t
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (s_pre[wave][mid] <= t) lo = mid; else hi = mid - 1;
+        }
+        s = s_start[wave][lo] + (t - s_pre[wave][lo]);
+        const int a = perm[s];
+        const float4 rj = xq[s];
+        const float xj[3] = {rj.x, rj.y, rj.z};
+        float dd = 0.f;
+        for (int d = 0; d < 3; ++d) {
+          float v = wrapf(xj[d], g.Lf[d], g.invLf[d]) - cen[d];
+          v -= g.Lf[d] * rintf(v * g.invLf[d]);
+          float e = fabsf(v) - half[d];
+          if (half[d] > 0.25f * g.Lf[d]) e = 0.f;
+          e = fmaxf(e, 0.f);
+          dd += e * e;
+        }
+        if (dd < pre2) {
+#pragma unroll
+          for (int ii = 0; ii < kClus; ++ii) {
+            float dx = xj[0] - xi[ii][0], dy = xj[1] - xi[ii][1], dz = xj[2] - xi[ii][2];
+            dx -= g.Lf[0] * rintf(dx * g.invLf[0]);
+            dy -= g.Lf[1] * rintf(dy * g.invLf[1]);
+            dz -= g.Lf[2] * rintf(dz * g.invLf[2]);
+            const float d2 = (dx * dx + dy * dy) + dz * dz;
+            if (d2 < inc2 && ai[ii] >= 0 && ai[ii] != a) mask |= 1u << ii;
+          }
+          if (mask) {                           // drop excluded (i, j)
+            for (int ii = 0; ii < kClus; ++ii) {
+              if (!((mask >> ii) & 1u)) continue;
+              bool ex = false;
+              for (int k = 0; k < s_nex[wave][ii]; ++k) ex |= (s_ex[wave][ii][k] == a);
+              if (ex) mask &= ~(1u << ii);
             }
           }
-          const unsigned long long bal = __ballot(mask != 0u);
-          if (mask) {
-            const int pos = count + __popcll(bal & lt);
-            if (pos < g.cap) out[pos] = ((unsigned)s << 8) | mask;
-          }
-          count += __popcll(bal);
         }
       }
+      const unsigned long long bal = __ballot(mask != 0u);
+      if (mask) {
+        const int pos = count + __popcll(bal & lt);
+        if (pos < g.cap) out[pos] = ((unsigned)s << 8) | mask;
+      }
+      count += __popcll(bal);
+    }
+    __builtin_amdgcn_wave_barrier();      // the chunk's tables are rewritten next
+  }
   if (count > g.cap) {
     if (lane == 0) { atomicOr(g.err, kErrListCap); atomicMax(g.need, count); }
     count = g.cap;
@@ -355,6 +413,7 @@ void launch_build(hipStream_t s, const LegDev* d, const LegHost* h, int nl) {
   if (nb) hipLaunchKernelGGL(k_cells_order, dim3(nb), dim3(256), 0, s, d, m);
   nb = make_map(m, nl, [&](int i) { return blocks_for((long long)h[i].W * h[i].npad, 256); });
   if (nb) hipLaunchKernelGGL(k_sorted_params, dim3(nb), dim3(256), 0, s, d, m);
+  launch_pack(s, d, h, nl);        // sorted coordinates for the box and candidate sweeps
   nb = make_map(m, nl, [&](int i) { return blocks_for((long long)h[i].W * h[i].nclus, 256); });
   if (nb) hipLaunchKernelGGL(k_bbox, dim3(nb), dim3(256), 0, s, d, m);
   nb = make_map(m, nl, [&](int i) { return blocks_for((long long)h[i].W * h[i].nclus, 4); });

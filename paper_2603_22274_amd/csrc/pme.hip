@@ -215,7 +215,9 @@ __device__ __forceinline__ int grid_base(float x, double invL, int K, float* f) 
   return (int)k;
 }
 
-// items: window x atom, 16 lanes per atom (lane = iy + 4 iz, loop over ix)
+// items: window x atom, 16 lanes per atom (lane = ix + 4 iy, loop over iz):
+// the four x points of a grid row are adjacent lanes, so each atomic
+// instruction touches 16 row segments of 32 contiguous bytes
 __global__ __launch_bounds__(256) void k_spread(const LegDev* legs, BlockMap map) {
   const int leg = find_leg(map, blockIdx.x);
   const LegDev& g = legs[leg];
@@ -223,7 +225,7 @@ __global__ __launch_bounds__(256) void k_spread(const LegDev* legs, BlockMap map
   if (local >= (long long)g.W * g.n) return;
   const int w = (int)(local / g.n);
   const int a = (int)(local - (long long)w * g.n);
-  const int sub = threadIdx.x & 15, iy = sub & 3, iz = sub >> 2;
+  const int sub = threadIdx.x & 15, ix = sub & 3, iy = sub >> 2;
   const size_t o = (size_t)w * g.n + a;
   const float q = g.q[a] * (g.lig[a] ? g.lam[4 * w] : 1.0f);
   float fxr, fyr, fzr, wx[4], wy[4], wz[4];
@@ -233,15 +235,15 @@ __global__ __launch_bounds__(256) void k_spread(const LegDev* legs, BlockMap map
   bspline4(fxr, wx, nullptr);
   bspline4(fyr, wy, nullptr);
   bspline4(fzr, wz, nullptr);
+  int gx = bx - ix; if (gx < 0) gx += g.K[0];
   int gy = by - iy; if (gy < 0) gy += g.K[1];
-  int gz = bz - iz; if (gz < 0) gz += g.K[2];
-  long long* grid = g.grid64 + (size_t)w * g.Ktot + ((size_t)gz * g.K[1] + gy) * g.K[0];
-  const double qyz = (double)(q * wy[iy] * wz[iz]);
+  long long* grid = g.grid64 + (size_t)w * g.Ktot + (size_t)gy * g.K[0] + gx;
+  const double qxy = (double)(q * wx[ix] * wy[iy]);
 #pragma unroll
-  for (int ix = 0; ix < 4; ++ix) {
-    int gx = bx - ix; if (gx < 0) gx += g.K[0];
-    const long long v = __double2ll_rn(qyz * (double)wx[ix] * kGridScale);
-    if (v) atomicAdd((unsigned long long*)&grid[gx], (unsigned long long)v);
+  for (int iz = 0; iz < 4; ++iz) {
+    int gz = bz - iz; if (gz < 0) gz += g.K[2];
+    const long long v = __double2ll_rn(qxy * (double)wz[iz] * kGridScale);
+    if (v) atomicAdd((unsigned long long*)&grid[(size_t)gz * g.K[0] * g.K[1]], (unsigned long long)v);
   }
 }
 

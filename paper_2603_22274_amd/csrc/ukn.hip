@@ -69,7 +69,7 @@ __device__ __forceinline__ float3 min_img(const LegDev& g, float dx, float dy, f
 
 __device__ __forceinline__ void acc_add(const LegDev& g, int f, int slot, double e) {
   atomicAdd((unsigned long long*)&g.uacc[(size_t)f * kNU + slot],
-            (unsigned long long)to_fixed(e, kEnergyScale, g.err));
+            (unsigned long long)to_fixed(e, kEnergyScale, g.err, kSiteUkn, f));
 }
 
 // items: frame x atom, 16 lanes per atom; environment charges into grid 2f,
@@ -186,9 +186,13 @@ __global__ __launch_bounds__(256) void k_ukn_pairs(const LegDev* legs, UknArgs A
       if (lane == kv) esc += tot;
     }
   }
+  // per-wave FP64 partials (unbounded: a frame evaluated at a state it was
+  // not sampled in may carry enormous overlap energies); summed in a fixed
+  // order by k_ukn_combine
   ec = wave_sum(ec);
-  if (lane == 0 && ec != 0.0) acc_add(g, f, 0, ec);
-  if (lane < A.KV && esc != 0.0) acc_add(g, f, 3 + lane, esc);
+  double* part = g.upart + ((size_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * (1 + kMaxLamV);
+  if (lane == 0) part[0] = ec;
+  if (lane < A.KV) part[1 + lane] = esc;
 }
 
 // one block per frame: ligand-ligand pairs, excluded-pair corrections and the
@@ -244,8 +248,9 @@ __global__ __launch_bounds__(256) void k_ukn_ligand(const LegDev* legs, UknArgs 
     }
   }
   ell = wave_sum(ell);
-  if (lane == 0 && ell != 0.0) acc_add(g, f, 1, ell);
-  if (lane < A.KV && esc != 0.0) acc_add(g, f, 3 + lane, esc);
+  double* part = g.lpart + ((size_t)f * 4 + (threadIdx.x >> 6)) * (1 + kMaxLamV);
+  if (lane == 0) part[0] = ell;
+  if (lane < A.KV) part[1 + lane] = esc;
   if (threadIdx.x == 0 && g.has_rest) {
     v3 p[6];
     const size_t o1 = fo + g.ranch[0];
@@ -296,10 +301,22 @@ __global__ __launch_bounds__(256) void k_ukn_combine(const LegDev* legs, UknArgs
   const int f = (int)(i / K), k = (int)(i - (long long)(i / K) * K);
   const long long* acc = g.uacc + (size_t)f * kNU;
   const double s = 1.0 / kEnergyScale;
-  const double ele = (double)acc[0] * s + cst[0];
-  const double ell = (double)acc[1] * s + cst[1];
+  const int kv = C.kv[k];
+  double ele = (double)acc[0] * s + cst[0];
+  double ell = (double)acc[1] * s + cst[1];
   const double ub = (double)acc[2] * s;
-  const double esc = (double)acc[3 + C.kv[k]] * s;
+  double esc = 0.0;
+  const int nb = g.nlig > 0 ? (g.n + 255) / 256 : 0;     // no ligand: no pair partials
+  const double* pp = g.upart + (size_t)f * nb * 4 * (1 + kMaxLamV);
+  for (int t = 0; t < 4 * nb; ++t) {
+    ele += pp[(size_t)t * (1 + kMaxLamV)];
+    esc += pp[(size_t)t * (1 + kMaxLamV) + 1 + kv];
+  }
+  const double* lp = g.lpart + (size_t)f * 4 * (1 + kMaxLamV);
+  for (int t = 0; t < (g.nlig > 0 ? 4 : 0); ++t) {
+    ell += lp[t * (1 + kMaxLamV)];
+    esc += lp[t * (1 + kMaxLamV) + 1 + kv];
+  }
   const double le = C.le[k], lr = C.lr[k];
   u[(long long)k * u_stride + A.f0 + f] = beta * (le * ele + le * le * ell + esc + lr * ub);
 }
