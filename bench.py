@@ -83,6 +83,9 @@ def main():
     ap.add_argument('--md', type=int, default=50, help='MD steps per bench step (u_kn sample interval)')
     ap.add_argument('--no-cpu-baseline', action='store_true')
     ap.add_argument('--no-per-window', action='store_true')
+    ap.add_argument('--equil', type=int, default=200, help='untimed equilibration MD steps')
+    ap.add_argument('--copy-calibration', action='store_true',
+                    help='run a plain 256 MiB device copy first (reference for traffic counters)')
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get('WORLD_SIZE', '1')) > 1:
         print("bench.py measures one GPU: the path needs no collective and nothing here runs on a second GPU; "
@@ -92,6 +95,12 @@ def main():
     import torch
     from paper_2603_22274_amd import felis, gen
 
+    if args.copy_calibration:
+        src = torch.empty(256 << 20, dtype=torch.uint8, device='cuda')
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     sysd = gen.config1()
     ctx = felis.Context(0)
     leg = felis.Leg(ctx, sysd, seed=22274)
@@ -99,7 +108,7 @@ def main():
     beta = 1.0 / (KB * 300.0)
     felis.build_nlist(ctx, [leg], force=True)
     # settle the lattice start before anything is measured
-    felis.step(ctx, [leg], 200, DT, 300.0, 5.0)
+    felis.step(ctx, [leg], args.equil, DT, 300.0, 5.0)
     ctx.device_check()
     # algorithmic work: unique pairs within r_c per window (FP64 distances)
     felis.build_nlist(ctx, [leg])
