@@ -129,9 +129,16 @@ const char* felis_last_error(const felis_ctx* ctx);
  * Clears the word. */
 int felis_check(felis_ctx* ctx, int32_t* needed_cap);
 
+/* As felis_check, and also reports where the first fixed-point overflow was
+ * latched: the leg's position in the batch of the failing call, the window
+ * and the atom (-1 where unknown or when no error is latched).  Lets a caller
+ * running many legs in one batch evict only the failing leg. */
+int felis_check_detail(felis_ctx* ctx, int32_t* needed_cap, int32_t* leg, int32_t* window, int32_t* atom);
+
 /* Bytes of device scratch a leg needs (lists, sorted copies, PME grids,
  * accumulators).  Validates the leg's sizes: FELIS_E_BOX, FELIS_E_UNSUPPORTED,
- * FELIS_E_INVAL. */
+ * FELIS_E_INVAL.  The descriptor's array pointers are checked for null but
+ * never dereferenced, so a size query needs no allocation. */
 int felis_leg_work_size(const felis_leg* leg, size_t* bytes);
 
 /* Fill the leg's scratch (lambda table, FFT tables, water/ligand index

@@ -170,7 +170,7 @@ int make_plan(felis_ctx* c, const felis_leg* L, Plan& P) {
   return FELIS_OK;
 }
 
-LegDev make_dev(const felis_ctx* c, const felis_leg* L, const Plan& p, const Meta& m) {
+LegDev make_dev(const felis_ctx* c, const felis_leg* L, const Plan& p, const Meta& m, int index) {
   LegDev g;
   std::memset(&g, 0, sizeof(g));
   const LegHost& h = p.h;
@@ -240,6 +240,7 @@ LegDev make_dev(const felis_ctx* c, const felis_leg* L, const Plan& p, const Met
   g.lpart = (double*)(w + y.lpart);
   g.err = c->d_err;
   g.need = c->d_err + 1;
+  g.leg_index = index;
   return g;
 }
 
@@ -259,7 +260,7 @@ int prepare(felis_ctx* c, const felis_leg* legs, int n_legs, std::vector<LegHost
     p.h.nfree = it->second.nfree;
     p.h.nlig = it->second.nlig;
     hs[i] = p.h;
-    devs[i] = make_dev(c, &legs[i], p, it->second);
+    devs[i] = make_dev(c, &legs[i], p, it->second, i);
   }
   if ((int)c->cache.size() == n_legs && std::memcmp(c->cache.data(), devs.data(), sizeof(LegDev) * n_legs) == 0)
     return FELIS_OK;
@@ -306,9 +307,9 @@ int felis_create(felis_ctx** out, int device, void* hip_stream) {
   c->stream = (hipStream_t)hip_stream;
   if (hipMalloc((void**)&c->d_legs, sizeof(LegDev) * kMaxLegs) != hipSuccess ||
       hipHostMalloc((void**)&c->h_stage, sizeof(LegDev) * kMaxLegs, hipHostMallocDefault) != hipSuccess ||
-      hipMalloc((void**)&c->d_err, 4 * sizeof(int)) != hipSuccess ||
+      hipMalloc((void**)&c->d_err, 8 * sizeof(int)) != hipSuccess ||
       hipMalloc((void**)&c->d_count, sizeof(unsigned long long)) != hipSuccess ||
-      hipMemset(c->d_err, 0, 4 * sizeof(int)) != hipSuccess) {
+      hipMemset(c->d_err, 0, 8 * sizeof(int)) != hipSuccess) {
     felis_destroy(c);
     return FELIS_E_DEVICE;
   }
@@ -331,21 +332,34 @@ void felis_destroy(felis_ctx* c) {
 const char* felis_last_error(const felis_ctx* c) { return c ? c->last_error.c_str() : "null context"; }
 
 int felis_check(felis_ctx* c, int32_t* needed_cap) {
+  return felis_check_detail(c, needed_cap, nullptr, nullptr, nullptr);
+}
+
+int felis_check_detail(felis_ctx* c, int32_t* needed_cap, int32_t* leg, int32_t* window, int32_t* atom) {
   if (!c) return FELIS_E_INVAL;
-  int e[4] = {0, 0, 0, 0};
+  int e[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   if (hipStreamSynchronize(c->stream) != hipSuccess ||
       hipMemcpy(e, c->d_err, sizeof(e), hipMemcpyDeviceToHost) != hipSuccess ||
-      hipMemset(c->d_err, 0, 4 * sizeof(int)) != hipSuccess)
+      hipMemset(c->d_err, 0, 8 * sizeof(int)) != hipSuccess)
     return fail(c, FELIS_E_DEVICE, "device error word unreadable");
   if (needed_cap) *needed_cap = e[1];
-  if (e[0] & kErrListCap) return fail(c, FELIS_E_CAPACITY, "neighbour list capacity exceeded (raise list_cap)");
+  if (leg) *leg = e[0] ? e[4] : -1;
+  if (window) *window = (e[0] && e[3] >= 0) ? (e[3] >> 20) : -1;
+  if (atom) *atom = (e[0] && e[3] >= 0) ? (e[3] & 0xfffff) : -1;
+  if (e[0] & kErrListCap) {
+    char msg[160];
+    std::snprintf(msg, sizeof msg, "neighbour list capacity exceeded (raise list_cap; leg %d, window %d)", e[4],
+                  e[3] >> 20);
+    return fail(c, FELIS_E_CAPACITY, msg);
+  }
   if (e[0] & kErrOverflow) {
     static const char* sites[] = {"?", "pair forces", "pair energies", "excluded pairs", "bonded/restraint",
-                                  "PME gather", "PME energy", "u_kn", "self", "energy sum"};
+                                  "PME gather", "PME energy", "u_kn", "self", "energy sum", "list", "exclusions"};
     char msg[200];
-    const int st = (e[2] >= 0 && e[2] <= 9) ? e[2] : 0;
-    std::snprintf(msg, sizeof msg, "fixed-point overflow or non-finite value (first at %s, window %d, atom %d)",
-                  sites[st], e[3] >> 20, e[3] & 0xfffff);
+    const int st = (e[2] >= 0 && e[2] <= 11) ? e[2] : 0;
+    std::snprintf(msg, sizeof msg,
+                  "fixed-point overflow or non-finite value (first at %s, leg %d, window %d, atom %d)", sites[st],
+                  e[4], e[3] >> 20, e[3] & 0xfffff);
     return fail(c, FELIS_E_OVERFLOW, msg);
   }
   if (e[0] & kErrExcl) return fail(c, FELIS_E_UNSUPPORTED, "an atom has more than 8 exclusions");

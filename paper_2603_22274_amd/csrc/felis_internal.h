@@ -89,6 +89,7 @@ struct LegDev {
   double* lpart;                        // [npair][4][1 + kMaxLamV] ligand-ligand partials
   int* err;                             // context error word
   int* need;                            // context: largest list length seen
+  int leg_index;                        // position of this leg in the launched batch
 };
 
 // Maps a flat block index to (leg, block within leg) for batched launches.
@@ -110,14 +111,23 @@ __device__ __forceinline__ int find_leg(const BlockMap& m, int b) {
 // the window/atom (or item) it happened at in err[2], err[3].
 enum : int {
   kSitePairs = 1, kSitePairsE = 2, kSiteExcl = 3, kSiteBonded = 4, kSiteGather = 5, kSiteGatherE = 6,
-  kSiteUkn = 7, kSiteSelf = 8, kSiteEnergy = 9
+  kSiteUkn = 7, kSiteSelf = 8, kSiteEnergy = 9, kSiteList = 10, kSiteExclCount = 11
 };
 
-__device__ __forceinline__ long long to_fixed(double v, double scale, int* err, int site = 0, int where = -1) {
+// err[2] = site, err[3] = where (window << 20 | atom for per-atom sites),
+// err[4] = leg index in the batch, all recorded by the first overflow only.
+// Latch an error bit; the first error to arrive also records where it
+// happened (site code, window << 20 | atom, leg index in the batch).
+__device__ __forceinline__ void latch(int* err, int bit, int site, int where, int leg) {
+  atomicOr(err, bit);
+  if (atomicCAS(&err[2], 0, site ? site : -1) == 0) { err[3] = where; err[4] = leg; }
+}
+
+__device__ __forceinline__ long long to_fixed(double v, double scale, int* err, int site = 0, int where = -1,
+                                              int leg = -1) {
   double s = v * scale;
   if (!(fabs(s) < 9.0e18)) {
-    atomicOr(err, kErrOverflow);
-    if (atomicCAS(&err[2], 0, site ? site : -1) == 0) err[3] = where;
+    latch(err, kErrOverflow, site, where, leg);
     return 0;
   }
   return __double2ll_rn(s);
@@ -130,7 +140,8 @@ __device__ __forceinline__ T wave_sum(T v) {
 }
 
 __device__ __forceinline__ float wrapf(float x, float L, float invL) {
-  return x - L * floorf(x * invL);
+  const float r = x - L * floorf(x * invL);
+  return (r >= 0.f && r < L) ? r : 0.f;          // non-finite input -> 0 (keeps indices in range)
 }
 
 // Block-map construction on the host: blocks_of(leg) blocks for each leg.

@@ -215,7 +215,7 @@ __global__ __launch_bounds__(256) void k_build(const LegDev* legs, BlockMap map)
       s_xi[wave][lane][2] = (double)g.z[o + a];
       const int e0 = g.excl_ptr[a], e1 = g.excl_ptr[a + 1];
       ne = e1 - e0;
-      if (ne > kMaxExcl) { atomicOr(g.err, kErrExcl); ne = kMaxExcl; }
+      if (ne > kMaxExcl) { latch(g.err, kErrExcl, kSiteExclCount, (w << 20) | a, g.leg_index); ne = kMaxExcl; }
       for (int k = 0; k < ne; ++k) s_ex[wave][lane][k] = g.excl_idx[e0 + k];
     }
     s_nex[wave][lane] = ne;
@@ -232,9 +232,10 @@ __global__ __launch_bounds__(256) void k_build(const LegDev* legs, BlockMap map)
   for (int d = 0; d < 3; ++d) {
     cen[d] = 0.5f * (lo[d] + hi[d]);
     half[d] = 0.5f * (hi[d] - lo[d]);
+    if (!(half[d] >= 0.f && half[d] <= g.Lf[d])) { cen[d] = 0.f; half[d] = g.Lf[d]; }   // no valid atom
     const float cs = g.Lf[d] / (float)nf;
-    r0[d] = (int)floorf((lo[d] - (float)g.rlist - 0.05f) / cs);
-    r1[d] = (int)floorf((hi[d] + (float)g.rlist + 0.05f) / cs);
+    r0[d] = (int)floorf((cen[d] - half[d] - (float)g.rlist - 0.05f) / cs);
+    r1[d] = (int)floorf((cen[d] + half[d] + (float)g.rlist + 0.05f) / cs);
     if (r1[d] - r0[d] + 1 >= nf) { r0[d] = 0; r1[d] = nf - 1; all_cells = true; }
   }
   const float4* __restrict__ xq = g.xyzq + (size_t)w * g.npad;
@@ -346,7 +347,10 @@ __global__ __launch_bounds__(256) void k_build(const LegDev* legs, BlockMap map)
     __builtin_amdgcn_wave_barrier();      // the chunk's tables are rewritten next
   }
   if (count > g.cap) {
-    if (lane == 0) { atomicOr(g.err, kErrListCap); atomicMax(g.need, count); }
+    if (lane == 0) {
+      latch(g.err, kErrListCap, kSiteList, (w << 20) | max(s_ai[wave][0], 0), g.leg_index);
+      atomicMax(g.need, count);
+    }
     count = g.cap;
   }
   const int padded = min(g.cap, (count + 7) & ~7);

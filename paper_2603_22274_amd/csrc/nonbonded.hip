@@ -133,9 +133,9 @@ __global__ __launch_bounds__(256) void k_pairs(const LegDev* legs, BlockMap map)
     if (a >= 0) {
       const size_t o = (size_t)w * g.n + a;
       const int where = (w << 20) | a;
-      g.fx[o] = to_fixed((double)fx, kForceScale, g.err, kSitePairs, where);
-      g.fy[o] = to_fixed((double)fy, kForceScale, g.err, kSitePairs, where);
-      g.fz[o] = to_fixed((double)fz, kForceScale, g.err, kSitePairs, where);
+      g.fx[o] = to_fixed((double)fx, kForceScale, g.err, kSitePairs, where, g.leg_index);
+      g.fy[o] = to_fixed((double)fy, kForceScale, g.err, kSitePairs, where, g.leg_index);
+      g.fz[o] = to_fixed((double)fz, kForceScale, g.err, kSitePairs, where, g.leg_index);
     }
   }
   if (ENERGY) {
@@ -152,10 +152,10 @@ __global__ __launch_bounds__(256) void k_pairs(const LegDev* legs, BlockMap map)
 }
 
 __device__ __forceinline__ void add_force(const LegDev& g, size_t o, float fx, float fy, float fz, int site) {
-  const int where = (int)o;
-  atomicAdd((unsigned long long*)&g.fx[o], (unsigned long long)to_fixed((double)fx, kForceScale, g.err, site, where));
-  atomicAdd((unsigned long long*)&g.fy[o], (unsigned long long)to_fixed((double)fy, kForceScale, g.err, site, where));
-  atomicAdd((unsigned long long*)&g.fz[o], (unsigned long long)to_fixed((double)fz, kForceScale, g.err, site, where));
+  const int where = (int)(((o / g.n) << 20) | (o % g.n));     // window << 20 | atom
+  atomicAdd((unsigned long long*)&g.fx[o], (unsigned long long)to_fixed((double)fx, kForceScale, g.err, site, where, g.leg_index));
+  atomicAdd((unsigned long long*)&g.fy[o], (unsigned long long)to_fixed((double)fy, kForceScale, g.err, site, where, g.leg_index));
+  atomicAdd((unsigned long long*)&g.fz[o], (unsigned long long)to_fixed((double)fz, kForceScale, g.err, site, where, g.leg_index));
 }
 
 __device__ __forceinline__ void add_energy(const LegDev& g, int w, int comp, double e, int lane) {

@@ -207,7 +207,8 @@ __device__ __forceinline__ void bspline4(float f, float* w, float* dw) {
 
 // fractional grid coordinate in FP64: base index and offset f in [0, 1)
 __device__ __forceinline__ int grid_base(float x, double invL, int K, float* f) {
-  const double u = (double)x * invL * (double)K;
+  double u = (double)x * invL * (double)K;
+  if (!(fabs(u) < 1.0e15)) u = 0.0;              // non-finite input -> 0 (keeps indices in range)
   const double b = floor(u);
   *f = (float)(u - b);
   long long k = (long long)b % K;
@@ -297,9 +298,9 @@ __global__ __launch_bounds__(256) void k_gather(const LegDev* legs, BlockMap map
     const float fy = -q * gys * (float)g.K[1] * g.invLf[1];
     const float fz = -q * gzs * (float)g.K[2] * g.invLf[2];
     const int where = (w << 20) | a;
-    g.fx[o] += to_fixed((double)fx, kForceScale, g.err, kSiteGather, where);
-    g.fy[o] += to_fixed((double)fy, kForceScale, g.err, kSiteGather, where);
-    g.fz[o] += to_fixed((double)fz, kForceScale, g.err, kSiteGather, where);
+    g.fx[o] += to_fixed((double)fx, kForceScale, g.err, kSiteGather, where, g.leg_index);
+    g.fy[o] += to_fixed((double)fy, kForceScale, g.err, kSiteGather, where, g.leg_index);
+    g.fz[o] += to_fixed((double)fz, kForceScale, g.err, kSiteGather, where, g.leg_index);
   }
   if (ENERGY) {
     double e = (valid && sub == 0) ? 0.5 * (double)q * (double)pot : 0.0;

@@ -52,7 +52,8 @@ __device__ __forceinline__ void bspline4(float f, float* w) {
 }
 
 __device__ __forceinline__ int grid_base(float x, double invL, int K, float* f) {
-  const double u = (double)x * invL * (double)K;
+  double u = (double)x * invL * (double)K;
+  if (!(fabs(u) < 1.0e15)) u = 0.0;              // non-finite input -> 0 (keeps indices in range)
   const double b = floor(u);
   *f = (float)(u - b);
   long long k = (long long)b % K;

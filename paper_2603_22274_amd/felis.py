@@ -69,6 +69,7 @@ def lib():
         'felis_destroy': (None, [vp]),
         'felis_last_error': (C.c_char_p, [vp]),
         'felis_check': (C.c_int, [vp, P(C.c_int32)]),
+        'felis_check_detail': (C.c_int, [vp, P(C.c_int32), P(C.c_int32), P(C.c_int32), P(C.c_int32)]),
         'felis_leg_work_size': (C.c_int, [P(FelisLeg), P(C.c_size_t)]),
         'felis_leg_init': (C.c_int, [vp, P(FelisLeg)]),
         'felis_build_nlist': (C.c_int, [vp, P(FelisLeg), C.c_int, C.c_int]),
@@ -114,10 +115,12 @@ class Context:
             raise FelisError(rc, lib().felis_last_error(self.h).decode())
 
     def device_check(self):
-        need = C.c_int32(0)
-        rc = lib().felis_check(self.h, C.byref(need))
+        need, leg, win, atom = C.c_int32(0), C.c_int32(-1), C.c_int32(-1), C.c_int32(-1)
+        rc = lib().felis_check_detail(self.h, C.byref(need), C.byref(leg), C.byref(win), C.byref(atom))
         if rc:
-            raise FelisError(rc, lib().felis_last_error(self.h).decode() + f" (longest list {need.value})")
+            e = FelisError(rc, lib().felis_last_error(self.h).decode() + f" (longest list {need.value})")
+            e.needed_cap, e.leg, e.window, e.atom = need.value, leg.value, win.value, atom.value
+            raise e
 
     def close(self):
         if self.h:
@@ -234,6 +237,34 @@ class Leg:
     def state_bytes(self):
         tens = [self.x, self.y, self.z, self.vx, self.vy, self.vz, self.fx, self.fy, self.fz, self.energy, self.work]
         return sum(t.numel() * t.element_size() for t in tens)
+
+
+def leg_footprint(sysd, n_windows=None, list_cap=0):
+    """Device bytes a ``Leg`` of ``sysd`` holds (library scratch + state and
+    topology tensors), computed without allocating anything."""
+    W, N = (sysd.n_windows if n_windows is None else n_windows), sysd.n_atoms
+    s = FelisLeg()
+    s.n_atoms, s.n_windows = N, W
+    s.box = (C.c_double * 3)(*[float(v) for v in sysd.box])
+    s.r_cut, s.skin, s.ewald_alpha = sysd.r_cut, sysd.skin, sysd.ewald_alpha
+    s.sc_alpha, s.sc_p = sysd.sc_alpha, sysd.sc_p
+    s.grid = (C.c_int32 * 3)(*sysd.grid)
+    s.spline_order = sysd.spline_order
+    s.list_cap = list_cap
+    s.n_excl, s.n_bonds, s.n_waters = len(sysd.excl), len(sysd.bonds), len(sysd.waters)
+    # felis_leg_work_size validates but never dereferences the arrays
+    fake = C.c_void_p(256)
+    for k in ('charge', 'sigma', 'epsilon', 'mass', 'is_ligand', 'excl_ij', 'excl_ptr', 'excl_idx', 'bond_ij',
+              'bond_k', 'bond_r0', 'water_ohh', 'lambdas', 'x', 'y', 'z', 'vx', 'vy', 'vz', 'fx', 'fy', 'fz',
+              'energy'):
+        setattr(s, k, fake)
+    nbytes = C.c_size_t(0)
+    rc = lib().felis_leg_work_size(C.byref(s), C.byref(nbytes))
+    if rc:
+        raise FelisError(rc, "leg configuration rejected")
+    state = W * N * (6 * 4 + 3 * 8) + W * NE * 8
+    topo = N * 17 + (N + 1) * 4 + len(sysd.excl) * 12 + len(sysd.bonds) * 16 + len(sysd.waters) * 12
+    return int(nbytes.value) + state + topo
 
 
 def _batch(legs):
