@@ -23,7 +23,8 @@
  * felis_leg_work_size.
  * Streams: every call is enqueued on the HIP stream given to felis_create and
  * returns without waiting, except felis_leg_init, felis_check,
- * felis_nlist_export_pairs and felis_mbar (they synchronise that stream).
+ * felis_check_detail, felis_leg_rebuilds, felis_nlist_export_pairs and
+ * felis_mbar (they synchronise that stream).
  * Errors: every function returns FELIS_OK (0) or a negative FELIS_E_* code; no
  * exception crosses the ABI and nothing aborts.  Device-side faults (list
  * capacity, fixed-point overflow, non-finite forces) are latched in a device
@@ -148,12 +149,16 @@ int felis_leg_work_size(const felis_leg* leg, size_t* bytes);
 int felis_leg_init(felis_ctx* ctx, felis_leg* leg);
 
 /* Neighbour lists (appendix B cutoffs; list radius r_cut + skin).  Per window,
- * atoms are sorted along a Morton curve of fine cells and grouped into
+ * atoms are sorted along a Hilbert curve of fine cells and grouped into
  * 8-atom clusters; each cluster lists every atom j with, for each of its atoms
  * i, a bit: |d_ij| < r_cut + skin in FP64 minimum image, j != i, (i, j) not
  * excluded.  With force = 0 only windows whose atoms moved more than skin/2
  * since their last build are rebuilt; force = 1 rebuilds all. */
 int felis_build_nlist(felis_ctx* ctx, felis_leg* legs, int n_legs, int force);
+
+/* Neighbour-list builds of each window since felis_leg_init (forced builds
+ * included): counts (host) [n_windows].  Synchronises the stream. */
+int felis_leg_rebuilds(felis_ctx* ctx, const felis_leg* leg, int64_t* counts);
 
 /* Test/diagnostic export of window `window`'s list: every pair (i < j) whose
  * list bit is set and whose FP64 minimum-image distance is < r (pass

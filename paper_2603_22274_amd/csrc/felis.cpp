@@ -18,7 +18,7 @@ using namespace felis;
 namespace {
 
 struct Layout {
-  size_t lam, free_atoms, lig_idx, xr, yr, zr, flag, perm, cellcode, cellstart, cursor, xyzq, prm, bblo,
+  size_t lam, free_atoms, lig_idx, xr, yr, zr, flag, nbuild, perm, cellcode, cellstart, cursor, xyzq, prm, bblo,
       bbhi, lcount, lent, grid64, cgrid, tw[3], bmod[3], eacc, uacc, upart, lpart, ucst, total;
 };
 
@@ -116,9 +116,9 @@ int make_plan(felis_ctx* c, const felis_leg* L, Plan& P) {
   int cap = L->list_cap;
   if (cap <= 0) {
     const double rho = h.n / V;
-    // union of r_list spheres around a cluster's atoms, with room for clusters
-    // that straddle a jump of the Morton order (up to ~2x the compact size)
-    cap = (int)std::ceil(3.0 * rho * 4.0 / 3.0 * M_PI * std::pow(rl + 1.5, 3) + 64.0);
+    // union of r_list spheres around a compact cluster (Hilbert-ordered
+    // clusters span a few A), with 2x room for density fluctuations
+    cap = (int)std::ceil(2.0 * rho * 4.0 / 3.0 * M_PI * std::pow(rl + 1.5, 3) + 64.0);
   }
   cap = std::min((cap + 7) & ~7, h.npad);
   h.cap = std::max(cap, 8);
@@ -148,6 +148,7 @@ int make_plan(felis_ctx* c, const felis_leg* L, Plan& P) {
   y.lig_idx = put(n * 4);
   y.xr = put(W * n * 4); y.yr = put(W * n * 4); y.zr = put(W * n * 4);
   y.flag = put(W * 4);
+  y.nbuild = put(W * 8);
   y.perm = put(W * npad * 4);
   y.cellcode = put(W * n * 4);
   y.cellstart = put(W * (h.ncell + 1) * 4);
@@ -221,6 +222,7 @@ LegDev make_dev(const felis_ctx* c, const felis_leg* L, const Plan& p, const Met
   g.lig_idx = (int*)(w + y.lig_idx);
   g.xr = (float*)(w + y.xr); g.yr = (float*)(w + y.yr); g.zr = (float*)(w + y.zr);
   g.flag = (int*)(w + y.flag);
+  g.nbuild = (long long*)(w + y.nbuild);
   g.perm = (int*)(w + y.perm);
   g.cellcode = (int*)(w + y.cellcode);
   g.cellstart = (int*)(w + y.cellstart);
@@ -376,6 +378,18 @@ int felis_leg_work_size(const felis_leg* leg, size_t* bytes) {
   return FELIS_OK;
 }
 
+int felis_leg_rebuilds(felis_ctx* c, const felis_leg* L, int64_t* counts) {
+  if (!c || !counts) return FELIS_E_INVAL;
+  Plan p;
+  int rc = make_plan(c, L, p);
+  if (rc) return rc;
+  if (!L->work || L->work_bytes < p.lay.total) return fail(c, FELIS_E_INVAL, "leg work buffer too small");
+  if (hipStreamSynchronize(c->stream) != hipSuccess ||
+      hipMemcpy(counts, (char*)L->work + p.lay.nbuild, sizeof(int64_t) * p.h.W, hipMemcpyDeviceToHost) != hipSuccess)
+    return fail(c, FELIS_E_DEVICE, "rebuild counters unreadable");
+  return FELIS_OK;
+}
+
 int felis_leg_init(felis_ctx* c, felis_leg* L) {
   if (!c) return FELIS_E_INVAL;
   Plan p;
@@ -434,6 +448,7 @@ int felis_leg_init(felis_ctx* c, felis_leg* L) {
   std::memcpy(&farbits, &far, 4);
   ok &= hipMemsetD32Async((hipDeviceptr_t)(w + y.xr), farbits, 3 * ((y.yr - y.xr) / 4), c->stream) == hipSuccess;
   ok &= hipMemsetD32Async((hipDeviceptr_t)(w + y.flag), 1, h.W, c->stream) == hipSuccess;
+  ok &= hipMemsetAsync(w + y.nbuild, 0, h.W * 8, c->stream) == hipSuccess;
   ok &= hipMemsetAsync(w + y.lcount, 0, (size_t)h.W * h.nclus * 4, c->stream) == hipSuccess;
   ok &= hipMemsetAsync(w + y.grid64, 0, y.cgrid - y.grid64, c->stream) == hipSuccess;
   ok &= hipMemsetAsync(w + y.eacc, 0, y.ucst - y.eacc, c->stream) == hipSuccess;

@@ -40,7 +40,7 @@ struct LegDev {
   int n, W, npad, nclus, cap;           // atoms, windows, padded atoms, clusters, list cap
   int nexcl, nbonds, nwat, nfree, nlig;
   int K[3], Ktot, npair;
-  int nbits, ncoarse, ncell;            // fine cells = 2^nbits per axis (Morton order)
+  int nbits, ncoarse, ncell;            // fine cells = 2^nbits per axis (Hilbert order)
   int nrad[3], rad[3][kMaxRadix];       // FFT radix plan per axis
   int has_rest, ranch[6];
   float rg0[6], rk[6];
@@ -69,6 +69,7 @@ struct LegDev {
   int* lig_idx;                         // [nlig] ligand atoms
   float *xr, *yr, *zr;                  // [W][n] positions at the last list build
   int* flag;                            // [W] rebuild flags
+  long long* nbuild;                    // [W] list builds since init
   int* perm;                            // [W][npad] sorted slot -> atom (-1 = padding)
   int* cellcode;                        // [W][n]
   int* cellstart;                       // [W][ncell + 1]

@@ -1,4 +1,4 @@
-// Neighbour lists: displacement check, Morton cell sort, 8-atom clusters and
+// Neighbour lists: displacement check, Hilbert cell sort, 8-atom clusters and
 // per-cluster j-lists (appendix B cutoffs).
 //
 // A cluster lists every atom j that lies within r_list + 0.01 A (FP32
@@ -14,14 +14,36 @@
 namespace felis {
 namespace {
 
-__device__ __forceinline__ unsigned morton3(unsigned x, unsigned y, unsigned z, int bits) {
-  unsigned c = 0;
-  for (int b = 0; b < bits; ++b) {
-    c |= ((x >> b) & 1u) << (3 * b);
-    c |= ((y >> b) & 1u) << (3 * b + 1);
-    c |= ((z >> b) & 1u) << (3 * b + 2);
+// Index of cell (x, y, z) along a 3D Hilbert curve of 2^bits cells per axis
+// (Skilling's transpose construction: undo excess work, Gray-code, then
+// interleave).  Consecutive indices are face-adjacent cells, and the 8
+// children of every aligned 2x2x2 block hold 8 consecutive indices, so a
+// coarse block's atoms form one contiguous range of the sorted order.
+__device__ __forceinline__ unsigned hilbert3(unsigned x, unsigned y, unsigned z, int bits) {
+  unsigned X[3] = {x, y, z};
+  for (unsigned Q = 1u << (bits - 1); Q > 1u; Q >>= 1) {
+    const unsigned P = Q - 1u;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      if (X[i] & Q) {
+        X[0] ^= P;
+      } else {
+        const unsigned t = (X[0] ^ X[i]) & P;
+        X[0] ^= t;
+        X[i] ^= t;
+      }
+    }
   }
-  return c;
+  X[1] ^= X[0];
+  X[2] ^= X[1];
+  unsigned t = 0;
+  for (unsigned Q = 1u << (bits - 1); Q > 1u; Q >>= 1)
+    if (X[2] & Q) t ^= Q - 1u;
+  X[0] ^= t; X[1] ^= t; X[2] ^= t;
+  unsigned h = 0;
+  for (int b = bits - 1; b >= 0; --b)
+    h = (h << 3) | (((X[0] >> b) & 1u) << 2) | (((X[1] >> b) & 1u) << 1) | ((X[2] >> b) & 1u);
+  return h;
 }
 
 __device__ __forceinline__ int cell_of(float v, float L, float invL, int n) {
@@ -50,7 +72,11 @@ __global__ __launch_bounds__(256) void k_check(const LegDev* legs, BlockMap map,
     if (threadIdx.x < s) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + s]);
     __syncthreads();
   }
-  if (threadIdx.x == 0) g.flag[w] = (force || !(red[0] <= g.skin_half2)) ? 1 : 0;
+  if (threadIdx.x == 0) {
+    const int f = (force || !(red[0] <= g.skin_half2)) ? 1 : 0;
+    g.flag[w] = f;
+    g.nbuild[w] += f;
+  }
 }
 
 // items: window x cell -- zero the per-cell counters of windows being rebuilt
@@ -64,7 +90,7 @@ __global__ __launch_bounds__(256) void k_cells_zero(const LegDev* legs, BlockMap
   g.cursor[i] = 0;
 }
 
-// items: window x atom -- Morton cell code, per-cell counts, reference positions
+// items: window x atom -- Hilbert cell code, per-cell counts, reference positions
 __global__ __launch_bounds__(256) void k_cells_count(const LegDev* legs, BlockMap map) {
   const int leg = find_leg(map, blockIdx.x);
   const LegDev& g = legs[leg];
@@ -74,8 +100,8 @@ __global__ __launch_bounds__(256) void k_cells_count(const LegDev* legs, BlockMa
   if (!g.flag[w]) return;
   const int nf = 1 << g.nbits;
   const float x = g.x[i], y = g.y[i], z = g.z[i];
-  const unsigned c = morton3(cell_of(x, g.Lf[0], g.invLf[0], nf), cell_of(y, g.Lf[1], g.invLf[1], nf),
-                             cell_of(z, g.Lf[2], g.invLf[2], nf), g.nbits);
+  const unsigned c = hilbert3(cell_of(x, g.Lf[0], g.invLf[0], nf), cell_of(y, g.Lf[1], g.invLf[1], nf),
+                              cell_of(z, g.Lf[2], g.invLf[2], nf), g.nbits);
   g.cellcode[i] = (int)c;
   atomicAdd(&g.cursor[(size_t)w * g.ncell + c], 1);
   g.xr[i] = x; g.yr[i] = y; g.zr[i] = z;
@@ -186,125 +212,132 @@ __global__ __launch_bounds__(256) void k_bbox(const LegDev* legs, BlockMap map) 
   g.bbhi[i] = make_float4(hi[0], hi[1], hi[2], 0.f);
 }
 
-// One wave per cluster: scan the coarse cells within r_list of the cluster's
-// box and list every atom j with at least one i of the cluster in range.
+// One block per cluster: sweep the coarse blocks (aligned 2x2x2 fine cells)
+// within r_list of the cluster's box, 256 blocks per round, and list every
+// atom j with at least one i of the cluster in range.  The four waves take
+// consecutive quarters of each 256-candidate step and append in wave order,
+// so the list order is fixed (cells in sweep order, slots ascending) while a
+// cluster's candidates are spread over 256 lanes.
 __global__ __launch_bounds__(256) void k_build(const LegDev* legs, BlockMap map) {
   const int leg = find_leg(map, blockIdx.x);
   const LegDev& g = legs[leg];
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const long long item = (long long)(blockIdx.x - map.start[leg]) * 4 + wave;
-  const long long total = (long long)g.W * g.nclus;
-  const long long itm = item < total ? item : total - 1;
-  const int w = (int)(itm / g.nclus);
-  const bool active = item < total && g.flag[w] != 0;   // uniform per wave
-  const int c = (int)(itm - (long long)w * g.nclus);
+  const long long item = (long long)blockIdx.x - map.start[leg];
+  const int w = (int)(item / g.nclus);
+  if (!g.flag[w]) return;                       // uniform over the block
+  const int c = (int)(item - (long long)w * g.nclus);
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
 
-  __shared__ int s_ai[4][kClus];
-  __shared__ double s_xi[4][kClus][3];
-  __shared__ int s_ex[4][kClus][kMaxExcl];
-  __shared__ int s_nex[4][kClus];
+  __shared__ int s_ai[kClus];
+  __shared__ float s_xi[kClus][3];
+  __shared__ int s_ex[kClus][kMaxExcl];
+  __shared__ int s_nex[kClus];
+  __shared__ unsigned s_bloom[64];              // 2048-bit filter of excluded atoms
+  __shared__ int s_start[256];                  // first sorted slot of each block in the round
+  __shared__ int s_pre[256];                    // exclusive prefix of candidate counts
+  __shared__ int s_wsum[4];
+  __shared__ int s_wc[2][4];
   const size_t o = (size_t)w * g.n;
   const int* perm = g.perm + (size_t)w * g.npad;
-  if (active && lane < kClus) {
-    const int a = perm[c * kClus + lane];
-    s_ai[wave][lane] = a;
+  if (tid < 64) s_bloom[tid] = 0u;
+  __syncthreads();
+  if (tid < kClus) {
+    const int a = perm[c * kClus + tid];
+    s_ai[tid] = a;
     int ne = 0;
     if (a >= 0) {
-      s_xi[wave][lane][0] = (double)g.x[o + a];
-      s_xi[wave][lane][1] = (double)g.y[o + a];
-      s_xi[wave][lane][2] = (double)g.z[o + a];
+      s_xi[tid][0] = g.x[o + a];
+      s_xi[tid][1] = g.y[o + a];
+      s_xi[tid][2] = g.z[o + a];
       const int e0 = g.excl_ptr[a], e1 = g.excl_ptr[a + 1];
       ne = e1 - e0;
       if (ne > kMaxExcl) { latch(g.err, kErrExcl, kSiteExclCount, (w << 20) | a, g.leg_index); ne = kMaxExcl; }
-      for (int k = 0; k < ne; ++k) s_ex[wave][lane][k] = g.excl_idx[e0 + k];
+      for (int k = 0; k < ne; ++k) {
+        const int e = g.excl_idx[e0 + k];
+        s_ex[tid][k] = e;
+        atomicOr(&s_bloom[(e >> 5) & 63], 1u << (e & 31));
+      }
     }
-    s_nex[wave][lane] = ne;
+    s_nex[tid] = ne;
   }
-  __syncthreads();            // every wave of the block reaches this barrier
-  if (!active) return;
+  __syncthreads();
 
   const float4 lo4 = g.bblo[item], hi4 = g.bbhi[item];
   const float lo[3] = {lo4.x, lo4.y, lo4.z}, hi[3] = {hi4.x, hi4.y, hi4.z};
+  const int nf = g.ncoarse;
+  const float pre = (float)g.rlist + 0.05f;
+  const float pre2 = pre * pre;
+  int r0[3], nC[3];
+  bool full[3];
   float cen[3], half[3];
-  int r0[3], r1[3];
-  const int nf = g.ncoarse;          // search blocks: aligned 2x2x2 groups of fine cells
-  bool all_cells = false;
   for (int d = 0; d < 3; ++d) {
     cen[d] = 0.5f * (lo[d] + hi[d]);
     half[d] = 0.5f * (hi[d] - lo[d]);
     if (!(half[d] >= 0.f && half[d] <= g.Lf[d])) { cen[d] = 0.f; half[d] = g.Lf[d]; }   // no valid atom
     const float cs = g.Lf[d] / (float)nf;
-    r0[d] = (int)floorf((cen[d] - half[d] - (float)g.rlist - 0.05f) / cs);
-    r1[d] = (int)floorf((cen[d] + half[d] + (float)g.rlist + 0.05f) / cs);
-    if (r1[d] - r0[d] + 1 >= nf) { r0[d] = 0; r1[d] = nf - 1; all_cells = true; }
+    const int a0 = (int)floorf((cen[d] - half[d] - pre) / cs);
+    const int a1 = (int)floorf((cen[d] + half[d] + pre) / cs);
+    full[d] = a1 - a0 + 1 >= nf;               // the range wraps onto itself: every cell, no gap test
+    r0[d] = full[d] ? 0 : a0;
+    nC[d] = full[d] ? nf : a1 - a0 + 1;
   }
   const float4* __restrict__ xq = g.xyzq + (size_t)w * g.npad;
-  const float pre = (float)g.rlist + 0.05f;
-  const float pre2 = pre * pre;
   const float incl = (float)g.rlist + 0.01f;
   const float inc2 = incl * incl;
   float xi[kClus][3];
   int ai[kClus];
 #pragma unroll
   for (int ii = 0; ii < kClus; ++ii) {
-    ai[ii] = __builtin_amdgcn_readfirstlane(s_ai[wave][ii]);        // wave-uniform: SGPRs
-    for (int d = 0; d < 3; ++d)
-      xi[ii][d] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int((float)s_xi[wave][ii][d])));
+    ai[ii] = __builtin_amdgcn_readfirstlane(s_ai[ii]);           // uniform: scalar registers
+    for (int d = 0; d < 3; ++d) xi[ii][d] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(s_xi[ii][d])));
   }
   const int* cst = g.cellstart + (size_t)w * (g.ncell + 1);
   unsigned* out = g.lent + (size_t)item * g.cap;
-  int count = 0;
   const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  const int nX = r1[0] - r0[0] + 1, nY = r1[1] - r0[1] + 1, nZ = r1[2] - r0[2] + 1;
-  const int ncells = nX * nY * nZ;
-  __shared__ int s_start[4][64];     // first sorted slot of each cell in the chunk
-  __shared__ int s_pre[4][64];       // exclusive prefix of candidate counts
-
-  // Cells are taken 64 at a time: lanes fetch their cell's slot range in
-  // parallel, a wave scan lays the candidates of the chunk end to end, and the
-  // wave sweeps that flat range 64 candidates per iteration (cell order, then
-  // sorted order within a cell: deterministic).
-  for (int cb = 0; cb < ncells; cb += 64) {
-    const int ci = cb + lane;
+  const int ncells = nC[0] * nC[1] * nC[2];
+  int count = 0, par = 0;
+  for (int cb = 0; cb < ncells; cb += 256) {
+    const int ci = cb + tid;
     int s0 = 0, cnt = 0;
     if (ci < ncells) {
-      const int C[3] = {r0[0] + ci / (nY * nZ), r0[1] + (ci / nZ) % nY, r0[2] + ci % nZ};
-      // distance from the cell (unwrapped frame of the cluster box) to the box;
-      // when the range wraps onto itself every cell is kept
+      const int C[3] = {r0[0] + ci / (nC[1] * nC[2]), r0[1] + (ci / nC[2]) % nC[1], r0[2] + ci % nC[2]};
       float gap2 = 0.f;
       for (int d = 0; d < 3; ++d) {
+        if (full[d]) continue;
         const float cs = g.Lf[d] / (float)nf;
         const float gp = fmaxf(0.f, fmaxf((float)C[d] * cs - hi[d], lo[d] - (float)(C[d] + 1) * cs));
         gap2 += gp * gp;
       }
-      if (all_cells || gap2 < pre2) {
-        const unsigned cc = morton3((unsigned)((C[0] % nf + nf) % nf), (unsigned)((C[1] % nf + nf) % nf),
-                                    (unsigned)((C[2] % nf + nf) % nf), g.nbits - 1);
-        s0 = cst[8 * cc];                // fine cells 8cc .. 8cc+7 are contiguous
+      if (gap2 < pre2) {
+        const unsigned cc = hilbert3(2u * (unsigned)((C[0] % nf + nf) % nf), 2u * (unsigned)((C[1] % nf + nf) % nf),
+                                     2u * (unsigned)((C[2] % nf + nf) % nf), g.nbits) >> 3;
+        s0 = cst[8 * cc];                        // fine cells 8cc .. 8cc+7 are contiguous
         cnt = cst[8 * cc + 8] - s0;
       }
     }
     int inc = cnt;
-    for (int o = 1; o < 64; o <<= 1) {
-      const int v = __shfl_up(inc, o, 64);
-      if (lane >= o) inc += v;
+    for (int k = 1; k < 64; k <<= 1) {
+      const int v = __shfl_up(inc, k, 64);
+      if (lane >= k) inc += v;
     }
-    const int total = __shfl(inc, 63, 64);
-    s_start[wave][lane] = s0;
-    s_pre[wave][lane] = inc - cnt;
-    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    for (int t0 = 0; t0 < total; t0 += 64) {
-      const int t = t0 + lane;
+    if (lane == 63) s_wsum[wave] = inc;
+    s_start[tid] = s0;
+    __syncthreads();
+    int woff = 0;
+    for (int k = 0; k < wave; ++k) woff += s_wsum[k];
+    const int total = s_wsum[0] + s_wsum[1] + s_wsum[2] + s_wsum[3];
+    s_pre[tid] = woff + inc - cnt;
+    __syncthreads();
+    for (int t0 = 0; t0 < total; t0 += 256) {
+      const int t = t0 + tid;
       unsigned mask = 0;
       int s = 0;
       if (t < total) {
-        int lo = 0, hi = 63;                     // last cell with prefix <= t
-        while (lo < hi) {
-          const int mid = (lo + hi + 1) >> 1;
-          if (s_pre[wave][mid] <= t) lo = mid; else hi = mid - 1;
+        int l = 0, h = 255;                      // last block with prefix <= t
+        while (l < h) {
+          const int mid = (l + h + 1) >> 1;
+          if (s_pre[mid] <= t) l = mid; else h = mid - 1;
         }
-        s = s_start[wave][lo] + (t - s_pre[wave][lo]);
+        s = s_start[l] + (t - s_pre[l]);
         const int a = perm[s];
         const float4 rj = xq[s];
         const float xj[3] = {rj.x, rj.y, rj.z};
@@ -327,35 +360,38 @@ __global__ __launch_bounds__(256) void k_build(const LegDev* legs, BlockMap map)
             const float d2 = (dx * dx + dy * dy) + dz * dz;
             if (d2 < inc2 && ai[ii] >= 0 && ai[ii] != a) mask |= 1u << ii;
           }
-          if (mask) {                           // drop excluded (i, j)
+          if (mask && ((s_bloom[(a >> 5) & 63] >> (a & 31)) & 1u)) {   // possibly excluded
             for (int ii = 0; ii < kClus; ++ii) {
               if (!((mask >> ii) & 1u)) continue;
               bool ex = false;
-              for (int k = 0; k < s_nex[wave][ii]; ++k) ex |= (s_ex[wave][ii][k] == a);
+              for (int k = 0; k < s_nex[ii]; ++k) ex |= (s_ex[ii][k] == a);
               if (ex) mask &= ~(1u << ii);
             }
           }
         }
       }
       const unsigned long long bal = __ballot(mask != 0u);
+      if (lane == 0) s_wc[par][wave] = __popcll(bal);
+      __syncthreads();
+      int off = count;
+      for (int k = 0; k < wave; ++k) off += s_wc[par][k];
+      count += s_wc[par][0] + s_wc[par][1] + s_wc[par][2] + s_wc[par][3];
       if (mask) {
-        const int pos = count + __popcll(bal & lt);
+        const int pos = off + __popcll(bal & lt);
         if (pos < g.cap) out[pos] = ((unsigned)s << 8) | mask;
       }
-      count += __popcll(bal);
+      par ^= 1;
     }
-    __builtin_amdgcn_wave_barrier();      // the chunk's tables are rewritten next
+    __syncthreads();                            // the round's tables are rewritten next
   }
   if (count > g.cap) {
-    if (lane == 0) {
-      latch(g.err, kErrListCap, kSiteList, (w << 20) | max(s_ai[wave][0], 0), g.leg_index);
+    if (tid == 0) {
+      latch(g.err, kErrListCap, kSiteList, (w << 20) | max(s_ai[0], 0), g.leg_index);
       atomicMax(g.need, count);
     }
     count = g.cap;
   }
-  const int padded = min(g.cap, (count + 7) & ~7);
-  for (int p = count + lane; p < padded; p += 64) out[p] = 0u;
-  if (lane == 0) g.lcount[item] = padded;
+  if (tid == 0) g.lcount[item] = count;
 }
 
 // Export pairs i < j with a set list bit and FP64 distance < r.
@@ -420,7 +456,7 @@ void launch_build(hipStream_t s, const LegDev* d, const LegHost* h, int nl) {
   launch_pack(s, d, h, nl);        // sorted coordinates for the box and candidate sweeps
   nb = make_map(m, nl, [&](int i) { return blocks_for((long long)h[i].W * h[i].nclus, 256); });
   if (nb) hipLaunchKernelGGL(k_bbox, dim3(nb), dim3(256), 0, s, d, m);
-  nb = make_map(m, nl, [&](int i) { return blocks_for((long long)h[i].W * h[i].nclus, 4); });
+  nb = make_map(m, nl, [&](int i) { return h[i].W * h[i].nclus; });
   if (nb) hipLaunchKernelGGL(k_build, dim3(nb), dim3(256), 0, s, d, m);
 }
 

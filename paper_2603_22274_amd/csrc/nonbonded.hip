@@ -7,12 +7,14 @@
 // the ligand and 1 otherwise; Lorentz-Berthelot mixing; everything cut at r_c
 // (appendix B).  Real-space Coulomb is the Ewald direct term erfc(a r)/r.
 //
-// Pair kernel layout (gfx950, wave64): one wave per 8-atom i-cluster; lane
-// l = ii + 8 jj holds i-atom ii and, per iteration, the jj-th of 8 listed
-// j-atoms.  Each cluster lists all its partners (both directions), so every
-// atom's pair force is summed by one wave in a fixed order and written once:
-// no atomics and no cross-wave ordering.  FP32 arithmetic; energies summed in
-// FP64 per lane and combined in int64 fixed point.
+// Pair kernel layout (gfx950, wave64): one wave per 8-atom i-cluster; the
+// cluster's i-atoms are wave-uniform and each lane takes one listed j-atom per
+// iteration and interacts it with all 8 i-atoms, so a j entry is loaded,
+// decoded and imaged once for 8 pairs.  Each cluster lists all its partners
+// (both directions), so every atom's pair force is summed by one wave in a
+// fixed order and written once: no atomics and no cross-wave ordering.  FP32
+// arithmetic; energies summed in FP64 per lane and combined in int64 fixed
+// point.
 #include "felis_internal.h"
 #include "erfc_coeffs.h"
 #include "restraint.h"
@@ -47,95 +49,156 @@ __global__ __launch_bounds__(256) void k_pack(const LegDev* legs, BlockMap map) 
   g.xyzq[i] = v;
 }
 
-template <bool ENERGY>
-__global__ __launch_bounds__(256) void k_pairs(const LegDev* legs, BlockMap map) {
-  const int leg = find_leg(map, blockIdx.x);
-  const LegDev& g = legs[leg];
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const long long item = (long long)(blockIdx.x - map.start[leg]) * 4 + wave;
-  if (item >= (long long)g.W * g.nclus) return;
-  const int w = (int)(item / g.nclus);
-  const int c = (int)(item - (long long)w * g.nclus);
-  const int ii = lane & 7, jj = lane >> 3;
-  const float4* __restrict__ xq = g.xyzq + (size_t)w * g.npad;
-  const float4* __restrict__ pr = g.prm + (size_t)w * g.npad;
-  const float4 xi = xq[c * kClus + ii];
-  const float4 pi = pr[c * kClus + ii];
-  const float lam_v = g.lam[4 * w + 1];
-  const float a_sc = g.lam[4 * w + 3];
-  const bool soft_window = lam_v < 1.0f;
+// The 8 i-atoms of a cluster, wave-uniform (held in scalar registers).
+struct ICluster {
+  float x[kClus], y[kClus], z[kClus], q[kClus], sig[kClus], eps[kClus], lig[kClus];
+};
+
+__device__ __forceinline__ float uniform(float v) {
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+
+// Sweep a cluster's j-list: lane = listed j, unrolled loop over the cluster's
+// i-atoms.  SHIFT: the periodic image of j is chosen once against the
+// cluster's first atom (exact when r_c + cluster extent < L/2 on every axis);
+// otherwise every (i, j) takes its own minimum image.
+template <bool ENERGY, bool SHIFT>
+__device__ __forceinline__ void sweep(const LegDev& g, const ICluster& I, const unsigned* __restrict__ ent, int cnt,
+                                      const float4* __restrict__ xq, const float4* __restrict__ pr, int lane,
+                                      float lam_v, float a_sc, bool soft_window, float (&fx)[kClus],
+                                      float (&fy)[kClus], float (&fz)[kClus], double& ec, double& el) {
   const float Lx = g.Lf[0], Ly = g.Lf[1], Lz = g.Lf[2];
   const float iLx = g.invLf[0], iLy = g.invLf[1], iLz = g.invLf[2];
   const float rc2 = g.rc2, alpha = g.alpha;
   const float c2a = 2.0f * alpha * 0.56418958354775628f;   // 2 alpha / sqrt(pi)
-  const unsigned* __restrict__ ent = g.lent + (size_t)item * g.cap;
-  const int cnt = g.lcount[item];
-  float fx = 0.f, fy = 0.f, fz = 0.f;
-  double ec = 0.0, el = 0.0;
-  for (int it = 0; it < cnt; it += 8) {
-    const unsigned e = ent[it + jj];
+  for (int it = 0; it < cnt; it += 64) {
+    const int idx = it + lane;
+    const unsigned e = idx < cnt ? ent[idx] : 0u;            // slot 0 with an empty mask
     const int s = (int)(e >> 8);
-    const bool m = (e >> ii) & 1u;
     const float4 xj = xq[s];
     const float4 pj = pr[s];
-    float dx = xj.x - xi.x, dy = xj.y - xi.y, dz = xj.z - xi.z;
-    dx = fmaf(-Lx, rintf(dx * iLx), dx);
-    dy = fmaf(-Ly, rintf(dy * iLy), dy);
-    dz = fmaf(-Lz, rintf(dz * iLz), dz);
-    const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-    const bool in = m && (r2 < rc2);
-    const float r2s = in ? r2 : 1.0f;
-    const float rinv = __builtin_amdgcn_rsqf(r2s);
-    const float rinv2 = rinv * rinv;
-    const float r = r2s * rinv;
-    float ex;
-    const float erfcv = erfc_fit(alpha * r, &ex);
-    const float qq = xi.w * xj.w;
-    const float fc = qq * fmaf(erfcv, rinv, c2a * ex) * rinv2;
-    const float sig = pi.x + pj.x;
-    const float eps4 = pi.y * pj.y;
-    const bool ligp = (pi.z + pj.z) > 0.0f;
-    float flj, elj = 0.0f;
-    if (soft_window && __ballot(in && ligp) != 0ull) {
-      const float lam = ligp ? lam_v : 1.0f;
-      const float a = ligp ? a_sc : 0.0f;
-      const float s2 = sig * sig;
-      const float s6 = s2 * s2 * s2;
-      const float r4 = r2s * r2s;
-      const float den = fmaf(a, s6, r4 * r2s);
-      const float inv = __builtin_amdgcn_rcpf(den);
-      const float u = s6 * inv;
-      const float le = lam * eps4;
-      flj = 6.0f * le * fmaf(2.0f, u, -1.0f) * u * inv * r4;
-      if (ENERGY) elj = le * fmaf(u, u, -u);
-    } else {
-      const float s2 = sig * sig * rinv2;
-      const float s6 = s2 * s2 * s2;
-      flj = eps4 * fmaf(12.0f, s6, -6.0f) * s6 * rinv2;
-      if (ENERGY) elj = eps4 * fmaf(s6, s6, -s6);
+    float jx = xj.x, jy = xj.y, jz = xj.z;
+    if (SHIFT) {
+      jx = fmaf(-Lx, rintf((jx - I.x[0]) * iLx), jx);
+      jy = fmaf(-Ly, rintf((jy - I.y[0]) * iLy), jy);
+      jz = fmaf(-Lz, rintf((jz - I.z[0]) * iLz), jz);
     }
-    const float fs = in ? (fc + flj) : 0.0f;
-    fx = fmaf(-fs, dx, fx);
-    fy = fmaf(-fs, dy, fy);
-    fz = fmaf(-fs, dz, fz);
-    if (ENERGY && in) {
-      ec += (double)(qq * erfcv * rinv);
-      el += (double)elj;
+#pragma unroll
+    for (int ii = 0; ii < kClus; ++ii) {
+      float dx = jx - I.x[ii], dy = jy - I.y[ii], dz = jz - I.z[ii];
+      if (!SHIFT) {
+        dx = fmaf(-Lx, rintf(dx * iLx), dx);
+        dy = fmaf(-Ly, rintf(dy * iLy), dy);
+        dz = fmaf(-Lz, rintf(dz * iLz), dz);
+      }
+      const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+      const bool in = ((e >> ii) & 1u) && (r2 < rc2);
+      const float r2s = in ? r2 : 1.0f;
+      const float rinv = __builtin_amdgcn_rsqf(r2s);
+      const float rinv2 = rinv * rinv;
+      const float r = r2s * rinv;
+      float ex;
+      const float erfcv = erfc_fit(alpha * r, &ex);
+      const float qq = I.q[ii] * xj.w;
+      const float fc = qq * fmaf(erfcv, rinv, c2a * ex) * rinv2;
+      const float sig = I.sig[ii] + pj.x;
+      const float eps4 = I.eps[ii] * pj.y;
+      const bool ligp = (I.lig[ii] + pj.z) > 0.0f;
+      float flj, elj = 0.0f;
+      if (soft_window && __ballot(in && ligp) != 0ull) {
+        const float lam = ligp ? lam_v : 1.0f;
+        const float a = ligp ? a_sc : 0.0f;
+        const float s2 = sig * sig;
+        const float s6 = s2 * s2 * s2;
+        const float r4 = r2s * r2s;
+        const float den = fmaf(a, s6, r4 * r2s);
+        const float inv = __builtin_amdgcn_rcpf(den);
+        const float u = s6 * inv;
+        const float le = lam * eps4;
+        flj = 6.0f * le * fmaf(2.0f, u, -1.0f) * u * inv * r4;
+        if (ENERGY) elj = le * fmaf(u, u, -u);
+      } else {
+        const float s2 = sig * sig * rinv2;
+        const float s6 = s2 * s2 * s2;
+        flj = eps4 * fmaf(12.0f, s6, -6.0f) * s6 * rinv2;
+        if (ENERGY) elj = eps4 * fmaf(s6, s6, -s6);
+      }
+      const float fs = in ? (fc + flj) : 0.0f;
+      fx[ii] = fmaf(-fs, dx, fx[ii]);
+      fy[ii] = fmaf(-fs, dy, fy[ii]);
+      fz[ii] = fmaf(-fs, dz, fz[ii]);
+      if (ENERGY && in) {
+        ec += (double)(qq * erfcv * rinv);
+        el += (double)elj;
+      }
     }
   }
-  for (int o = 8; o < 64; o <<= 1) {
-    fx += __shfl_xor(fx, o, 64);
-    fy += __shfl_xor(fy, o, 64);
-    fz += __shfl_xor(fz, o, 64);
+}
+
+template <bool ENERGY>
+__global__ __launch_bounds__(256) void k_pairs(const LegDev* legs, BlockMap map) {
+  const int leg = find_leg(map, blockIdx.x);
+  const LegDev& g = legs[leg];
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const long long item = (long long)(blockIdx.x - map.start[leg]) * 4 + wave;
+  if (item >= (long long)g.W * g.nclus) return;
+  const int w = (int)(item / g.nclus);
+  const int c = (int)(item - (long long)w * g.nclus);
+  const float4* __restrict__ xq = g.xyzq + (size_t)w * g.npad;
+  const float4* __restrict__ pr = g.prm + (size_t)w * g.npad;
+  const float lam_v = g.lam[4 * w + 1];
+  const float a_sc = g.lam[4 * w + 3];
+  const bool soft_window = lam_v < 1.0f;
+
+  // i-atoms: images nearest the cluster's first atom (always a real atom:
+  // padding only follows the last atom), and the cluster's extent
+  ICluster I;
+  float ext[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+  for (int ii = 0; ii < kClus; ++ii) {
+    const float4 a = xq[c * kClus + ii];
+    const float4 p = pr[c * kClus + ii];
+    float v[3] = {uniform(a.x), uniform(a.y), uniform(a.z)};
+    if (ii > 0) {
+      const float r0[3] = {I.x[0], I.y[0], I.z[0]};
+      for (int d = 0; d < 3; ++d) {
+        v[d] = fmaf(-g.Lf[d], rintf((v[d] - r0[d]) * g.invLf[d]), v[d]);
+        if (c * kClus + ii < g.n) ext[d] = fmaxf(ext[d], fabsf(v[d] - r0[d]));
+      }
+    }
+    I.x[ii] = v[0]; I.y[ii] = v[1]; I.z[ii] = v[2];
+    I.q[ii] = uniform(a.w);
+    I.sig[ii] = uniform(p.x);
+    I.eps[ii] = uniform(p.y);
+    I.lig[ii] = uniform(p.z);
   }
-  if (jj == 0) {
-    const int a = g.perm[(size_t)w * g.npad + c * kClus + ii];
+  const float rc = sqrtf(g.rc2) + 0.01f;
+  const bool shift = rc + ext[0] < 0.5f * g.Lf[0] && rc + ext[1] < 0.5f * g.Lf[1] && rc + ext[2] < 0.5f * g.Lf[2];
+  const unsigned* __restrict__ ent = g.lent + (size_t)item * g.cap;
+  const int cnt = g.lcount[item];
+  float fx[kClus], fy[kClus], fz[kClus];
+#pragma unroll
+  for (int ii = 0; ii < kClus; ++ii) fx[ii] = fy[ii] = fz[ii] = 0.f;
+  double ec = 0.0, el = 0.0;
+  if (shift)
+    sweep<ENERGY, true>(g, I, ent, cnt, xq, pr, lane, lam_v, a_sc, soft_window, fx, fy, fz, ec, el);
+  else
+    sweep<ENERGY, false>(g, I, ent, cnt, xq, pr, lane, lam_v, a_sc, soft_window, fx, fy, fz, ec, el);
+
+  float ox = 0.f, oy = 0.f, oz = 0.f;
+#pragma unroll
+  for (int ii = 0; ii < kClus; ++ii) {
+    const float sx = wave_sum(fx[ii]), sy = wave_sum(fy[ii]), sz = wave_sum(fz[ii]);
+    if (lane == ii) { ox = sx; oy = sy; oz = sz; }
+  }
+  if (lane < kClus) {
+    const int a = g.perm[(size_t)w * g.npad + c * kClus + lane];
     if (a >= 0) {
       const size_t o = (size_t)w * g.n + a;
       const int where = (w << 20) | a;
-      g.fx[o] = to_fixed((double)fx, kForceScale, g.err, kSitePairs, where, g.leg_index);
-      g.fy[o] = to_fixed((double)fy, kForceScale, g.err, kSitePairs, where, g.leg_index);
-      g.fz[o] = to_fixed((double)fz, kForceScale, g.err, kSitePairs, where, g.leg_index);
+      g.fx[o] = to_fixed((double)ox, kForceScale, g.err, kSitePairs, where, g.leg_index);
+      g.fy[o] = to_fixed((double)oy, kForceScale, g.err, kSitePairs, where, g.leg_index);
+      g.fz[o] = to_fixed((double)oz, kForceScale, g.err, kSitePairs, where, g.leg_index);
     }
   }
   if (ENERGY) {

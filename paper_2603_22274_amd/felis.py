@@ -73,6 +73,7 @@ def lib():
         'felis_leg_work_size': (C.c_int, [P(FelisLeg), P(C.c_size_t)]),
         'felis_leg_init': (C.c_int, [vp, P(FelisLeg)]),
         'felis_build_nlist': (C.c_int, [vp, P(FelisLeg), C.c_int, C.c_int]),
+        'felis_leg_rebuilds': (C.c_int, [vp, P(FelisLeg), vp]),
         'felis_nlist_export_pairs': (C.c_int, [vp, P(FelisLeg), C.c_int, C.c_double, vp, C.c_int64, P(C.c_int64)]),
         'felis_nonbonded': (C.c_int, [vp, P(FelisLeg), C.c_int, C.c_int]),
         'felis_pme': (C.c_int, [vp, P(FelisLeg), C.c_int, C.c_int]),
@@ -282,6 +283,13 @@ def _sync_back(legs, arr):
 def build_nlist(ctx, legs, force=False):
     arr = _batch(legs)
     ctx.check(lib().felis_build_nlist(ctx.h, arr, len(legs), 1 if force else 0))
+
+
+def leg_rebuilds(ctx, leg):
+    """List builds per window since the leg was initialised (numpy int64)."""
+    out = np.zeros(leg.n_windows, np.int64)
+    ctx.check(lib().felis_leg_rebuilds(ctx.h, C.byref(leg.s), out.ctypes.data_as(C.c_void_p)))
+    return out
 
 
 def nlist_export_pairs(ctx, leg, window, r=None, cap=None):
