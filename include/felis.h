@@ -222,15 +222,20 @@ enum {
 int felis_profile(felis_ctx* ctx, int enable);
 int felis_profile_read(felis_ctx* ctx, int which, double* total_ms, int64_t* launches);
 
-/* Scratch bytes for felis_mbar. */
+/* Scratch bytes for felis_mbar: about (K + 1) n_total + K^2 (n_total/4096 + 1)
+ * doubles. */
 int felis_mbar_work_size(int K, int64_t n_total, size_t* bytes);
 
-/* MBAR (Shirts & Chodera 2008; "Simulation protocol"): self-consistent
- * iteration in log-sum-exp form on u (dev, FP64, [K][n_total] row-major),
- * N_k (host, samples per state in column order), gauge f_0 = 0, until
- * max|f_new - f| <= rel_tol * max(1, max|f|).  f_out (host) [K] dimensionless
- * free energies; *iters the iterations used.  FELIS_E_NOCONV at max_iter.
- * Synchronises. */
+/* MBAR (Shirts & Chodera 2008; "Simulation protocol") on u (dev, FP64,
+ * [K][n_total] row-major, reduced potentials of every sample at every state)
+ * and N_k (host, samples drawn from each state; only the counts matter, not
+ * the column order).  Solves the MBAR equations by Newton's method on their
+ * convex objective (self-consistent steps where the Newton system is
+ * singular) until the last step satisfies max|df| <= rel_tol * max(1, max|f|);
+ * states with N_k = 0 follow from the converged denominators.  f_out (host)
+ * [K] dimensionless free energies, gauge f_0 = 0; *iters the Newton
+ * iterations used.  FELIS_E_NOCONV at max_iter or on a non-finite result.
+ * K in [2, 512].  Synchronises. */
 int felis_mbar(felis_ctx* ctx, const double* u, const int32_t* N_k, int K, int64_t n_total,
                double rel_tol, int max_iter, double* f_out, int* iters, void* work,
                size_t work_bytes);

@@ -1,113 +1,220 @@
 // MBAR (Shirts & Chodera 2008), named in section "Simulation protocol" as the
-// estimator of each segment's free energy.  FP64 self-consistent iteration in
-// log-sum-exp form on u[K][N]:
-//   logden_n = LSE_k (ln N_k + f_k - u_kn)
-//   f_i <- f_i - ln sum_n exp(f_i - u_in - logden_n)     (terms <= 1/N_i)
-// then the gauge f_0 = 0; converged when max|df| <= tol max(1, max|f|).
-// Each iteration: one pass computing logden (thread per sample), one pass of
-// fixed-order partial sums per (state, chunk), one single-block update; the
-// result is independent of launch timing.  After convergence the kernels do
-// nothing, so iterations can be queued in batches between host checks.
+// estimator of each segment's free energy.  The free energies f solve
+//   f_i = -ln sum_n exp(-u_in) / sum_k N_k exp(f_k - u_kn),
+// the stationary point of the convex function
+//   F(f) = sum_n logden_n(f) - sum_i N_i f_i,  logden_n = LSE_k(ln N_k + f_k - u_kn),
+// with gradient g_i = N_i (sum_n W_in - 1) and Hessian
+//   H_ij = delta_ij N_i sum_n W_in - N_i N_j sum_n W_in W_jn,
+// W_in = exp(f_i - u_in - logden_n).  Newton steps on the sampled states
+// (gauge: the first sampled state is held fixed), with a backtracking line
+// search on F while steps are large, and a self-consistent step
+// f_i <- f_i - ln sum_n W_in when the Newton system is singular.  Unsampled
+// states follow from the converged denominators.  Converged when
+// max|step| <= tol * max(1, max|f|); final gauge f_0 = 0.
+//
+// Device work per evaluation (FP64, fixed summation order, so the result is
+// independent of launch timing): logden per sample with per-block objective
+// partials, the weight matrix W [K][N], per-chunk partial sums of W rows and
+// of the 16x16 tiles of W W^T, and a fixed-order reduction over chunks.  The
+// K x K Newton system is solved on the host.
+#include <cmath>
+#include <vector>
+
 #include "felis_internal.h"
 
 namespace felis {
 namespace {
 
-constexpr int kChunk = 4096;
+constexpr int kChunk = 4096;      // samples per partial-sum chunk
+constexpr int kTile = 16;         // Hessian tile edge
+constexpr int kStage = 64;        // samples staged in LDS per tile step
+
+inline size_t al256(size_t b) { return (b + 255) / 256 * 256; }
 
 struct MbarWork {
   double* logden;   // [N]
-  double* part;     // [K][nch]
+  double* fpart;    // [ceil(N/256)] block sums of logden
+  double* W;        // [K][N]
+  double* gpart;    // [nch][K]
+  double* hpart;    // [nch][K][K]
+  double* G;        // [K] sum_n W_in
+  double* H;        // [K][K] sum_n W_in W_jn
   double* f;        // [K]
   double* logN;     // [K] (-inf for N_k = 0)
-  int* state;       // [0] done, [1] iterations
 };
 
-__global__ __launch_bounds__(256) void k_logden(const double* __restrict__ u, MbarWork w, int K, long long N,
-                                                int max_iter) {
-  if (w.state[0] || w.state[1] >= max_iter) return;
+MbarWork carve(void* work, int K, long long N) {
+  const long long nch = (N + kChunk - 1) / kChunk, nb = (N + 255) / 256;
+  char* p = (char*)work;
+  MbarWork w;
+  w.logden = (double*)p; p += al256(N * 8);
+  w.fpart = (double*)p; p += al256(nb * 8);
+  w.W = (double*)p; p += al256((size_t)K * N * 8);
+  w.gpart = (double*)p; p += al256((size_t)nch * K * 8);
+  w.hpart = (double*)p; p += al256((size_t)nch * K * K * 8);
+  w.G = (double*)p; p += al256((size_t)K * 8);
+  w.H = (double*)p; p += al256((size_t)K * K * 8);
+  w.f = (double*)p; p += al256((size_t)K * 8);
+  w.logN = (double*)p; p += al256((size_t)K * 8);
+  return w;
+}
+
+// thread per sample: logden_n; block sums of logden (objective)
+__global__ __launch_bounds__(256) void k_logden(const double* __restrict__ u, MbarWork w, int K, long long N) {
   __shared__ double s_b[512];
+  __shared__ double red[256];
   for (int k = threadIdx.x; k < K; k += blockDim.x) s_b[k] = w.logN[k] + w.f[k];
   __syncthreads();
   const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= N) return;
-  double m = -INFINITY;
-  for (int k = 0; k < K; ++k) m = fmax(m, s_b[k] - u[(long long)k * N + n]);
-  double s = 0.0;
-  for (int k = 0; k < K; ++k) s += exp(s_b[k] - u[(long long)k * N + n] - m);
-  w.logden[n] = m + log(s);
-}
-
-// block (i, chunk): sum_n exp(f_i - u_in - logden_n) over the chunk
-__global__ __launch_bounds__(256) void k_partial(const double* __restrict__ u, MbarWork w, int K, long long N,
-                                                 int nch, int max_iter) {
-  if (w.state[0] || w.state[1] >= max_iter) return;
-  const int i = blockIdx.x / nch, c = blockIdx.x - (blockIdx.x / nch) * nch;
-  const double fi = w.f[i];
-  const long long n0 = (long long)c * kChunk, n1 = min(N, n0 + kChunk);
-  double s = 0.0;
-  for (long long n = n0 + threadIdx.x; n < n1; n += blockDim.x)
-    s += exp(fi - u[(long long)i * N + n] - w.logden[n]);
-  __shared__ double red[256];
-  red[threadIdx.x] = s;
+  double ld = 0.0;
+  if (n < N) {
+    double m = -INFINITY;
+    for (int k = 0; k < K; ++k) m = fmax(m, s_b[k] - u[(long long)k * N + n]);
+    double s = 0.0;
+    for (int k = 0; k < K; ++k) s += exp(s_b[k] - u[(long long)k * N + n] - m);
+    ld = m + log(s);
+    w.logden[n] = ld;
+  }
+  red[threadIdx.x] = ld;
   __syncthreads();
   for (int o = 128; o > 0; o >>= 1) {
     if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
     __syncthreads();
   }
-  if (threadIdx.x == 0) w.part[(long long)i * nch + c] = red[0];
+  if (threadIdx.x == 0) w.fpart[blockIdx.x] = red[0];
 }
 
-__global__ __launch_bounds__(256) void k_update(MbarWork w, int K, int nch, double tol, int max_iter) {
-  if (w.state[0] || w.state[1] >= max_iter) return;
-  __shared__ double fn[512];
-  for (int i = threadIdx.x; i < K; i += blockDim.x) {
-    double s = 0.0;
-    for (int c = 0; c < nch; ++c) s += w.part[(long long)i * nch + c];
-    fn[i] = w.f[i] - log(s);
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const double g0 = fn[0];
-    double delta = 0.0, fmaxv = 0.0;
-    for (int i = 0; i < K; ++i) {
-      const double v = fn[i] - g0;
-      delta = fmax(delta, fabs(v - w.f[i]));
-      fmaxv = fmax(fmaxv, fabs(v));
-      w.f[i] = v;
+// thread per (i, n): W_in
+__global__ __launch_bounds__(256) void k_weights(const double* __restrict__ u, MbarWork w, int K, long long N) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long long)K * N) return;
+  const int i = (int)(t / N);
+  const long long n = t - (long long)i * N;
+  w.W[t] = exp(w.f[i] - u[t] - w.logden[n]);
+}
+
+// block (chunk, tile i, tile j): partial sums over the chunk of W_in W_jn for a
+// 16x16 tile (thread = one (i, j)); tiles on the diagonal also sum W_in
+__global__ __launch_bounds__(256) void k_gram(MbarWork w, int K, long long N, int ntile) {
+  const int per = ntile * ntile;
+  const int c = blockIdx.x / per;
+  const int tt = blockIdx.x - c * per;
+  const int ti = tt / ntile, tj = tt - ti * ntile;
+  const int a = threadIdx.x / kTile, b = threadIdx.x % kTile;
+  const int i = ti * kTile + a, j = tj * kTile + b;
+  const long long n0 = (long long)c * kChunk, n1 = min(N, n0 + kChunk);
+  __shared__ double si[kTile][kStage + 1], sj[kTile][kStage + 1];
+  double acc = 0.0, gs = 0.0;
+  for (long long s0 = n0; s0 < n1; s0 += kStage) {
+    const int len = (int)min((long long)kStage, n1 - s0);
+    for (int e = threadIdx.x; e < kTile * kStage; e += blockDim.x) {
+      const int r = e / kStage, q = e % kStage;
+      const int ri = ti * kTile + r, rj = tj * kTile + r;
+      si[r][q] = (q < len && ri < K) ? w.W[(long long)ri * N + s0 + q] : 0.0;
+      sj[r][q] = (q < len && rj < K) ? w.W[(long long)rj * N + s0 + q] : 0.0;
     }
-    w.state[1] += 1;
-    if (delta <= tol * fmax(1.0, fmaxv)) w.state[0] = 1;
+    __syncthreads();
+    for (int q = 0; q < len; ++q) acc += si[a][q] * sj[b][q];
+    if (ti == tj && b == 0)
+      for (int q = 0; q < len; ++q) gs += si[a][q];
+    __syncthreads();
+  }
+  if (i < K && j < K) w.hpart[((long long)c * K + i) * K + j] = acc;
+  if (ti == tj && b == 0 && i < K) w.gpart[(long long)c * K + i] = gs;
+}
+
+// thread per (i, j): fixed-order sum over chunks
+__global__ __launch_bounds__(256) void k_reduce(MbarWork w, int K, int nch) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= K * K) return;
+  double s = 0.0;
+  for (int c = 0; c < nch; ++c) s += w.hpart[(long long)c * K * K + t];
+  w.H[t] = s;
+  if (t < K) {
+    double g = 0.0;
+    for (int c = 0; c < nch; ++c) g += w.gpart[(long long)c * K + t];
+    w.G[t] = g;
   }
 }
 
-__global__ void k_init(MbarWork w, const double* logN, int K) {
-  const int i = threadIdx.x;
-  if (i < K) { w.f[i] = 0.0; w.logN[i] = logN[i]; }
-  if (i == 0) { w.state[0] = 0; w.state[1] = 0; }
+struct Eval {
+  double F;                      // objective
+  std::vector<double> G, H;      // sum_n W_in, sum_n W_in W_jn
+};
+
+// Upload f, run the device passes, bring back what the host step needs.
+int evaluate(hipStream_t s, const double* u, const MbarWork& w, int K, long long N, const std::vector<double>& f,
+             const std::vector<double>& Nk, bool full, Eval& ev) {
+  const long long nb = (N + 255) / 256;
+  const int nch = (int)((N + kChunk - 1) / kChunk);
+  const int ntile = (K + kTile - 1) / kTile;
+  if (hipMemcpyAsync(w.f, f.data(), sizeof(double) * K, hipMemcpyHostToDevice, s) != hipSuccess) return FELIS_E_DEVICE;
+  hipLaunchKernelGGL(k_logden, dim3((unsigned)nb), dim3(256), 0, s, u, w, K, N);
+  std::vector<double> fp(nb);
+  if (full) {
+    hipLaunchKernelGGL(k_weights, dim3((unsigned)(((long long)K * N + 255) / 256)), dim3(256), 0, s, u, w, K, N);
+    hipLaunchKernelGGL(k_gram, dim3((unsigned)(nch * ntile * ntile)), dim3(256), 0, s, w, K, N, ntile);
+    hipLaunchKernelGGL(k_reduce, dim3((unsigned)((K * K + 255) / 256)), dim3(256), 0, s, w, K, nch);
+    ev.G.resize(K);
+    ev.H.resize((size_t)K * K);
+    if (hipMemcpyAsync(ev.G.data(), w.G, sizeof(double) * K, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipMemcpyAsync(ev.H.data(), w.H, sizeof(double) * K * K, hipMemcpyDeviceToHost, s) != hipSuccess)
+      return FELIS_E_DEVICE;
+  }
+  if (hipMemcpyAsync(fp.data(), w.fpart, sizeof(double) * nb, hipMemcpyDeviceToHost, s) != hipSuccess)
+    return FELIS_E_DEVICE;
+  if (hipStreamSynchronize(s) != hipSuccess) return FELIS_E_DEVICE;
+  double F = 0.0;
+  for (long long b = 0; b < nb; ++b) F += fp[b];
+  for (int i = 0; i < K; ++i)
+    if (Nk[i] > 0) F -= Nk[i] * f[i];
+  ev.F = F;
+  return FELIS_OK;
 }
 
-MbarWork carve(void* work, int K, long long N, int nch) {
-  char* p = (char*)work;
-  MbarWork w;
-  w.logden = (double*)p; p += ((N * 8 + 255) / 256) * 256;
-  w.part = (double*)p; p += (((long long)K * nch * 8 + 255) / 256) * 256;
-  w.f = (double*)p; p += 4096;
-  w.logN = (double*)p; p += 4096;
-  w.state = (int*)p;
-  return w;
+// Solve A x = b (m x m, row-major, overwritten) by Gaussian elimination with
+// partial pivoting; false if a pivot vanishes or the result is not finite.
+bool solve(std::vector<double>& A, std::vector<double>& b, int m) {
+  double scale = 0.0;
+  for (double v : A) scale = std::fmax(scale, std::fabs(v));
+  if (!(scale > 0.0)) return m == 0;
+  for (int k = 0; k < m; ++k) {
+    int p = k;
+    for (int r = k + 1; r < m; ++r)
+      if (std::fabs(A[(size_t)r * m + k]) > std::fabs(A[(size_t)p * m + k])) p = r;
+    if (!(std::fabs(A[(size_t)p * m + k]) > 1e-14 * scale)) return false;
+    if (p != k) {
+      for (int c = 0; c < m; ++c) std::swap(A[(size_t)k * m + c], A[(size_t)p * m + c]);
+      std::swap(b[k], b[p]);
+    }
+    for (int r = k + 1; r < m; ++r) {
+      const double l = A[(size_t)r * m + k] / A[(size_t)k * m + k];
+      if (l == 0.0) continue;
+      for (int c = k; c < m; ++c) A[(size_t)r * m + c] -= l * A[(size_t)k * m + c];
+      b[r] -= l * b[k];
+    }
+  }
+  for (int k = m - 1; k >= 0; --k) {
+    double v = b[k];
+    for (int c = k + 1; c < m; ++c) v -= A[(size_t)k * m + c] * b[c];
+    b[k] = v / A[(size_t)k * m + k];
+    if (!std::isfinite(b[k])) return false;
+  }
+  return true;
 }
 
 }  // namespace
 
 size_t mbar_work_bytes(int K, long long N) {
-  const int nch = (int)((N + kChunk - 1) / kChunk);
-  return ((N * 8 + 255) / 256) * 256 + (((long long)K * nch * 8 + 255) / 256) * 256 + 4096 * 2 + 256;
+  const long long nch = (N + kChunk - 1) / kChunk, nb = (N + 255) / 256;
+  return al256(N * 8) + al256(nb * 8) + al256((size_t)K * N * 8) + al256((size_t)nch * K * 8) +
+         al256((size_t)nch * K * K * 8) + al256((size_t)K * 8) + al256((size_t)K * K * 8) + 2 * al256((size_t)K * 8);
 }
 
 int launch_mbar(hipStream_t s, const double* u, const int* N_k, int K, long long N, double tol, int max_iter,
                 double* f_out, int* iters, void* work, size_t work_bytes) {
-  if (K < 2 || K > 512 || N < 1 || !u || !N_k || !f_out || !work) return FELIS_E_INVAL;
+  if (K < 2 || K > 512 || N < 1 || !u || !N_k || !f_out || !work || !(tol > 0) || max_iter < 1)
+    return FELIS_E_INVAL;
   if (work_bytes < mbar_work_bytes(K, N)) return FELIS_E_INVAL;
   long long tot = 0;
   for (int k = 0; k < K; ++k) {
@@ -115,30 +222,96 @@ int launch_mbar(hipStream_t s, const double* u, const int* N_k, int K, long long
     tot += N_k[k];
   }
   if (tot != N) return FELIS_E_INVAL;
-  const int nch = (int)((N + kChunk - 1) / kChunk);
-  MbarWork w = carve(work, K, N, nch);
-  // ln N_k is staged through the partial-sum buffer before k_init copies it
-  double logN[512];
-  for (int k = 0; k < K; ++k) logN[k] = N_k[k] > 0 ? log((double)N_k[k]) : -INFINITY;
-  if (hipMemcpyAsync(w.part, logN, sizeof(double) * K, hipMemcpyHostToDevice, s) != hipSuccess) return FELIS_E_DEVICE;
-  hipLaunchKernelGGL(k_init, dim3(1), dim3(512), 0, s, w, (const double*)w.part, K);
-  if (hipStreamSynchronize(s) != hipSuccess) return FELIS_E_DEVICE;
-  const int per = 25;
-  int state[2] = {0, 0};
-  while (true) {
-    for (int it = 0; it < per; ++it) {
-      hipLaunchKernelGGL(k_logden, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, u, w, K, N, max_iter);
-      hipLaunchKernelGGL(k_partial, dim3((unsigned)(K * nch)), dim3(256), 0, s, u, w, K, N, nch, max_iter);
-      hipLaunchKernelGGL(k_update, dim3(1), dim3(256), 0, s, w, K, nch, tol, max_iter);
+  MbarWork w = carve(work, K, N);
+  std::vector<double> Nk(K), logN(K);
+  std::vector<int> idx;                 // sampled states other than the gauge state
+  int ref = -1;
+  for (int k = 0; k < K; ++k) {
+    Nk[k] = N_k[k];
+    logN[k] = N_k[k] > 0 ? std::log((double)N_k[k]) : -INFINITY;
+    if (N_k[k] > 0) {
+      if (ref < 0) ref = k;
+      else idx.push_back(k);
     }
-    if (hipMemcpyAsync(state, w.state, sizeof(state), hipMemcpyDeviceToHost, s) != hipSuccess) return FELIS_E_DEVICE;
-    if (hipStreamSynchronize(s) != hipSuccess) return FELIS_E_DEVICE;
-    if (state[0] || state[1] >= max_iter) break;
   }
-  if (hipMemcpyAsync(f_out, w.f, sizeof(double) * K, hipMemcpyDeviceToHost, s) != hipSuccess) return FELIS_E_DEVICE;
-  if (hipStreamSynchronize(s) != hipSuccess) return FELIS_E_DEVICE;
-  if (iters) *iters = state[1];
-  return state[0] ? FELIS_OK : FELIS_E_NOCONV;
+  if (hipMemcpyAsync(w.logN, logN.data(), sizeof(double) * K, hipMemcpyHostToDevice, s) != hipSuccess)
+    return FELIS_E_DEVICE;
+  const int m = (int)idx.size();
+  std::vector<double> f(K, 0.0), step(K), ftry(K);
+  Eval ev, trial;
+  bool done = false;
+  int it = 0;
+  while (it < max_iter) {
+    int rc = evaluate(s, u, w, K, N, f, Nk, true, ev);
+    if (rc) return rc;
+    ++it;
+    // gradient of F on the free states and the Newton system H d = -g
+    std::vector<double> A((size_t)m * m), b(m);
+    for (int r = 0; r < m; ++r) {
+      const int i = idx[r];
+      b[r] = -Nk[i] * (ev.G[i] - 1.0);
+      for (int c = 0; c < m; ++c) {
+        const int j = idx[c];
+        A[(size_t)r * m + c] = (i == j ? Nk[i] * ev.G[i] : 0.0) - Nk[i] * Nk[j] * ev.H[(size_t)i * K + j];
+      }
+    }
+    std::vector<double> g(b);            // -gradient
+    std::fill(step.begin(), step.end(), 0.0);
+    bool newton = solve(A, b, m);
+    double slope = 0.0;                  // g . d (negative for a descent direction)
+    if (newton) {
+      for (int r = 0; r < m; ++r) { step[idx[r]] = b[r]; slope -= g[r] * b[r]; }
+      newton = slope < 0.0 || m == 0;
+    }
+    if (!newton) {                       // self-consistent step
+      std::fill(step.begin(), step.end(), 0.0);
+      if (ev.G[ref] > 0.0)
+        for (int r = 0; r < m; ++r) step[idx[r]] = -std::log(ev.G[idx[r]]) + std::log(ev.G[ref]);
+    }
+    double smax = 0.0;
+    for (int k = 0; k < K; ++k) {
+      if (!std::isfinite(step[k])) return FELIS_E_NOCONV;
+      smax = std::fmax(smax, std::fabs(step[k]));
+    }
+    double t = 1.0;
+    if (newton && smax > 1e-3) {         // backtracking on F while the step is large
+      bool ok = false;
+      for (int ls = 0; ls < 30 && !ok; ++ls) {
+        for (int k = 0; k < K; ++k) ftry[k] = f[k] + t * step[k];
+        rc = evaluate(s, u, w, K, N, ftry, Nk, false, trial);
+        if (rc) return rc;
+        ok = trial.F <= ev.F + 1e-4 * t * slope;
+        if (!ok) t *= 0.5;
+      }
+      if (!ok) {                         // no decrease found: self-consistent step instead
+        t = 1.0;
+        smax = 0.0;
+        std::fill(step.begin(), step.end(), 0.0);
+        if (ev.G[ref] > 0.0)
+          for (int r = 0; r < m; ++r) {
+            step[idx[r]] = -std::log(ev.G[idx[r]]) + std::log(ev.G[ref]);
+            smax = std::fmax(smax, std::fabs(step[idx[r]]));
+          }
+      }
+    }
+    double fmaxv = 0.0;
+    for (int k = 0; k < K; ++k) {
+      f[k] += t * step[k];
+      fmaxv = std::fmax(fmaxv, std::fabs(f[k]));
+    }
+    if (t * smax <= tol * std::fmax(1.0, fmaxv)) { done = true; break; }
+  }
+  // unsampled states from the final denominators, then the gauge f_0 = 0
+  int rc = evaluate(s, u, w, K, N, f, Nk, true, ev);
+  if (rc) return rc;
+  for (int k = 0; k < K; ++k)
+    if (Nk[k] == 0) f[k] -= std::log(ev.G[k]);
+  const double f0 = f[0];
+  for (int k = 0; k < K; ++k) f_out[k] = f[k] - f0;
+  if (iters) *iters = it;
+  for (int k = 0; k < K; ++k)
+    if (!std::isfinite(f_out[k])) return FELIS_E_NOCONV;
+  return done ? FELIS_OK : FELIS_E_NOCONV;
 }
 
 }  // namespace felis

@@ -283,6 +283,7 @@ class _Builder:
     def __init__(self):
         self.pos, self.q, self.sig, self.eps, self.m, self.lig = [], [], [], [], [], []
         self.bonds, self.excl, self.waters = [], [], []
+        self.extra = []            # (i, j, r0): bonds with their own rest length
         self.n = 0
 
     def add(self, xyz, q, sig, eps, m, lig):
@@ -300,6 +301,9 @@ class _Builder:
         self.bonds.append(b); self.excl.append(e)
         return first
 
+    def add_bond(self, i, j, r0):
+        self.extra.append((int(i), int(j), float(r0)))
+
     def add_waters(self, wxyz):
         for w in wxyz:
             o = self.add(w, [Q_OW, Q_HW, Q_HW], [SIG_OW, 1.0, 1.0], [EPS_OW, 0.0, 0.0],
@@ -315,6 +319,10 @@ class _Builder:
         m = np.concatenate(self.m).astype(np.float32)
         lig = np.concatenate(self.lig).astype(np.uint8)
         bonds = (np.concatenate(self.bonds) if self.bonds else np.zeros((0, 2))).astype(np.int32)
+        r0 = np.full(len(bonds), BOND_R0, np.float32)
+        if self.extra:
+            bonds = np.concatenate([bonds, np.array([[i, j] for i, j, _ in self.extra], np.int32)])
+            r0 = np.concatenate([r0, np.array([v for _, _, v in self.extra], np.float32)])
         excl = np.concatenate(self.excl).astype(np.int32)
         excl = np.sort(excl, axis=1)
         excl = np.unique(excl, axis=0)
@@ -322,7 +330,7 @@ class _Builder:
         nb = len(bonds)
         sysd = System(name=name, box=np.asarray(box, np.float64), pos=pos.astype(np.float32),
                       charge=q, sigma=sig, epsilon=eps, mass=m, is_ligand=lig, bonds=bonds,
-                      bond_k=np.full(nb, BOND_K, np.float32), bond_r0=np.full(nb, BOND_R0, np.float32),
+                      bond_k=np.full(nb, BOND_K, np.float32), bond_r0=r0,
                       waters=waters, excl=excl, lambdas=lambdas, r_cut=r_cut, skin=skin,
                       ewald_alpha=ewald_alpha(r_cut, tol), grid=tuple(int(g) for g in grid))
         if restraint is not None:
@@ -567,6 +575,12 @@ def complex_leg(config=2, seed=BASE_SEED, n_prot=5000, n_lig=50, box_edge=88.0, 
         b.add(sites[s][None], ion['q'], ion['sigma'], ion['eps'], ion['mass'], 0)
     b.add_waters(wxyz)
     anchors = [pf + p1, pf + p2, pf + p3, lf + l1, lf + l2, lf + l3]
+    # The chains carry no angle terms, so the anchor triples' own angles
+    # (which enter the Boresch dihedrals and make them singular at 180 deg)
+    # are held near their initial values by a 1-3 bond each, as a force
+    # field's angle terms would.  Both pairs are already 1-3 exclusions.
+    b.add_bond(pf + p1, pf + p3, np.linalg.norm(P[p1] - P[p3]))
+    b.add_bond(lf + l1, lf + l3, np.linalg.norm(L[l1] - L[l3]))
     ks = [k_r, k_theta, k_theta, k_phi, k_phi, k_phi]
     sysd = b.finish(f'complex{config}', box, schedule(sched), r_cut, skin, 5e-4, grid,
                     restraint=(anchors, g0, ks))

@@ -265,6 +265,21 @@ class FelisEngine:
         h.u = None
 
 
+def relax_start(ctx, sysd, steps=400, seed=7, dt=0.002, temperature=300.0):
+    """Replace ``sysd.pos`` with coordinates relaxed by high-friction Langevin
+    dynamics of the fully coupled state (first window): a synthetic lattice
+    start releases enough potential energy to heat a leg far above the target
+    temperature under the production friction.  Input preparation, done before
+    a leg is submitted."""
+    from . import felis
+    leg = felis.Leg(ctx, sysd, windows=[0], seed=seed)
+    felis.step(ctx, [leg], steps // 2, dt, temperature, 20.0)
+    felis.step(ctx, [leg], steps - steps // 2, dt, temperature, 5.0)
+    ctx.device_check()
+    sysd.pos = leg.positions()[0].cpu().numpy().astype(np.float32)
+    return sysd
+
+
 def poisson_requests(n, rate, seed, make_system, n_steps, sample_every):
     """n requests with exponential inter-arrival times (mean 1/rate s)."""
     rng = np.random.default_rng(seed)

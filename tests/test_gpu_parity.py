@@ -212,6 +212,27 @@ def test_mbar_matches_oracle(F):
     assert np.max(np.abs(f - f_ref)) < 1e-9, (f, f_ref)
 
 
+def test_mbar_unsampled_states_and_column_order(F):
+    """States with no samples get their f from the converged denominators;
+    the result does not depend on the order of the sample columns; widely
+    spaced states (slow for plain fixed-point iteration) converge in a few
+    Newton steps."""
+    felis, ctx = F
+    rng = np.random.default_rng(5)
+    ks = np.array([1.0, 1.6, 2.6, 4.2, 6.8, 11.0])
+    n = 800
+    N = np.array([n, 0, n, 0, n, n])
+    x2 = np.concatenate([(rng.normal(0, 1 / np.sqrt(k), (c, 3)) ** 2).sum(1) for k, c in zip(ks, N) if c])
+    u = 0.5 * ks[:, None] * x2[None, :]
+    f_ref, it_ref = ombar.mbar(u, N, tol=1e-14)
+    f, it = felis.mbar(ctx, torch.as_tensor(u).cuda(), N, tol=1e-12)
+    assert np.max(np.abs(f - f_ref)) < 1e-9, (f, f_ref)
+    assert it <= 30 < it_ref
+    perm = rng.permutation(u.shape[1])
+    f2, _ = felis.mbar(ctx, torch.as_tensor(np.ascontiguousarray(u[:, perm])).cuda(), N, tol=1e-12)
+    assert np.max(np.abs(f2 - f)) < 1e-9
+
+
 def test_ddg_from_gpu_frames(F):
     """Short sampled leg: GPU dynamics -> frames; Delta G from GPU u_kn + GPU
     MBAR equals the oracle's u_kn + MBAR on the same frames."""
