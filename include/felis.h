@@ -177,7 +177,10 @@ int felis_nlist_export_pairs(felis_ctx* ctx, const felis_leg* leg, int window, d
 int felis_nonbonded(felis_ctx* ctx, felis_leg* legs, int n_legs, int flags);
 
 /* PME reciprocal space (order-4 B-spline spreading, 3D FFT, influence function,
- * gather); forces are ADDED; with FELIS_ENERGY writes RECIP and TOTAL. */
+ * gather); forces are ADDED; with FELIS_ENERGY writes RECIP and TOTAL.
+ * Spreading locates atoms through the neighbour-list cell sort, so this call
+ * first rebuilds the lists of windows that moved more than skin/2 (as
+ * felis_build_nlist with force = 0 does). */
 int felis_pme(felis_ctx* ctx, felis_leg* legs, int n_legs, int flags);
 
 /* Harmonic bonds and lambda_restraint-scaled Boresch restraint (section

@@ -509,6 +509,10 @@ int felis_pme(felis_ctx* c, felis_leg* legs, int n_legs, int flags) {
   if (rc) return rc;
   const bool en = flags & FELIS_ENERGY;
   if (en) launch_zero_energy(c->stream, c->d_legs, hs.data(), n_legs, FELIS_E_RECIP, FELIS_E_RECIP + 1);
+  // spreading finds atoms through the cell sort of the last list build: bring
+  // it up to date (rebuilds only windows that moved more than skin/2)
+  launch_check(c->stream, c->d_legs, hs.data(), n_legs, 0);
+  launch_build(c->stream, c->d_legs, hs.data(), n_legs);
   launch_pme(c->stream, c->d_legs, hs.data(), n_legs, en);
   if (en) launch_finish_energy(c->stream, c->d_legs, hs.data(), n_legs, FELIS_E_RECIP, FELIS_E_RECIP + 1);
   return launched(c);

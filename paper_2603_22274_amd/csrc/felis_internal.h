@@ -140,6 +140,38 @@ __device__ __forceinline__ T wave_sum(T v) {
   return v;
 }
 
+// Index of cell (x, y, z) along a 3D Hilbert curve of 2^bits cells per axis
+// (Skilling's transpose construction: undo excess work, Gray-code, then
+// interleave).  Consecutive indices are face-adjacent cells, and the 8
+// children of every aligned 2x2x2 block hold 8 consecutive indices, so a
+// coarse block's atoms form one contiguous range of the sorted order.
+__device__ __forceinline__ unsigned hilbert3(unsigned x, unsigned y, unsigned z, int bits) {
+  unsigned X[3] = {x, y, z};
+  for (unsigned Q = 1u << (bits - 1); Q > 1u; Q >>= 1) {
+    const unsigned P = Q - 1u;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      if (X[i] & Q) {
+        X[0] ^= P;
+      } else {
+        const unsigned t = (X[0] ^ X[i]) & P;
+        X[0] ^= t;
+        X[i] ^= t;
+      }
+    }
+  }
+  X[1] ^= X[0];
+  X[2] ^= X[1];
+  unsigned t = 0;
+  for (unsigned Q = 1u << (bits - 1); Q > 1u; Q >>= 1)
+    if (X[2] & Q) t ^= Q - 1u;
+  X[0] ^= t; X[1] ^= t; X[2] ^= t;
+  unsigned h = 0;
+  for (int b = bits - 1; b >= 0; --b)
+    h = (h << 3) | (((X[0] >> b) & 1u) << 2) | (((X[1] >> b) & 1u) << 1) | ((X[2] >> b) & 1u);
+  return h;
+}
+
 __device__ __forceinline__ float wrapf(float x, float L, float invL) {
   const float r = x - L * floorf(x * invL);
   return (r >= 0.f && r < L) ? r : 0.f;          // non-finite input -> 0 (keeps indices in range)
@@ -178,7 +210,7 @@ void launch_integrate(hipStream_t s, const LegDev* d, const LegHost* h, int nl,
 void launch_zero_energy(hipStream_t s, const LegDev* d, const LegHost* h, int nl, int c0, int c1);
 void launch_finish_energy(hipStream_t s, const LegDev* d, const LegHost* h, int nl, int c0, int c1);
 void launch_fill_i64(hipStream_t s, long long* p, size_t n);
-void launch_pme_fft(hipStream_t s, const LegDev* d, const LegHost* h, int nl);
+void launch_pme_fft(hipStream_t s, const LegDev* d, const LegHost* h, int nl, bool from_int64);
 int launch_ukn(hipStream_t s, const LegDev* d, const LegHost& h, double sc_alpha, const double* lambdas,
                int K, const float* fx, const float* fy, const float* fz, long long frame_stride,
                long long n_frames, double beta, double* u, long long u_stride, long long* uacc,

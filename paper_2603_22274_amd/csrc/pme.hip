@@ -2,8 +2,8 @@
 // with a 1 nm real-space cutoff in appendix B and prints no PME formulas).
 //
 // Per window: charges q~ (ligand x lambda_elec) spread with order-4 cardinal
-// B-splines into an int64 fixed-point grid (order-independent atomics, so the
-// grid is bitwise reproducible).  Two windows of one leg share a complex grid
+// B-splines, summed in int64 fixed point (order-independent, so the grid is
+// bitwise reproducible) by the workgroup that owns each brick of the grid.  Two windows of one leg share a complex grid
 // Z = Q_a + i Q_b: with a real, even influence function G the convolution
 // IDFT(G DFT(Z)) = phi_a + i phi_b, so one complex FFT pair serves two
 // windows.  phi = IDFT_unnormalised(G DFT(Q)), G(m) = KE/(pi V)
@@ -216,35 +216,161 @@ __device__ __forceinline__ int grid_base(float x, double invL, int K, float* f) 
   return (int)k;
 }
 
-// items: window x atom, 16 lanes per atom (lane = ix + 4 iy, loop over iz):
-// the four x points of a grid row are adjacent lanes, so each atomic
-// instruction touches 16 row segments of 32 contiguous bytes
+constexpr int kBrick = 8;                      // brick edge in grid points
+
+// Grid points of axis d that an atom with base index b touches, as a 4-bit
+// mask over the stencil offsets (point b - k, k = 0..3, periodic) that fall in
+// [P0, P1).
+__device__ __forceinline__ unsigned brick_mask(int b, int K, int P0, int P1) {
+  unsigned m = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    int p = b - k;
+    if (p < 0) p += K;
+    if (p >= P0 && p < P1) m |= 1u << k;
+  }
+  return m;
+}
+
+// One block per (window pair, 8x8x8 brick of grid points): the block owns
+// its brick.  Candidate atoms come from the coarse cells of each window's
+// last list build that can hold an atom whose stencil reaches the brick (the
+// brick's extent plus 3 grid spacings on the upper side, widened by skin/2
+// for the drift since that build); each contributing atom adds its stencil
+// points inside the brick to an int64 fixed-point tile in LDS (integer sums:
+// the tile does not depend on the order of the adds), and the block writes
+// its brick of the complex grid Z = Q_a + i Q_b once, with plain stores.
 __global__ __launch_bounds__(256) void k_spread(const LegDev* legs, BlockMap map) {
   const int leg = find_leg(map, blockIdx.x);
   const LegDev& g = legs[leg];
-  const long long local = (long long)(blockIdx.x - map.start[leg]) * 16 + (threadIdx.x >> 4);
-  if (local >= (long long)g.W * g.n) return;
-  const int w = (int)(local / g.n);
-  const int a = (int)(local - (long long)w * g.n);
-  const int sub = threadIdx.x & 15, ix = sub & 3, iy = sub >> 2;
-  const size_t o = (size_t)w * g.n + a;
-  const float q = g.q[a] * (g.lig[a] ? g.lam[4 * w] : 1.0f);
-  float fxr, fyr, fzr, wx[4], wy[4], wz[4];
-  const int bx = grid_base(g.x[o], g.invL[0], g.K[0], &fxr);
-  const int by = grid_base(g.y[o], g.invL[1], g.K[1], &fyr);
-  const int bz = grid_base(g.z[o], g.invL[2], g.K[2], &fzr);
-  bspline4(fxr, wx, nullptr);
-  bspline4(fyr, wy, nullptr);
-  bspline4(fzr, wz, nullptr);
-  int gx = bx - ix; if (gx < 0) gx += g.K[0];
-  int gy = by - iy; if (gy < 0) gy += g.K[1];
-  long long* grid = g.grid64 + (size_t)w * g.Ktot + (size_t)gy * g.K[0] + gx;
-  const double qxy = (double)(q * wx[ix] * wy[iy]);
+  const int tid = threadIdx.x;
+  const int nbx = (g.K[0] + kBrick - 1) / kBrick, nby = (g.K[1] + kBrick - 1) / kBrick;
+  const int nbz = (g.K[2] + kBrick - 1) / kBrick;
+  const int bl = blockIdx.x - map.start[leg];
+  const int per = nbx * nby * nbz;
+  const int p = bl / per;
+  int r = bl - p * per;
+  const int bz = r / (nbx * nby);
+  r -= bz * nbx * nby;
+  const int by = r / nbx, bx = r - by * nbx;
+  const int P0[3] = {bx * kBrick, by * kBrick, bz * kBrick};
+  const int P1[3] = {min(P0[0] + kBrick, g.K[0]), min(P0[1] + kBrick, g.K[1]), min(P0[2] + kBrick, g.K[2])};
+
+  __shared__ long long tile[2][kBrick * kBrick * kBrick];
+  __shared__ int s_start[256], s_pre[256], s_wsum[4];
+  __shared__ int s_n;
+  __shared__ float s_q[256], s_w[256][12];
+  __shared__ int s_b[256][3];
+  __shared__ unsigned s_m[256];
+  for (int e = tid; e < 2 * kBrick * kBrick * kBrick; e += 256) (&tile[0][0])[e] = 0;
+  if (tid == 0) s_n = 0;
+
+  // candidate coarse cells per axis
+  const int nc = g.ncoarse;
+  const float margin = sqrtf(g.skin_half2) + 0.05f;
+  int c0[3], nspan[3];
+  for (int d = 0; d < 3; ++d) {
+    const float Lc = g.Lf[d] / (float)nc, hgrid = g.Lf[d] / (float)g.K[d];
+    const int a0 = (int)floorf(((float)P0[d] * hgrid - margin) / Lc);
+    const int a1 = (int)floorf(((float)(P1[d] + 3) * hgrid + margin) / Lc);
+    const bool full = a1 - a0 + 1 >= nc;
+    c0[d] = full ? 0 : a0;
+    nspan[d] = full ? nc : a1 - a0 + 1;
+  }
+  const int ncells = nspan[0] * nspan[1] * nspan[2];
+  const int wave = tid >> 6, lane = tid & 63;
+  __syncthreads();
+  for (int half = 0; half < 2; ++half) {
+    const int w = 2 * p + half;
+    if (w >= g.W) break;                         // uniform: odd window count, imaginary part stays 0
+    const int* cst = g.cellstart + (size_t)w * (g.ncell + 1);
+    const int* perm = g.perm + (size_t)w * g.npad;
+    const float4* __restrict__ xq = g.xyzq + (size_t)w * g.npad;
+    const float le = g.lam[4 * w];
+    long long* T = tile[half];
+    for (int cb = 0; cb < ncells; cb += 256) {
+      const int ci = cb + tid;
+      int s0 = 0, cnt = 0;
+      if (ci < ncells) {
+        const int C[3] = {c0[0] + ci / (nspan[1] * nspan[2]), c0[1] + (ci / nspan[2]) % nspan[1],
+                          c0[2] + ci % nspan[2]};
+        const unsigned cc = hilbert3(2u * (unsigned)((C[0] % nc + nc) % nc), 2u * (unsigned)((C[1] % nc + nc) % nc),
+                                     2u * (unsigned)((C[2] % nc + nc) % nc), g.nbits) >> 3;
+        s0 = cst[8 * cc];
+        cnt = cst[8 * cc + 8] - s0;
+      }
+      int inc = cnt;
+      for (int k = 1; k < 64; k <<= 1) {
+        const int v = __shfl_up(inc, k, 64);
+        if (lane >= k) inc += v;
+      }
+      if (lane == 63) s_wsum[wave] = inc;
+      s_start[tid] = s0;
+      __syncthreads();
+      int woff = 0;
+      for (int k = 0; k < wave; ++k) woff += s_wsum[k];
+      const int total = s_wsum[0] + s_wsum[1] + s_wsum[2] + s_wsum[3];
+      s_pre[tid] = woff + inc - cnt;
+      __syncthreads();
+      for (int t0 = 0; t0 < total; t0 += 256) {
+        const int t = t0 + tid;
+        if (t < total) {
+          int l = 0, hh = 255;                    // last cell with prefix <= t
+          while (l < hh) {
+            const int mid = (l + hh + 1) >> 1;
+            if (s_pre[mid] <= t) l = mid; else hh = mid - 1;
+          }
+          const int s = s_start[l] + (t - s_pre[l]);
+          const float4 rj = xq[s];
+          float fr[3];
+          const int b0 = grid_base(rj.x, g.invL[0], g.K[0], &fr[0]);
+          const int b1 = grid_base(rj.y, g.invL[1], g.K[1], &fr[1]);
+          const int b2 = grid_base(rj.z, g.invL[2], g.K[2], &fr[2]);
+          const unsigned mx = brick_mask(b0, g.K[0], P0[0], P1[0]);
+          const unsigned my = brick_mask(b1, g.K[1], P0[1], P1[1]);
+          const unsigned mz = brick_mask(b2, g.K[2], P0[2], P1[2]);
+          if (mx && my && mz) {
+            const int a = perm[s];
+            const int k = atomicAdd(&s_n, 1);
+            s_q[k] = g.q[a] * (g.lig[a] ? le : 1.0f);
+            bspline4(fr[0], &s_w[k][0], nullptr);
+            bspline4(fr[1], &s_w[k][4], nullptr);
+            bspline4(fr[2], &s_w[k][8], nullptr);
+            s_b[k][0] = b0; s_b[k][1] = b1; s_b[k][2] = b2;
+            s_m[k] = mx | (my << 4) | (mz << 8);
+          }
+        }
+        __syncthreads();
+        const int na = s_n;
+        for (int task = tid; task < 16 * na; task += 256) {   // (atom, ix, iy), loop over iz
+          const int k = task >> 4, ix = task & 3, iy = (task >> 2) & 3;
+          const unsigned m = s_m[k];
+          if (!((m >> ix) & 1u) || !((m >> (4 + iy)) & 1u)) continue;
+          int px = s_b[k][0] - ix; if (px < 0) px += g.K[0];
+          int py = s_b[k][1] - iy; if (py < 0) py += g.K[1];
+          const double qxy = (double)(s_q[k] * s_w[k][ix] * s_w[k][4 + iy]);
+          const int row = ((py - P0[1]) * kBrick + (px - P0[0]));
 #pragma unroll
-  for (int iz = 0; iz < 4; ++iz) {
-    int gz = bz - iz; if (gz < 0) gz += g.K[2];
-    const long long v = __double2ll_rn(qxy * (double)wz[iz] * kGridScale);
-    if (v) atomicAdd((unsigned long long*)&grid[(size_t)gz * g.K[0] * g.K[1]], (unsigned long long)v);
+          for (int iz = 0; iz < 4; ++iz) {
+            if (!((m >> (8 + iz)) & 1u)) continue;
+            int pz = s_b[k][2] - iz; if (pz < 0) pz += g.K[2];
+            const long long v = __double2ll_rn(qxy * (double)s_w[k][8 + iz] * kGridScale);
+            atomicAdd((unsigned long long*)&T[(pz - P0[2]) * kBrick * kBrick + row], (unsigned long long)v);
+          }
+        }
+        __syncthreads();
+        if (tid == 0) s_n = 0;
+        __syncthreads();
+      }
+    }
+  }
+  float2* cg = g.cgrid + (size_t)p * g.Ktot;
+  for (int e = tid; e < kBrick * kBrick * kBrick; e += 256) {
+    const int lx = e % kBrick, ly = (e / kBrick) % kBrick, lz = e / (kBrick * kBrick);
+    const int x = P0[0] + lx, y = P0[1] + ly, z = P0[2] + lz;
+    if (x >= P1[0] || y >= P1[1] || z >= P1[2]) continue;
+    cg[((size_t)z * g.K[1] + y) * g.K[0] + x] =
+        make_float2((float)((double)tile[0][e] * (1.0 / kGridScale)), (float)((double)tile[1][e] * (1.0 / kGridScale)));
   }
 }
 
@@ -334,8 +460,9 @@ void fft_pass(hipStream_t s, const LegDev* d, const LegHost* h, int nl) {
 
 }  // namespace
 
-void launch_pme_fft(hipStream_t s, const LegDev* d, const LegHost* h, int nl) {
-  fft_pass<0, 2>(s, d, h, nl);
+void launch_pme_fft(hipStream_t s, const LegDev* d, const LegHost* h, int nl, bool from_int64) {
+  if (from_int64) fft_pass<0, 2>(s, d, h, nl);
+  else fft_pass<0, 0>(s, d, h, nl);
   fft_pass<1, 0>(s, d, h, nl);
   fft_pass<2, 3>(s, d, h, nl);
   fft_pass<1, 1>(s, d, h, nl);
@@ -344,10 +471,15 @@ void launch_pme_fft(hipStream_t s, const LegDev* d, const LegHost* h, int nl) {
 
 void launch_pme(hipStream_t s, const LegDev* d, const LegHost* h, int nl, bool energy) {
   BlockMap m;
-  int nb = make_map(m, nl, [&](int i) { return blocks_for((long long)h[i].W * h[i].n, 16); });
+  int nb = make_map(m, nl, [&](int i) {
+    const int nbr = ((h[i].K[0] + kBrick - 1) / kBrick) * ((h[i].K[1] + kBrick - 1) / kBrick) *
+                    ((h[i].K[2] + kBrick - 1) / kBrick);
+    return h[i].npair * nbr;
+  });
   if (!nb) return;
   hipLaunchKernelGGL(k_spread, dim3(nb), dim3(256), 0, s, d, m);
-  launch_pme_fft(s, d, h, nl);
+  launch_pme_fft(s, d, h, nl, false);
+  nb = make_map(m, nl, [&](int i) { return blocks_for((long long)h[i].W * h[i].n, 16); });
   if (energy) hipLaunchKernelGGL(k_gather<true>, dim3(nb), dim3(256), 0, s, d, m);
   else hipLaunchKernelGGL(k_gather<false>, dim3(nb), dim3(256), 0, s, d, m);
 }

@@ -359,7 +359,7 @@ int launch_ukn(hipStream_t s, const LegDev* d, const LegHost& h, double sc_alpha
     A.nf = nf;
     launch_fill_i64(s, uacc, (size_t)nf * kNU);
     hipLaunchKernelGGL(k_ukn_spread, dim3((unsigned)(((long long)nf * h.n + 15) / 16)), dim3(256), 0, s, d, A);
-    launch_pme_fft(s, d, &h, 1);
+    launch_pme_fft(s, d, &h, 1, true);
     if (h.nlig) {
       hipLaunchKernelGGL(k_ukn_gather, dim3((unsigned)(((long long)nf * h.nlig + 15) / 16)), dim3(256), 0, s, d, A);
       hipLaunchKernelGGL(k_ukn_pairs, dim3((unsigned)(nf * ((h.n + 255) / 256))), dim3(256), 0, s, d, A);

@@ -68,7 +68,7 @@ def _sum_abs_pairs(s, pos, lam):
 
 
 @pytest.mark.parametrize('name,windows', [('config0', list(range(12))), ('small_complex', [0, 12, 16, 25, 35, 41]),
-                                          ('config1', [0, 9, 19])])
+                                          ('config1', [0, 9, 19]), ('small_complex', [20])])
 def test_nonbonded_and_pme(F, name, windows):
     felis, ctx = F
     s = getattr(gen, name)()
