@@ -49,6 +49,13 @@ __global__ __launch_bounds__(256) void k_pack(const LegDev* legs, BlockMap map) 
   g.xyzq[i] = v;
 }
 
+__device__ __forceinline__ float3 min_img(const LegDev& g, float dx, float dy, float dz) {
+  dx = fmaf(-g.Lf[0], rintf(dx * g.invLf[0]), dx);
+  dy = fmaf(-g.Lf[1], rintf(dy * g.invLf[1]), dy);
+  dz = fmaf(-g.Lf[2], rintf(dz * g.invLf[2]), dz);
+  return make_float3(dx, dy, dz);
+}
+
 // The 8 i-atoms of a cluster, wave-uniform (held in scalar registers).
 struct ICluster {
   float x[kClus], y[kClus], z[kClus], q[kClus], sig[kClus], eps[kClus], lig[kClus];
@@ -185,14 +192,51 @@ __global__ __launch_bounds__(256) void k_pairs(const LegDev* legs, BlockMap map)
   else
     sweep<ENERGY, false>(g, I, ent, cnt, xq, pr, lane, lam_v, a_sc, soft_window, fx, fy, fz, ec, el);
 
-  float ox = 0.f, oy = 0.f, oz = 0.f;
+  // Excluded pairs: remove their reciprocal-space (erf) interaction, each
+  // pair from both of its sides; lane = ii + 8 k takes the k-th exclusion of
+  // i-atom ii (at most kMaxExcl = 8 per atom).
+  const int ai = g.perm[(size_t)w * g.npad + c * kClus + (lane & 7)];
+  float cx = 0.f, cy = 0.f, cz = 0.f;
+  double ex = 0.0;
+  if (ai >= 0) {
+    const int e0 = g.excl_ptr[ai], ne = min(g.excl_ptr[ai + 1] - e0, kMaxExcl);
+    const int k = lane >> 3;
+    if (k < ne) {
+      const int b = g.excl_idx[e0 + k];
+      const float le = g.lam[4 * w];
+      const float qa = g.q[ai] * (g.lig[ai] ? le : 1.f), qb = g.q[b] * (g.lig[b] ? le : 1.f);
+      const size_t oa = (size_t)w * g.n + ai, ob = (size_t)w * g.n + b;
+      const float3 d = min_img(g, g.x[ob] - g.x[oa], g.y[ob] - g.y[oa], g.z[ob] - g.z[oa]);
+      const float r2 = d.x * d.x + d.y * d.y + d.z * d.z;
+      const float qq = (float)kKE * qa * qb;
+      const float c2a = 2.0f * g.alpha * 0.56418958354775628f;
+      float fs, en;
+      if (r2 > 1e-8f) {
+        const float r = sqrtf(r2), rinv = 1.0f / r;
+        const float erfv = erff(g.alpha * r);
+        en = -qq * erfv * rinv;
+        fs = qq * (c2a * __expf(-g.alpha * g.alpha * r2) - erfv * rinv) * rinv * rinv;
+      } else {
+        en = -qq * c2a;
+        fs = 0.f;
+      }
+      cx = -fs * d.x; cy = -fs * d.y; cz = -fs * d.z;      // F_i = fs (r_i - r_j)
+      ex = 0.5 * (double)en;
+    }
+  }
+  for (int o = 8; o < 64; o <<= 1) {
+    cx += __shfl_xor(cx, o, 64);
+    cy += __shfl_xor(cy, o, 64);
+    cz += __shfl_xor(cz, o, 64);
+  }
+  float ox = cx, oy = cy, oz = cz;
 #pragma unroll
   for (int ii = 0; ii < kClus; ++ii) {
     const float sx = wave_sum(fx[ii]), sy = wave_sum(fy[ii]), sz = wave_sum(fz[ii]);
-    if (lane == ii) { ox = sx; oy = sy; oz = sz; }
+    if (lane == ii) { ox += sx; oy += sy; oz += sz; }
   }
   if (lane < kClus) {
-    const int a = g.perm[(size_t)w * g.npad + c * kClus + lane];
+    const int a = ai;
     if (a >= 0) {
       const size_t o = (size_t)w * g.n + a;
       const int where = (w << 20) | a;
@@ -204,12 +248,15 @@ __global__ __launch_bounds__(256) void k_pairs(const LegDev* legs, BlockMap map)
   if (ENERGY) {
     ec = wave_sum(ec);
     el = wave_sum(el);
+    ex = wave_sum(ex);
     if (lane == 0) {
       long long* acc = g.eacc + (size_t)w * FELIS_NE;
       atomicAdd((unsigned long long*)&acc[FELIS_E_COUL_REAL],
                 (unsigned long long)to_fixed(0.5 * ec, kEnergyScale, g.err, kSitePairsE, w));
       atomicAdd((unsigned long long*)&acc[FELIS_E_LJ],
                 (unsigned long long)to_fixed(0.5 * el, kEnergyScale, g.err, kSitePairsE, w));
+      atomicAdd((unsigned long long*)&acc[FELIS_E_EXCL],
+                (unsigned long long)to_fixed(ex, kEnergyScale, g.err, kSitePairsE, w));
     }
   }
 }
@@ -228,58 +275,6 @@ __device__ __forceinline__ void add_energy(const LegDev& g, int w, int comp, dou
               (unsigned long long)to_fixed(e, kEnergyScale, g.err, kSiteEnergy, comp));
 }
 
-__device__ __forceinline__ float3 min_img(const LegDev& g, float dx, float dy, float dz) {
-  dx = fmaf(-g.Lf[0], rintf(dx * g.invLf[0]), dx);
-  dy = fmaf(-g.Lf[1], rintf(dy * g.invLf[1]), dy);
-  dz = fmaf(-g.Lf[2], rintf(dz * g.invLf[2]), dz);
-  return make_float3(dx, dy, dz);
-}
-
-// items: window x excluded pair -- remove the reciprocal interaction of
-// excluded pairs: E = -KE q_i q_j erf(alpha r)/r.
-template <bool ENERGY>
-__global__ __launch_bounds__(256) void k_excl(const LegDev* legs, BlockMap map) {
-  const int leg = find_leg(map, blockIdx.x);
-  const LegDev& g = legs[leg];
-  const long long i = (long long)(blockIdx.x - map.start[leg]) * blockDim.x + threadIdx.x;
-  const long long tot = (long long)g.W * g.nexcl;
-  const int lane = threadIdx.x & 63;
-  double e = 0.0;
-  int w = (int)(min(i, tot - 1) / max(g.nexcl, 1));
-  if (i < tot) {
-    const int p = (int)(i - (long long)w * g.nexcl);
-    const int a = g.excl_ij[2 * p], b = g.excl_ij[2 * p + 1];
-    const float le = g.lam[4 * w];
-    const float qa = g.q[a] * (g.lig[a] ? le : 1.f), qb = g.q[b] * (g.lig[b] ? le : 1.f);
-    const size_t oa = (size_t)w * g.n + a, ob = (size_t)w * g.n + b;
-    const float3 d = min_img(g, g.x[ob] - g.x[oa], g.y[ob] - g.y[oa], g.z[ob] - g.z[oa]);
-    const float r2 = d.x * d.x + d.y * d.y + d.z * d.z;
-    const float qq = (float)kKE * qa * qb;
-    const float c2a = 2.0f * g.alpha * 0.56418958354775628f;
-    float fs, en;
-    if (r2 > 1e-8f) {
-      const float r = sqrtf(r2), rinv = 1.0f / r;
-      const float erfv = erff(g.alpha * r);
-      en = -qq * erfv * rinv;
-      fs = qq * (c2a * __expf(-g.alpha * g.alpha * r2) - erfv * rinv) * rinv * rinv;
-    } else {
-      en = -qq * c2a;
-      fs = 0.f;
-    }
-    // F_a = fs (r_a - r_b) = -fs d
-    add_force(g, oa, -fs * d.x, -fs * d.y, -fs * d.z, kSiteExcl);
-    add_force(g, ob, fs * d.x, fs * d.y, fs * d.z, kSiteExcl);
-    e = en;
-  }
-  if (ENERGY) {
-    // waves may straddle windows: reduce per window present in the wave
-    const int w0 = __shfl(w, 0, 64);
-    const bool same = __ballot(i < tot && w != w0) == 0ull;
-    if (same) add_energy(g, w0, FELIS_E_EXCL, e, lane);
-    else if (i < tot) atomicAdd((unsigned long long*)&g.eacc[(size_t)w * FELIS_NE + FELIS_E_EXCL],
-                                (unsigned long long)to_fixed(e, kEnergyScale, g.err));
-  }
-}
 
 // one block per window: Ewald self term and neutralising background
 __global__ __launch_bounds__(256) void k_self(const LegDev* legs, BlockMap map) {
@@ -409,13 +404,8 @@ void launch_pairs(hipStream_t s, const LegDev* d, const LegHost* h, int nl, bool
 
 void launch_corrections(hipStream_t s, const LegDev* d, const LegHost* h, int nl, bool energy) {
   BlockMap m;
-  int nb = make_map(m, nl, [&](int i) { return blocks_for((long long)h[i].W * h[i].nexcl, 256); });
-  if (nb) {
-    if (energy) hipLaunchKernelGGL(k_excl<true>, dim3(nb), dim3(256), 0, s, d, m);
-    else hipLaunchKernelGGL(k_excl<false>, dim3(nb), dim3(256), 0, s, d, m);
-  }
-  if (energy) {
-    nb = make_map(m, nl, [&](int i) { return h[i].W; });
+  if (energy) {             // excluded-pair corrections are part of the pair kernel
+    const int nb = make_map(m, nl, [&](int i) { return h[i].W; });
     if (nb) hipLaunchKernelGGL(k_self, dim3(nb), dim3(256), 0, s, d, m);
   }
 }

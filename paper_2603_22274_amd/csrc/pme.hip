@@ -14,6 +14,8 @@
 // holds 16 lines in LDS ([element][line] layout, coalesced loads for every
 // axis).  The inverse transform is conj(DFT(conj(.))).  The z pass fuses
 // forward transform, multiplication by G and inverse transform.
+#include <algorithm>
+
 #include "felis_internal.h"
 
 namespace felis {
@@ -122,8 +124,9 @@ __global__ __launch_bounds__(256) void k_fft(const LegDev* legs, BlockMap map) {
   const int rem = bl - p * outer * nch;
   const int o = rem / nch, ch = rem - (rem / nch) * nch;
   if (p >= g.npair) return;
-  __shared__ float2 bufA[kMaxFFT * kLines];
-  __shared__ float2 bufB[kMaxFFT * kLines];
+  extern __shared__ float2 smem[];               // two buffers of n * kLines (sized at launch)
+  float2* bufA = smem;
+  float2* bufB = smem + (size_t)n * kLines;
   float2* cg = g.cgrid + (size_t)p * g.Ktot;
   const int KxKy = Kx * Ky;
   auto offs = [&](int e, int b) -> long long {
@@ -450,12 +453,15 @@ inline int blocks_for(long long items, int per) { return (int)((items + per - 1)
 template <int AXIS, int MODE>
 void fft_pass(hipStream_t s, const LegDev* d, const LegHost* h, int nl) {
   BlockMap m;
+  int nmax = 0;
   const int nb = make_map(m, nl, [&](int i) {
     const int inner = (AXIS == 0) ? h[i].K[1] : h[i].K[0];
     const int outer = (AXIS == 2) ? h[i].K[1] : h[i].K[2];
+    nmax = std::max(nmax, h[i].K[AXIS]);
     return h[i].npair * outer * ((inner + kLines - 1) / kLines);
   });
-  if (nb) hipLaunchKernelGGL((k_fft<AXIS, MODE>), dim3(nb), dim3(256), 0, s, d, m);
+  const size_t lds = 2 * (size_t)nmax * kLines * sizeof(float2);
+  if (nb) hipLaunchKernelGGL((k_fft<AXIS, MODE>), dim3(nb), dim3(256), lds, s, d, m);
 }
 
 }  // namespace
