@@ -236,7 +236,7 @@ __device__ __forceinline__ unsigned brick_mask(int b, int K, int P0, int P1) {
 }
 
 // One block per (window pair, 8x8x8 brick of grid points): the block owns
-// its brick.  Candidate atoms come from the coarse cells of each window's
+// its brick.  Candidate atoms come from the fine cells of each window's
 // last list build that can hold an atom whose stencil reaches the brick (the
 // brick's extent plus 3 grid spacings on the upper side, widened by skin/2
 // for the drift since that build); each contributing atom adds its stencil
@@ -268,8 +268,8 @@ __global__ __launch_bounds__(256) void k_spread(const LegDev* legs, BlockMap map
   for (int e = tid; e < 2 * kBrick * kBrick * kBrick; e += 256) (&tile[0][0])[e] = 0;
   if (tid == 0) s_n = 0;
 
-  // candidate coarse cells per axis
-  const int nc = g.ncoarse;
+  // candidate fine cells per axis
+  const int nc = 1 << g.nbits;
   const float margin = sqrtf(g.skin_half2) + 0.05f;
   int c0[3], nspan[3];
   for (int d = 0; d < 3; ++d) {
@@ -297,10 +297,10 @@ __global__ __launch_bounds__(256) void k_spread(const LegDev* legs, BlockMap map
       if (ci < ncells) {
         const int C[3] = {c0[0] + ci / (nspan[1] * nspan[2]), c0[1] + (ci / nspan[2]) % nspan[1],
                           c0[2] + ci % nspan[2]};
-        const unsigned cc = hilbert3(2u * (unsigned)((C[0] % nc + nc) % nc), 2u * (unsigned)((C[1] % nc + nc) % nc),
-                                     2u * (unsigned)((C[2] % nc + nc) % nc), g.nbits) >> 3;
-        s0 = cst[8 * cc];
-        cnt = cst[8 * cc + 8] - s0;
+        const unsigned cc = hilbert3((unsigned)((C[0] % nc + nc) % nc), (unsigned)((C[1] % nc + nc) % nc),
+                                     (unsigned)((C[2] % nc + nc) % nc), g.nbits);
+        s0 = cst[cc];
+        cnt = cst[cc + 1] - s0;
       }
       int inc = cnt;
       for (int k = 1; k < 64; k <<= 1) {
