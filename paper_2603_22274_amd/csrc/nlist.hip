@@ -14,6 +14,8 @@
 namespace felis {
 namespace {
 
+constexpr int kCellOf = 4096;                 // candidates per table window in k_build
+
 __device__ __forceinline__ int cell_of(float v, float L, float invL, int n) {
   float u = wrapf(v, L, invL) * invL;
   int c = (int)(u * (float)n);
@@ -204,6 +206,7 @@ __global__ __launch_bounds__(256) void k_build(const LegDev* legs, BlockMap map)
   __shared__ int s_pre[256];                    // exclusive prefix of candidate counts
   __shared__ int s_wsum[4];
   __shared__ int s_wc[2][4];
+  __shared__ unsigned char s_cellof[kCellOf];   // candidate -> block of the round, one window at a time
   const size_t o = (size_t)w * g.n;
   const int* perm = g.perm + (size_t)w * g.npad;
   if (tid < 64) s_bloom[tid] = 0u;
@@ -251,13 +254,24 @@ __global__ __launch_bounds__(256) void k_build(const LegDev* legs, BlockMap map)
   const float4* __restrict__ xq = g.xyzq + (size_t)w * g.npad;
   const float incl = (float)g.rlist + 0.01f;
   const float inc2 = incl * incl;
-  float xi[kClus][3];
+  float xi[kClus][3], ri[kClus][3];
   int ai[kClus];
+  float ext[3] = {0.f, 0.f, 0.f};
 #pragma unroll
   for (int ii = 0; ii < kClus; ++ii) {
     ai[ii] = __builtin_amdgcn_readfirstlane(s_ai[ii]);           // uniform: scalar registers
-    for (int d = 0; d < 3; ++d) xi[ii][d] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(s_xi[ii][d])));
+    for (int d = 0; d < 3; ++d) {
+      xi[ii][d] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(s_xi[ii][d])));
+      // position relative to the cluster's first atom (always a real atom), nearest image
+      const float v = xi[ii][d] - xi[0][d];
+      ri[ii][d] = __fmaf_rn(-g.Lf[d], rintf(v * g.invLf[d]), v);
+      if (ai[ii] >= 0) ext[d] = fmaxf(ext[d], fabsf(ri[ii][d]));
+    }
   }
+  // one periodic image per candidate (taken against the first atom) is the
+  // nearest image for every i whenever extent + r_list + margin < L/2
+  const bool shift = ext[0] + incl + 0.02f < 0.5f * g.Lf[0] && ext[1] + incl + 0.02f < 0.5f * g.Lf[1] &&
+                     ext[2] + incl + 0.02f < 0.5f * g.Lf[2];
   const int* cst = g.cellstart + (size_t)w * (g.ncell + 1);
   unsigned* out = g.lent + (size_t)item * g.cap;
   const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
@@ -293,40 +307,50 @@ __global__ __launch_bounds__(256) void k_build(const LegDev* legs, BlockMap map)
     int woff = 0;
     for (int k = 0; k < wave; ++k) woff += s_wsum[k];
     const int total = s_wsum[0] + s_wsum[1] + s_wsum[2] + s_wsum[3];
-    s_pre[tid] = woff + inc - cnt;
+    const int pre_t = woff + inc - cnt;
+    s_pre[tid] = pre_t;
+    // candidates are taken kCellOf at a time: each block writes its index over
+    // its share of the window, then a candidate finds its block in one read
+    for (int T0 = 0; T0 < total; T0 += kCellOf) {
+    {
+      const int b0 = max(pre_t, T0), b1 = min(pre_t + cnt, T0 + kCellOf);
+      for (int q = b0; q < b1; ++q) s_cellof[q - T0] = (unsigned char)tid;
+    }
     __syncthreads();
-    for (int t0 = 0; t0 < total; t0 += 256) {
+    const int T1 = min(total, T0 + kCellOf);
+    for (int t0 = T0; t0 < T1; t0 += 256) {
       const int t = t0 + tid;
       unsigned mask = 0;
       int s = 0;
-      if (t < total) {
-        int l = 0, h = 255;                      // last block with prefix <= t
-        while (l < h) {
-          const int mid = (l + h + 1) >> 1;
-          if (s_pre[mid] <= t) l = mid; else h = mid - 1;
-        }
+      if (t < T1) {
+        const int l = s_cellof[t - T0];
         s = s_start[l] + (t - s_pre[l]);
         const int a = perm[s];
         const float4 rj = xq[s];
         const float xj[3] = {rj.x, rj.y, rj.z};
-        float dd = 0.f;
-        for (int d = 0; d < 3; ++d) {
-          float v = wrapf(xj[d], g.Lf[d], g.invLf[d]) - cen[d];
-          v -= g.Lf[d] * rintf(v * g.invLf[d]);
-          float e = fabsf(v) - half[d];
-          if (half[d] > 0.25f * g.Lf[d]) e = 0.f;
-          e = fmaxf(e, 0.f);
-          dd += e * e;
-        }
-        if (dd < pre2) {
+        {
+          if (shift) {
+            float rj3[3];
+            for (int d = 0; d < 3; ++d) {
+              const float v = xj[d] - xi[0][d];
+              rj3[d] = __fmaf_rn(-g.Lf[d], rintf(v * g.invLf[d]), v);
+            }
 #pragma unroll
-          for (int ii = 0; ii < kClus; ++ii) {
-            float dx = xj[0] - xi[ii][0], dy = xj[1] - xi[ii][1], dz = xj[2] - xi[ii][2];
-            dx -= g.Lf[0] * rintf(dx * g.invLf[0]);
-            dy -= g.Lf[1] * rintf(dy * g.invLf[1]);
-            dz -= g.Lf[2] * rintf(dz * g.invLf[2]);
-            const float d2 = (dx * dx + dy * dy) + dz * dz;
-            if (d2 < inc2 && ai[ii] >= 0 && ai[ii] != a) mask |= 1u << ii;
+            for (int ii = 0; ii < kClus; ++ii) {
+              const float dx = rj3[0] - ri[ii][0], dy = rj3[1] - ri[ii][1], dz = rj3[2] - ri[ii][2];
+              const float d2 = __fmaf_rn(dx, dx, __fmaf_rn(dy, dy, dz * dz));
+              if (d2 < inc2 && ai[ii] >= 0 && ai[ii] != a) mask |= 1u << ii;
+            }
+          } else {
+#pragma unroll
+            for (int ii = 0; ii < kClus; ++ii) {
+              float dx = xj[0] - xi[ii][0], dy = xj[1] - xi[ii][1], dz = xj[2] - xi[ii][2];
+              dx -= g.Lf[0] * rintf(dx * g.invLf[0]);
+              dy -= g.Lf[1] * rintf(dy * g.invLf[1]);
+              dz -= g.Lf[2] * rintf(dz * g.invLf[2]);
+              const float d2 = (dx * dx + dy * dy) + dz * dz;
+              if (d2 < inc2 && ai[ii] >= 0 && ai[ii] != a) mask |= 1u << ii;
+            }
           }
           if (mask && ((s_bloom[(a >> 5) & 63] >> (a & 31)) & 1u)) {   // possibly excluded
             for (int ii = 0; ii < kClus; ++ii) {
@@ -349,6 +373,8 @@ __global__ __launch_bounds__(256) void k_build(const LegDev* legs, BlockMap map)
         if (pos < g.cap) out[pos] = ((unsigned)s << 8) | mask;
       }
       par ^= 1;
+    }
+    __syncthreads();                            // the window's table is rewritten next
     }
     __syncthreads();                            // the round's tables are rewritten next
   }

@@ -2,6 +2,7 @@
 
     python -m paper_2603_22274_amd.profiling stats <trace_dir> [n]
     python -m paper_2603_22274_amd.profiling traffic <fetch_dir> <write_dir> <kernel-substring>
+    python -m paper_2603_22274_amd.profiling counters <pmc_dir> <kernel-substring> ...
 
 ``stats`` prints per-kernel call counts, average and total durations.
 ``traffic`` scales the FETCH_SIZE / WRITE_SIZE counters (KiB per dispatch)
@@ -68,8 +69,23 @@ def traffic(fetch_dir, write_dir, kernel_sub, copy_bytes=256 << 20):
             "bytes_per_launch": fetch + write}
 
 
+def counters(pmc_dir, kernels):
+    """Per-dispatch averages of every counter collected in ``pmc_dir`` for the
+    kernels whose names contain one of ``kernels``."""
+    con = _db(pmc_dir)
+    rows = con.execute("select kernel_name, counter_name, value from counters_collection").fetchall()
+    out = {}
+    for name, cname, v in rows:
+        for k in kernels:
+            if k in name:
+                out.setdefault(k, {}).setdefault(cname, []).append(v)
+    return {k: {c: sum(v) / len(v) for c, v in d.items()} for k, d in out.items()}
+
+
 if __name__ == '__main__':
     if sys.argv[1] == 'stats':
         print(kernel_stats(sys.argv[2], int(sys.argv[3]) if len(sys.argv) > 3 else 25))
+    elif sys.argv[1] == 'counters':
+        print(json.dumps(counters(sys.argv[2], sys.argv[3:]), indent=1))
     elif sys.argv[1] == 'traffic':
         print(json.dumps(traffic(sys.argv[2], sys.argv[3], sys.argv[4]), indent=1))
