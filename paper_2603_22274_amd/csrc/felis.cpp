@@ -88,6 +88,9 @@ int make_plan(felis_ctx* c, const felis_leg* L, Plan& P) {
   if (L->sc_p != 1) return fail(c, FELIS_E_UNSUPPORTED, "softcore p must be 1");
   if (L->spline_order != 4) return fail(c, FELIS_E_UNSUPPORTED, "PME spline order must be 4");
   if (!(L->sc_alpha >= 0)) return fail(c, FELIS_E_INVAL, "sc_alpha");
+  // the real-space erfc is a fit on [0, 3.5] (Ewald tolerances down to ~4e-7)
+  if (!(L->ewald_alpha * L->r_cut <= 3.5))
+    return fail(c, FELIS_E_UNSUPPORTED, "ewald_alpha * r_cut must not exceed 3.5");
   if (!L->charge || !L->sigma || !L->epsilon || !L->mass || !L->is_ligand)
     return fail(c, FELIS_E_INVAL, "null parameter array");
   if (!L->x || !L->y || !L->z || !L->vx || !L->vy || !L->vz || !L->fx || !L->fy || !L->fz || !L->energy)

@@ -108,11 +108,13 @@ __device__ __forceinline__ void sweep(const LegDev& g, const ICluster& I, const 
       const float erfcv = erfc_fit(alpha * r, &ex);
       const float qq = I.q[ii] * xj.w;
       const float fc = qq * fmaf(erfcv, rinv, c2a * ex) * rinv2;
-      const float sig = I.sig[ii] + pj.x;
-      const float eps4 = I.eps[ii] * pj.y;
-      const bool ligp = (I.lig[ii] + pj.z) > 0.0f;
-      float flj, elj = 0.0f;
-      if (soft_window && __ballot(in && ligp) != 0ull) {
+      float flj = 0.0f, elj = 0.0f;
+      if (I.eps[ii] == 0.0f) {
+        // wave-uniform: an i-atom without LJ (a water hydrogen) contributes
+        // exactly zero LJ force and energy with every partner
+      } else if (const float sig = I.sig[ii] + pj.x, eps4 = I.eps[ii] * pj.y;
+                 soft_window && __ballot(in && (I.lig[ii] + pj.z) > 0.0f) != 0ull) {
+        const bool ligp = (I.lig[ii] + pj.z) > 0.0f;
         const float lam = ligp ? lam_v : 1.0f;
         const float a = ligp ? a_sc : 0.0f;
         const float s2 = sig * sig;
