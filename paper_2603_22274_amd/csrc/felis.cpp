@@ -18,7 +18,7 @@ using namespace felis;
 namespace {
 
 struct Layout {
-  size_t lam, free_atoms, lig_idx, xr, yr, zr, flag, nbuild, perm, cellcode, cellstart, cursor, xyzq, prm, bblo,
+  size_t lam, free_atoms, lig_idx, xr, yr, zr, flag, nbuild, maxdisp, wmax, perm, cellcode, cellstart, cursor, xyzq, prm, bblo,
       bbhi, lcount, lent, grid64, cgrid, tw[3], bmod[3], eacc, uacc, upart, lpart, ucst, total;
 };
 
@@ -152,6 +152,8 @@ int make_plan(felis_ctx* c, const felis_leg* L, Plan& P) {
   y.xr = put(W * n * 4); y.yr = put(W * n * 4); y.zr = put(W * n * 4);
   y.flag = put(W * 4);
   y.nbuild = put(W * 8);
+  y.maxdisp = put(W * 4);
+  y.wmax = put(((W * (size_t)(h.nwat + h.nfree) + 63) / 64) * 8);
   y.perm = put(W * npad * 4);
   y.cellcode = put(W * n * 4);
   y.cellstart = put(W * (h.ncell + 1) * 4);
@@ -226,6 +228,9 @@ LegDev make_dev(const felis_ctx* c, const felis_leg* L, const Plan& p, const Met
   g.xr = (float*)(w + y.xr); g.yr = (float*)(w + y.yr); g.zr = (float*)(w + y.zr);
   g.flag = (int*)(w + y.flag);
   g.nbuild = (long long*)(w + y.nbuild);
+  g.maxdisp = (unsigned*)(w + y.maxdisp);
+  g.wmax = (unsigned*)(w + y.wmax);
+  g.units = p.h.nwat + p.h.nfree;
   g.perm = (int*)(w + y.perm);
   g.cellcode = (int*)(w + y.cellcode);
   g.cellstart = (int*)(w + y.cellstart);
@@ -452,6 +457,8 @@ int felis_leg_init(felis_ctx* c, felis_leg* L) {
   ok &= hipMemsetD32Async((hipDeviceptr_t)(w + y.xr), farbits, 3 * ((y.yr - y.xr) / 4), c->stream) == hipSuccess;
   ok &= hipMemsetD32Async((hipDeviceptr_t)(w + y.flag), 1, h.W, c->stream) == hipSuccess;
   ok &= hipMemsetAsync(w + y.nbuild, 0, h.W * 8, c->stream) == hipSuccess;
+  ok &= hipMemsetAsync(w + y.maxdisp, 0, h.W * 4, c->stream) == hipSuccess;
+  ok &= hipMemsetAsync(w + y.wmax, 0, y.perm - y.wmax, c->stream) == hipSuccess;
   ok &= hipMemsetAsync(w + y.lcount, 0, (size_t)h.W * h.nclus * 4, c->stream) == hipSuccess;
   ok &= hipMemsetAsync(w + y.grid64, 0, y.cgrid - y.grid64, c->stream) == hipSuccess;
   ok &= hipMemsetAsync(w + y.eacc, 0, y.ucst - y.eacc, c->stream) == hipSuccess;
@@ -470,7 +477,7 @@ int felis_build_nlist(felis_ctx* c, felis_leg* legs, int n_legs, int force) {
   std::vector<LegHost> hs;
   int rc = prepare(c, legs, n_legs, hs);
   if (rc) return rc;
-  launch_check(c->stream, c->d_legs, hs.data(), n_legs, force ? 1 : 0);
+  launch_check(c->stream, c->d_legs, hs.data(), n_legs, force ? 1 : 0, false);
   launch_build(c->stream, c->d_legs, hs.data(), n_legs);
   return launched(c);
 }
@@ -499,7 +506,7 @@ int felis_nonbonded(felis_ctx* c, felis_leg* legs, int n_legs, int flags) {
   if (rc) return rc;
   const bool en = flags & FELIS_ENERGY;
   if (en) launch_zero_energy(c->stream, c->d_legs, hs.data(), n_legs, FELIS_E_COUL_REAL, FELIS_E_SELF + 1);
-  launch_pack(c->stream, c->d_legs, hs.data(), n_legs);
+  launch_pack(c->stream, c->d_legs, hs.data(), n_legs, false);
   launch_pairs(c->stream, c->d_legs, hs.data(), n_legs, en);
   launch_corrections(c->stream, c->d_legs, hs.data(), n_legs, en);
   if (en) launch_finish_energy(c->stream, c->d_legs, hs.data(), n_legs, FELIS_E_COUL_REAL, FELIS_E_SELF + 1);
@@ -514,7 +521,7 @@ int felis_pme(felis_ctx* c, felis_leg* legs, int n_legs, int flags) {
   if (en) launch_zero_energy(c->stream, c->d_legs, hs.data(), n_legs, FELIS_E_RECIP, FELIS_E_RECIP + 1);
   // spreading finds atoms through the cell sort of the last list build: bring
   // it up to date (rebuilds only windows that moved more than skin/2)
-  launch_check(c->stream, c->d_legs, hs.data(), n_legs, 0);
+  launch_check(c->stream, c->d_legs, hs.data(), n_legs, 0, false);
   launch_build(c->stream, c->d_legs, hs.data(), n_legs);
   launch_pme(c->stream, c->d_legs, hs.data(), n_legs, en);
   if (en) launch_finish_energy(c->stream, c->d_legs, hs.data(), n_legs, FELIS_E_RECIP, FELIS_E_RECIP + 1);
@@ -544,7 +551,9 @@ int felis_step(felis_ctx* c, felis_leg* legs, int n_legs, int n_steps, double dt
   for (int s = 0; s < n_steps; ++s) {
     for (int i = 0; i < n_legs; ++i) { step[i] = legs[i].step + s; seed[i] = legs[i].seed; }
     mark(c, FELIS_PROF_NLIST, false);
-    launch_check(c->stream, c->d_legs, hs.data(), n_legs, 0);
+    // the first step scans positions; later steps read the largest
+    // displacement the previous step's integrator recorded
+    launch_check(c->stream, c->d_legs, hs.data(), n_legs, 0, s > 0);
     launch_build(c->stream, c->d_legs, hs.data(), n_legs);
     mark(c, FELIS_PROF_NLIST, true);       // the build stage also packs the sorted coordinates
     mark(c, FELIS_PROF_PAIRS, false);

@@ -70,6 +70,11 @@ struct LegDev {
   float *xr, *yr, *zr;                  // [W][n] positions at the last list build
   int* flag;                            // [W] rebuild flags
   long long* nbuild;                    // [W] list builds since init
+  unsigned* maxdisp;                    // [W] largest squared displacement since the last check (float bits),
+                                        // used when a window has fewer than 64 integration units
+  unsigned* wmax;                       // [waves][2] per integrator wave: largest squared displacement in
+                                        // its first and in its second window (float bits)
+  int units;                            // integration units per window (rigid waters + other atoms)
   int* perm;                            // [W][npad] sorted slot -> atom (-1 = padding)
   int* cellcode;                        // [W][n]
   int* cellstart;                       // [W][ncell + 1]
@@ -195,11 +200,11 @@ struct LegHost {
 };
 
 // ---- launchers (one per translation unit) ----
-void launch_check(hipStream_t s, const LegDev* d, const LegHost* h, int nl, int force);
+void launch_check(hipStream_t s, const LegDev* d, const LegHost* h, int nl, int force, bool from_word);
 void launch_build(hipStream_t s, const LegDev* d, const LegHost* h, int nl);
 void launch_export(hipStream_t s, const LegDev* d, const LegHost& h, int window, double r,
                    int* pairs, long long cap, unsigned long long* count);
-void launch_pack(hipStream_t s, const LegDev* d, const LegHost* h, int nl);
+void launch_pack(hipStream_t s, const LegDev* d, const LegHost* h, int nl, bool rebuild);
 void launch_pairs(hipStream_t s, const LegDev* d, const LegHost* h, int nl, bool energy);
 void launch_corrections(hipStream_t s, const LegDev* d, const LegHost* h, int nl, bool energy);
 void launch_bonded(hipStream_t s, const LegDev* d, const LegHost* h, int nl, bool energy);

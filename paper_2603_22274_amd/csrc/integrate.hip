@@ -69,27 +69,26 @@ __device__ __forceinline__ void advance(const LegDev& g, const StepArgs& S, int 
   vel = v;
 }
 
-__device__ __forceinline__ void store(const LegDev& g, int w, int a, v3 dx, v3 v) {
+// writes the new position and velocity; returns the squared displacement
+// from the position of the window's last list build, in the list check's own
+// arithmetic (separately rounded products and sums)
+__device__ __forceinline__ float store(const LegDev& g, int w, int a, v3 dx, v3 v) {
   const size_t o = (size_t)w * g.n + a;
-  g.x[o] += dx.x; g.y[o] += dx.y; g.z[o] += dx.z;
+  const float x = g.x[o] + dx.x, y = g.y[o] + dx.y, z = g.z[o] + dx.z;
+  g.x[o] = x; g.y[o] = y; g.z[o] = z;
   g.vx[o] = v.x; g.vy[o] = v.y; g.vz[o] = v.z;
+  const float ex = __fsub_rn(x, g.xr[o]), ey = __fsub_rn(y, g.yr[o]), ez = __fsub_rn(z, g.zr[o]);
+  return __fadd_rn(__fadd_rn(__fmul_rn(ex, ex), __fmul_rn(ey, ey)), __fmul_rn(ez, ez));
 }
 
-// items: window x unit (rigid waters first, then every other atom)
-__global__ __launch_bounds__(256) void k_integrate(const LegDev* legs, BlockMap map, StepArgs S) {
-  const int leg = find_leg(map, blockIdx.x);
-  const LegDev& g = legs[leg];
-  const long long i = (long long)(blockIdx.x - map.start[leg]) * blockDim.x + threadIdx.x;
-  const int units = g.nwat + g.nfree;
-  if (i >= (long long)g.W * units) return;
-  const int w = (int)(i / units);
-  const int u = (int)(i - (long long)w * units);
+// one unit (a rigid water, or any other atom): Langevin-middle update, SETTLE
+// for waters; returns the largest squared displacement since the list build
+__device__ __forceinline__ float unit_step(const LegDev& g, const StepArgs& S, int leg, int w, int u) {
   if (u >= g.nwat) {
     const int a = g.free_atoms[u - g.nwat];
     v3 dx, v;
     advance(g, S, leg, w, a, dx, v);
-    store(g, w, a, dx, v);
-    return;
+    return store(g, w, a, dx, v);
   }
   const int ao = g.water[3 * u], ah1 = g.water[3 * u + 1], ah2 = g.water[3 * u + 2];
   v3 dO, dH1, dH2, vO, vH1, vH2;
@@ -107,9 +106,41 @@ __global__ __launch_bounds__(256) void k_integrate(const LegDev* legs, BlockMap 
   vO = vadd(vO, vmul(vsub(a1, a1u), idt));
   vH1 = vadd(vH1, vmul(vsub(b1, b1u), idt));
   vH2 = vadd(vH2, vmul(vsub(c1, c1u), idt));
-  store(g, w, ao, a1, vO);
-  store(g, w, ah1, vsub(b1, b0), vH1);
-  store(g, w, ah2, vsub(c1, c0), vH2);
+  const float m0 = store(g, w, ao, a1, vO);
+  const float m1 = store(g, w, ah1, vsub(b1, b0), vH1);
+  const float m2 = store(g, w, ah2, vsub(c1, c0), vH2);
+  return fmaxf(m0, fmaxf(m1, m2));
+}
+
+// items: window x unit (rigid waters first, then every other atom).  Each
+// wave also records, for the next step's list check, the largest squared
+// displacement in its first window and in its second (a wave of 64 units
+// spans at most two windows when a window has at least 64 units; smaller
+// windows use one atomic per lane instead).
+__global__ __launch_bounds__(256) void k_integrate(const LegDev* legs, BlockMap map, StepArgs S) {
+  const int leg = find_leg(map, blockIdx.x);
+  const LegDev& g = legs[leg];
+  const long long i = (long long)(blockIdx.x - map.start[leg]) * blockDim.x + threadIdx.x;
+  const int units = g.units;
+  const bool valid = i < (long long)g.W * units;
+  const int w = valid ? (int)(i / units) : g.W - 1;
+  float d2 = 0.f;
+  if (valid) d2 = unit_step(g, S, leg, w, (int)(i - (long long)w * units));
+  if (units < 64) {
+    if (valid) atomicMax(&g.maxdisp[w], __float_as_uint(d2));
+    return;
+  }
+  const int w0 = __shfl(w, 0, 64);
+  float a = (w == w0) ? d2 : 0.f, b = (w == w0) ? 0.f : d2;
+  for (int k = 32; k > 0; k >>= 1) {
+    a = fmaxf(a, __shfl_xor(a, k, 64));
+    b = fmaxf(b, __shfl_xor(b, k, 64));
+  }
+  const long long wave = i >> 6;
+  if ((threadIdx.x & 63) == 0 && wave * 64 < (long long)g.W * units) {
+    g.wmax[2 * wave] = __float_as_uint(a);
+    g.wmax[2 * wave + 1] = __float_as_uint(b);
+  }
 }
 
 }  // namespace

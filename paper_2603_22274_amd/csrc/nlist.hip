@@ -22,17 +22,34 @@ __device__ __forceinline__ int cell_of(float v, float L, float invL, int n) {
   return c < 0 ? 0 : (c >= n ? n - 1 : c);
 }
 
-// One block per window: rebuild flag = force || max displacement > skin/2.
+// One block per window: rebuild flag = force || max displacement > skin/2;
+// a window being rebuilt gets its per-cell counters zeroed.  FROM_WORD: the
+// largest squared displacement was recorded by the previous step's
+// integrator (same arithmetic as the scan below); either way the word is
+// cleared for the next step.
+template <bool FROM_WORD>
 __global__ __launch_bounds__(256) void k_check(const LegDev* legs, BlockMap map, int force) {
   const int leg = find_leg(map, blockIdx.x);
   const LegDev& g = legs[leg];
   const int w = blockIdx.x - map.start[leg];
   __shared__ float red[256];
+  __shared__ int s_flag;
   float m = 0.f;
-  if (!force) {
+  if (FROM_WORD) {
+    if (g.units < 64) {
+      if (threadIdx.x == 0) m = __uint_as_float(g.maxdisp[w]);
+    } else {
+      // integrator waves covering this window's units
+      const long long u0 = (long long)w * g.units, u1 = u0 + g.units;
+      for (long long q = (u0 >> 6) + threadIdx.x; q <= ((u1 - 1) >> 6); q += blockDim.x) {
+        const bool first = (q * 64) / g.units == w;         // this window is the wave's first
+        m = fmaxf(m, __uint_as_float(g.wmax[2 * q + (first ? 0 : 1)]));
+      }
+    }
+  } else if (!force) {
     const size_t o = (size_t)w * g.n;
     for (int a = threadIdx.x; a < g.n; a += blockDim.x) {
-      float dx = g.x[o + a] - g.xr[o + a], dy = g.y[o + a] - g.yr[o + a], dz = g.z[o + a] - g.zr[o + a];
+      const float dx = g.x[o + a] - g.xr[o + a], dy = g.y[o + a] - g.yr[o + a], dz = g.z[o + a] - g.zr[o + a];
       m = fmaxf(m, dx * dx + dy * dy + dz * dz);
     }
   }
@@ -46,18 +63,12 @@ __global__ __launch_bounds__(256) void k_check(const LegDev* legs, BlockMap map,
     const int f = (force || !(red[0] <= g.skin_half2)) ? 1 : 0;
     g.flag[w] = f;
     g.nbuild[w] += f;
+    g.maxdisp[w] = 0u;
+    s_flag = f;
   }
-}
-
-// items: window x cell -- zero the per-cell counters of windows being rebuilt
-__global__ __launch_bounds__(256) void k_cells_zero(const LegDev* legs, BlockMap map) {
-  const int leg = find_leg(map, blockIdx.x);
-  const LegDev& g = legs[leg];
-  const long long i = (long long)(blockIdx.x - map.start[leg]) * blockDim.x + threadIdx.x;
-  if (i >= (long long)g.W * g.ncell) return;
-  const int w = (int)(i / g.ncell);
-  if (!g.flag[w]) return;
-  g.cursor[i] = 0;
+  __syncthreads();
+  if (s_flag)
+    for (int c = threadIdx.x; c < g.ncell; c += blockDim.x) g.cursor[(size_t)w * g.ncell + c] = 0;
 }
 
 // items: window x atom -- Hilbert cell code, per-cell counts, reference positions
@@ -143,43 +154,6 @@ __global__ __launch_bounds__(256) void k_cells_order(const LegDev* legs, BlockMa
   }
   if (c == 0)
     for (int s = g.n; s < g.npad; ++s) p[s] = -1;
-}
-
-// items: window x slot -- per-slot constant parameters in sorted order
-__global__ __launch_bounds__(256) void k_sorted_params(const LegDev* legs, BlockMap map) {
-  const int leg = find_leg(map, blockIdx.x);
-  const LegDev& g = legs[leg];
-  const long long i = (long long)(blockIdx.x - map.start[leg]) * blockDim.x + threadIdx.x;
-  if (i >= (long long)g.W * g.npad) return;
-  const int w = (int)(i / g.npad);
-  if (!g.flag[w]) return;
-  const int a = g.perm[i];
-  float4 p = make_float4(0.f, 0.f, 0.f, 0.f);
-  if (a >= 0) p = make_float4(0.5f * g.sig[a], 2.0f * sqrtf(g.eps[a]), g.lig[a] ? 1.f : 0.f, g.q[a]);
-  g.prm[i] = p;
-}
-
-// items: window x cluster -- bounding box of wrapped positions
-__global__ __launch_bounds__(256) void k_bbox(const LegDev* legs, BlockMap map) {
-  const int leg = find_leg(map, blockIdx.x);
-  const LegDev& g = legs[leg];
-  const long long i = (long long)(blockIdx.x - map.start[leg]) * blockDim.x + threadIdx.x;
-  if (i >= (long long)g.W * g.nclus) return;
-  const int w = (int)(i / g.nclus);
-  if (!g.flag[w]) return;
-  const int c = (int)(i - (long long)w * g.nclus);
-  const int* p = g.perm + (size_t)w * g.npad + c * kClus;
-  const float4* xq = g.xyzq + (size_t)w * g.npad + c * kClus;
-  float lo[3] = {3.0e38f, 3.0e38f, 3.0e38f}, hi[3] = {-3.0e38f, -3.0e38f, -3.0e38f};
-  for (int k = 0; k < kClus; ++k) {
-    if (p[k] < 0) continue;
-    const float4 r = xq[k];
-    const float v[3] = {wrapf(r.x, g.Lf[0], g.invLf[0]), wrapf(r.y, g.Lf[1], g.invLf[1]),
-                        wrapf(r.z, g.Lf[2], g.invLf[2])};
-    for (int d = 0; d < 3; ++d) { lo[d] = fminf(lo[d], v[d]); hi[d] = fmaxf(hi[d], v[d]); }
-  }
-  g.bblo[i] = make_float4(lo[0], lo[1], lo[2], 0.f);
-  g.bbhi[i] = make_float4(hi[0], hi[1], hi[2], 0.f);
 }
 
 // One block per cluster: sweep the coarse blocks (aligned 2x2x2 fine cells)
@@ -427,17 +401,17 @@ inline int blocks_for(long long items, int per) { return (int)((items + per - 1)
 
 }  // namespace
 
-void launch_check(hipStream_t s, const LegDev* d, const LegHost* h, int nl, int force) {
+void launch_check(hipStream_t s, const LegDev* d, const LegHost* h, int nl, int force, bool from_word) {
   BlockMap m;
   const int nb = make_map(m, nl, [&](int i) { return h[i].W; });
-  if (nb) hipLaunchKernelGGL(k_check, dim3(nb), dim3(256), 0, s, d, m, force);
+  if (!nb) return;
+  if (from_word) hipLaunchKernelGGL(k_check<true>, dim3(nb), dim3(256), 0, s, d, m, force);
+  else hipLaunchKernelGGL(k_check<false>, dim3(nb), dim3(256), 0, s, d, m, force);
 }
 
 void launch_build(hipStream_t s, const LegDev* d, const LegHost* h, int nl) {
   BlockMap m;
-  int nb = make_map(m, nl, [&](int i) { return blocks_for((long long)h[i].W * h[i].ncell, 256); });
-  if (nb) hipLaunchKernelGGL(k_cells_zero, dim3(nb), dim3(256), 0, s, d, m);
-  nb = make_map(m, nl, [&](int i) { return blocks_for((long long)h[i].W * h[i].n, 256); });
+  int nb = make_map(m, nl, [&](int i) { return blocks_for((long long)h[i].W * h[i].n, 256); });
   if (nb) hipLaunchKernelGGL(k_cells_count, dim3(nb), dim3(256), 0, s, d, m);
   nb = make_map(m, nl, [&](int i) { return h[i].W; });
   if (nb) hipLaunchKernelGGL(k_cells_scan, dim3(nb), dim3(1024), 0, s, d, m);
@@ -445,11 +419,9 @@ void launch_build(hipStream_t s, const LegDev* d, const LegHost* h, int nl) {
   if (nb) hipLaunchKernelGGL(k_cells_scatter, dim3(nb), dim3(256), 0, s, d, m);
   nb = make_map(m, nl, [&](int i) { return blocks_for((long long)h[i].W * h[i].ncell, 256); });
   if (nb) hipLaunchKernelGGL(k_cells_order, dim3(nb), dim3(256), 0, s, d, m);
-  nb = make_map(m, nl, [&](int i) { return blocks_for((long long)h[i].W * h[i].npad, 256); });
-  if (nb) hipLaunchKernelGGL(k_sorted_params, dim3(nb), dim3(256), 0, s, d, m);
-  launch_pack(s, d, h, nl);        // sorted coordinates for the box and candidate sweeps
-  nb = make_map(m, nl, [&](int i) { return blocks_for((long long)h[i].W * h[i].nclus, 256); });
-  if (nb) hipLaunchKernelGGL(k_bbox, dim3(nb), dim3(256), 0, s, d, m);
+  // sorted coordinates every step; sorted parameters and cluster boxes for
+  // the windows being rebuilt
+  launch_pack(s, d, h, nl, true);
   nb = make_map(m, nl, [&](int i) { return h[i].W * h[i].nclus; });
   if (nb) hipLaunchKernelGGL(k_build, dim3(nb), dim3(256), 0, s, d, m);
 }

@@ -32,21 +32,50 @@ __device__ __forceinline__ float erfc_fit(float x, float* ex) {
   return p * t * e;
 }
 
-// items: window x slot -- current coordinates and scaled charges in sorted order
+// items: window x slot -- current coordinates and scaled charges in sorted
+// order.  REBUILD (inside a list build): for windows being rebuilt also the
+// sorted per-slot parameters and each 8-slot cluster's bounding box of
+// wrapped positions (8 consecutive lanes hold one cluster: N_pad is a
+// multiple of 8).
+template <bool REBUILD>
 __global__ __launch_bounds__(256) void k_pack(const LegDev* legs, BlockMap map) {
   const int leg = find_leg(map, blockIdx.x);
   const LegDev& g = legs[leg];
   const long long i = (long long)(blockIdx.x - map.start[leg]) * blockDim.x + threadIdx.x;
-  if (i >= (long long)g.W * g.npad) return;
-  const int w = (int)(i / g.npad);
-  const int a = g.perm[i];
+  const bool valid = i < (long long)g.W * g.npad;
+  const long long ic = valid ? i : (long long)g.W * g.npad - 1;
+  const int w = (int)(ic / g.npad);
+  const int a = valid ? g.perm[ic] : -1;
   float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
   if (a >= 0) {
     const size_t o = (size_t)w * g.n + a;
     const float q = g.q[a] * (g.lig[a] ? g.lam[4 * w] : 1.0f);
     v = make_float4(g.x[o], g.y[o], g.z[o], q * (float)sqrt(kKE));
   }
-  g.xyzq[i] = v;
+  if (valid) g.xyzq[i] = v;
+  if (REBUILD) {
+    const bool fl = valid && g.flag[w] != 0;
+    if (fl) {
+      float4 p = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (a >= 0) p = make_float4(0.5f * g.sig[a], 2.0f * sqrtf(g.eps[a]), g.lig[a] ? 1.f : 0.f, g.q[a]);
+      g.prm[i] = p;
+    }
+    float lo[3] = {3.0e38f, 3.0e38f, 3.0e38f}, hi[3] = {-3.0e38f, -3.0e38f, -3.0e38f};
+    if (a >= 0) {
+      const float r[3] = {wrapf(v.x, g.Lf[0], g.invLf[0]), wrapf(v.y, g.Lf[1], g.invLf[1]),
+                          wrapf(v.z, g.Lf[2], g.invLf[2])};
+      for (int d = 0; d < 3; ++d) { lo[d] = r[d]; hi[d] = r[d]; }
+    }
+    for (int k = 1; k < kClus; k <<= 1)
+      for (int d = 0; d < 3; ++d) {
+        lo[d] = fminf(lo[d], __shfl_xor(lo[d], k, 64));
+        hi[d] = fmaxf(hi[d], __shfl_xor(hi[d], k, 64));
+      }
+    if (fl && (i & (kClus - 1)) == 0) {
+      g.bblo[i / kClus] = make_float4(lo[0], lo[1], lo[2], 0.f);
+      g.bbhi[i / kClus] = make_float4(hi[0], hi[1], hi[2], 0.f);
+    }
+  }
 }
 
 __device__ __forceinline__ float3 min_img(const LegDev& g, float dx, float dy, float dz) {
@@ -390,10 +419,12 @@ inline int blocks_for(long long items, int per) { return (int)((items + per - 1)
 
 }  // namespace
 
-void launch_pack(hipStream_t s, const LegDev* d, const LegHost* h, int nl) {
+void launch_pack(hipStream_t s, const LegDev* d, const LegHost* h, int nl, bool rebuild) {
   BlockMap m;
-  const int nb = make_map(m, nl, [&](int i) { return blocks_for((long long)h[i].W * h[i].npad, 256); });
-  if (nb) hipLaunchKernelGGL(k_pack, dim3(nb), dim3(256), 0, s, d, m);
+  const int nb = make_map(m, nl, [&](int i) { return (int)(((long long)h[i].W * h[i].npad + 255) / 256); });
+  if (!nb) return;
+  if (rebuild) hipLaunchKernelGGL(k_pack<true>, dim3(nb), dim3(256), 0, s, d, m);
+  else hipLaunchKernelGGL(k_pack<false>, dim3(nb), dim3(256), 0, s, d, m);
 }
 
 void launch_pairs(hipStream_t s, const LegDev* d, const LegHost* h, int nl, bool energy) {
