@@ -100,6 +100,55 @@ def test_nonbonded_and_pme(F, name, windows):
         assert rel_rms(f_all[k], fr + fx + frec) <= 1e-5, (w, 'forces', rel_rms(f_all[k], fr + fx + frec))
 
 
+def _sample_atoms(s, k=40, seed=11):
+    rng = np.random.default_rng(seed)
+    pick = list(np.where(s.is_ligand)[0][:8])
+    if s.restraint_atoms is not None:
+        pick += [int(a) for a in s.restraint_atoms]
+    pick += [int(a) for a in rng.choice(s.n_atoms, k, replace=False)]
+    return np.unique(np.array(pick, np.int64))
+
+
+@pytest.mark.parametrize('name', ['config1', 'config2'])
+def test_full_size_launch_sampled_atoms(F, name):
+    """Every window of a full-size leg in one launch, as the bench and the
+    served batches run them (20-window solvent leg; 42-window, ~70k-atom
+    complex leg with a 96^3 grid), each window on its own perturbed
+    coordinates: real-space + excluded-pair forces of sampled atoms against
+    the oracle's per-atom brute force, reciprocal forces of the same atoms and
+    the whole-system reciprocal, excluded-pair and self energies against the
+    FP64 PME and closed forms."""
+    felis, ctx = F
+    s = getattr(gen, name)()
+    W = s.n_windows
+    pos = _jitter(s, W, amp=0.03, seed=5)
+    leg = _leg(felis, ctx, s, positions=pos)
+    felis.nonbonded(ctx, [leg])
+    f_real = leg.forces().cpu().numpy()
+    felis.pme(ctx, [leg])
+    f_all = leg.forces().cpu().numpy()
+    f_rec = f_all - f_real
+    E = leg.energy.cpu().numpy()
+    ctx.device_check()
+    atoms = _sample_atoms(s)
+    pme = PME(s.box, s.grid, s.ewald_alpha)
+    windows = range(W) if W <= 20 else [0, 11, 12, 21, 22, 41]
+    for w in windows:
+        lam = s.lambdas[w]
+        x = pos[w].astype(np.float64)
+        fo, _ = opairs.real_space_atoms(x, s, lam, atoms)
+        ex, fx = opairs.exclusion_correction(x, s, lam)
+        es = opairs.self_and_background(s, lam)
+        er, frec = pme.energy_forces(x, opairs.scaled_charges(s, lam[0]))
+        ref_real = fo + fx[atoms]
+        assert rel_rms(f_real[w][atoms], ref_real) <= 1e-5, (w, 'real', rel_rms(f_real[w][atoms], ref_real))
+        assert rel_rms(f_rec[w][atoms], frec[atoms]) <= 1e-4, (w, 'recip', rel_rms(f_rec[w][atoms], frec[atoms]))
+        assert rel_rms(f_all[w][atoms], ref_real + frec[atoms]) <= 1e-5, (w, 'total')
+        assert abs(E[w, 2] - ex) <= 1e-6 * abs(ex), (w, 'excl', E[w, 2], ex)
+        assert abs(E[w, 3] - es) <= 1e-6 * abs(es), (w, 'self', E[w, 3], es)
+        assert abs(E[w, 4] - er) <= 1e-6 * abs(er) + 1e-4, (w, 'recip', E[w, 4], er)
+
+
 def test_bonded_and_restraint(F):
     felis, ctx = F
     s = gen.small_complex()
