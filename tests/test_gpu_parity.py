@@ -248,6 +248,44 @@ def test_ukn_matches_oracle(F):
     assert np.max(np.abs(u - ref)) <= 1e-6 * np.abs(ref).max() + 2e-4
 
 
+def test_ukn_full_size_complex(F):
+    """u_kn of the ~70k-atom complex leg (96^3 grid) at all 42 states for
+    perturbed frames, through the leg's 42-window scratch, against the oracle
+    frame by frame."""
+    felis, ctx = F
+    s = gen.config2()
+    nf = 4
+    frames = _jitter(s, nf, amp=0.05, seed=13)
+    leg = _leg(felis, ctx, s)
+    xt = torch.as_tensor(frames[..., 0]).cuda()
+    yt = torch.as_tensor(frames[..., 1]).cuda()
+    zt = torch.as_tensor(frames[..., 2]).cuda()
+    beta = 1.0 / (KB * 300.0)
+    u = felis.ukn(ctx, leg, s.lambdas, xt, yt, zt, beta).cpu().numpy()
+    ctx.device_check()
+    ref = oukn.ukn(s, frames.astype(np.float64), s.lambdas, beta)
+    du = (u - u[0]) - (ref - ref[0])
+    scale = np.abs(ref - ref[0]).max()
+    assert np.max(np.abs(du)) <= 1e-6 * scale + 2e-4, (np.max(np.abs(du)), scale)
+    assert np.max(np.abs(u - ref)) <= 1e-6 * np.abs(ref).max() + 2e-4
+
+
+def test_mbar_full_size(F):
+    """MBAR at 42 states x 84,000 samples (2,000 per state): harmonic states
+    whose exact free energies are known; GPU against the oracle's fixed point."""
+    felis, ctx = F
+    rng = np.random.default_rng(17)
+    K, n = 42, 2000
+    ks = np.exp(np.linspace(0.0, np.log(3.0), K))
+    x2 = np.concatenate([(rng.normal(0, 1 / np.sqrt(k), (n, 3)) ** 2).sum(1) for k in ks])
+    u = 0.5 * ks[:, None] * x2[None, :]
+    N = np.full(K, n)
+    f_ref, _ = ombar.mbar(u, N, tol=1e-13)
+    f, it = felis.mbar(ctx, torch.as_tensor(u).cuda(), N, tol=1e-12)
+    assert np.max(np.abs(f - f_ref)) < 1e-8, np.max(np.abs(f - f_ref))
+    assert abs((f[-1] - f[0]) - 1.5 * np.log(ks[-1] / ks[0])) < 0.02        # sampling error only
+
+
 def test_mbar_matches_oracle(F):
     felis, ctx = F
     rng = np.random.default_rng(2)
