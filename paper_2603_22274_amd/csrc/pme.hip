@@ -10,10 +10,12 @@
 // exp(-pi^2 |m|^2/alpha^2)/|m|^2 |b1 b2 b3|^2, G(0) = 0;
 // E_rec = 1/2 sum_i q~_i phi(r_i); F_i = -q~_i grad(spline weights) . phi.
 //
-// FFT: Stockham autosort, radices 4/2/3/5, one kernel per axis; a workgroup
-// holds 16 lines in LDS ([element][line] layout, coalesced loads for every
-// axis).  The inverse transform is conj(DFT(conj(.))).  The z pass fuses
-// forward transform, multiplication by G and inverse transform.
+// FFT: Stockham autosort, radices 4/2/3/5.  Grids whose x-y planes fit in
+// LDS (<= 4096 points) are transformed by whole planes (x then y in one
+// workgroup), otherwise one kernel per axis with 16 lines per workgroup
+// ([element][line] layout, coalesced loads for every axis).  The inverse
+// transform is conj(DFT(conj(.))).  The z pass fuses forward transform,
+// multiplication by G and inverse transform.
 #include <algorithm>
 
 #include "felis_internal.h"
@@ -22,6 +24,7 @@ namespace felis {
 namespace {
 
 constexpr int kLines = 16;
+constexpr int kMaxPlane = 4096;                 // x-y plane points transformed whole in LDS (2 x 32 KB)
 
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
   return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
@@ -191,6 +194,85 @@ __global__ __launch_bounds__(256) void k_fft(const LegDev* legs, BlockMap map) {
     float2 v = res[e * kLines + b];
     if (MODE == 1 || MODE == 3) v = conj2(v);
     cg[off] = v;
+  }
+}
+
+// One Stockham stage of radix R over nl lines held as buf[e * nl + b].
+template <int R>
+__device__ __forceinline__ void stage_nl(const float2* src, float2* dst, int n, int Ns, int nl,
+                                         const float2* __restrict__ tw) {
+  const int nR = n / R;
+  const int step = n / (Ns * R);
+  for (int t = threadIdx.x; t < nR * nl; t += blockDim.x) {
+    const int j = t / nl, b = t - j * nl;
+    const int k = j % Ns;
+    float2 v[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      v[r] = src[(j + r * nR) * nl + b];
+      if (r) v[r] = cmul(v[r], tw[r * k * step]);
+    }
+    dft<R>(v);
+    const int o = (j / Ns) * Ns * R + k;
+#pragma unroll
+    for (int r = 0; r < R; ++r) dst[(o + r * Ns) * nl + b] = v[r];
+  }
+}
+
+__device__ float2* fft_lines_nl(float2* src, float2* dst, int n, int nl, const int* rad, int nrad,
+                                const float2* __restrict__ tw) {
+  int Ns = 1;
+  for (int st = 0; st < nrad; ++st) {
+    const int R = rad[st];
+    switch (R) {
+      case 2: stage_nl<2>(src, dst, n, Ns, nl, tw); break;
+      case 3: stage_nl<3>(src, dst, n, Ns, nl, tw); break;
+      case 4: stage_nl<4>(src, dst, n, Ns, nl, tw); break;
+      default: stage_nl<5>(src, dst, n, Ns, nl, tw); break;
+    }
+    __syncthreads();
+    float2* t = src; src = dst; dst = t;
+    Ns *= R;
+  }
+  return src;
+}
+
+// One workgroup per (window pair, z plane): 2D transform of the Kx x Ky
+// plane in LDS -- x lines, transpose, y lines -- so a forward (or inverse)
+// transform over x and y reads and writes the grid once.  INVERSE uses
+// conj(DFT(conj(.))).
+template <bool INVERSE>
+__global__ __launch_bounds__(256) void k_fft_xy(const LegDev* legs, BlockMap map) {
+  const int leg = find_leg(map, blockIdx.x);
+  const LegDev& g = legs[leg];
+  const int Kx = g.K[0], Ky = g.K[1], Kz = g.K[2];
+  const int bl = blockIdx.x - map.start[leg];
+  const int p = bl / Kz, z = bl - p * Kz;
+  if (p >= g.npair) return;
+  extern __shared__ float2 smem[];
+  float2* A = smem;
+  float2* B = smem + (size_t)Kx * Ky;
+  float2* cg = g.cgrid + (size_t)p * g.Ktot + (size_t)z * Kx * Ky;
+  const int np = Kx * Ky;
+  for (int idx = threadIdx.x; idx < np; idx += blockDim.x) {       // [x][y]: lines along x
+    const int y = idx / Kx, x = idx - y * Kx;
+    float2 v = cg[idx];
+    if (INVERSE) v = conj2(v);
+    A[x * Ky + y] = v;
+  }
+  __syncthreads();
+  float2* r = fft_lines_nl(A, B, Kx, Ky, g.rad[0], g.nrad[0], g.tw[0]);
+  float2* o = (r == A) ? B : A;
+  for (int idx = threadIdx.x; idx < np; idx += blockDim.x) {       // -> [y][x]: lines along y
+    const int x = idx / Ky, y = idx - x * Ky;
+    o[y * Kx + x] = r[idx];
+  }
+  __syncthreads();
+  r = fft_lines_nl(o, r, Ky, Kx, g.rad[1], g.nrad[1], g.tw[1]);
+  for (int idx = threadIdx.x; idx < np; idx += blockDim.x) {
+    float2 v = r[idx];                                              // [y][x] = grid order
+    if (INVERSE) v = conj2(v);
+    cg[idx] = v;
   }
 }
 
@@ -467,6 +549,17 @@ void fft_pass(hipStream_t s, const LegDev* d, const LegHost* h, int nl) {
 }  // namespace
 
 void launch_pme_fft(hipStream_t s, const LegDev* d, const LegHost* h, int nl, bool from_int64) {
+  int plane = 0;
+  for (int i = 0; i < nl; ++i) plane = std::max(plane, h[i].K[0] * h[i].K[1]);
+  if (!from_int64 && plane <= kMaxPlane) {           // whole x-y planes in LDS
+    BlockMap m;
+    const int nb = make_map(m, nl, [&](int i) { return h[i].npair * h[i].K[2]; });
+    const size_t lds = 2 * (size_t)plane * sizeof(float2);
+    if (nb) hipLaunchKernelGGL(k_fft_xy<false>, dim3(nb), dim3(256), lds, s, d, m);
+    fft_pass<2, 3>(s, d, h, nl);
+    if (nb) hipLaunchKernelGGL(k_fft_xy<true>, dim3(nb), dim3(256), lds, s, d, m);
+    return;
+  }
   if (from_int64) fft_pass<0, 2>(s, d, h, nl);
   else fft_pass<0, 0>(s, d, h, nl);
   fft_pass<1, 0>(s, d, h, nl);
