@@ -296,9 +296,12 @@ __device__ __forceinline__ int grid_base(float x, double invL, int K, float* f) 
   if (!(fabs(u) < 1.0e15)) u = 0.0;              // non-finite input -> 0 (keeps indices in range)
   const double b = floor(u);
   *f = (float)(u - b);
-  long long k = (long long)b % K;
+  // b mod K without 64-bit integer division: |b| < 2^53, so the FP64 floor
+  // of b / K is off by at most one, which the integer fix-ups absorb
+  int k = (int)(b - (double)K * floor(b * (1.0 / (double)K)));
   if (k < 0) k += K;
-  return (int)k;
+  if (k >= K) k -= K;
+  return k;
 }
 
 constexpr int kBrick = 8;                      // brick edge in grid points
@@ -463,19 +466,23 @@ template <bool ENERGY>
 __global__ __launch_bounds__(256) void k_gather(const LegDev* legs, BlockMap map) {
   const int leg = find_leg(map, blockIdx.x);
   const LegDev& g = legs[leg];
+  // atoms are taken in the neighbour-list sort order (spatially coherent:
+  // the four atoms of a wave share most of their stencil points in cache)
   const long long local = (long long)(blockIdx.x - map.start[leg]) * 16 + (threadIdx.x >> 4);
-  const long long tot = (long long)g.W * g.n;
-  const bool valid = local < tot;
-  const long long lc = valid ? local : tot - 1;
-  const int w = (int)(lc / g.n);
-  const int a = (int)(lc - (long long)w * g.n);
+  const long long tot = (long long)g.W * g.npad;
+  const long long lc = local < tot ? local : tot - 1;
+  const int w = (int)(lc / g.npad);
+  const int ap = g.perm[lc];
+  const bool valid = local < tot && ap >= 0;
+  const int a = ap >= 0 ? ap : 0;
   const int sub = threadIdx.x & 15, iy = sub & 3, iz = sub >> 2;
   const size_t o = (size_t)w * g.n + a;
   const float q = g.q[a] * (g.lig[a] ? g.lam[4 * w] : 1.0f);
+  const float4 xa = g.xyzq[lc];
   float fxr, fyr, fzr, wx[4], wy[4], wz[4], dx[4], dy[4], dz[4];
-  const int bx = grid_base(g.x[o], g.invL[0], g.K[0], &fxr);
-  const int by = grid_base(g.y[o], g.invL[1], g.K[1], &fyr);
-  const int bz = grid_base(g.z[o], g.invL[2], g.K[2], &fzr);
+  const int bx = grid_base(xa.x, g.invL[0], g.K[0], &fxr);
+  const int by = grid_base(xa.y, g.invL[1], g.K[1], &fyr);
+  const int bz = grid_base(xa.z, g.invL[2], g.K[2], &fzr);
   bspline4(fxr, wx, dx);
   bspline4(fyr, wy, dy);
   bspline4(fzr, wz, dz);
@@ -578,7 +585,7 @@ void launch_pme(hipStream_t s, const LegDev* d, const LegHost* h, int nl, bool e
   if (!nb) return;
   hipLaunchKernelGGL(k_spread, dim3(nb), dim3(256), 0, s, d, m);
   launch_pme_fft(s, d, h, nl, false);
-  nb = make_map(m, nl, [&](int i) { return blocks_for((long long)h[i].W * h[i].n, 16); });
+  nb = make_map(m, nl, [&](int i) { return blocks_for((long long)h[i].W * h[i].npad, 16); });
   if (energy) hipLaunchKernelGGL(k_gather<true>, dim3(nb), dim3(256), 0, s, d, m);
   else hipLaunchKernelGGL(k_gather<false>, dim3(nb), dim3(256), 0, s, d, m);
 }

@@ -56,9 +56,12 @@ __device__ __forceinline__ int grid_base(float x, double invL, int K, float* f) 
   if (!(fabs(u) < 1.0e15)) u = 0.0;              // non-finite input -> 0 (keeps indices in range)
   const double b = floor(u);
   *f = (float)(u - b);
-  long long k = (long long)b % K;
+  // b mod K without 64-bit integer division: |b| < 2^53, so the FP64 floor
+  // of b / K is off by at most one, which the integer fix-ups absorb
+  int k = (int)(b - (double)K * floor(b * (1.0 / (double)K)));
   if (k < 0) k += K;
-  return (int)k;
+  if (k >= K) k -= K;
+  return k;
 }
 
 __device__ __forceinline__ float3 min_img(const LegDev& g, float dx, float dy, float dz) {
