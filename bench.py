@@ -34,7 +34,8 @@ if ROOT not in sys.path:
 METRIC = "aggregate ns·windows/day at |ΔΔG|≤0.01 kcal/mol; p50/p99 leg latency"
 KB = 0.0019872043
 DT = 0.002                      # ps
-PEAK_FP32 = 157.3               # TFLOP/s, MI355X FP32 vector (published)
+PEAK_FP32 = 157.3               # TFLOP/s, MI355X FP32 vector (published; counts packed FP32)
+ISSUE_FP32 = 78.6               # TFLOP/s, non-packed FP32 issue: 256 CU x 4 SIMD x 16 lanes x 2 x 2.4 GHz
 FLOP_PER_PAIR = 75              # FP32 flops per in-cutoff pair (FMA = 2)
 TRAFFIC_FILE = os.path.join(ROOT, 'profiles', 'pairs_traffic_solvent20.json')
 
@@ -217,6 +218,8 @@ def main():
                    "ukn_states": W, "mbar_samples": int(W * n_samples)},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32, "traffic": traffic,
+                     "nonpacked_issue_peak": ISSUE_FP32, "frac_of_nonpacked_peak": achieved / ISSUE_FP32,
+                     "traffic_gb_per_s": (traffic / avg_pairs_s / 1e9) if traffic else None,
                      "kernel": "k_pairs (real-space pair kernel, all 20 windows per launch)",
                      "pairs_in_cutoff_per_launch": int(npairs_cut), "flop_per_pair": FLOP_PER_PAIR,
                      "avg_launch_ms": avg_pairs_s * 1000.0, "launches": pairs_n},
