@@ -162,8 +162,8 @@ int make_plan(felis_ctx* c, const felis_leg* L, Plan& P) {
   y.prm = put(W * npad * 16);
   y.bblo = put(W * nc * 16);
   y.bbhi = put(W * nc * 16);
-  y.lcount = put(W * nc * 4);
-  y.lent = put(W * nc * (size_t)h.cap * 4);
+  y.lcount = put(W * nc * 2 * 4);
+  y.lent = put(W * nc * 2 * (size_t)h.cap * 4);
   y.grid64 = put(2 * (size_t)h.npair * h.Ktot * 8);
   y.cgrid = put((size_t)h.npair * h.Ktot * 8);
   for (int d = 0; d < 3; ++d) { y.tw[d] = put(h.K[d] * 8); y.bmod[d] = put(h.K[d] * 4); }
@@ -459,7 +459,7 @@ int felis_leg_init(felis_ctx* c, felis_leg* L) {
   ok &= hipMemsetAsync(w + y.nbuild, 0, h.W * 8, c->stream) == hipSuccess;
   ok &= hipMemsetAsync(w + y.maxdisp, 0, h.W * 4, c->stream) == hipSuccess;
   ok &= hipMemsetAsync(w + y.wmax, 0, y.perm - y.wmax, c->stream) == hipSuccess;
-  ok &= hipMemsetAsync(w + y.lcount, 0, (size_t)h.W * h.nclus * 4, c->stream) == hipSuccess;
+  ok &= hipMemsetAsync(w + y.lcount, 0, (size_t)h.W * h.nclus * 2 * 4, c->stream) == hipSuccess;
   ok &= hipMemsetAsync(w + y.grid64, 0, y.cgrid - y.grid64, c->stream) == hipSuccess;
   ok &= hipMemsetAsync(w + y.eacc, 0, y.ucst - y.eacc, c->stream) == hipSuccess;
   ok &= hipStreamSynchronize(c->stream) == hipSuccess;

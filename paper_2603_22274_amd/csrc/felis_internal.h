@@ -83,8 +83,9 @@ struct LegDev {
   float4* prm;                          // [W][npad] sigma/2, 2 sqrt(eps), ligand flag, q
   float4* bblo;                         // [W][nclus] cluster bounding boxes (wrapped)
   float4* bbhi;
-  int* lcount;                          // [W][nclus]
-  unsigned* lent;                       // [W][nclus][cap] (slot << 8 | 8-bit i mask)
+  int* lcount;                          // [W][nclus][2] entries per half-cluster list
+  unsigned* lent;                       // [W][nclus][2][cap]: list of the cluster's atoms 0-3 and of
+                                        // atoms 4-7 (slot << 8 | 4-bit mask over the half's atoms)
   long long* grid64;                    // [W][Ktot] fixed-point charge grids
   float2* cgrid;                        // [npair][Ktot] complex grids
   float2* tw[3];                        // [K] exp(-2 pi i k / K) per axis

@@ -179,7 +179,7 @@ __global__ __launch_bounds__(256) void k_build(const LegDev* legs, BlockMap map)
   __shared__ int s_start[256];                  // first sorted slot of each block in the round
   __shared__ int s_pre[256];                    // exclusive prefix of candidate counts
   __shared__ int s_wsum[4];
-  __shared__ int s_wc[2][4];
+  __shared__ int s_wc[2][2][4];
   __shared__ unsigned char s_cellof[kCellOf];   // candidate -> block of the round, one window at a time
   const size_t o = (size_t)w * g.n;
   const int* perm = g.perm + (size_t)w * g.npad;
@@ -247,10 +247,11 @@ __global__ __launch_bounds__(256) void k_build(const LegDev* legs, BlockMap map)
   const bool shift = ext[0] + incl + 0.02f < 0.5f * g.Lf[0] && ext[1] + incl + 0.02f < 0.5f * g.Lf[1] &&
                      ext[2] + incl + 0.02f < 0.5f * g.Lf[2];
   const int* cst = g.cellstart + (size_t)w * (g.ncell + 1);
-  unsigned* out = g.lent + (size_t)item * g.cap;
+  unsigned* outL = g.lent + (size_t)item * 2 * g.cap;      // partners of atoms 0-3
+  unsigned* outH = outL + g.cap;                            // partners of atoms 4-7
   const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   const int ncells = nC[0] * nC[1] * nC[2];
-  int count = 0, par = 0;
+  int countL = 0, countH = 0, par = 0;
   for (int cb = 0; cb < ncells; cb += 256) {
     const int ci = cb + tid;
     int s0 = 0, cnt = 0;
@@ -336,15 +337,21 @@ __global__ __launch_bounds__(256) void k_build(const LegDev* legs, BlockMap map)
           }
         }
       }
-      const unsigned long long bal = __ballot(mask != 0u);
-      if (lane == 0) s_wc[par][wave] = __popcll(bal);
+      const unsigned mL = mask & 0xFu, mH = mask >> 4;
+      const unsigned long long bL = __ballot(mL != 0u), bH = __ballot(mH != 0u);
+      if (lane == 0) { s_wc[par][0][wave] = __popcll(bL); s_wc[par][1][wave] = __popcll(bH); }
       __syncthreads();
-      int off = count;
-      for (int k = 0; k < wave; ++k) off += s_wc[par][k];
-      count += s_wc[par][0] + s_wc[par][1] + s_wc[par][2] + s_wc[par][3];
-      if (mask) {
-        const int pos = off + __popcll(bal & lt);
-        if (pos < g.cap) out[pos] = ((unsigned)s << 8) | mask;
+      int offL = countL, offH = countH;
+      for (int k = 0; k < wave; ++k) { offL += s_wc[par][0][k]; offH += s_wc[par][1][k]; }
+      countL += s_wc[par][0][0] + s_wc[par][0][1] + s_wc[par][0][2] + s_wc[par][0][3];
+      countH += s_wc[par][1][0] + s_wc[par][1][1] + s_wc[par][1][2] + s_wc[par][1][3];
+      if (mL) {
+        const int pos = offL + __popcll(bL & lt);
+        if (pos < g.cap) outL[pos] = ((unsigned)s << 8) | mL;
+      }
+      if (mH) {
+        const int pos = offH + __popcll(bH & lt);
+        if (pos < g.cap) outH[pos] = ((unsigned)s << 8) | mH;
       }
       par ^= 1;
     }
@@ -352,17 +359,21 @@ __global__ __launch_bounds__(256) void k_build(const LegDev* legs, BlockMap map)
     }
     __syncthreads();                            // the round's tables are rewritten next
   }
+  const int count = max(countL, countH);
   if (count > g.cap) {
     if (tid == 0) {
       latch(g.err, kErrListCap, kSiteList, (w << 20) | max(s_ai[0], 0), g.leg_index);
       atomicMax(g.need, count);
     }
-    count = g.cap;
   }
-  if (tid == 0) g.lcount[item] = count;
+  if (tid == 0) {
+    g.lcount[2 * item] = min(countL, g.cap);
+    g.lcount[2 * item + 1] = min(countH, g.cap);
+  }
 }
 
-// Export pairs i < j with a set list bit and FP64 distance < r.
+// Export pairs i < j with a set list bit and FP64 distance < r (both
+// half-cluster lists).
 __global__ __launch_bounds__(256) void k_export(const LegDev* legs, int leg, int w, double r2,
                                                 int* pairs, long long cap,
                                                 unsigned long long* count) {
@@ -371,28 +382,30 @@ __global__ __launch_bounds__(256) void k_export(const LegDev* legs, int leg, int
   if (c >= g.nclus) return;
   const size_t item = (size_t)w * g.nclus + c;
   const int* perm = g.perm + (size_t)w * g.npad;
-  const unsigned* ent = g.lent + item * g.cap;
-  const int cnt = g.lcount[item];
   const size_t o = (size_t)w * g.n;
-  for (int e = threadIdx.x; e < cnt; e += blockDim.x) {
-    const unsigned v = ent[e];
-    const unsigned m = v & 0xffu;
-    if (!m) continue;
-    const int aj = perm[v >> 8];
-    for (int ii = 0; ii < kClus; ++ii) {
-      if (!((m >> ii) & 1u)) continue;
-      const int ai = perm[c * kClus + ii];
-      if (ai >= aj) continue;
-      double dx = (double)g.x[o + aj] - (double)g.x[o + ai];
-      double dy = (double)g.y[o + aj] - (double)g.y[o + ai];
-      double dz = (double)g.z[o + aj] - (double)g.z[o + ai];
-      dx = dx - g.L[0] * rint(dx * g.invL[0]);
-      dy = dy - g.L[1] * rint(dy * g.invL[1]);
-      dz = dz - g.L[2] * rint(dz * g.invL[2]);
-      const double d2 = (dx * dx + dy * dy) + dz * dz;
-      if (!(d2 < r2)) continue;
-      const unsigned long long k = atomicAdd(count, 1ull);
-      if ((long long)k < cap) { pairs[2 * k] = ai; pairs[2 * k + 1] = aj; }
+  for (int half = 0; half < 2; ++half) {
+    const unsigned* ent = g.lent + (item * 2 + half) * g.cap;
+    const int cnt = g.lcount[item * 2 + half];
+    for (int e = threadIdx.x; e < cnt; e += blockDim.x) {
+      const unsigned v = ent[e];
+      const unsigned m = v & 0xfu;
+      if (!m) continue;
+      const int aj = perm[v >> 8];
+      for (int k = 0; k < 4; ++k) {
+        if (!((m >> k) & 1u)) continue;
+        const int ai = perm[c * kClus + 4 * half + k];
+        if (ai >= aj) continue;
+        double dx = (double)g.x[o + aj] - (double)g.x[o + ai];
+        double dy = (double)g.y[o + aj] - (double)g.y[o + ai];
+        double dz = (double)g.z[o + aj] - (double)g.z[o + ai];
+        dx = dx - g.L[0] * rint(dx * g.invL[0]);
+        dy = dy - g.L[1] * rint(dy * g.invL[1]);
+        dz = dz - g.L[2] * rint(dz * g.invL[2]);
+        const double d2 = (dx * dx + dy * dy) + dz * dz;
+        if (!(d2 < r2)) continue;
+        const unsigned long long k2 = atomicAdd(count, 1ull);
+        if ((long long)k2 < cap) { pairs[2 * k2] = ai; pairs[2 * k2 + 1] = aj; }
+      }
     }
   }
 }

@@ -98,11 +98,11 @@ __device__ __forceinline__ float uniform(float v) {
 // i-atoms.  SHIFT: the periodic image of j is chosen once against the
 // cluster's first atom (exact when r_c + cluster extent < L/2 on every axis);
 // otherwise every (i, j) takes its own minimum image.
-template <bool ENERGY, bool SHIFT>
+template <bool ENERGY, bool SHIFT, int HALF>
 __device__ __forceinline__ void sweep(const LegDev& g, const ICluster& I, const unsigned* __restrict__ ent, int cnt,
                                       const float4* __restrict__ xq, const float4* __restrict__ pr, int lane,
-                                      float lam_v, float a_sc, bool soft_window, float (&fx)[kClus],
-                                      float (&fy)[kClus], float (&fz)[kClus], double& ec, double& el) {
+                                      float lam_v, float a_sc, bool soft_window, float (&fx)[4],
+                                      float (&fy)[4], float (&fz)[4], double& ec, double& el) {
   const float Lx = g.Lf[0], Ly = g.Lf[1], Lz = g.Lf[2];
   const float iLx = g.invLf[0], iLy = g.invLf[1], iLz = g.invLf[2];
   const float rc2 = g.rc2, alpha = g.alpha;
@@ -120,7 +120,8 @@ __device__ __forceinline__ void sweep(const LegDev& g, const ICluster& I, const 
       jz = fmaf(-Lz, rintf((jz - I.z[0]) * iLz), jz);
     }
 #pragma unroll
-    for (int ii = 0; ii < kClus; ++ii) {
+    for (int k = 0; k < 4; ++k) {
+      const int ii = 4 * HALF + k;
       float dx = jx - I.x[ii], dy = jy - I.y[ii], dz = jz - I.z[ii];
       if (!SHIFT) {
         dx = fmaf(-Lx, rintf(dx * iLx), dx);
@@ -128,7 +129,7 @@ __device__ __forceinline__ void sweep(const LegDev& g, const ICluster& I, const 
         dz = fmaf(-Lz, rintf(dz * iLz), dz);
       }
       const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-      const bool in = ((e >> ii) & 1u) && (r2 < rc2);
+      const bool in = ((e >> k) & 1u) && (r2 < rc2);
       const float r2s = in ? r2 : 1.0f;
       const float rinv = __builtin_amdgcn_rsqf(r2s);
       const float rinv2 = rinv * rinv;
@@ -162,9 +163,9 @@ __device__ __forceinline__ void sweep(const LegDev& g, const ICluster& I, const 
         if (ENERGY) elj = eps4 * fmaf(s6, s6, -s6);
       }
       const float fs = in ? (fc + flj) : 0.0f;
-      fx[ii] = fmaf(-fs, dx, fx[ii]);
-      fy[ii] = fmaf(-fs, dy, fy[ii]);
-      fz[ii] = fmaf(-fs, dz, fz[ii]);
+      fx[k] = fmaf(-fs, dx, fx[k]);
+      fy[k] = fmaf(-fs, dy, fy[k]);
+      fz[k] = fmaf(-fs, dz, fz[k]);
       if (ENERGY && in) {
         ec += (double)(qq * erfcv * rinv);
         el += (double)elj;
@@ -174,7 +175,8 @@ __device__ __forceinline__ void sweep(const LegDev& g, const ICluster& I, const 
 }
 
 template <bool ENERGY>
-__global__ __launch_bounds__(256) void k_pairs(const LegDev* legs, BlockMap map) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_pairs(const LegDev* legs,
+                                                                                      BlockMap map) {
   const int leg = find_leg(map, blockIdx.x);
   const LegDev& g = legs[leg];
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
@@ -212,16 +214,29 @@ __global__ __launch_bounds__(256) void k_pairs(const LegDev* legs, BlockMap map)
   }
   const float rc = sqrtf(g.rc2) + 0.01f;
   const bool shift = rc + ext[0] < 0.5f * g.Lf[0] && rc + ext[1] < 0.5f * g.Lf[1] && rc + ext[2] < 0.5f * g.Lf[2];
-  const unsigned* __restrict__ ent = g.lent + (size_t)item * g.cap;
-  const int cnt = g.lcount[item];
-  float fx[kClus], fy[kClus], fz[kClus];
-#pragma unroll
-  for (int ii = 0; ii < kClus; ++ii) fx[ii] = fy[ii] = fz[ii] = 0.f;
+  // the two half-cluster lists (partners of atoms 0-3, then of atoms 4-7);
+  // each half's forces are reduced over the wave before the next half
+  const unsigned* __restrict__ ent = g.lent + (size_t)item * 2 * g.cap;
   double ec = 0.0, el = 0.0;
-  if (shift)
-    sweep<ENERGY, true>(g, I, ent, cnt, xq, pr, lane, lam_v, a_sc, soft_window, fx, fy, fz, ec, el);
-  else
-    sweep<ENERGY, false>(g, I, ent, cnt, xq, pr, lane, lam_v, a_sc, soft_window, fx, fy, fz, ec, el);
+  float ox = 0.f, oy = 0.f, oz = 0.f;                 // lane ii < 8 ends with atom ii's pair force
+#pragma unroll
+  for (int half = 0; half < 2; ++half) {
+    float fx[4] = {0.f, 0.f, 0.f, 0.f}, fy[4] = {0.f, 0.f, 0.f, 0.f}, fz[4] = {0.f, 0.f, 0.f, 0.f};
+    const unsigned* __restrict__ eh = ent + half * g.cap;
+    const int cnt = g.lcount[2 * item + half];
+    if (half == 0) {
+      if (shift) sweep<ENERGY, true, 0>(g, I, eh, cnt, xq, pr, lane, lam_v, a_sc, soft_window, fx, fy, fz, ec, el);
+      else sweep<ENERGY, false, 0>(g, I, eh, cnt, xq, pr, lane, lam_v, a_sc, soft_window, fx, fy, fz, ec, el);
+    } else {
+      if (shift) sweep<ENERGY, true, 1>(g, I, eh, cnt, xq, pr, lane, lam_v, a_sc, soft_window, fx, fy, fz, ec, el);
+      else sweep<ENERGY, false, 1>(g, I, eh, cnt, xq, pr, lane, lam_v, a_sc, soft_window, fx, fy, fz, ec, el);
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const float sx = wave_sum(fx[k]), sy = wave_sum(fy[k]), sz = wave_sum(fz[k]);
+      if (lane == 4 * half + k) { ox = sx; oy = sy; oz = sz; }
+    }
+  }
 
   // Excluded pairs: remove their reciprocal-space (erf) interaction, each
   // pair from both of its sides; lane = ii + 8 k takes the k-th exclusion of
@@ -260,12 +275,7 @@ __global__ __launch_bounds__(256) void k_pairs(const LegDev* legs, BlockMap map)
     cy += __shfl_xor(cy, o, 64);
     cz += __shfl_xor(cz, o, 64);
   }
-  float ox = cx, oy = cy, oz = cz;
-#pragma unroll
-  for (int ii = 0; ii < kClus; ++ii) {
-    const float sx = wave_sum(fx[ii]), sy = wave_sum(fy[ii]), sz = wave_sum(fz[ii]);
-    if (lane == ii) { ox += sx; oy += sy; oz += sz; }
-  }
+  ox += cx; oy += cy; oz += cz;
   if (lane < kClus) {
     const int a = ai;
     if (a >= 0) {
