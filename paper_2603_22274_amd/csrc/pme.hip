@@ -466,16 +466,16 @@ template <bool ENERGY>
 __global__ __launch_bounds__(256) void k_gather(const LegDev* legs, BlockMap map) {
   const int leg = find_leg(map, blockIdx.x);
   const LegDev& g = legs[leg];
-  // atoms are taken in the neighbour-list sort order (spatially coherent:
-  // the four atoms of a wave share most of their stencil points in cache)
-  const long long local = (long long)(blockIdx.x - map.start[leg]) * 16 + (threadIdx.x >> 4);
+  // atoms in the neighbour-list sort order (spatially coherent); 4 lanes per
+  // atom, lane iz sums the 16 stencil points of plane z = bz - iz
+  const long long local = (long long)(blockIdx.x - map.start[leg]) * 64 + (threadIdx.x >> 2);
   const long long tot = (long long)g.W * g.npad;
   const long long lc = local < tot ? local : tot - 1;
   const int w = (int)(lc / g.npad);
   const int ap = g.perm[lc];
   const bool valid = local < tot && ap >= 0;
   const int a = ap >= 0 ? ap : 0;
-  const int sub = threadIdx.x & 15, iy = sub & 3, iz = sub >> 2;
+  const int iz = threadIdx.x & 3;
   const size_t o = (size_t)w * g.n + a;
   const float q = g.q[a] * (g.lig[a] ? g.lam[4 * w] : 1.0f);
   const float4 xa = g.xyzq[lc];
@@ -486,31 +486,37 @@ __global__ __launch_bounds__(256) void k_gather(const LegDev* legs, BlockMap map
   bspline4(fxr, wx, dx);
   bspline4(fyr, wy, dy);
   bspline4(fzr, wz, dz);
-  int gy = by - iy; if (gy < 0) gy += g.K[1];
   int gz = bz - iz; if (gz < 0) gz += g.K[2];
-  const float2* cg = g.cgrid + (size_t)(w >> 1) * g.Ktot + ((size_t)gz * g.K[1] + gy) * g.K[0];
-  const bool im = w & 1;
-  float pot = 0.f, gxs = 0.f, gys = 0.f, gzs = 0.f;
+  int gxv[4];
 #pragma unroll
-  for (int ix = 0; ix < 4; ++ix) {
-    int gx = bx - ix; if (gx < 0) gx += g.K[0];
-    const float2 c = cg[gx];
-    const float phi = im ? c.y : c.x;
-    pot = fmaf(wx[ix], phi, pot);
-    gxs = fmaf(dx[ix], phi, gxs);
+  for (int ix = 0; ix < 4; ++ix) { gxv[ix] = bx - ix; if (gxv[ix] < 0) gxv[ix] += g.K[0]; }
+  const float2* plane = g.cgrid + (size_t)(w >> 1) * g.Ktot + (size_t)gz * g.K[1] * g.K[0];
+  const bool im = w & 1;
+  float p0 = 0.f, px = 0.f, py = 0.f;          // sum w phi, sum dwx phi, sum dwy phi over the plane
+#pragma unroll
+  for (int iy = 0; iy < 4; ++iy) {
+    int gy = by - iy; if (gy < 0) gy += g.K[1];
+    const float2* row = plane + (size_t)gy * g.K[0];
+    float s0 = 0.f, s1 = 0.f;
+#pragma unroll
+    for (int ix = 0; ix < 4; ++ix) {
+      const float2 c = row[gxv[ix]];
+      const float phi = im ? c.y : c.x;
+      s0 = fmaf(wx[ix], phi, s0);
+      s1 = fmaf(dx[ix], phi, s1);
+    }
+    p0 = fmaf(wy[iy], s0, p0);
+    px = fmaf(wy[iy], s1, px);
+    py = fmaf(dy[iy], s0, py);
   }
-  const float wyz = wy[iy] * wz[iz];
-  float gyz = pot * dy[iy] * wz[iz];
-  float gzz = pot * wy[iy] * dz[iz];
-  gxs *= wyz;
-  pot *= wyz;
-  gys = gyz; gzs = gzz;
-  for (int off = 1; off < 16; off <<= 1) {
+  float pot = p0 * wz[iz], gxs = px * wz[iz], gys = py * wz[iz], gzs = p0 * dz[iz];
+  for (int off = 1; off < 4; off <<= 1) {
     pot += __shfl_xor(pot, off, 64);
     gxs += __shfl_xor(gxs, off, 64);
     gys += __shfl_xor(gys, off, 64);
     gzs += __shfl_xor(gzs, off, 64);
   }
+  const int sub = iz;
   if (valid && sub == 0) {
     const float fx = -q * gxs * (float)g.K[0] * g.invLf[0];
     const float fy = -q * gys * (float)g.K[1] * g.invLf[1];
@@ -585,7 +591,7 @@ void launch_pme(hipStream_t s, const LegDev* d, const LegHost* h, int nl, bool e
   if (!nb) return;
   hipLaunchKernelGGL(k_spread, dim3(nb), dim3(256), 0, s, d, m);
   launch_pme_fft(s, d, h, nl, false);
-  nb = make_map(m, nl, [&](int i) { return blocks_for((long long)h[i].W * h[i].npad, 16); });
+  nb = make_map(m, nl, [&](int i) { return blocks_for((long long)h[i].W * h[i].npad, 64); });
   if (energy) hipLaunchKernelGGL(k_gather<true>, dim3(nb), dim3(256), 0, s, d, m);
   else hipLaunchKernelGGL(k_gather<false>, dim3(nb), dim3(256), 0, s, d, m);
 }
