@@ -78,11 +78,12 @@ def cpu_baseline(sysd):
 
 def serve_mix(ctx, n_legs, per_window):
     """A seeded stream of uneven legs (4,000-12,000 atoms; 12, 20 or 42
-    windows; 200 steps, u_kn every 50; Poisson arrivals at 4 legs/s) served
-    with continuous batching, then the same stream one leg and one window at a
-    time.  Latency = arrival to Delta G."""
+    windows; 400 steps, u_kn every 50; Poisson arrivals at 8 legs/s, so the
+    stream arrives faster than the GPU finishes it) served with continuous
+    batching, then the same stream one leg and one window at a time.
+    Latency = arrival to Delta G."""
     from paper_2603_22274_amd import serve
-    reqs = serve.served_workload(n_legs=n_legs, rate=4.0, seed=22274, atoms=(4000, 12000), n_steps=200,
+    reqs = serve.served_workload(n_legs=n_legs, rate=8.0, seed=22274, atoms=(4000, 12000), n_steps=400,
                                  sample_every=50)
     for r in reqs:                      # relaxed starting coordinates (input preparation, untimed)
         serve.relax_start(ctx, r.sysd)
@@ -91,7 +92,7 @@ def serve_mix(ctx, n_legs, per_window):
     out, stats = srv.serve(reqs)
     stats = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in stats.items()}
     stats["workload"] = (f"{n_legs} legs, atoms {sorted(r.sysd.n_atoms for r in reqs)}, windows "
-                         f"{[r.sysd.n_windows for r in reqs]}, 200 steps each, u_kn every 50, Poisson 4 legs/s, "
+                         f"{[r.sysd.n_windows for r in reqs]}, 400 steps each, u_kn every 50, Poisson 8 legs/s, "
                          f"starts relaxed by 400 high-friction steps of the coupled state")
     stats["mbar_converged"] = sum(1 for r in out if r.status == 'ok')
     if per_window:

@@ -107,9 +107,11 @@ __device__ __forceinline__ void sweep(const LegDev& g, const ICluster& I, const 
   const float iLx = g.invLf[0], iLy = g.invLf[1], iLz = g.invLf[2];
   const float rc2 = g.rc2, alpha = g.alpha;
   const float c2a = 2.0f * alpha * 0.56418958354775628f;   // 2 alpha / sqrt(pi)
+  unsigned e_next = lane < cnt ? ent[lane] : 0u;          // slot 0 with an empty mask
   for (int it = 0; it < cnt; it += 64) {
-    const int idx = it + lane;
-    const unsigned e = idx < cnt ? ent[idx] : 0u;            // slot 0 with an empty mask
+    const unsigned e = e_next;
+    const int nidx = it + 64 + lane;
+    e_next = nidx < cnt ? ent[nidx] : 0u;                  // in flight during this iteration
     const int s = (int)(e >> 8);
     const float4 xj = xq[s];
     const float4 pj = pr[s];
