@@ -314,7 +314,7 @@ __global__ __launch_bounds__(256) void k_build(const LegDev* legs, BlockMap map)
             for (int ii = 0; ii < kClus; ++ii) {
               const float dx = rj3[0] - ri[ii][0], dy = rj3[1] - ri[ii][1], dz = rj3[2] - ri[ii][2];
               const float d2 = __fmaf_rn(dx, dx, __fmaf_rn(dy, dy, dz * dz));
-              if (d2 < inc2 && ai[ii] >= 0 && ai[ii] != a) mask |= 1u << ii;
+              if (d2 < inc2 && ai[ii] >= 0) mask |= 1u << ii;
             }
           } else {
 #pragma unroll
@@ -324,9 +324,11 @@ __global__ __launch_bounds__(256) void k_build(const LegDev* legs, BlockMap map)
               dy -= g.Lf[1] * rintf(dy * g.invLf[1]);
               dz -= g.Lf[2] * rintf(dz * g.invLf[2]);
               const float d2 = (dx * dx + dy * dy) + dz * dz;
-              if (d2 < inc2 && ai[ii] >= 0 && ai[ii] != a) mask |= 1u << ii;
+              if (d2 < inc2 && ai[ii] >= 0) mask |= 1u << ii;
             }
           }
+          const unsigned self = (unsigned)(s - c * kClus);       // the cluster's own atom: no i == j pair
+          if (self < (unsigned)kClus) mask &= ~(1u << self);
           if (mask && ((s_bloom[(a >> 5) & 63] >> (a & 31)) & 1u)) {   // possibly excluded
             for (int ii = 0; ii < kClus; ++ii) {
               if (!((mask >> ii) & 1u)) continue;
