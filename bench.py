@@ -19,7 +19,6 @@ the same leg for comparison.
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -40,19 +39,13 @@ FLOP_PER_PAIR = 75              # FP32 flops per in-cutoff pair (FMA = 2)
 TRAFFIC_FILE = os.path.join(ROOT, 'profiles', 'pairs_traffic_solvent20.json')
 
 
-def _src_digest():
-    h = hashlib.sha256()
-    for f in ('nonbonded.hip', 'erfc_coeffs.h', 'felis_internal.h'):
-        h.update(open(os.path.join(ROOT, 'paper_2603_22274_amd', 'csrc', f), 'rb').read())
-    return h.hexdigest()[:16]
-
-
 def _traffic():
     try:
         t = json.load(open(TRAFFIC_FILE))
     except (OSError, ValueError):
         return None
-    if t.get('kernel_digest') != _src_digest():
+    from paper_2603_22274_amd.profiling import src_digest
+    if t.get('kernel_digest') != src_digest():
         return None
     return t.get('bytes_per_launch')
 

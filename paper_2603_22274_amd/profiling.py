@@ -3,8 +3,13 @@
     python -m paper_2603_22274_amd.profiling stats <trace_dir> [n]
     python -m paper_2603_22274_amd.profiling traffic <fetch_dir> <write_dir> <kernel-substring>
     python -m paper_2603_22274_amd.profiling counters <pmc_dir> <kernel-substring> ...
+    python -m paper_2603_22274_amd.profiling profiles <gpurun_out> <profiles_dir>
 
 ``stats`` prints per-kernel call counts, average and total durations.
+``profiles`` writes the committed summaries of the pair kernel's HBM traffic
+(JSON with the digest of the kernel's sources, read by bench.py) and of the
+VALU counters of the main kernels from the four counter passes
+(pmc_A, pmc_B, pmc_FETCH_SIZE, pmc_WRITE_SIZE under <gpurun_out>).
 ``traffic`` scales the FETCH_SIZE / WRITE_SIZE counters (KiB per dispatch)
 of one kernel by what the same counters read for the largest plain device
 copy in the run (bytes actually moved / bytes counted), and prints the
@@ -13,7 +18,9 @@ per-launch HBM traffic as JSON.
 from __future__ import annotations
 
 import glob
+import hashlib
 import json
+import os
 import sqlite3
 import sys
 
@@ -82,9 +89,85 @@ def counters(pmc_dir, kernels):
     return {k: {c: sum(v) / len(v) for c, v in d.items()} for k, d in out.items()}
 
 
+_CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), 'csrc')
+PAIR_SOURCES = ('nonbonded.hip', 'erfc_coeffs.h', 'felis_internal.h')
+_BENCH = ("python -u <repo>/bench.py --steps 2 --warmup 0 --md 10 --equil 20 --no-cpu-baseline "
+          "--no-per-window --serve-legs 0 --copy-calibration")
+_PASSES = {
+    'A': 'SQ_WAVES SQ_WAVE_CYCLES SQ_BUSY_CYCLES SQ_WAIT_ANY SQ_WAIT_INST_ANY SQ_ACTIVE_INST_VALU '
+         'SQ_ACTIVE_INST_LDS SQ_ACTIVE_INST_VMEM',
+    'B': 'SQ_INSTS_VALU SQ_INSTS_SALU SQ_INSTS_LDS SQ_INSTS_VMEM_RD SQ_INSTS_VALU_FLOPS_FP32 '
+         'SQ_INSTS_VALU_TRANS_F32 SQ_THREAD_CYCLES_VALU GRBM_GUI_ACTIVE',
+    'FETCH_SIZE': 'FETCH_SIZE', 'WRITE_SIZE': 'WRITE_SIZE'}
+
+
+def src_digest():
+    """Digest of the pair kernel's sources (a stored traffic figure is valid
+    only for these)."""
+    h = hashlib.sha256()
+    for f in PAIR_SOURCES:
+        with open(os.path.join(_CSRC, f), 'rb') as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _cmd(name):
+    return (f"cd /tmp && TMPDIR=/tmp timeout -s KILL 120 rocprofv3 --pmc {_PASSES[name]} "
+            f"-d <repo>/gpurun_out/pmc_{name} -o run -- {_BENCH}")
+
+
+def write_profiles(out_dir, prof_dir, kernel='k_pairs<false>'):
+    t = traffic(os.path.join(out_dir, 'pmc_FETCH_SIZE'), os.path.join(out_dir, 'pmc_WRITE_SIZE'), kernel)
+    t['kernel_digest'] = src_digest()
+    t['commands'] = [_cmd('FETCH_SIZE'), _cmd('WRITE_SIZE'),
+                     f"python -m paper_2603_22274_amd.profiling profiles gpurun_out profiles"]
+    with open(os.path.join(prof_dir, 'pairs_traffic_solvent20.json'), 'w') as fh:
+        json.dump(t, fh, indent=1)
+    f, w, c = t['fetch_bytes_per_launch'] / 1e6, t['write_bytes_per_launch'] / 1e6, t['copy_reference']
+    txt = [f"HBM traffic of the real-space pair kernel {kernel}, 20-window solvent leg (7540 atoms), MI355X.",
+           "Two rocprofv3 --pmc passes (FETCH_SIZE, then WRITE_SIZE) of bench.py with a 256 MiB device copy at start.",
+           f"Copy reference: FETCH_SIZE {c['fetch_kib']:.0f} KiB and WRITE_SIZE {c['write_kib']:.0f} KiB for 262144 KiB "
+           f"read + 262144 KiB written -> scale {c['fetch_scale']:.3f} (fetch), {c['write_scale']:.3f} (write).",
+           f"{kernel}: FETCH_SIZE {t['fetch_kib_per_dispatch']:.1f} KiB/dispatch, WRITE_SIZE "
+           f"{t['write_kib_per_dispatch']:.1f} KiB/dispatch",
+           f"  -> {f:.1f} MB read + {w:.1f} MB written = {f + w:.1f} MB per launch ({t['dispatches'][0]} dispatches)",
+           "  (the half-cluster lists are read once; forces 20 x 7540 x 3 x 8 B = 3.6 MB are written once;",
+           "   the rest is partner coordinates and parameters re-read through L2)",
+           f"kernel source digest: {t['kernel_digest']}", "Commands:"] + t['commands']
+    with open(os.path.join(prof_dir, 'pairs_traffic_solvent20.txt'), 'w') as fh:
+        fh.write("\n".join(txt) + "\n")
+    ks = ['k_pairs<false>', 'k_build', 'k_spread', 'k_gather<false>', 'k_fft_xy<false>', 'k_fft<2, 3>',
+          'k_fft_xy<true>', 'k_integrate']
+    A = counters(os.path.join(out_dir, 'pmc_A'), ks)
+    B = counters(os.path.join(out_dir, 'pmc_B'), ks)
+    lines = ["VALU counters per dispatch, bench.py workload (20-window solvent leg, 7540 atoms), MI355X.",
+             "issue_util = SQ_INSTS_VALU / (1024 SIMDs x GRBM_GUI_ACTIVE/8 cycles / 4 cycles per wave64 instruction);",
+             "FP32 flops = SQ_INSTS_VALU_FLOPS_FP32 x 64 lanes; duration = GRBM_GUI_ACTIVE/8 at 2.4 GHz (under "
+             "counter collection).", "",
+             f"{'kernel':18s} {'us':>7s} {'VALU instr':>11s} {'issue_util':>10s} {'FP32 Gflop':>10s} {'TFLOP/s':>8s} "
+             f"{'LDS instr':>10s} {'VMEM rd':>9s} {'wait/wave-cyc':>13s}"]
+    for k in ks:
+        a, b = A.get(k, {}), B.get(k, {})
+        if not b:
+            continue
+        cyc = b['GRBM_GUI_ACTIVE'] / 8
+        us = cyc / 2400
+        fl = b['SQ_INSTS_VALU_FLOPS_FP32'] * 64
+        lines.append(f"{k:18s} {us:7.1f} {b['SQ_INSTS_VALU']:11.3g} {b['SQ_INSTS_VALU'] / (1024 * cyc / 4):10.2f} "
+                     f"{fl / 1e9:10.2f} {fl / us / 1e6:8.1f} {b['SQ_INSTS_LDS']:10.3g} {b['SQ_INSTS_VMEM_RD']:9.3g} "
+                     f"{a.get('SQ_WAIT_ANY', 0) / max(a.get('SQ_WAVE_CYCLES', 1), 1):13.2f}")
+    lines += ["", "Commands (one pass each):", _cmd('A'), _cmd('B'),
+              "python -m paper_2603_22274_amd.profiling profiles gpurun_out profiles"]
+    with open(os.path.join(prof_dir, 'valu_counters_solvent20.txt'), 'w') as fh:
+        fh.write("\n".join(lines) + "\n")
+    return t
+
+
 if __name__ == '__main__':
     if sys.argv[1] == 'stats':
         print(kernel_stats(sys.argv[2], int(sys.argv[3]) if len(sys.argv) > 3 else 25))
+    elif sys.argv[1] == 'profiles':
+        print(json.dumps(write_profiles(sys.argv[2], sys.argv[3]), indent=1))
     elif sys.argv[1] == 'counters':
         print(json.dumps(counters(sys.argv[2], sys.argv[3:]), indent=1))
     elif sys.argv[1] == 'traffic':
