@@ -83,6 +83,21 @@ def test_work_size_validation():
     leg.spline_order = 4
     leg.grid = (C.c_int32 * 3)(20, 21 * 7, 20)
     assert L.felis_leg_work_size(C.byref(leg), C.byref(n)) == felis.E_UNSUPPORTED
+    leg.grid = (C.c_int32 * 3)(20, 20, 20)
+    leg.ewald_alpha = 3.6 / 9.0             # the real-space erfc fit covers alpha r_c <= 3.5
+    assert L.felis_leg_work_size(C.byref(leg), C.byref(n)) == felis.E_UNSUPPORTED
+
+
+def test_leg_footprint_without_allocation():
+    from paper_2603_22274_amd import felis, gen
+    s0, s1 = gen.config0(), gen.config1()
+    a = felis.leg_footprint(s0)
+    b = felis.leg_footprint(s0, n_windows=2 * s0.n_windows)
+    c = felis.leg_footprint(s1)
+    # state, lists and grids scale with the windows; a larger system costs more
+    assert 0 < a < b < 2.2 * a
+    assert c > 5 * a
+    assert felis.leg_footprint(s1, list_cap=4096) > c
 
 
 def test_settle_matches_oracle_shake():
