@@ -116,15 +116,6 @@ int make_plan(felis_ctx* c, const felis_leg* L, Plan& P) {
   h.nclus = h.npad / 8;
   const double V = L->box[0] * L->box[1] * L->box[2];
   const double rl = L->r_cut + L->skin;
-  int cap = L->list_cap;
-  if (cap <= 0) {
-    const double rho = h.n / V;
-    // union of r_list spheres around a compact cluster (Hilbert-ordered
-    // clusters span a few A), with 2x room for density fluctuations
-    cap = (int)std::ceil(2.0 * rho * 4.0 / 3.0 * M_PI * std::pow(rl + 1.5, 3) + 64.0);
-  }
-  cap = std::min((cap + 7) & ~7, h.npad);
-  h.cap = std::max(cap, 8);
   h.nexcl = L->n_excl;
   h.nbonds = L->n_bonds;
   h.nwat = L->n_waters;
@@ -142,6 +133,18 @@ int make_plan(felis_ctx* c, const felis_leg* L, Plan& P) {
   nbits = std::max(1, std::min(7, nbits));
   p.nbits = nbits;
   h.ncell = 1 << (3 * nbits);
+  int cap = L->list_cap;
+  if (cap <= 0) {
+    const double rho = h.n / V;
+    // union of r_list spheres around a half-cluster: four atoms consecutive
+    // along the Hilbert curve lie within about one cell edge of their centre
+    // (cells are 2.4-4.8 A: a power-of-two split of the box), with 2x room
+    // for density fluctuations
+    const double cs = std::max(L->box[0], std::max(L->box[1], L->box[2])) / (double)(1 << nbits);
+    cap = (int)std::ceil(2.0 * rho * 4.0 / 3.0 * M_PI * std::pow(rl + cs, 3) + 64.0);
+  }
+  cap = std::min((cap + 7) & ~7, h.npad);
+  h.cap = std::max(cap, 8);
   Layout& y = p.lay;
   size_t o = 0;
   auto put = [&](size_t bytes) { size_t r = o; o += al(bytes); return r; };

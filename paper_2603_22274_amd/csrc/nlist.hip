@@ -156,6 +156,114 @@ __global__ __launch_bounds__(256) void k_cells_order(const LegDev* legs, BlockMa
     for (int s = g.n; s < g.npad; ++s) p[s] = -1;
 }
 
+// Legs whose cell grid and atom count fit in LDS run the check and the whole
+// cell sort in one block per window: Hilbert codes and per-cell counts in
+// LDS, an exclusive scan into cellstart, placement by LDS atomics, then each
+// cell's atoms in index order (the same deterministic order as the grid-wide
+// kernels above).
+constexpr int kSortCells = 4096;
+constexpr int kSortAtoms = 12288;
+
+template <bool FROM_WORD>
+__global__ __launch_bounds__(1024) void k_check_sort(const LegDev* legs, BlockMap map, int force) {
+  const int leg = find_leg(map, blockIdx.x);
+  const LegDev& g = legs[leg];
+  const int w = blockIdx.x - map.start[leg];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  __shared__ int s_cur[kSortCells];               // counts, then next free slot per cell
+  __shared__ int s_st[kSortCells + 1];
+  __shared__ unsigned short s_code[kSortAtoms];
+  __shared__ int s_perm[kSortAtoms];
+  __shared__ float s_red[16];
+  __shared__ int s_wsum[16];
+  __shared__ int s_flag;
+  const size_t o = (size_t)w * g.n;
+  float m = 0.f;
+  if (FROM_WORD) {
+    if (g.units < 64) {
+      if (tid == 0) m = __uint_as_float(g.maxdisp[w]);
+    } else {
+      const long long u0 = (long long)w * g.units, u1 = u0 + g.units;
+      for (long long q = (u0 >> 6) + tid; q <= ((u1 - 1) >> 6); q += blockDim.x) {
+        const bool first = (q * 64) / g.units == w;
+        m = fmaxf(m, __uint_as_float(g.wmax[2 * q + (first ? 0 : 1)]));
+      }
+    }
+  } else if (!force) {
+    for (int a = tid; a < g.n; a += blockDim.x) {
+      const float dx = g.x[o + a] - g.xr[o + a], dy = g.y[o + a] - g.yr[o + a], dz = g.z[o + a] - g.zr[o + a];
+      m = fmaxf(m, dx * dx + dy * dy + dz * dz);
+    }
+  }
+  for (int k = 32; k > 0; k >>= 1) m = fmaxf(m, __shfl_xor(m, k, 64));
+  if (lane == 0) s_red[wave] = m;
+  __syncthreads();
+  if (tid == 0) {
+    float r = s_red[0];
+    for (int k = 1; k < (int)(blockDim.x >> 6); ++k) r = fmaxf(r, s_red[k]);
+    const int f = (force || !(r <= g.skin_half2)) ? 1 : 0;
+    g.flag[w] = f;
+    g.nbuild[w] += f;
+    g.maxdisp[w] = 0u;
+    s_flag = f;
+  }
+  __syncthreads();
+  if (!s_flag) return;                            // uniform over the block
+
+  const int nc = g.ncell, n = g.n, nf = 1 << g.nbits;
+  for (int c = tid; c < nc; c += blockDim.x) s_cur[c] = 0;
+  __syncthreads();
+  for (int a = tid; a < n; a += blockDim.x) {
+    const float x = g.x[o + a], y = g.y[o + a], z = g.z[o + a];
+    const unsigned c = hilbert3(cell_of(x, g.Lf[0], g.invLf[0], nf), cell_of(y, g.Lf[1], g.invLf[1], nf),
+                                cell_of(z, g.Lf[2], g.invLf[2], nf), g.nbits);
+    s_code[a] = (unsigned short)c;
+    atomicAdd(&s_cur[c], 1);
+    g.xr[o + a] = x; g.yr[o + a] = y; g.zr[o + a] = z;
+  }
+  __syncthreads();
+  // exclusive scan: each thread takes a run of consecutive cells
+  const int per = (nc + (int)blockDim.x - 1) / (int)blockDim.x;
+  const int c0 = min(nc, tid * per), c1 = min(nc, c0 + per);
+  int sum = 0;
+  for (int c = c0; c < c1; ++c) sum += s_cur[c];
+  int inc = sum;
+  for (int k = 1; k < 64; k <<= 1) {
+    const int v = __shfl_up(inc, k, 64);
+    if (lane >= k) inc += v;
+  }
+  if (lane == 63) s_wsum[wave] = inc;
+  __syncthreads();
+  int run = inc - sum;
+  for (int k = 0; k < wave; ++k) run += s_wsum[k];
+  int* cst = g.cellstart + (size_t)w * (nc + 1);
+  for (int c = c0; c < c1; ++c) {
+    const int cnt = s_cur[c];
+    s_st[c] = run;
+    cst[c] = run;
+    s_cur[c] = run;
+    run += cnt;
+  }
+  if (tid == 0) { s_st[nc] = n; cst[nc] = n; }
+  __syncthreads();
+  for (int a = tid; a < n; a += blockDim.x) s_perm[atomicAdd(&s_cur[s_code[a]], 1)] = a;
+  __syncthreads();
+  for (int c = tid; c < nc; c += blockDim.x) {    // index order within each cell
+    const int b0 = s_st[c], b1 = s_st[c + 1];
+    for (int q = b0 + 1; q < b1; ++q) {
+      const int v = s_perm[q];
+      int t = q - 1;
+      while (t >= b0 && s_perm[t] > v) { s_perm[t + 1] = s_perm[t]; --t; }
+      s_perm[t + 1] = v;
+    }
+  }
+  __syncthreads();
+  int* p = g.perm + (size_t)w * g.npad;
+  for (int q = tid; q < g.npad; q += blockDim.x) p[q] = q < n ? s_perm[q] : -1;
+}
+
+bool sort_in_lds(const LegHost& h) { return h.ncell <= kSortCells && h.n <= kSortAtoms; }
+
 // One block per cluster: sweep the coarse blocks (aligned 2x2x2 fine cells)
 // within r_list of the cluster's box, 256 blocks per round, and list every
 // atom j with at least one i of the cluster in range.  The four waves take
@@ -246,6 +354,17 @@ __global__ __launch_bounds__(256) void k_build(const LegDev* legs, BlockMap map)
   // nearest image for every i whenever extent + r_list + margin < L/2
   const bool shift = ext[0] + incl + 0.02f < 0.5f * g.Lf[0] && ext[1] + incl + 0.02f < 0.5f * g.Lf[1] &&
                      ext[2] + incl + 0.02f < 0.5f * g.Lf[2];
+  // i-side terms of |r_j - r_i|^2 = |r_j|^2 - 2 r_i.r_j + |r_i|^2 in the
+  // shifted frame (|r| < 25 A there, so the FP32 error of the expanded form
+  // stays below 1e-3 A^2, far inside the 0.01 A margin); a padding slot gets
+  // |r_i|^2 = 1e30 and never passes
+  float m2[kClus][3], c2[kClus];
+#pragma unroll
+  for (int ii = 0; ii < kClus; ++ii) {
+    for (int d = 0; d < 3; ++d) m2[ii][d] = -2.0f * ri[ii][d];
+    c2[ii] = ai[ii] >= 0 ? __fmaf_rn(ri[ii][0], ri[ii][0], __fmaf_rn(ri[ii][1], ri[ii][1], ri[ii][2] * ri[ii][2]))
+                         : 1.0e30f;
+  }
   const int* cst = g.cellstart + (size_t)w * (g.ncell + 1);
   unsigned* outL = g.lent + (size_t)item * 2 * g.cap;      // partners of atoms 0-3
   unsigned* outH = outL + g.cap;                            // partners of atoms 4-7
@@ -310,11 +429,11 @@ __global__ __launch_bounds__(256) void k_build(const LegDev* legs, BlockMap map)
               const float v = xj[d] - xi[0][d];
               rj3[d] = __fmaf_rn(-g.Lf[d], rintf(v * g.invLf[d]), v);
             }
+            const float thr = inc2 - __fmaf_rn(rj3[0], rj3[0], __fmaf_rn(rj3[1], rj3[1], rj3[2] * rj3[2]));
 #pragma unroll
-            for (int ii = 0; ii < kClus; ++ii) {
-              const float dx = rj3[0] - ri[ii][0], dy = rj3[1] - ri[ii][1], dz = rj3[2] - ri[ii][2];
-              const float d2 = __fmaf_rn(dx, dx, __fmaf_rn(dy, dy, dz * dz));
-              if (d2 < inc2 && ai[ii] >= 0) mask |= 1u << ii;
+            for (int ii = kClus - 1; ii >= 0; --ii) {        // bit ii ends at position ii
+              const float q = __fmaf_rn(m2[ii][0], rj3[0], __fmaf_rn(m2[ii][1], rj3[1], __fmaf_rn(m2[ii][2], rj3[2], c2[ii])));
+              mask = 2u * mask + (q < thr ? 1u : 0u);
             }
           } else {
 #pragma unroll
@@ -418,21 +537,30 @@ inline int blocks_for(long long items, int per) { return (int)((items + per - 1)
 
 void launch_check(hipStream_t s, const LegDev* d, const LegHost* h, int nl, int force, bool from_word) {
   BlockMap m;
-  const int nb = make_map(m, nl, [&](int i) { return h[i].W; });
-  if (!nb) return;
-  if (from_word) hipLaunchKernelGGL(k_check<true>, dim3(nb), dim3(256), 0, s, d, m, force);
-  else hipLaunchKernelGGL(k_check<false>, dim3(nb), dim3(256), 0, s, d, m, force);
+  int nb = make_map(m, nl, [&](int i) { return sort_in_lds(h[i]) ? 0 : h[i].W; });
+  if (nb) {
+    if (from_word) hipLaunchKernelGGL(k_check<true>, dim3(nb), dim3(256), 0, s, d, m, force);
+    else hipLaunchKernelGGL(k_check<false>, dim3(nb), dim3(256), 0, s, d, m, force);
+  }
+  // small legs: the check and the whole cell sort in one launch
+  nb = make_map(m, nl, [&](int i) { return sort_in_lds(h[i]) ? h[i].W : 0; });
+  if (nb) {
+    if (from_word) hipLaunchKernelGGL(k_check_sort<true>, dim3(nb), dim3(1024), 0, s, d, m, force);
+    else hipLaunchKernelGGL(k_check_sort<false>, dim3(nb), dim3(1024), 0, s, d, m, force);
+  }
 }
 
 void launch_build(hipStream_t s, const LegDev* d, const LegHost* h, int nl) {
   BlockMap m;
-  int nb = make_map(m, nl, [&](int i) { return blocks_for((long long)h[i].W * h[i].n, 256); });
+  // grid-wide cell sort for the legs that launch_check did not sort
+  auto big = [&](int i) { return !sort_in_lds(h[i]); };
+  int nb = make_map(m, nl, [&](int i) { return big(i) ? blocks_for((long long)h[i].W * h[i].n, 256) : 0; });
   if (nb) hipLaunchKernelGGL(k_cells_count, dim3(nb), dim3(256), 0, s, d, m);
-  nb = make_map(m, nl, [&](int i) { return h[i].W; });
+  nb = make_map(m, nl, [&](int i) { return big(i) ? h[i].W : 0; });
   if (nb) hipLaunchKernelGGL(k_cells_scan, dim3(nb), dim3(1024), 0, s, d, m);
-  nb = make_map(m, nl, [&](int i) { return blocks_for((long long)h[i].W * h[i].n, 256); });
+  nb = make_map(m, nl, [&](int i) { return big(i) ? blocks_for((long long)h[i].W * h[i].n, 256) : 0; });
   if (nb) hipLaunchKernelGGL(k_cells_scatter, dim3(nb), dim3(256), 0, s, d, m);
-  nb = make_map(m, nl, [&](int i) { return blocks_for((long long)h[i].W * h[i].ncell, 256); });
+  nb = make_map(m, nl, [&](int i) { return big(i) ? blocks_for((long long)h[i].W * h[i].ncell, 256) : 0; });
   if (nb) hipLaunchKernelGGL(k_cells_order, dim3(nb), dim3(256), 0, s, d, m);
   // sorted coordinates every step; sorted parameters and cluster boxes for
   // the windows being rebuilt

@@ -22,16 +22,6 @@
 namespace felis {
 namespace {
 
-__device__ __forceinline__ float erfc_fit(float x, float* ex) {
-  const float t = __builtin_amdgcn_rcpf(fmaf(FELIS_ERFC_P, x, 1.0f));
-  float p = felis_erfc_c[0];
-#pragma unroll
-  for (int k = 1; k < FELIS_ERFC_NC; ++k) p = fmaf(p, t, felis_erfc_c[k]);
-  const float e = __expf(-x * x);
-  *ex = e;
-  return p * t * e;
-}
-
 // items: window x slot -- current coordinates and scaled charges in sorted
 // order.  REBUILD (inside a list build): for windows being rebuilt also the
 // sorted per-slot parameters and each 8-slot cluster's bounding box of
@@ -107,6 +97,8 @@ __device__ __forceinline__ void sweep(const LegDev& g, const ICluster& I, const 
   const float iLx = g.invLf[0], iLy = g.invLf[1], iLz = g.invLf[2];
   const float rc2 = g.rc2, alpha = g.alpha;
   const float c2a = 2.0f * alpha * 0.56418958354775628f;   // 2 alpha / sqrt(pi)
+  const float pa = FELIS_ERFC_P * alpha;                    // fit variable t = 1 / (1 + P alpha r)
+  const float kx2 = -alpha * alpha * 1.4426950408889634f;   // exp(-alpha^2 r^2) = 2^(kx2 r^2)
   unsigned e_next = lane < cnt ? ent[lane] : 0u;          // slot 0 with an empty mask
   for (int it = 0; it < cnt; it += 64) {
     const unsigned e = e_next;
@@ -121,6 +113,8 @@ __device__ __forceinline__ void sweep(const LegDev& g, const ICluster& I, const 
       jy = fmaf(-Ly, rintf((jy - I.y[0]) * iLy), jy);
       jz = fmaf(-Lz, rintf((jz - I.z[0]) * iLz), jz);
     }
+    // wave-uniform: does any listed j of this step belong to the ligand?
+    const bool jlig = soft_window && __ballot(pj.z > 0.0f) != 0ull;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       const int ii = 4 * HALF + k;
@@ -136,16 +130,23 @@ __device__ __forceinline__ void sweep(const LegDev& g, const ICluster& I, const 
       const float rinv = __builtin_amdgcn_rsqf(r2s);
       const float rinv2 = rinv * rinv;
       const float r = r2s * rinv;
-      float ex;
-      const float erfcv = erfc_fit(alpha * r, &ex);
+      // erfc(alpha r) = t P(t) exp(-alpha^2 r^2), t = 1 / (1 + P alpha r): the
+      // degree-6 fit of erfc_coeffs.h with alpha folded into its constants
+      const float t = __builtin_amdgcn_rcpf(fmaf(pa, r, 1.0f));
+      float pt = felis_erfc_c[0];
+#pragma unroll
+      for (int c = 1; c < FELIS_ERFC_NC; ++c) pt = fmaf(pt, t, felis_erfc_c[c]);
+      pt *= t;
+      const float ex = __builtin_amdgcn_exp2f(kx2 * r2s);
       const float qq = I.q[ii] * xj.w;
-      const float fc = qq * fmaf(erfcv, rinv, c2a * ex) * rinv2;
+      const float fc = qq * (ex * fmaf(pt, rinv, c2a)) * rinv2;
       float flj = 0.0f, elj = 0.0f;
       if (I.eps[ii] == 0.0f) {
         // wave-uniform: an i-atom without LJ (a water hydrogen) contributes
         // exactly zero LJ force and energy with every partner
       } else if (const float sig = I.sig[ii] + pj.x, eps4 = I.eps[ii] * pj.y;
-                 soft_window && __ballot(in && (I.lig[ii] + pj.z) > 0.0f) != 0ull) {
+                 (jlig || (soft_window && I.lig[ii] > 0.0f)) &&
+                 __ballot(in && (I.lig[ii] + pj.z) > 0.0f) != 0ull) {
         const bool ligp = (I.lig[ii] + pj.z) > 0.0f;
         const float lam = ligp ? lam_v : 1.0f;
         const float a = ligp ? a_sc : 0.0f;
@@ -169,7 +170,7 @@ __device__ __forceinline__ void sweep(const LegDev& g, const ICluster& I, const 
       fy[k] = fmaf(-fs, dy, fy[k]);
       fz[k] = fmaf(-fs, dz, fz[k]);
       if (ENERGY && in) {
-        ec += (double)(qq * erfcv * rinv);
+        ec += (double)(qq * (pt * ex) * rinv);
         el += (double)elj;
       }
     }
@@ -220,7 +221,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
   // each half's forces are reduced over the wave before the next half
   const unsigned* __restrict__ ent = g.lent + (size_t)item * 2 * g.cap;
   double ec = 0.0, el = 0.0;
-  float ox = 0.f, oy = 0.f, oz = 0.f;                 // lane ii < 8 ends with atom ii's pair force
+  __shared__ float s_f[4][kClus][3];                  // per wave: the 8 atoms' pair forces
 #pragma unroll
   for (int half = 0; half < 2; ++half) {
     float fx[4] = {0.f, 0.f, 0.f, 0.f}, fy[4] = {0.f, 0.f, 0.f, 0.f}, fz[4] = {0.f, 0.f, 0.f, 0.f};
@@ -236,9 +237,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       const float sx = wave_sum(fx[k]), sy = wave_sum(fy[k]), sz = wave_sum(fz[k]);
-      if (lane == 4 * half + k) { ox = sx; oy = sy; oz = sz; }
+      if (lane == 0) {
+        s_f[wave][4 * half + k][0] = sx;
+        s_f[wave][4 * half + k][1] = sy;
+        s_f[wave][4 * half + k][2] = sz;
+      }
     }
   }
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  __builtin_amdgcn_wave_barrier();
 
   // Excluded pairs: remove their reciprocal-space (erf) interaction, each
   // pair from both of its sides; lane = ii + 8 k takes the k-th exclusion of
@@ -277,7 +284,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
     cy += __shfl_xor(cy, o, 64);
     cz += __shfl_xor(cz, o, 64);
   }
-  ox += cx; oy += cy; oz += cz;
+  float ox = cx, oy = cy, oz = cz;
+  if (lane < kClus) { ox += s_f[wave][lane][0]; oy += s_f[wave][lane][1]; oz += s_f[wave][lane][2]; }
   if (lane < kClus) {
     const int a = ai;
     if (a >= 0) {

@@ -34,6 +34,21 @@ __device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(
 __device__ __forceinline__ float2 mul_mi(float2 a) { return make_float2(a.y, -a.x); }   // a * (-i)
 __device__ __forceinline__ float2 conj2(float2 a) { return make_float2(a.x, -a.y); }
 
+// Quotient and remainder of 0 <= x < 2^22 by a block-uniform d >= 1 through a
+// float reciprocal: the estimate is within 0.75 of x / d, so one correction
+// in either direction makes it exact.
+struct FastDiv {
+  int d;
+  float inv;
+  __device__ explicit FastDiv(int d_) : d(d_), inv(1.0f / (float)d_) {}
+  __device__ __forceinline__ int div(int x) const {
+    int q = (int)((float)x * inv);               // >= 0
+    const int r = x - (int)__umul24((unsigned)q, (unsigned)d);
+    q += (r < 0) ? -1 : (r >= d ? 1 : 0);
+    return q;
+  }
+};
+
 // forward DFT (sign -1) of size R in place
 template <int R>
 __device__ __forceinline__ void dft(float2* v) {
@@ -70,30 +85,33 @@ __device__ __forceinline__ void dft(float2* v) {
 
 // One Stockham stage of radix R over kLines lines (buf[e * kLines + b]).
 template <int R>
-__device__ __forceinline__ void stage(const float2* src, float2* dst, int n, int Ns,
-                                      const float2* __restrict__ tw) {
+__device__ __forceinline__ void stage(const float2* src, float2* dst, int n, int Ns, const float2* tw) {
   const int nR = n / R;
   const int step = n / (Ns * R);
+  const int s_in = nR * kLines, s_out = Ns * kLines;
+  const FastDiv dNs(Ns);
   for (int t = threadIdx.x; t < nR * kLines; t += blockDim.x) {
-    const int j = t / kLines, b = t - j * kLines;
-    const int k = j % Ns;
+    // element j = t / kLines of line b = t % kLines; j = jq Ns + k
+    const int j = t / kLines;
+    const int jq = dNs.div(j);
+    const int k = j - (int)__umul24((unsigned)jq, (unsigned)Ns);
+    const int tk = (int)__umul24((unsigned)k, (unsigned)step);
     float2 v[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      v[r] = src[(j + r * nR) * kLines + b];
-      if (r) v[r] = cmul(v[r], tw[r * k * step]);       // r k step < n
+      v[r] = src[t + r * s_in];                        // element j + r nR
+      if (r) v[r] = cmul(v[r], tw[r * tk]);            // r k step < n
     }
     dft<R>(v);
-    const int o = (j / Ns) * Ns * R + k;
+    const int o = t + (int)__umul24((unsigned)jq, (unsigned)((R - 1) * s_out));   // element jq Ns R + k
 #pragma unroll
-    for (int r = 0; r < R; ++r) dst[(o + r * Ns) * kLines + b] = v[r];
+    for (int r = 0; r < R; ++r) dst[o + r * s_out] = v[r];
   }
 }
 
 // Forward transform of kLines lines of length n held in src[e * kLines + b];
 // returns the buffer that holds the result.
-__device__ float2* fft_lines(float2* src, float2* dst, int n, const int* rad, int nrad,
-                             const float2* __restrict__ tw) {
+__device__ __forceinline__ float2* fft_lines(float2* src, float2* dst, int n, const int* rad, int nrad, const float2* tw) {
   int Ns = 1;
   for (int st = 0; st < nrad; ++st) {
     const int R = rad[st];
@@ -127,9 +145,12 @@ __global__ __launch_bounds__(256) void k_fft(const LegDev* legs, BlockMap map) {
   const int rem = bl - p * outer * nch;
   const int o = rem / nch, ch = rem - (rem / nch) * nch;
   if (p >= g.npair) return;
-  extern __shared__ float2 smem[];               // two buffers of n * kLines (sized at launch)
+  extern __shared__ float2 smem[];               // two buffers of n * kLines, then n twiddles
   float2* bufA = smem;
   float2* bufB = smem + (size_t)n * kLines;
+  float2* tw = bufB + (size_t)n * kLines;
+  for (int e = threadIdx.x; e < n; e += blockDim.x) tw[e] = g.tw[AXIS][e];
+  const FastDiv dn(n);
   float2* cg = g.cgrid + (size_t)p * g.Ktot;
   const int KxKy = Kx * Ky;
   auto offs = [&](int e, int b) -> long long {
@@ -141,7 +162,7 @@ __global__ __launch_bounds__(256) void k_fft(const LegDev* legs, BlockMap map) {
   };
   for (int idx = threadIdx.x; idx < n * kLines; idx += blockDim.x) {
     int e, b;
-    if (AXIS == 0) { b = idx / n; e = idx - b * n; } else { e = idx / kLines; b = idx - e * kLines; }
+    if (AXIS == 0) { b = dn.div(idx); e = idx - b * n; } else { e = idx / kLines; b = idx - e * kLines; }
     const long long off = offs(e, b);
     float2 v = make_float2(0.f, 0.f);
     if (off >= 0) {
@@ -161,7 +182,6 @@ __global__ __launch_bounds__(256) void k_fft(const LegDev* legs, BlockMap map) {
     bufA[e * kLines + b] = v;
   }
   __syncthreads();
-  const float2* tw = g.tw[AXIS];
   float2* res = fft_lines(bufA, bufB, n, g.rad[AXIS], g.nrad[AXIS], tw);
   if (MODE == 3) {
     // multiply by G(kx, ky, kz): element e = kz of line (ky = o, kx = ch*kLines + b)
@@ -188,7 +208,7 @@ __global__ __launch_bounds__(256) void k_fft(const LegDev* legs, BlockMap map) {
   }
   for (int idx = threadIdx.x; idx < n * kLines; idx += blockDim.x) {
     int e, b;
-    if (AXIS == 0) { b = idx / n; e = idx - b * n; } else { e = idx / kLines; b = idx - e * kLines; }
+    if (AXIS == 0) { b = dn.div(idx); e = idx - b * n; } else { e = idx / kLines; b = idx - e * kLines; }
     const long long off = offs(e, b);
     if (off < 0) continue;
     float2 v = res[e * kLines + b];
@@ -199,36 +219,42 @@ __global__ __launch_bounds__(256) void k_fft(const LegDev* legs, BlockMap map) {
 
 // One Stockham stage of radix R over nl lines held as buf[e * nl + b].
 template <int R>
-__device__ __forceinline__ void stage_nl(const float2* src, float2* dst, int n, int Ns, int nl,
-                                         const float2* __restrict__ tw) {
+__device__ __forceinline__ void stage_nl(const float2* src, float2* dst, int n, int Ns, const FastDiv& dnl,
+                                         const float2* tw) {
+  const int nl = dnl.d;
   const int nR = n / R;
   const int step = n / (Ns * R);
+  const int s_in = nR * nl, s_out = Ns * nl;
+  const FastDiv dNs(Ns);
   for (int t = threadIdx.x; t < nR * nl; t += blockDim.x) {
-    const int j = t / nl, b = t - j * nl;
-    const int k = j % Ns;
+    // element j = t / nl of line t % nl; j = jq Ns + k
+    const int j = dnl.div(t);
+    const int jq = dNs.div(j);
+    const int k = j - (int)__umul24((unsigned)jq, (unsigned)Ns);
+    const int tk = (int)__umul24((unsigned)k, (unsigned)step);
     float2 v[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      v[r] = src[(j + r * nR) * nl + b];
-      if (r) v[r] = cmul(v[r], tw[r * k * step]);
+      v[r] = src[t + r * s_in];
+      if (r) v[r] = cmul(v[r], tw[r * tk]);
     }
     dft<R>(v);
-    const int o = (j / Ns) * Ns * R + k;
+    const int o = t + (int)__umul24((unsigned)jq, (unsigned)((R - 1) * s_out));
 #pragma unroll
-    for (int r = 0; r < R; ++r) dst[(o + r * Ns) * nl + b] = v[r];
+    for (int r = 0; r < R; ++r) dst[o + r * s_out] = v[r];
   }
 }
 
-__device__ float2* fft_lines_nl(float2* src, float2* dst, int n, int nl, const int* rad, int nrad,
-                                const float2* __restrict__ tw) {
+__device__ __forceinline__ float2* fft_lines_nl(float2* src, float2* dst, int n, const FastDiv& dnl, const int* rad, int nrad,
+                                const float2* tw) {
   int Ns = 1;
   for (int st = 0; st < nrad; ++st) {
     const int R = rad[st];
     switch (R) {
-      case 2: stage_nl<2>(src, dst, n, Ns, nl, tw); break;
-      case 3: stage_nl<3>(src, dst, n, Ns, nl, tw); break;
-      case 4: stage_nl<4>(src, dst, n, Ns, nl, tw); break;
-      default: stage_nl<5>(src, dst, n, Ns, nl, tw); break;
+      case 2: stage_nl<2>(src, dst, n, Ns, dnl, tw); break;
+      case 3: stage_nl<3>(src, dst, n, Ns, dnl, tw); break;
+      case 4: stage_nl<4>(src, dst, n, Ns, dnl, tw); break;
+      default: stage_nl<5>(src, dst, n, Ns, dnl, tw); break;
     }
     __syncthreads();
     float2* t = src; src = dst; dst = t;
@@ -249,26 +275,31 @@ __global__ __launch_bounds__(256) void k_fft_xy(const LegDev* legs, BlockMap map
   const int bl = blockIdx.x - map.start[leg];
   const int p = bl / Kz, z = bl - p * Kz;
   if (p >= g.npair) return;
-  extern __shared__ float2 smem[];
-  float2* A = smem;
-  float2* B = smem + (size_t)Kx * Ky;
-  float2* cg = g.cgrid + (size_t)p * g.Ktot + (size_t)z * Kx * Ky;
+  extern __shared__ float2 smem[];                // A, B: one plane each; then the x and y twiddles
   const int np = Kx * Ky;
+  float2* A = smem;
+  float2* B = smem + np;
+  float2* twx = B + np;
+  float2* twy = twx + Kx;
+  float2* cg = g.cgrid + (size_t)p * g.Ktot + (size_t)z * np;
+  const FastDiv dKx(Kx), dKy(Ky);
+  for (int e = threadIdx.x; e < Kx; e += blockDim.x) twx[e] = g.tw[0][e];
+  for (int e = threadIdx.x; e < Ky; e += blockDim.x) twy[e] = g.tw[1][e];
   for (int idx = threadIdx.x; idx < np; idx += blockDim.x) {       // [x][y]: lines along x
-    const int y = idx / Kx, x = idx - y * Kx;
+    const int y = dKx.div(idx), x = idx - y * Kx;
     float2 v = cg[idx];
     if (INVERSE) v = conj2(v);
     A[x * Ky + y] = v;
   }
   __syncthreads();
-  float2* r = fft_lines_nl(A, B, Kx, Ky, g.rad[0], g.nrad[0], g.tw[0]);
+  float2* r = fft_lines_nl(A, B, Kx, dKy, g.rad[0], g.nrad[0], twx);
   float2* o = (r == A) ? B : A;
   for (int idx = threadIdx.x; idx < np; idx += blockDim.x) {       // -> [y][x]: lines along y
-    const int x = idx / Ky, y = idx - x * Ky;
+    const int x = dKy.div(idx), y = idx - x * Ky;
     o[y * Kx + x] = r[idx];
   }
   __syncthreads();
-  r = fft_lines_nl(o, r, Ky, Kx, g.rad[1], g.nrad[1], g.tw[1]);
+  r = fft_lines_nl(o, r, Ky, dKx, g.rad[1], g.nrad[1], twy);
   for (int idx = threadIdx.x; idx < np; idx += blockDim.x) {
     float2 v = r[idx];                                              // [y][x] = grid order
     if (INVERSE) v = conj2(v);
@@ -305,6 +336,7 @@ __device__ __forceinline__ int grid_base(float x, double invL, int K, float* f) 
 }
 
 constexpr int kBrick = 8;                      // brick edge in grid points
+constexpr int kSpreadCellOf = 2048;            // candidates per table window in spreading
 
 // Grid points of axis d that an atom with base index b touches, as a 4-bit
 // mask over the stencil offsets (point b - k, k = 0..3, periodic) that fall in
@@ -320,14 +352,16 @@ __device__ __forceinline__ unsigned brick_mask(int b, int K, int P0, int P1) {
   return m;
 }
 
-// One block per (window pair, 8x8x8 brick of grid points): the block owns
-// its brick.  Candidate atoms come from the fine cells of each window's
-// last list build that can hold an atom whose stencil reaches the brick (the
-// brick's extent plus 3 grid spacings on the upper side, widened by skin/2
-// for the drift since that build); each contributing atom adds its stencil
-// points inside the brick to an int64 fixed-point tile in LDS (integer sums:
-// the tile does not depend on the order of the adds), and the block writes
-// its brick of the complex grid Z = Q_a + i Q_b once, with plain stores.
+// One block per (window, 8x8x8 brick of grid points): the block owns its
+// window's component of the brick (the real part of the pair's complex grid
+// for the even window, the imaginary part for the odd one).  Candidate atoms
+// come from the fine cells of the window's last list build that can hold an
+// atom whose stencil reaches the brick (the brick's extent plus 3 grid
+// spacings on the upper side, widened by skin/2 for the drift since that
+// build); each contributing atom adds its stencil points inside the brick to
+// an int64 fixed-point tile in LDS (integer sums: the tile does not depend on
+// the order of the adds), and the block writes its component of the brick
+// once, with plain stores.
 __global__ __launch_bounds__(256) void k_spread(const LegDev* legs, BlockMap map) {
   const int leg = find_leg(map, blockIdx.x);
   const LegDev& g = legs[leg];
@@ -336,21 +370,22 @@ __global__ __launch_bounds__(256) void k_spread(const LegDev* legs, BlockMap map
   const int nbz = (g.K[2] + kBrick - 1) / kBrick;
   const int bl = blockIdx.x - map.start[leg];
   const int per = nbx * nby * nbz;
-  const int p = bl / per;
-  int r = bl - p * per;
+  const int w = bl / per;
+  int r = bl - w * per;
   const int bz = r / (nbx * nby);
   r -= bz * nbx * nby;
   const int by = r / nbx, bx = r - by * nbx;
   const int P0[3] = {bx * kBrick, by * kBrick, bz * kBrick};
   const int P1[3] = {min(P0[0] + kBrick, g.K[0]), min(P0[1] + kBrick, g.K[1]), min(P0[2] + kBrick, g.K[2])};
 
-  __shared__ long long tile[2][kBrick * kBrick * kBrick];
+  __shared__ long long tile[kBrick * kBrick * kBrick];
   __shared__ int s_start[256], s_pre[256], s_wsum[4];
+  __shared__ unsigned char s_cellof[kSpreadCellOf];   // candidate -> cell of the round
   __shared__ int s_n;
   __shared__ float s_q[256], s_w[256][12];
   __shared__ int s_b[256][3];
   __shared__ unsigned s_m[256];
-  for (int e = tid; e < 2 * kBrick * kBrick * kBrick; e += 256) (&tile[0][0])[e] = 0;
+  for (int e = tid; e < kBrick * kBrick * kBrick; e += 256) tile[e] = 0;
   if (tid == 0) s_n = 0;
 
   // candidate fine cells per axis
@@ -367,47 +402,46 @@ __global__ __launch_bounds__(256) void k_spread(const LegDev* legs, BlockMap map
   }
   const int ncells = nspan[0] * nspan[1] * nspan[2];
   const int wave = tid >> 6, lane = tid & 63;
+  const int* cst = g.cellstart + (size_t)w * (g.ncell + 1);
+  const float4* __restrict__ xq = g.xyzq + (size_t)w * g.npad;
+  const float4* __restrict__ pr = g.prm + (size_t)w * g.npad;
+  const float le = g.lam[4 * w];
   __syncthreads();
-  for (int half = 0; half < 2; ++half) {
-    const int w = 2 * p + half;
-    if (w >= g.W) break;                         // uniform: odd window count, imaginary part stays 0
-    const int* cst = g.cellstart + (size_t)w * (g.ncell + 1);
-    const int* perm = g.perm + (size_t)w * g.npad;
-    const float4* __restrict__ xq = g.xyzq + (size_t)w * g.npad;
-    const float le = g.lam[4 * w];
-    long long* T = tile[half];
-    for (int cb = 0; cb < ncells; cb += 256) {
-      const int ci = cb + tid;
-      int s0 = 0, cnt = 0;
-      if (ci < ncells) {
-        const int C[3] = {c0[0] + ci / (nspan[1] * nspan[2]), c0[1] + (ci / nspan[2]) % nspan[1],
-                          c0[2] + ci % nspan[2]};
-        const unsigned cc = hilbert3((unsigned)((C[0] % nc + nc) % nc), (unsigned)((C[1] % nc + nc) % nc),
-                                     (unsigned)((C[2] % nc + nc) % nc), g.nbits);
-        s0 = cst[cc];
-        cnt = cst[cc + 1] - s0;
+  for (int cb = 0; cb < ncells; cb += 256) {
+    const int ci = cb + tid;
+    int s0 = 0, cnt = 0;
+    if (ci < ncells) {
+      const int C[3] = {c0[0] + ci / (nspan[1] * nspan[2]), c0[1] + (ci / nspan[2]) % nspan[1],
+                        c0[2] + ci % nspan[2]};
+      const unsigned cc = hilbert3((unsigned)((C[0] % nc + nc) % nc), (unsigned)((C[1] % nc + nc) % nc),
+                                   (unsigned)((C[2] % nc + nc) % nc), g.nbits);
+      s0 = cst[cc];
+      cnt = cst[cc + 1] - s0;
+    }
+    int inc = cnt;
+    for (int k = 1; k < 64; k <<= 1) {
+      const int v = __shfl_up(inc, k, 64);
+      if (lane >= k) inc += v;
+    }
+    if (lane == 63) s_wsum[wave] = inc;
+    s_start[tid] = s0;
+    __syncthreads();
+    int woff = 0;
+    for (int k = 0; k < wave; ++k) woff += s_wsum[k];
+    const int total = s_wsum[0] + s_wsum[1] + s_wsum[2] + s_wsum[3];
+    const int pre_t = woff + inc - cnt;
+    s_pre[tid] = pre_t;
+    for (int T0 = 0; T0 < total; T0 += kSpreadCellOf) {
+      {
+        const int b0 = max(pre_t, T0), b1 = min(pre_t + cnt, T0 + kSpreadCellOf);
+        for (int q = b0; q < b1; ++q) s_cellof[q - T0] = (unsigned char)tid;
       }
-      int inc = cnt;
-      for (int k = 1; k < 64; k <<= 1) {
-        const int v = __shfl_up(inc, k, 64);
-        if (lane >= k) inc += v;
-      }
-      if (lane == 63) s_wsum[wave] = inc;
-      s_start[tid] = s0;
       __syncthreads();
-      int woff = 0;
-      for (int k = 0; k < wave; ++k) woff += s_wsum[k];
-      const int total = s_wsum[0] + s_wsum[1] + s_wsum[2] + s_wsum[3];
-      s_pre[tid] = woff + inc - cnt;
-      __syncthreads();
-      for (int t0 = 0; t0 < total; t0 += 256) {
+      const int T1 = min(total, T0 + kSpreadCellOf);
+      for (int t0 = T0; t0 < T1; t0 += 256) {
         const int t = t0 + tid;
-        if (t < total) {
-          int l = 0, hh = 255;                    // last cell with prefix <= t
-          while (l < hh) {
-            const int mid = (l + hh + 1) >> 1;
-            if (s_pre[mid] <= t) l = mid; else hh = mid - 1;
-          }
+        if (t < T1) {
+          const int l = s_cellof[t - T0];
           const int s = s_start[l] + (t - s_pre[l]);
           const float4 rj = xq[s];
           float fr[3];
@@ -418,9 +452,9 @@ __global__ __launch_bounds__(256) void k_spread(const LegDev* legs, BlockMap map
           const unsigned my = brick_mask(b1, g.K[1], P0[1], P1[1]);
           const unsigned mz = brick_mask(b2, g.K[2], P0[2], P1[2]);
           if (mx && my && mz) {
-            const int a = perm[s];
+            const float4 pa = pr[s];                 // sorted parameters: .z ligand flag, .w charge
             const int k = atomicAdd(&s_n, 1);
-            s_q[k] = g.q[a] * (g.lig[a] ? le : 1.0f);
+            s_q[k] = pa.w * (pa.z > 0.0f ? le : 1.0f);
             bspline4(fr[0], &s_w[k][0], nullptr);
             bspline4(fr[1], &s_w[k][4], nullptr);
             bspline4(fr[2], &s_w[k][8], nullptr);
@@ -443,7 +477,7 @@ __global__ __launch_bounds__(256) void k_spread(const LegDev* legs, BlockMap map
             if (!((m >> (8 + iz)) & 1u)) continue;
             int pz = s_b[k][2] - iz; if (pz < 0) pz += g.K[2];
             const long long v = __double2ll_rn(qxy * (double)s_w[k][8 + iz] * kGridScale);
-            atomicAdd((unsigned long long*)&T[(pz - P0[2]) * kBrick * kBrick + row], (unsigned long long)v);
+            atomicAdd((unsigned long long*)&tile[(pz - P0[2]) * kBrick * kBrick + row], (unsigned long long)v);
           }
         }
         __syncthreads();
@@ -451,14 +485,20 @@ __global__ __launch_bounds__(256) void k_spread(const LegDev* legs, BlockMap map
         __syncthreads();
       }
     }
+    __syncthreads();                              // the round's tables are rewritten next
   }
-  float2* cg = g.cgrid + (size_t)p * g.Ktot;
+  // this window's component of the pair's complex grid; an unpaired last
+  // window also clears the imaginary part
+  float* cg = reinterpret_cast<float*>(g.cgrid + (size_t)(w >> 1) * g.Ktot);
+  const int comp = w & 1;
+  const bool clear_im = comp == 0 && w + 1 >= g.W;
   for (int e = tid; e < kBrick * kBrick * kBrick; e += 256) {
     const int lx = e % kBrick, ly = (e / kBrick) % kBrick, lz = e / (kBrick * kBrick);
     const int x = P0[0] + lx, y = P0[1] + ly, z = P0[2] + lz;
     if (x >= P1[0] || y >= P1[1] || z >= P1[2]) continue;
-    cg[((size_t)z * g.K[1] + y) * g.K[0] + x] =
-        make_float2((float)((double)tile[0][e] * (1.0 / kGridScale)), (float)((double)tile[1][e] * (1.0 / kGridScale)));
+    const size_t off = ((size_t)z * g.K[1] + y) * g.K[0] + x;
+    cg[2 * off + comp] = (float)((double)tile[e] * (1.0 / kGridScale));
+    if (clear_im) cg[2 * off + 1] = 0.f;
   }
 }
 
@@ -468,16 +508,17 @@ __global__ __launch_bounds__(256) void k_gather(const LegDev* legs, BlockMap map
   const LegDev& g = legs[leg];
   // atoms in the neighbour-list sort order (spatially coherent); 4 lanes per
   // atom, lane iz sums the 16 stencil points of plane z = bz - iz
-  const long long local = (long long)(blockIdx.x - map.start[leg]) * 64 + (threadIdx.x >> 2);
-  const long long tot = (long long)g.W * g.npad;
-  const long long lc = local < tot ? local : tot - 1;
-  const int w = (int)(lc / g.npad);
+  const int local = (blockIdx.x - map.start[leg]) * 64 + (threadIdx.x >> 2);   // W N_pad < 2^31
+  const int tot = g.W * g.npad;
+  const int lc = local < tot ? local : tot - 1;
+  const int w = lc / g.npad;
   const int ap = g.perm[lc];
   const bool valid = local < tot && ap >= 0;
   const int a = ap >= 0 ? ap : 0;
   const int iz = threadIdx.x & 3;
   const size_t o = (size_t)w * g.n + a;
-  const float q = g.q[a] * (g.lig[a] ? g.lam[4 * w] : 1.0f);
+  const float4 pa = g.prm[lc];                  // sorted parameters: .z ligand flag, .w charge
+  const float q = pa.w * (pa.z > 0.0f ? g.lam[4 * w] : 1.0f);
   const float4 xa = g.xyzq[lc];
   float fxr, fyr, fzr, wx[4], wy[4], wz[4], dx[4], dy[4], dz[4];
   const int bx = grid_base(xa.x, g.invL[0], g.K[0], &fxr);
@@ -522,9 +563,14 @@ __global__ __launch_bounds__(256) void k_gather(const LegDev* legs, BlockMap map
     const float fy = -q * gys * (float)g.K[1] * g.invLf[1];
     const float fz = -q * gzs * (float)g.K[2] * g.invLf[2];
     const int where = (w << 20) | a;
-    g.fx[o] += to_fixed((double)fx, kForceScale, g.err, kSiteGather, where, g.leg_index);
-    g.fy[o] += to_fixed((double)fy, kForceScale, g.err, kSiteGather, where, g.leg_index);
-    g.fz[o] += to_fixed((double)fz, kForceScale, g.err, kSiteGather, where, g.leg_index);
+    // one writer per atom; atomics without a return value let the wave
+    // retire without waiting for the read-modify-write
+    atomicAdd((unsigned long long*)&g.fx[o],
+              (unsigned long long)to_fixed((double)fx, kForceScale, g.err, kSiteGather, where, g.leg_index));
+    atomicAdd((unsigned long long*)&g.fy[o],
+              (unsigned long long)to_fixed((double)fy, kForceScale, g.err, kSiteGather, where, g.leg_index));
+    atomicAdd((unsigned long long*)&g.fz[o],
+              (unsigned long long)to_fixed((double)fz, kForceScale, g.err, kSiteGather, where, g.leg_index));
   }
   if (ENERGY) {
     double e = (valid && sub == 0) ? 0.5 * (double)q * (double)pot : 0.0;
@@ -555,19 +601,22 @@ void fft_pass(hipStream_t s, const LegDev* d, const LegHost* h, int nl) {
     nmax = std::max(nmax, h[i].K[AXIS]);
     return h[i].npair * outer * ((inner + kLines - 1) / kLines);
   });
-  const size_t lds = 2 * (size_t)nmax * kLines * sizeof(float2);
+  const size_t lds = (2 * (size_t)nmax * kLines + nmax) * sizeof(float2);
   if (nb) hipLaunchKernelGGL((k_fft<AXIS, MODE>), dim3(nb), dim3(256), lds, s, d, m);
 }
 
 }  // namespace
 
 void launch_pme_fft(hipStream_t s, const LegDev* d, const LegHost* h, int nl, bool from_int64) {
-  int plane = 0;
-  for (int i = 0; i < nl; ++i) plane = std::max(plane, h[i].K[0] * h[i].K[1]);
+  int plane = 0, kxy = 0;
+  for (int i = 0; i < nl; ++i) {
+    plane = std::max(plane, h[i].K[0] * h[i].K[1]);
+    kxy = std::max(kxy, h[i].K[0] + h[i].K[1]);
+  }
   if (!from_int64 && plane <= kMaxPlane) {           // whole x-y planes in LDS
     BlockMap m;
     const int nb = make_map(m, nl, [&](int i) { return h[i].npair * h[i].K[2]; });
-    const size_t lds = 2 * (size_t)plane * sizeof(float2);
+    const size_t lds = (2 * (size_t)plane + kxy) * sizeof(float2);
     if (nb) hipLaunchKernelGGL(k_fft_xy<false>, dim3(nb), dim3(256), lds, s, d, m);
     fft_pass<2, 3>(s, d, h, nl);
     if (nb) hipLaunchKernelGGL(k_fft_xy<true>, dim3(nb), dim3(256), lds, s, d, m);
@@ -586,7 +635,7 @@ void launch_pme(hipStream_t s, const LegDev* d, const LegHost* h, int nl, bool e
   int nb = make_map(m, nl, [&](int i) {
     const int nbr = ((h[i].K[0] + kBrick - 1) / kBrick) * ((h[i].K[1] + kBrick - 1) / kBrick) *
                     ((h[i].K[2] + kBrick - 1) / kBrick);
-    return h[i].npair * nbr;
+    return h[i].W * nbr;
   });
   if (!nb) return;
   hipLaunchKernelGGL(k_spread, dim3(nb), dim3(256), 0, s, d, m);
