@@ -75,6 +75,8 @@ struct LegDev {
   unsigned* wmax;                       // [waves][2] per integrator wave: largest squared displacement in
                                         // its first and in its second window (float bits)
   int units;                            // integration units per window (rigid waters + other atoms)
+  const unsigned* hcell;                // [ncell] Hilbert index of fine cell (x * 2^nbits + y) * 2^nbits + z
+  const unsigned* hcoarse;              // [ncell / 8] Hilbert index / 8 of coarse block (x, y, z), same order
   int* perm;                            // [W][npad] sorted slot -> atom (-1 = padding)
   int* cellcode;                        // [W][n]
   int* cellstart;                       // [W][ncell + 1]
@@ -150,8 +152,9 @@ __device__ __forceinline__ T wave_sum(T v) {
 // (Skilling's transpose construction: undo excess work, Gray-code, then
 // interleave).  Consecutive indices are face-adjacent cells, and the 8
 // children of every aligned 2x2x2 block hold 8 consecutive indices, so a
-// coarse block's atoms form one contiguous range of the sorted order.
-__device__ __forceinline__ unsigned hilbert3(unsigned x, unsigned y, unsigned z, int bits) {
+// coarse block's atoms form one contiguous range of the sorted order.  The
+// kernels read it from per-leg tables filled on the host at leg set-up.
+__host__ __device__ inline unsigned hilbert3(unsigned x, unsigned y, unsigned z, int bits) {
   unsigned X[3] = {x, y, z};
   for (unsigned Q = 1u << (bits - 1); Q > 1u; Q >>= 1) {
     const unsigned P = Q - 1u;

@@ -16,6 +16,11 @@ namespace {
 
 constexpr int kCellOf = 4096;                 // candidates per table window in k_build
 
+// a wave-uniform float moved to a scalar register
+__device__ __forceinline__ float scalar(float v) {
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+
 __device__ __forceinline__ int cell_of(float v, float L, float invL, int n) {
   float u = wrapf(v, L, invL) * invL;
   int c = (int)(u * (float)n);
@@ -81,8 +86,8 @@ __global__ __launch_bounds__(256) void k_cells_count(const LegDev* legs, BlockMa
   if (!g.flag[w]) return;
   const int nf = 1 << g.nbits;
   const float x = g.x[i], y = g.y[i], z = g.z[i];
-  const unsigned c = hilbert3(cell_of(x, g.Lf[0], g.invLf[0], nf), cell_of(y, g.Lf[1], g.invLf[1], nf),
-                              cell_of(z, g.Lf[2], g.invLf[2], nf), g.nbits);
+  const unsigned c = g.hcell[(cell_of(x, g.Lf[0], g.invLf[0], nf) * nf + cell_of(y, g.Lf[1], g.invLf[1], nf)) * nf +
+                            cell_of(z, g.Lf[2], g.invLf[2], nf)];
   g.cellcode[i] = (int)c;
   atomicAdd(&g.cursor[(size_t)w * g.ncell + c], 1);
   g.xr[i] = x; g.yr[i] = y; g.zr[i] = z;
@@ -166,6 +171,7 @@ constexpr int kSortAtoms = 12288;
 
 template <bool FROM_WORD>
 __global__ __launch_bounds__(1024) void k_check_sort(const LegDev* legs, BlockMap map, int force) {
+  static_assert(kSortAtoms % 1024 == 0, "one block of 1024 threads sorts a window");
   const int leg = find_leg(map, blockIdx.x);
   const LegDev& g = legs[leg];
   const int w = blockIdx.x - map.start[leg];
@@ -212,14 +218,26 @@ __global__ __launch_bounds__(1024) void k_check_sort(const LegDev* legs, BlockMa
 
   const int nc = g.ncell, n = g.n, nf = 1 << g.nbits;
   for (int c = tid; c < nc; c += blockDim.x) s_cur[c] = 0;
+  // every position this thread sorts is loaded before any is used (at most
+  // kSortAtoms / 1024 per thread), so the loads overlap
+  constexpr int kPer = kSortAtoms / 1024;
+  float px[kPer], py[kPer], pz[kPer];
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    const int a = tid + k * 1024;
+    if (a < n) { px[k] = g.x[o + a]; py[k] = g.y[o + a]; pz[k] = g.z[o + a]; }
+  }
   __syncthreads();
-  for (int a = tid; a < n; a += blockDim.x) {
-    const float x = g.x[o + a], y = g.y[o + a], z = g.z[o + a];
-    const unsigned c = hilbert3(cell_of(x, g.Lf[0], g.invLf[0], nf), cell_of(y, g.Lf[1], g.invLf[1], nf),
-                                cell_of(z, g.Lf[2], g.invLf[2], nf), g.nbits);
-    s_code[a] = (unsigned short)c;
-    atomicAdd(&s_cur[c], 1);
-    g.xr[o + a] = x; g.yr[o + a] = y; g.zr[o + a] = z;
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    const int a = tid + k * 1024;
+    if (a < n) {
+      const unsigned c = g.hcell[(cell_of(px[k], g.Lf[0], g.invLf[0], nf) * nf + cell_of(py[k], g.Lf[1], g.invLf[1], nf)) *
+                                     nf + cell_of(pz[k], g.Lf[2], g.invLf[2], nf)];
+      s_code[a] = (unsigned short)c;
+      atomicAdd(&s_cur[c], 1);
+      g.xr[o + a] = px[k]; g.yr[o + a] = py[k]; g.zr[o + a] = pz[k];
+    }
   }
   __syncthreads();
   // exclusive scan: each thread takes a run of consecutive cells
@@ -356,14 +374,14 @@ __global__ __launch_bounds__(256) void k_build(const LegDev* legs, BlockMap map)
                      ext[2] + incl + 0.02f < 0.5f * g.Lf[2];
   // i-side terms of |r_j - r_i|^2 = |r_j|^2 - 2 r_i.r_j + |r_i|^2 in the
   // shifted frame (|r| < 25 A there, so the FP32 error of the expanded form
-  // stays below 1e-3 A^2, far inside the 0.01 A margin); a padding slot gets
-  // |r_i|^2 = 1e30 and never passes
-  float m2[kClus][3], c2[kClus];
+  // stays below 1e-3 A^2, far inside the 0.01 A margin), held in scalar
+  // registers; a padding slot gets |r_i|^2 = 1e30 and never passes
+  float m2[kClus][3], nc2[kClus];
 #pragma unroll
   for (int ii = 0; ii < kClus; ++ii) {
-    for (int d = 0; d < 3; ++d) m2[ii][d] = -2.0f * ri[ii][d];
-    c2[ii] = ai[ii] >= 0 ? __fmaf_rn(ri[ii][0], ri[ii][0], __fmaf_rn(ri[ii][1], ri[ii][1], ri[ii][2] * ri[ii][2]))
-                         : 1.0e30f;
+    for (int d = 0; d < 3; ++d) m2[ii][d] = scalar(-2.0f * ri[ii][d]);
+    nc2[ii] = scalar(ai[ii] >= 0 ? -__fmaf_rn(ri[ii][0], ri[ii][0], __fmaf_rn(ri[ii][1], ri[ii][1], ri[ii][2] * ri[ii][2]))
+                                 : -1.0e30f);
   }
   const int* cst = g.cellstart + (size_t)w * (g.ncell + 1);
   unsigned* outL = g.lent + (size_t)item * 2 * g.cap;      // partners of atoms 0-3
@@ -384,8 +402,7 @@ __global__ __launch_bounds__(256) void k_build(const LegDev* legs, BlockMap map)
         gap2 += gp * gp;
       }
       if (gap2 < pre2) {
-        const unsigned cc = hilbert3(2u * (unsigned)((C[0] % nf + nf) % nf), 2u * (unsigned)((C[1] % nf + nf) % nf),
-                                     2u * (unsigned)((C[2] % nf + nf) % nf), g.nbits) >> 3;
+        const unsigned cc = g.hcoarse[(((C[0] % nf + nf) % nf) * nf + (C[1] % nf + nf) % nf) * nf + (C[2] % nf + nf) % nf];
         s0 = cst[8 * cc];                        // fine cells 8cc .. 8cc+7 are contiguous
         cnt = cst[8 * cc + 8] - s0;
       }
@@ -429,16 +446,19 @@ __global__ __launch_bounds__(256) void k_build(const LegDev* legs, BlockMap map)
               const float v = xj[d] - xi[0][d];
               rj3[d] = __fmaf_rn(-g.Lf[d], rintf(v * g.invLf[d]), v);
             }
-            const float thr = inc2 - __fmaf_rn(rj3[0], rj3[0], __fmaf_rn(rj3[1], rj3[1], rj3[2] * rj3[2]));
+            // |r_j|^2 - 2 r_i.r_j - (r_list + 0.01)^2 < -|r_i|^2
+            const float nthr = __fmaf_rn(rj3[0], rj3[0], __fmaf_rn(rj3[1], rj3[1], rj3[2] * rj3[2])) - inc2;
 #pragma unroll
             for (int ii = kClus - 1; ii >= 0; --ii) {        // bit ii ends at position ii
-              const float q = __fmaf_rn(m2[ii][0], rj3[0], __fmaf_rn(m2[ii][1], rj3[1], __fmaf_rn(m2[ii][2], rj3[2], c2[ii])));
-              mask = 2u * mask + (q < thr ? 1u : 0u);
+              const float q = __fmaf_rn(m2[ii][0], rj3[0], __fmaf_rn(m2[ii][1], rj3[1], __fmaf_rn(m2[ii][2], rj3[2], nthr)));
+              mask = 2u * mask + (q < nc2[ii] ? 1u : 0u);
             }
           } else {
-#pragma unroll
+            // rare (small boxes, spread clusters): positions from LDS and no
+            // unrolling, so this path adds no registers to the common one
+#pragma unroll 1
             for (int ii = 0; ii < kClus; ++ii) {
-              float dx = xj[0] - xi[ii][0], dy = xj[1] - xi[ii][1], dz = xj[2] - xi[ii][2];
+              float dx = xj[0] - s_xi[ii][0], dy = xj[1] - s_xi[ii][1], dz = xj[2] - s_xi[ii][2];
               dx -= g.Lf[0] * rintf(dx * g.invLf[0]);
               dy -= g.Lf[1] * rintf(dy * g.invLf[1]);
               dz -= g.Lf[2] * rintf(dz * g.invLf[2]);

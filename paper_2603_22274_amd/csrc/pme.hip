@@ -25,6 +25,7 @@ namespace {
 
 constexpr int kLines = 16;
 constexpr int kMaxPlane = 4096;                 // x-y plane points transformed whole in LDS (2 x 32 KB)
+constexpr int kXYThreads = 512;                 // threads per whole-plane workgroup: ~one butterfly each
 
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
   return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
@@ -268,7 +269,7 @@ __device__ __forceinline__ float2* fft_lines_nl(float2* src, float2* dst, int n,
 // transform over x and y reads and writes the grid once.  INVERSE uses
 // conj(DFT(conj(.))).
 template <bool INVERSE>
-__global__ __launch_bounds__(256) void k_fft_xy(const LegDev* legs, BlockMap map) {
+__global__ __launch_bounds__(kXYThreads) void k_fft_xy(const LegDev* legs, BlockMap map) {
   const int leg = find_leg(map, blockIdx.x);
   const LegDev& g = legs[leg];
   const int Kx = g.K[0], Ky = g.K[1], Kz = g.K[2];
@@ -413,8 +414,7 @@ __global__ __launch_bounds__(256) void k_spread(const LegDev* legs, BlockMap map
     if (ci < ncells) {
       const int C[3] = {c0[0] + ci / (nspan[1] * nspan[2]), c0[1] + (ci / nspan[2]) % nspan[1],
                         c0[2] + ci % nspan[2]};
-      const unsigned cc = hilbert3((unsigned)((C[0] % nc + nc) % nc), (unsigned)((C[1] % nc + nc) % nc),
-                                   (unsigned)((C[2] % nc + nc) % nc), g.nbits);
+      const unsigned cc = g.hcell[(((C[0] % nc + nc) % nc) * nc + (C[1] % nc + nc) % nc) * nc + (C[2] % nc + nc) % nc];
       s0 = cst[cc];
       cnt = cst[cc + 1] - s0;
     }
@@ -617,9 +617,9 @@ void launch_pme_fft(hipStream_t s, const LegDev* d, const LegHost* h, int nl, bo
     BlockMap m;
     const int nb = make_map(m, nl, [&](int i) { return h[i].npair * h[i].K[2]; });
     const size_t lds = (2 * (size_t)plane + kxy) * sizeof(float2);
-    if (nb) hipLaunchKernelGGL(k_fft_xy<false>, dim3(nb), dim3(256), lds, s, d, m);
+    if (nb) hipLaunchKernelGGL(k_fft_xy<false>, dim3(nb), dim3(kXYThreads), lds, s, d, m);
     fft_pass<2, 3>(s, d, h, nl);
-    if (nb) hipLaunchKernelGGL(k_fft_xy<true>, dim3(nb), dim3(256), lds, s, d, m);
+    if (nb) hipLaunchKernelGGL(k_fft_xy<true>, dim3(nb), dim3(kXYThreads), lds, s, d, m);
     return;
   }
   if (from_int64) fft_pass<0, 2>(s, d, h, nl);
