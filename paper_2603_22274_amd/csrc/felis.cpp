@@ -19,7 +19,7 @@ namespace {
 
 struct Layout {
   size_t lam, free_atoms, lig_idx, xr, yr, zr, flag, nbuild, maxdisp, wmax, hcell, hcoarse, perm, cellcode, cellstart, cursor, xyzq, prm, bblo,
-      bbhi, lcount, lent, grid64, cgrid, tw[3], bmod[3], eacc, uacc, upart, lpart, ucst, total;
+      bbhi, lcount, lent, frx, fry, frz, grid64, cgrid, tw[3], bmod[3], eacc, uacc, upart, lpart, ucst, total;
 };
 
 struct Plan {
@@ -45,6 +45,10 @@ struct Timer {
 struct felis_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
+  // felis_step runs reciprocal space on a second stream (default priority)
+  // beside the list build and pair kernel; two events fork and join it
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   LegDev* d_legs = nullptr;          // device table of kMaxLegs descriptors
   LegDev* h_stage = nullptr;         // pinned staging
   std::vector<LegDev> cache;         // last uploaded table
@@ -169,6 +173,7 @@ int make_plan(felis_ctx* c, const felis_leg* L, Plan& P) {
   y.bbhi = put(W * nc * 16);
   y.lcount = put(W * nc * 2 * 4);
   y.lent = put(W * nc * 2 * (size_t)h.cap * 4);
+  y.frx = put(W * n * 8); y.fry = put(W * n * 8); y.frz = put(W * n * 8);
   y.grid64 = put(2 * (size_t)h.npair * h.Ktot * 8);
   y.cgrid = put((size_t)h.npair * h.Ktot * 8);
   for (int d = 0; d < 3; ++d) { y.tw[d] = put(h.K[d] * 8); y.bmod[d] = put(h.K[d] * 4); }
@@ -248,6 +253,7 @@ LegDev make_dev(const felis_ctx* c, const felis_leg* L, const Plan& p, const Met
   g.bbhi = (float4*)(w + y.bbhi);
   g.lcount = (int*)(w + y.lcount);
   g.lent = (unsigned*)(w + y.lent);
+  g.frx = (long long*)(w + y.frx); g.fry = (long long*)(w + y.fry); g.frz = (long long*)(w + y.frz);
   g.grid64 = (long long*)(w + y.grid64);
   g.cgrid = (float2*)(w + y.cgrid);
   for (int d = 0; d < 3; ++d) { g.tw[d] = (float2*)(w + y.tw[d]); g.bmod[d] = (float*)(w + y.bmod[d]); }
@@ -290,7 +296,7 @@ int prepare(felis_ctx* c, const felis_leg* legs, int n_legs, std::vector<LegHost
 }
 
 // Records an event for timer t when profiling is on (start when stop == false).
-void mark(felis_ctx* c, int t, bool stop) {
+void mark(felis_ctx* c, int t, bool stop, hipStream_t s) {
   if (!c->prof) return;
   Timer& T = c->timers[t];
   if (!stop && T.used + 2 > T.ev.size()) {
@@ -301,9 +307,10 @@ void mark(felis_ctx* c, int t, bool stop) {
     }
   }
   if (!stop && T.used + 2 > T.ev.size()) return;
-  (void)hipEventRecord(T.ev[T.used], c->stream);
+  (void)hipEventRecord(T.ev[T.used], s);
   ++T.used;
 }
+void mark(felis_ctx* c, int t, bool stop) { mark(c, t, stop, c->stream); }
 
 int launched(felis_ctx* c) {
   hipError_t e = hipGetLastError();
@@ -326,6 +333,9 @@ int felis_create(felis_ctx** out, int device, void* hip_stream) {
       hipHostMalloc((void**)&c->h_stage, sizeof(LegDev) * kMaxLegs, hipHostMallocDefault) != hipSuccess ||
       hipMalloc((void**)&c->d_err, 8 * sizeof(int)) != hipSuccess ||
       hipMalloc((void**)&c->d_count, sizeof(unsigned long long)) != hipSuccess ||
+      hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess ||
       hipMemset(c->d_err, 0, 8 * sizeof(int)) != hipSuccess) {
     felis_destroy(c);
     return FELIS_E_DEVICE;
@@ -341,6 +351,9 @@ void felis_destroy(felis_ctx* c) {
   if (c->h_stage) (void)hipHostFree(c->h_stage);
   if (c->d_err) (void)hipFree(c->d_err);
   if (c->d_count) (void)hipFree(c->d_count);
+  if (c->side) { (void)hipStreamSynchronize(c->side); (void)hipStreamDestroy(c->side); }
+  if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+  if (c->ev_join) (void)hipEventDestroy(c->ev_join);
   for (auto& T : c->timers)
     for (hipEvent_t e : T.ev) (void)hipEventDestroy(e);
   delete c;
@@ -574,16 +587,24 @@ int felis_step(felis_ctx* c, felis_leg* legs, int n_legs, int n_steps, double dt
     // the first step scans positions; later steps read the largest
     // displacement the previous step's integrator recorded
     launch_check(c->stream, c->d_legs, hs.data(), n_legs, 0, s > 0);
-    launch_build(c->stream, c->d_legs, hs.data(), n_legs);
+    launch_sort_pack(c->stream, c->d_legs, hs.data(), n_legs);
+    // reciprocal space needs only the cell sort and the packed coordinates
+    // and parameters: it runs on the side stream beside the list build, the
+    // pair kernel and the bonded terms, and stores its forces apart (frx..)
+    (void)hipEventRecord(c->ev_fork, c->stream);
+    (void)hipStreamWaitEvent(c->side, c->ev_fork, 0);
+    mark(c, FELIS_PROF_PME, false, c->side);
+    launch_pme(c->side, c->d_legs, hs.data(), n_legs, false, true);
+    mark(c, FELIS_PROF_PME, true, c->side);
+    (void)hipEventRecord(c->ev_join, c->side);
+    launch_lists(c->stream, c->d_legs, hs.data(), n_legs);
     mark(c, FELIS_PROF_NLIST, true);       // the build stage also packs the sorted coordinates
     mark(c, FELIS_PROF_PAIRS, false);
     launch_pairs(c->stream, c->d_legs, hs.data(), n_legs, false);
     mark(c, FELIS_PROF_PAIRS, true);
     launch_corrections(c->stream, c->d_legs, hs.data(), n_legs, false);
     launch_bonded(c->stream, c->d_legs, hs.data(), n_legs, false);
-    mark(c, FELIS_PROF_PME, false);
-    launch_pme(c->stream, c->d_legs, hs.data(), n_legs, false);
-    mark(c, FELIS_PROF_PME, true);
+    (void)hipStreamWaitEvent(c->stream, c->ev_join, 0);
     mark(c, FELIS_PROF_INTEGRATE, false);
     launch_integrate(c->stream, c->d_legs, hs.data(), n_legs, step.data(), seed.data(), (float)dt,
                      (float)temperature, (float)gamma);

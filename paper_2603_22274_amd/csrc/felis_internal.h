@@ -88,6 +88,7 @@ struct LegDev {
   int* lcount;                          // [W][nclus][2] entries per half-cluster list
   unsigned* lent;                       // [W][nclus][2][cap]: list of the cluster's atoms 0-3 and of
                                         // atoms 4-7 (slot << 8 | 4-bit mask over the half's atoms)
+  long long *frx, *fry, *frz;           // [W][n] reciprocal-space forces of the current MD step
   long long* grid64;                    // [W][Ktot] fixed-point charge grids
   float2* cgrid;                        // [npair][Ktot] complex grids
   float2* tw[3];                        // [K] exp(-2 pi i k / K) per axis
@@ -206,13 +207,19 @@ struct LegHost {
 // ---- launchers (one per translation unit) ----
 void launch_check(hipStream_t s, const LegDev* d, const LegHost* h, int nl, int force, bool from_word);
 void launch_build(hipStream_t s, const LegDev* d, const LegHost* h, int nl);
+// launch_build in two parts: the cell sort of large legs and the pack (all
+// that PME needs), then the cluster lists
+void launch_sort_pack(hipStream_t s, const LegDev* d, const LegHost* h, int nl);
+void launch_lists(hipStream_t s, const LegDev* d, const LegHost* h, int nl);
 void launch_export(hipStream_t s, const LegDev* d, const LegHost& h, int window, double r,
                    int* pairs, long long cap, unsigned long long* count);
 void launch_pack(hipStream_t s, const LegDev* d, const LegHost* h, int nl, bool rebuild);
 void launch_pairs(hipStream_t s, const LegDev* d, const LegHost* h, int nl, bool energy);
 void launch_corrections(hipStream_t s, const LegDev* d, const LegHost* h, int nl, bool energy);
 void launch_bonded(hipStream_t s, const LegDev* d, const LegHost* h, int nl, bool energy);
-void launch_pme(hipStream_t s, const LegDev* d, const LegHost* h, int nl, bool energy);
+// step_forces: the gather stores each atom's force in frx/fry/frz (read by the
+// integrator) instead of adding it to fx/fy/fz
+void launch_pme(hipStream_t s, const LegDev* d, const LegHost* h, int nl, bool energy, bool step_forces = false);
 void launch_integrate(hipStream_t s, const LegDev* d, const LegHost* h, int nl,
                       const long long* step, const unsigned long long* seed, float dt,
                       float temperature, float gamma);

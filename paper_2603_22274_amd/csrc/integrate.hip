@@ -55,9 +55,13 @@ __device__ __forceinline__ void advance(const LegDev& g, const StepArgs& S, int 
   const float m = g.mass[a];
   const float dt = S.dt;
   const float acc = (float)kAccel / m;
-  const float F[3] = {(float)((double)g.fx[o] * (1.0 / kForceScale)),
-                      (float)((double)g.fy[o] * (1.0 / kForceScale)),
-                      (float)((double)g.fz[o] * (1.0 / kForceScale))};
+  // total force: real-space, bonded and restraint terms in fx/fy/fz plus this
+  // step's reciprocal-space term; the sum is stored back so that fx/fy/fz
+  // hold the whole force of the step after the call
+  const long long tx = g.fx[o] + g.frx[o], ty = g.fy[o] + g.fry[o], tz = g.fz[o] + g.frz[o];
+  g.fx[o] = tx; g.fy[o] = ty; g.fz[o] = tz;
+  const float F[3] = {(float)((double)tx * (1.0 / kForceScale)), (float)((double)ty * (1.0 / kForceScale)),
+                      (float)((double)tz * (1.0 / kForceScale))};
   v3 v = mk(g.vx[o] + dt * F[0] * acc, g.vy[o] + dt * F[1] * acc, g.vz[o] + dt * F[2] * acc);
   const float hd = 0.5f * dt;
   dx = vmul(v, hd);

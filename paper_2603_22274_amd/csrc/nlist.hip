@@ -570,7 +570,7 @@ void launch_check(hipStream_t s, const LegDev* d, const LegHost* h, int nl, int 
   }
 }
 
-void launch_build(hipStream_t s, const LegDev* d, const LegHost* h, int nl) {
+void launch_sort_pack(hipStream_t s, const LegDev* d, const LegHost* h, int nl) {
   BlockMap m;
   // grid-wide cell sort for the legs that launch_check did not sort
   auto big = [&](int i) { return !sort_in_lds(h[i]); };
@@ -585,8 +585,17 @@ void launch_build(hipStream_t s, const LegDev* d, const LegHost* h, int nl) {
   // sorted coordinates every step; sorted parameters and cluster boxes for
   // the windows being rebuilt
   launch_pack(s, d, h, nl, true);
-  nb = make_map(m, nl, [&](int i) { return h[i].W * h[i].nclus; });
+}
+
+void launch_lists(hipStream_t s, const LegDev* d, const LegHost* h, int nl) {
+  BlockMap m;
+  const int nb = make_map(m, nl, [&](int i) { return h[i].W * h[i].nclus; });
   if (nb) hipLaunchKernelGGL(k_build, dim3(nb), dim3(256), 0, s, d, m);
+}
+
+void launch_build(hipStream_t s, const LegDev* d, const LegHost* h, int nl) {
+  launch_sort_pack(s, d, h, nl);
+  launch_lists(s, d, h, nl);
 }
 
 void launch_export(hipStream_t s, const LegDev* d, const LegHost& h, int window, double r,

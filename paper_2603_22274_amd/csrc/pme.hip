@@ -502,7 +502,9 @@ __global__ __launch_bounds__(256) void k_spread(const LegDev* legs, BlockMap map
   }
 }
 
-template <bool ENERGY>
+// STEP: store the force in frx/fry/frz (the integrator adds it to the
+// real-space force) instead of adding it to fx/fy/fz
+template <bool ENERGY, bool STEP>
 __global__ __launch_bounds__(256) void k_gather(const LegDev* legs, BlockMap map) {
   const int leg = find_leg(map, blockIdx.x);
   const LegDev& g = legs[leg];
@@ -563,14 +565,18 @@ __global__ __launch_bounds__(256) void k_gather(const LegDev* legs, BlockMap map
     const float fy = -q * gys * (float)g.K[1] * g.invLf[1];
     const float fz = -q * gzs * (float)g.K[2] * g.invLf[2];
     const int where = (w << 20) | a;
-    // one writer per atom; atomics without a return value let the wave
-    // retire without waiting for the read-modify-write
-    atomicAdd((unsigned long long*)&g.fx[o],
-              (unsigned long long)to_fixed((double)fx, kForceScale, g.err, kSiteGather, where, g.leg_index));
-    atomicAdd((unsigned long long*)&g.fy[o],
-              (unsigned long long)to_fixed((double)fy, kForceScale, g.err, kSiteGather, where, g.leg_index));
-    atomicAdd((unsigned long long*)&g.fz[o],
-              (unsigned long long)to_fixed((double)fz, kForceScale, g.err, kSiteGather, where, g.leg_index));
+    const long long ix = to_fixed((double)fx, kForceScale, g.err, kSiteGather, where, g.leg_index);
+    const long long iy = to_fixed((double)fy, kForceScale, g.err, kSiteGather, where, g.leg_index);
+    const long long iz = to_fixed((double)fz, kForceScale, g.err, kSiteGather, where, g.leg_index);
+    if (STEP) {
+      g.frx[o] = ix; g.fry[o] = iy; g.frz[o] = iz;
+    } else {
+      // one writer per atom; atomics without a return value let the wave
+      // retire without waiting for the read-modify-write
+      atomicAdd((unsigned long long*)&g.fx[o], (unsigned long long)ix);
+      atomicAdd((unsigned long long*)&g.fy[o], (unsigned long long)iy);
+      atomicAdd((unsigned long long*)&g.fz[o], (unsigned long long)iz);
+    }
   }
   if (ENERGY) {
     double e = (valid && sub == 0) ? 0.5 * (double)q * (double)pot : 0.0;
@@ -630,7 +636,7 @@ void launch_pme_fft(hipStream_t s, const LegDev* d, const LegHost* h, int nl, bo
   fft_pass<0, 1>(s, d, h, nl);
 }
 
-void launch_pme(hipStream_t s, const LegDev* d, const LegHost* h, int nl, bool energy) {
+void launch_pme(hipStream_t s, const LegDev* d, const LegHost* h, int nl, bool energy, bool step_forces) {
   BlockMap m;
   int nb = make_map(m, nl, [&](int i) {
     const int nbr = ((h[i].K[0] + kBrick - 1) / kBrick) * ((h[i].K[1] + kBrick - 1) / kBrick) *
@@ -641,8 +647,9 @@ void launch_pme(hipStream_t s, const LegDev* d, const LegHost* h, int nl, bool e
   hipLaunchKernelGGL(k_spread, dim3(nb), dim3(256), 0, s, d, m);
   launch_pme_fft(s, d, h, nl, false);
   nb = make_map(m, nl, [&](int i) { return blocks_for((long long)h[i].W * h[i].npad, 64); });
-  if (energy) hipLaunchKernelGGL(k_gather<true>, dim3(nb), dim3(256), 0, s, d, m);
-  else hipLaunchKernelGGL(k_gather<false>, dim3(nb), dim3(256), 0, s, d, m);
+  if (energy) hipLaunchKernelGGL((k_gather<true, false>), dim3(nb), dim3(256), 0, s, d, m);
+  else if (step_forces) hipLaunchKernelGGL((k_gather<false, true>), dim3(nb), dim3(256), 0, s, d, m);
+  else hipLaunchKernelGGL((k_gather<false, false>), dim3(nb), dim3(256), 0, s, d, m);
 }
 
 }  // namespace felis
