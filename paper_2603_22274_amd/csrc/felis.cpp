@@ -19,7 +19,7 @@ namespace {
 
 struct Layout {
   size_t lam, free_atoms, lig_idx, xr, yr, zr, flag, nbuild, maxdisp, wmax, hcell, hcoarse, perm, cellcode, cellstart, cursor, xyzq, prm, bblo,
-      bbhi, lcount, lent, frx, fry, frz, grid64, cgrid, tw[3], bmod[3], eacc, uacc, upart, lpart, ucst, total;
+      bbhi, gsten, lcount, lent, frx, fry, frz, grid64, cgrid, tw[3], bmod[3], eacc, uacc, upart, lpart, ucst, total;
 };
 
 struct Plan {
@@ -171,6 +171,7 @@ int make_plan(felis_ctx* c, const felis_leg* L, Plan& P) {
   y.prm = put(W * npad * 16);
   y.bblo = put(W * nc * 16);
   y.bbhi = put(W * nc * 16);
+  y.gsten = put(W * npad * 16);
   y.lcount = put(W * nc * 2 * 4);
   y.lent = put(W * nc * 2 * (size_t)h.cap * 4);
   y.frx = put(W * n * 8); y.fry = put(W * n * 8); y.frz = put(W * n * 8);
@@ -251,6 +252,7 @@ LegDev make_dev(const felis_ctx* c, const felis_leg* L, const Plan& p, const Met
   g.prm = (float4*)(w + y.prm);
   g.bblo = (float4*)(w + y.bblo);
   g.bbhi = (float4*)(w + y.bbhi);
+  g.gsten = (float4*)(w + y.gsten);
   g.lcount = (int*)(w + y.lcount);
   g.lent = (unsigned*)(w + y.lent);
   g.frx = (long long*)(w + y.frx); g.fry = (long long*)(w + y.fry); g.frz = (long long*)(w + y.frz);

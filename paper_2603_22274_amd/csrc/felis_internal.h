@@ -16,7 +16,7 @@ constexpr int kMaxLigand = 256;     // ligand atoms handled by the u_kn kernels
 constexpr int kMaxLamV = 64;        // distinct lambda_vdw values per u_kn call
 constexpr int kMaxStates = 128;     // lambda states per u_kn call
 constexpr int kMaxRadix = 8;        // FFT stages per axis
-constexpr int kMaxFFT = 128;        // largest PME grid dimension
+constexpr int kMaxFFT = 128;        // largest PME grid dimension (bases pack in 7 bits)
 constexpr int kClus = 8;            // atoms per i-cluster (pair kernel)
 
 constexpr double kKE = 332.06371;                 // kcal A / (mol e^2)
@@ -83,6 +83,7 @@ struct LegDev {
   int* cursor;                          // [W][ncell]
   float4* xyzq;                         // [W][npad] x, y, z, q_scaled * sqrt(KE)
   float4* prm;                          // [W][npad] sigma/2, 2 sqrt(eps), ligand flag, q
+  float4* gsten;                        // [W][npad] PME stencil: offsets fx, fy, fz and the packed bases
   float4* bblo;                         // [W][nclus] cluster bounding boxes (wrapped)
   float4* bbhi;
   int* lcount;                          // [W][nclus][2] entries per half-cluster list
@@ -155,6 +156,31 @@ __device__ __forceinline__ T wave_sum(T v) {
 // children of every aligned 2x2x2 block hold 8 consecutive indices, so a
 // coarse block's atoms form one contiguous range of the sorted order.  The
 // kernels read it from per-leg tables filled on the host at leg set-up.
+// PME grid coordinate of a position along one axis, in FP64: the base grid
+// index b (the stencil covers b, b-1, b-2, b-3, periodic) and the offset
+// f in [0, 1) of the order-4 B-spline weights
+__device__ __forceinline__ int grid_base(float x, double invL, int K, float* f) {
+  double u = (double)x * invL * (double)K;
+  if (!(fabs(u) < 1.0e15)) u = 0.0;              // non-finite input -> 0 (keeps indices in range)
+  const double b = floor(u);
+  *f = (float)(u - b);
+  // b mod K without 64-bit integer division: |b| < 2^53, so the FP64 floor
+  // of b / K is off by at most one, which the integer fix-ups absorb
+  int k = (int)(b - (double)K * floor(b * (1.0 / (double)K)));
+  if (k < 0) k += K;
+  if (k >= K) k -= K;
+  return k;
+}
+
+// a slot's three base indices (7 bits each: K <= 128) packed in one word
+__device__ __forceinline__ float pack_bases(int bx, int by, int bz) {
+  return __int_as_float(bx | (by << 7) | (bz << 14));
+}
+__device__ __forceinline__ void unpack_bases(float v, int* b) {
+  const int u = __float_as_int(v);
+  b[0] = u & 127; b[1] = (u >> 7) & 127; b[2] = (u >> 14) & 127;
+}
+
 __host__ __device__ inline unsigned hilbert3(unsigned x, unsigned y, unsigned z, int bits) {
   unsigned X[3] = {x, y, z};
   for (unsigned Q = 1u << (bits - 1); Q > 1u; Q >>= 1) {

@@ -339,12 +339,13 @@ __global__ __launch_bounds__(256) void k_build(const LegDev* legs, BlockMap map)
   const float pre2 = pre * pre;
   int r0[3], nC[3];
   bool full[3];
-  float cen[3], half[3];
+  float cen[3], half[3], csd[3];
   for (int d = 0; d < 3; ++d) {
     cen[d] = 0.5f * (lo[d] + hi[d]);
     half[d] = 0.5f * (hi[d] - lo[d]);
     if (!(half[d] >= 0.f && half[d] <= g.Lf[d])) { cen[d] = 0.f; half[d] = g.Lf[d]; }   // no valid atom
     const float cs = g.Lf[d] / (float)nf;
+    csd[d] = cs;
     const int a0 = (int)floorf((cen[d] - half[d] - pre) / cs);
     const int a1 = (int)floorf((cen[d] + half[d] + pre) / cs);
     full[d] = a1 - a0 + 1 >= nf;               // the range wraps onto itself: every cell, no gap test
@@ -389,20 +390,31 @@ __global__ __launch_bounds__(256) void k_build(const LegDev* legs, BlockMap map)
   const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   const int ncells = nC[0] * nC[1] * nC[2];
   int countL = 0, countH = 0, par = 0;
+  // block index ci -> (c0, c1, c2) by float-reciprocal quotients with one
+  // correction (exact for ci < 2^22); a block coordinate lies in (-nf, 2nf)
+  // (the range is narrower than the box unless full), so one wrap suffices
+  const int n12 = nC[1] * nC[2];
+  const float inv12 = 1.0f / (float)n12, inv2 = 1.0f / (float)nC[2];
+  auto wrapc = [nf](int c) { return c < 0 ? c + nf : (c >= nf ? c - nf : c); };
   for (int cb = 0; cb < ncells; cb += 256) {
     const int ci = cb + tid;
     int s0 = 0, cnt = 0;
     if (ci < ncells) {
-      const int C[3] = {r0[0] + ci / (nC[1] * nC[2]), r0[1] + (ci / nC[2]) % nC[1], r0[2] + ci % nC[2]};
+      int c0 = (int)((float)ci * inv12);
+      c0 += (ci - c0 * n12 < 0) ? -1 : (ci - c0 * n12 >= n12 ? 1 : 0);
+      const int rem = ci - c0 * n12;
+      int c1 = (int)((float)rem * inv2);
+      c1 += (rem - c1 * nC[2] < 0) ? -1 : (rem - c1 * nC[2] >= nC[2] ? 1 : 0);
+      const int C[3] = {r0[0] + c0, r0[1] + c1, r0[2] + rem - c1 * nC[2]};
       float gap2 = 0.f;
       for (int d = 0; d < 3; ++d) {
         if (full[d]) continue;
-        const float cs = g.Lf[d] / (float)nf;
+        const float cs = csd[d];
         const float gp = fmaxf(0.f, fmaxf((float)C[d] * cs - hi[d], lo[d] - (float)(C[d] + 1) * cs));
         gap2 += gp * gp;
       }
       if (gap2 < pre2) {
-        const unsigned cc = g.hcoarse[(((C[0] % nf + nf) % nf) * nf + (C[1] % nf + nf) % nf) * nf + (C[2] % nf + nf) % nf];
+        const unsigned cc = g.hcoarse[(wrapc(C[0]) * nf + wrapc(C[1])) * nf + wrapc(C[2])];
         s0 = cst[8 * cc];                        // fine cells 8cc .. 8cc+7 are contiguous
         cnt = cst[8 * cc + 8] - s0;
       }

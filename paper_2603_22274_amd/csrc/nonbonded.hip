@@ -23,7 +23,7 @@ namespace felis {
 namespace {
 
 // items: window x slot -- current coordinates and scaled charges in sorted
-// order.  REBUILD (inside a list build): for windows being rebuilt also the
+// order, and each slot's PME stencil (grid base and B-spline offsets).  REBUILD (inside a list build): for windows being rebuilt also the
 // sorted per-slot parameters and each 8-slot cluster's bounding box of
 // wrapped positions (8 consecutive lanes hold one cluster: N_pad is a
 // multiple of 8).
@@ -42,7 +42,15 @@ __global__ __launch_bounds__(256) void k_pack(const LegDev* legs, BlockMap map) 
     const float q = g.q[a] * (g.lig[a] ? g.lam[4 * w] : 1.0f);
     v = make_float4(g.x[o], g.y[o], g.z[o], q * (float)sqrt(kKE));
   }
-  if (valid) g.xyzq[i] = v;
+  if (valid) {
+    g.xyzq[i] = v;
+    // PME stencil of the slot (read by spreading and the gather)
+    float f[3];
+    const int bx = grid_base(v.x, g.invL[0], g.K[0], &f[0]);
+    const int by = grid_base(v.y, g.invL[1], g.K[1], &f[1]);
+    const int bz = grid_base(v.z, g.invL[2], g.K[2], &f[2]);
+    g.gsten[i] = make_float4(f[0], f[1], f[2], pack_bases(bx, by, bz));
+  }
   if (REBUILD) {
     const bool fl = valid && g.flag[w] != 0;
     if (fl) {

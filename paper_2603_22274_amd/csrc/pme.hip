@@ -322,19 +322,6 @@ __device__ __forceinline__ void bspline4(float f, float* w, float* dw) {
   }
 }
 
-// fractional grid coordinate in FP64: base index and offset f in [0, 1)
-__device__ __forceinline__ int grid_base(float x, double invL, int K, float* f) {
-  double u = (double)x * invL * (double)K;
-  if (!(fabs(u) < 1.0e15)) u = 0.0;              // non-finite input -> 0 (keeps indices in range)
-  const double b = floor(u);
-  *f = (float)(u - b);
-  // b mod K without 64-bit integer division: |b| < 2^53, so the FP64 floor
-  // of b / K is off by at most one, which the integer fix-ups absorb
-  int k = (int)(b - (double)K * floor(b * (1.0 / (double)K)));
-  if (k < 0) k += K;
-  if (k >= K) k -= K;
-  return k;
-}
 
 constexpr int kBrick = 8;                      // brick edge in grid points
 constexpr int kSpreadCellOf = 2048;            // candidates per table window in spreading
@@ -402,9 +389,11 @@ __global__ __launch_bounds__(256) void k_spread(const LegDev* legs, BlockMap map
     nspan[d] = full ? nc : a1 - a0 + 1;
   }
   const int ncells = nspan[0] * nspan[1] * nspan[2];
+  const int n12 = nspan[1] * nspan[2];
+  const float inv12 = 1.0f / (float)n12, inv2 = 1.0f / (float)nspan[2];
   const int wave = tid >> 6, lane = tid & 63;
   const int* cst = g.cellstart + (size_t)w * (g.ncell + 1);
-  const float4* __restrict__ xq = g.xyzq + (size_t)w * g.npad;
+  const float4* __restrict__ gs = g.gsten + (size_t)w * g.npad;
   const float4* __restrict__ pr = g.prm + (size_t)w * g.npad;
   const float le = g.lam[4 * w];
   __syncthreads();
@@ -412,9 +401,16 @@ __global__ __launch_bounds__(256) void k_spread(const LegDev* legs, BlockMap map
     const int ci = cb + tid;
     int s0 = 0, cnt = 0;
     if (ci < ncells) {
-      const int C[3] = {c0[0] + ci / (nspan[1] * nspan[2]), c0[1] + (ci / nspan[2]) % nspan[1],
-                        c0[2] + ci % nspan[2]};
-      const unsigned cc = g.hcell[(((C[0] % nc + nc) % nc) * nc + (C[1] % nc + nc) % nc) * nc + (C[2] % nc + nc) % nc];
+      // ci -> cell (float-reciprocal quotients, one correction each); a cell
+      // coordinate lies in (-nc, 2nc), so one wrap suffices
+      int q0 = (int)((float)ci * inv12);
+      q0 += (ci - q0 * n12 < 0) ? -1 : (ci - q0 * n12 >= n12 ? 1 : 0);
+      const int rem = ci - q0 * n12;
+      int q1 = (int)((float)rem * inv2);
+      q1 += (rem - q1 * nspan[2] < 0) ? -1 : (rem - q1 * nspan[2] >= nspan[2] ? 1 : 0);
+      const int C[3] = {c0[0] + q0, c0[1] + q1, c0[2] + rem - q1 * nspan[2]};
+      auto wrapc = [nc](int c) { return c < 0 ? c + nc : (c >= nc ? c - nc : c); };
+      const unsigned cc = g.hcell[(wrapc(C[0]) * nc + wrapc(C[1])) * nc + wrapc(C[2])];
       s0 = cst[cc];
       cnt = cst[cc + 1] - s0;
     }
@@ -443,11 +439,11 @@ __global__ __launch_bounds__(256) void k_spread(const LegDev* legs, BlockMap map
         if (t < T1) {
           const int l = s_cellof[t - T0];
           const int s = s_start[l] + (t - s_pre[l]);
-          const float4 rj = xq[s];
-          float fr[3];
-          const int b0 = grid_base(rj.x, g.invL[0], g.K[0], &fr[0]);
-          const int b1 = grid_base(rj.y, g.invL[1], g.K[1], &fr[1]);
-          const int b2 = grid_base(rj.z, g.invL[2], g.K[2], &fr[2]);
+          const float4 st = gs[s];               // stencil offsets and bases (from the pack)
+          int bb[3];
+          unpack_bases(st.w, bb);
+          const int b0 = bb[0], b1 = bb[1], b2 = bb[2];
+          const float fr[3] = {st.x, st.y, st.z};
           const unsigned mx = brick_mask(b0, g.K[0], P0[0], P1[0]);
           const unsigned my = brick_mask(b1, g.K[1], P0[1], P1[1]);
           const unsigned mz = brick_mask(b2, g.K[2], P0[2], P1[2]);
@@ -521,14 +517,14 @@ __global__ __launch_bounds__(256) void k_gather(const LegDev* legs, BlockMap map
   const size_t o = (size_t)w * g.n + a;
   const float4 pa = g.prm[lc];                  // sorted parameters: .z ligand flag, .w charge
   const float q = pa.w * (pa.z > 0.0f ? g.lam[4 * w] : 1.0f);
-  const float4 xa = g.xyzq[lc];
-  float fxr, fyr, fzr, wx[4], wy[4], wz[4], dx[4], dy[4], dz[4];
-  const int bx = grid_base(xa.x, g.invL[0], g.K[0], &fxr);
-  const int by = grid_base(xa.y, g.invL[1], g.K[1], &fyr);
-  const int bz = grid_base(xa.z, g.invL[2], g.K[2], &fzr);
-  bspline4(fxr, wx, dx);
-  bspline4(fyr, wy, dy);
-  bspline4(fzr, wz, dz);
+  const float4 st = g.gsten[lc];               // stencil offsets and bases (from the pack)
+  int bb[3];
+  unpack_bases(st.w, bb);
+  const int bx = bb[0], by = bb[1], bz = bb[2];
+  float wx[4], wy[4], wz[4], dx[4], dy[4], dz[4];
+  bspline4(st.x, wx, dx);
+  bspline4(st.y, wy, dy);
+  bspline4(st.z, wz, dz);
   int gz = bz - iz; if (gz < 0) gz += g.K[2];
   int gxv[4];
 #pragma unroll

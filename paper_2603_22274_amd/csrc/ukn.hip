@@ -51,18 +51,6 @@ __device__ __forceinline__ void bspline4(float f, float* w) {
   w[3] = g1 * g1 * g1 * (1.0f / 6.0f);
 }
 
-__device__ __forceinline__ int grid_base(float x, double invL, int K, float* f) {
-  double u = (double)x * invL * (double)K;
-  if (!(fabs(u) < 1.0e15)) u = 0.0;              // non-finite input -> 0 (keeps indices in range)
-  const double b = floor(u);
-  *f = (float)(u - b);
-  // b mod K without 64-bit integer division: |b| < 2^53, so the FP64 floor
-  // of b / K is off by at most one, which the integer fix-ups absorb
-  int k = (int)(b - (double)K * floor(b * (1.0 / (double)K)));
-  if (k < 0) k += K;
-  if (k >= K) k -= K;
-  return k;
-}
 
 __device__ __forceinline__ float3 min_img(const LegDev& g, float dx, float dy, float dz) {
   dx = fmaf(-g.Lf[0], rintf(dx * g.invLf[0]), dx);
