@@ -6,8 +6,9 @@ benchmark's CPU-baseline leg use it.  It shares no code with the HIP path:
 brute-force O(N^2) pair sums, direct Ewald, an independently written FP64
 smooth PME (numpy FFTs), bonded and Boresch terms, a Langevin-middle step with
 iterative SHAKE constraints and a Philox noise stream written from its
-published definition, the cross-lambda reduced potentials and a plain
-self-consistent MBAR.
+published definition, the cross-lambda reduced potentials, a plain
+self-consistent MBAR and Metropolis replica exchange between neighbouring
+windows.
 
 Citations name the paper's sections:
   * "Double annihilation protocol" -- Beutler softcore form, Lorentz-Berthelot
@@ -24,5 +25,6 @@ Philox), the oracle follows the method's own publication.
 Pinned by tests in ``tests/test_oracle_*.py`` (Madelung and Wigner constants,
 alpha independence, lambda end points, finite differences, Newton's third
 law, NVE drift, harmonic-oscillator statistics, analytic harmonic free
-energies, BAR and EXP reductions, Philox known-answer vectors).
+energies, BAR and EXP reductions, Philox known-answer vectors, the exact
+stationary distribution of replica exchange over permutations).
 """
