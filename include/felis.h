@@ -194,7 +194,11 @@ int felis_bonded(felis_ctx* ctx, felis_leg* legs, int n_legs, int flags);
  * SETTLE on rigid waters; v += (x_constrained - x_unconstrained)/dt, with
  * a = exp(-gamma dt) and xi from Philox4x32-10 keyed by (leg seed) and
  * counted by (atom, window, step), so a window's trajectory does not depend
- * on the batch it runs in.  Each leg's `step` advances by n_steps. */
+ * on the batch it runs in.  Each leg's `step` advances by n_steps.  Reciprocal
+ * space runs on a second stream owned by the context, forked after the cell
+ * sort and joined before the integrator, so all of the call's work is ordered
+ * on the context's stream; after the call fx/fy/fz hold the total force of
+ * the last step. */
 int felis_step(felis_ctx* ctx, felis_leg* legs, int n_legs, int n_steps, double dt,
                double temperature, double gamma);
 
@@ -208,6 +212,27 @@ int felis_ukn(felis_ctx* ctx, felis_leg* leg, const double* lambdas, int K, cons
               const float* fy, const float* fz, int64_t frame_stride, int64_t n_frames,
               double beta, double* u, int64_t u_stride);
 
+/* Hamiltonian replica exchange among the windows of one leg (simulation
+ * details: exchanges among one GPU's windows every 5 ps).  The leg's windows
+ * are replicas; window r holds state state_of_replica[r] (identity after
+ * felis_leg_init), and every kernel uses the lambda row of the state a replica
+ * holds.  One attempt swaps neighbouring states: pairs (0,1), (2,3), ... when
+ * `attempt` is even, (1,2), (3,4), ... when odd; the swap of states s, s+1
+ * held by replicas i, j is taken when D = u[s][j] + u[s+1][i] - u[s][i] -
+ * u[s+1][j] <= 0 or U < exp(-D), U from Philox4x32-10 on counter
+ * (s, 0x48524558, attempt) with key `seed`.  u (dev, FP64): u[k * u_stride + r]
+ * is the reduced potential of replica r's current coordinates in state k
+ * (felis_ukn of the leg's own lambda table over its n_windows current frames);
+ * u_stride >= n_windows.  Coordinates, velocities and lists stay with their
+ * replica.  n_accepted (host, may be NULL) receives the number of swaps taken
+ * (synchronises when given).  FELIS_E_UNSUPPORTED above 256 windows. */
+int felis_hrex(felis_ctx* ctx, felis_leg* leg, const double* u, int64_t u_stride, int64_t attempt, uint64_t seed,
+               int32_t* n_accepted);
+
+/* State held by each replica: state_of_replica (host) [n_windows].
+ * Synchronises the stream. */
+int felis_leg_states(felis_ctx* ctx, const felis_leg* leg, int32_t* state_of_replica);
+
 /* Kernel timing with HIP events recorded on the context's stream around the
  * launches of one stage inside felis_step / felis_ukn (the events bracket
  * exactly the stage's kernels, so their elapsed time is the stage's device
@@ -216,7 +241,9 @@ int felis_ukn(felis_ctx* ctx, felis_leg* leg, const double* lambdas, int K, cons
  * launches for stage `which` since the last read, and resets it. */
 enum {
   FELIS_PROF_PAIRS = 0,     /* the real-space pair kernel */
-  FELIS_PROF_PME = 1,       /* spreading, five FFT passes, gather */
+  FELIS_PROF_PME = 1,       /* spreading, FFT passes, gather (in felis_step on the context's
+                               second stream, sharing compute units with the list build and the
+                               pair kernel) */
   FELIS_PROF_NLIST = 2,     /* displacement check and list rebuild */
   FELIS_PROF_INTEGRATE = 3, /* Langevin-middle update with SETTLE */
   FELIS_PROF_UKN = 4,       /* one felis_ukn call */

@@ -30,6 +30,7 @@ UNITS = {
     'integrate.hip': [],
     'ukn.hip': [],
     'mbar.hip': [],
+    'hrex.hip': [],
     'felis.cpp': [],
 }
 

@@ -18,7 +18,7 @@ using namespace felis;
 namespace {
 
 struct Layout {
-  size_t lam, free_atoms, lig_idx, xr, yr, zr, flag, nbuild, maxdisp, wmax, hcell, hcoarse, perm, cellcode, cellstart, cursor, xyzq, prm, bblo,
+  size_t lam, lamS, rstate, free_atoms, lig_idx, xr, yr, zr, flag, nbuild, maxdisp, wmax, hcell, hcoarse, perm, cellcode, cellstart, cursor, xyzq, prm, bblo,
       bbhi, gsten, lcount, lent, frx, fry, frz, grid64, cgrid, tw[3], bmod[3], eacc, uacc, upart, lpart, ucst, total;
 };
 
@@ -154,6 +154,8 @@ int make_plan(felis_ctx* c, const felis_leg* L, Plan& P) {
   auto put = [&](size_t bytes) { size_t r = o; o += al(bytes); return r; };
   const size_t W = h.W, n = h.n, npad = h.npad, nc = h.nclus;
   y.lam = put(W * 4 * sizeof(float));
+  y.lamS = put(W * 4 * sizeof(float));
+  y.rstate = put(W * 4);
   y.free_atoms = put(n * 4);
   y.lig_idx = put(n * 4);
   y.hcell = put((size_t)h.ncell * 4);            // filled once at set-up (outside every cleared range)
@@ -234,6 +236,8 @@ LegDev make_dev(const felis_ctx* c, const felis_leg* L, const Plan& p, const Met
   char* w = (char*)L->work;
   const Layout& y = p.lay;
   g.lam = (float*)(w + y.lam);
+  g.lamS = (const float*)(w + y.lamS);
+  g.rstate = (int*)(w + y.rstate);
   g.free_atoms = (int*)(w + y.free_atoms);
   g.lig_idx = (int*)(w + y.lig_idx);
   g.xr = (float*)(w + y.xr); g.yr = (float*)(w + y.yr); g.zr = (float*)(w + y.zr);
@@ -420,6 +424,19 @@ int felis_leg_rebuilds(felis_ctx* c, const felis_leg* L, int64_t* counts) {
   return FELIS_OK;
 }
 
+int felis_leg_states(felis_ctx* c, const felis_leg* L, int32_t* state_of_replica) {
+  if (!c || !state_of_replica) return FELIS_E_INVAL;
+  Plan p;
+  int rc = make_plan(c, L, p);
+  if (rc) return rc;
+  if (!L->work || L->work_bytes < p.lay.total) return fail(c, FELIS_E_INVAL, "leg work buffer too small");
+  if (hipStreamSynchronize(c->stream) != hipSuccess ||
+      hipMemcpy(state_of_replica, (char*)L->work + p.lay.rstate, sizeof(int32_t) * p.h.W, hipMemcpyDeviceToHost) !=
+          hipSuccess)
+    return fail(c, FELIS_E_DEVICE, "replica states unreadable");
+  return FELIS_OK;
+}
+
 int felis_leg_init(felis_ctx* c, felis_leg* L) {
   if (!c) return FELIS_E_INVAL;
   Plan p;
@@ -457,6 +474,12 @@ int felis_leg_init(felis_ctx* c, felis_leg* L) {
     lam[4 * k + 3] = (float)(L->sc_alpha * (1.0 - lv));
   }
   bool ok = hipMemcpy(w + y.lam, lam.data(), lam.size() * 4, hipMemcpyHostToDevice) == hipSuccess;
+  ok &= hipMemcpy(w + y.lamS, lam.data(), lam.size() * 4, hipMemcpyHostToDevice) == hipSuccess;
+  {
+    std::vector<int> ident(h.W);
+    for (int k = 0; k < h.W; ++k) ident[k] = k;
+    ok &= hipMemcpy(w + y.rstate, ident.data(), ident.size() * 4, hipMemcpyHostToDevice) == hipSuccess;
+  }
   if (!freeat.empty()) ok &= hipMemcpy(w + y.free_atoms, freeat.data(), freeat.size() * 4, hipMemcpyHostToDevice) == hipSuccess;
   if (!ligi.empty()) ok &= hipMemcpy(w + y.lig_idx, ligi.data(), ligi.size() * 4, hipMemcpyHostToDevice) == hipSuccess;
   {
@@ -636,6 +659,24 @@ int felis_ukn(felis_ctx* c, felis_leg* leg, const double* lambdas, int K, const 
   mark(c, FELIS_PROF_UKN, true);
   if (rc) return fail(c, rc, "u_kn: more than 128 states, 64 distinct lambda_vdw or 256 ligand atoms");
   return launched(c);
+}
+
+int felis_hrex(felis_ctx* c, felis_leg* leg, const double* u, int64_t u_stride, int64_t attempt, uint64_t seed,
+               int32_t* n_accepted) {
+  std::vector<LegHost> hs;
+  int rc = prepare(c, leg, 1, hs);
+  if (rc) return rc;
+  if (!u || u_stride < leg->n_windows || attempt < 0) return fail(c, FELIS_E_INVAL, "replica exchange arguments");
+  if (leg->n_windows > kMaxHrex) return fail(c, FELIS_E_UNSUPPORTED, "replica exchange among at most 256 windows");
+  int* acc = reinterpret_cast<int*>(c->d_count);
+  launch_hrex(c->stream, c->d_legs, hs[0], u, u_stride, attempt, seed, acc);
+  if ((rc = launched(c))) return rc;
+  if (n_accepted) {
+    if (hipMemcpyAsync(n_accepted, acc, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess)
+      return fail(c, FELIS_E_DEVICE, "replica exchange count copy failed");
+  }
+  return FELIS_OK;
 }
 
 int felis_profile(felis_ctx* c, int enable) {

@@ -16,6 +16,7 @@ constexpr int kMaxLigand = 256;     // ligand atoms handled by the u_kn kernels
 constexpr int kMaxLamV = 64;        // distinct lambda_vdw values per u_kn call
 constexpr int kMaxStates = 128;     // lambda states per u_kn call
 constexpr int kMaxRadix = 8;        // FFT stages per axis
+constexpr int kMaxHrex = 256;       // most windows a leg may exchange among
 constexpr int kMaxFFT = 128;        // largest PME grid dimension (bases pack in 7 bits)
 constexpr int kClus = 8;            // atoms per i-cluster (pair kernel)
 
@@ -64,7 +65,10 @@ struct LegDev {
   long long *fx, *fy, *fz;
   double* energy;                       // [W][FELIS_NE]
   // workspace (library-owned layout)
-  float* lam;                           // [W][4] elec, vdw, restraint, sc_alpha*(1-vdw)
+  float* lam;                           // [W][4] per replica: elec, vdw, restraint, sc_alpha*(1-vdw) of
+                                        // the state it holds
+  const float* lamS;                    // [W][4] the same rows in state order (the leg's lambda table)
+  int* rstate;                          // [W] state held by each replica (identity until an exchange)
   int* free_atoms;                      // [nfree] atoms not in a rigid water
   int* lig_idx;                         // [nlig] ligand atoms
   float *xr, *yr, *zr;                  // [W][n] positions at the last list build
@@ -181,6 +185,20 @@ __device__ __forceinline__ void unpack_bases(float v, int* b) {
   b[0] = u & 127; b[1] = (u >> 7) & 127; b[2] = (u >> 14) & 127;
 }
 
+// Philox4x32-10 (Salmon et al. 2011): ten rounds on the counter c with key
+// (k0, k1); the output words replace c.
+__device__ __forceinline__ void philox(unsigned c[4], unsigned k0, unsigned k1) {
+  const unsigned M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const unsigned hi0 = __umulhi(M0, c[0]), lo0 = M0 * c[0];
+    const unsigned hi1 = __umulhi(M1, c[2]), lo1 = M1 * c[2];
+    const unsigned n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+    c[0] = n0; c[1] = lo1; c[2] = n2; c[3] = lo0;
+    k0 += 0x9E3779B9u; k1 += 0xBB67AE85u;
+  }
+}
+
 __host__ __device__ inline unsigned hilbert3(unsigned x, unsigned y, unsigned z, int bits) {
   unsigned X[3] = {x, y, z};
   for (unsigned Q = 1u << (bits - 1); Q > 1u; Q >>= 1) {
@@ -253,6 +271,8 @@ void launch_zero_energy(hipStream_t s, const LegDev* d, const LegHost* h, int nl
 void launch_finish_energy(hipStream_t s, const LegDev* d, const LegHost* h, int nl, int c0, int c1);
 void launch_fill_i64(hipStream_t s, long long* p, size_t n);
 void launch_pme_fft(hipStream_t s, const LegDev* d, const LegHost* h, int nl, bool from_int64);
+void launch_hrex(hipStream_t s, const LegDev* d, const LegHost& h, const double* u, long long u_stride,
+                 long long attempt, unsigned long long seed, int* accepted);
 int launch_ukn(hipStream_t s, const LegDev* d, const LegHost& h, double sc_alpha, const double* lambdas,
                int K, const float* fx, const float* fy, const float* fz, long long frame_stride,
                long long n_frames, double beta, double* u, long long u_stride, long long* uacc,

@@ -14,18 +14,6 @@
 namespace felis {
 namespace {
 
-__device__ __forceinline__ void philox(unsigned c[4], unsigned k0, unsigned k1) {
-  const unsigned M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
-#pragma unroll
-  for (int r = 0; r < 10; ++r) {
-    const unsigned hi0 = __umulhi(M0, c[0]), lo0 = M0 * c[0];
-    const unsigned hi1 = __umulhi(M1, c[2]), lo1 = M1 * c[2];
-    const unsigned n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
-    c[0] = n0; c[1] = lo1; c[2] = n2; c[3] = lo0;
-    k0 += 0x9E3779B9u; k1 += 0xBB67AE85u;
-  }
-}
-
 __device__ __forceinline__ v3 noise3(unsigned long long seed, int window, long long step, int atom) {
   unsigned c[4] = {(unsigned)atom, (unsigned)window, (unsigned)(step & 0xffffffffll),
                    (unsigned)((unsigned long long)step >> 32)};

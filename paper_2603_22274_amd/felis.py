@@ -74,6 +74,8 @@ def lib():
         'felis_leg_init': (C.c_int, [vp, P(FelisLeg)]),
         'felis_build_nlist': (C.c_int, [vp, P(FelisLeg), C.c_int, C.c_int]),
         'felis_leg_rebuilds': (C.c_int, [vp, P(FelisLeg), vp]),
+        'felis_leg_states': (C.c_int, [vp, P(FelisLeg), vp]),
+        'felis_hrex': (C.c_int, [vp, P(FelisLeg), vp, C.c_int64, C.c_int64, C.c_uint64, vp]),
         'felis_nlist_export_pairs': (C.c_int, [vp, P(FelisLeg), C.c_int, C.c_double, vp, C.c_int64, P(C.c_int64)]),
         'felis_nonbonded': (C.c_int, [vp, P(FelisLeg), C.c_int, C.c_int]),
         'felis_pme': (C.c_int, [vp, P(FelisLeg), C.c_int, C.c_int]),
@@ -290,6 +292,23 @@ def leg_rebuilds(ctx, leg):
     out = np.zeros(leg.n_windows, np.int64)
     ctx.check(lib().felis_leg_rebuilds(ctx.h, C.byref(leg.s), out.ctypes.data_as(C.c_void_p)))
     return out
+
+
+def leg_states(ctx, leg):
+    """State (index into the leg's lambda table) held by each replica (numpy int32)."""
+    out = np.zeros(leg.n_windows, np.int32)
+    ctx.check(lib().felis_leg_states(ctx.h, C.byref(leg.s), out.ctypes.data_as(C.c_void_p)))
+    return out
+
+
+def hrex(ctx, leg, u, attempt, seed, count=True):
+    """One replica-exchange attempt among the leg's windows from u[state][replica]
+    (device float64, at least n_windows columns).  Returns the number of swaps
+    taken (synchronises) when ``count``, else None."""
+    n = C.c_int32(0)
+    ctx.check(lib().felis_hrex(ctx.h, C.byref(leg.s), _ptr(u), u.stride(0), int(attempt), int(seed) & (2**64 - 1),
+                               C.byref(n) if count else None))
+    return n.value if count else None
 
 
 def nlist_export_pairs(ctx, leg, window, r=None, cap=None):
