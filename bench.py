@@ -103,6 +103,8 @@ def main():
     ap.add_argument('--no-cpu-baseline', action='store_true')
     ap.add_argument('--no-per-window', action='store_true')
     ap.add_argument('--equil', type=int, default=200, help='untimed equilibration MD steps')
+    ap.add_argument('--hrex-every', type=int, default=2500,
+                    help='MD steps between replica-exchange attempts among the windows (0: none); 5 ps as in the paper')
     ap.add_argument('--serve-legs', type=int, default=8, help='legs in the served mixed workload (0: skip)')
     ap.add_argument('--copy-calibration', action='store_true',
                     help='run a plain 256 MiB device copy first (reference for traffic counters)')
@@ -137,10 +139,17 @@ def main():
     n_samples = args.steps
     u = torch.empty((W, W * n_samples), dtype=torch.float64, device='cuda')
 
+    md_done = [0]
+    attempts = [0]
+
     def bench_step(k, timed):
         felis.step(ctx, [leg], args.md, DT, 300.0, 0.5)
         col = u[:, k * W:(k + 1) * W] if timed else None
-        felis.ukn(ctx, leg, sysd.lambdas, leg.x, leg.y, leg.z, beta, out=col)
+        col = felis.ukn(ctx, leg, sysd.lambdas, leg.x, leg.y, leg.z, beta, out=col)
+        md_done[0] += args.md
+        if args.hrex_every and md_done[0] % args.hrex_every == 0:
+            felis.hrex(ctx, leg, col, attempts[0], 22274, count=False)   # from this sample's u_kn
+            attempts[0] += 1
 
     for k in range(args.warmup):
         bench_step(0, False)
@@ -176,6 +185,17 @@ def main():
     achieved = flops / avg_pairs_s / 1e12
     traffic = _traffic()
     dg = float((f[-1] - f[0]) / beta) if f is not None else None
+    timed_attempts = attempts[0]
+    # device time of one replica-exchange attempt (its u_kn is the sample's)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ucol = u[:, :W]
+    felis.hrex(ctx, leg, ucol, attempts[0], 22274, count=False)
+    ev0.record()
+    for k in range(10):
+        felis.hrex(ctx, leg, ucol, attempts[0] + 1 + k, 22274, count=False)
+    ev1.record()
+    torch.cuda.synchronize()
+    hrex_us = ev0.elapsed_time(ev1) / 10 * 1000.0
 
     per_window = None
     if not args.no_per_window:
@@ -221,6 +241,9 @@ def main():
         "per_window_form": per_window,
         "stage_ms_per_md_step": {k: v[0] / max(v[1], 1) for k, v in prof.items() if k != 'ukn'},
         "ukn_ms_per_call": prof['ukn'][0] / max(prof['ukn'][1], 1),
+        "replica_exchange": {"every_md_steps": args.hrex_every, "attempts_in_timed_region": timed_attempts,
+                             "attempt_us": hrex_us,
+                             "note": "neighbour swaps from the sample-time u_kn; one single-workgroup kernel"},
         "mbar": {"converged": mbar_ok, "iterations": iters, "dG_kcal_per_mol": dg},
         "leg_latency_s": {"p50": wall, "p99": wall, "legs": 1,
                           "note": "one leg in this workload; the served mixed batch reports its own"},

@@ -315,6 +315,11 @@ __global__ __launch_bounds__(256) void k_build(const LegDev* legs, BlockMap map)
     const int a = perm[c * kClus + tid];
     s_ai[tid] = a;
     int ne = 0;
+    // a padding slot gets defined (zero) coordinates: nothing downstream may
+    // depend on what an earlier workgroup left in LDS
+    s_xi[tid][0] = 0.f;
+    s_xi[tid][1] = 0.f;
+    s_xi[tid][2] = 0.f;
     if (a >= 0) {
       s_xi[tid][0] = g.x[o + a];
       s_xi[tid][1] = g.y[o + a];
@@ -380,7 +385,7 @@ __global__ __launch_bounds__(256) void k_build(const LegDev* legs, BlockMap map)
   float m2[kClus][3], nc2[kClus];
 #pragma unroll
   for (int ii = 0; ii < kClus; ++ii) {
-    for (int d = 0; d < 3; ++d) m2[ii][d] = scalar(-2.0f * ri[ii][d]);
+    for (int d = 0; d < 3; ++d) m2[ii][d] = scalar(ai[ii] >= 0 ? -2.0f * ri[ii][d] : 0.0f);
     nc2[ii] = scalar(ai[ii] >= 0 ? -__fmaf_rn(ri[ii][0], ri[ii][0], __fmaf_rn(ri[ii][1], ri[ii][1], ri[ii][2] * ri[ii][2]))
                                  : -1.0e30f);
   }

@@ -42,6 +42,8 @@ class Request:
     sample_every: int         # steps between u_kn samples
     seed: int = 1
     list_cap: int = 0         # neighbour-list capacity per cluster (0: library default)
+    exchange_every: int = 0   # MD steps between replica-exchange attempts among the leg's windows
+                              # (a multiple of sample_every; 0: none; the paper uses 5 ps)
 
 
 @dataclasses.dataclass
@@ -122,7 +124,10 @@ class Server:
             res = results[r.rid]
             if exc.needed_cap > 0 and res.retries < self.max_retries:
                 res.retries += 1
-                cap = (int(exc.needed_cap * 1.25) + 7) // 8 * 8
+                # the failed epoch ran on truncated lists (wrong forces), so the
+                # longest list it saw understates the lists of the correct run:
+                # retry with twice that length
+                cap = (2 * int(exc.needed_cap) + 7) // 8 * 8
                 waiting.insert(0, dataclasses.replace(r, list_cap=cap))
                 self.log.append({'t': now(), 'event': 'retry', 'rid': r.rid, 'list_cap': cap})
             else:
@@ -217,7 +222,7 @@ class FelisEngine:
     def admit(self, r):
         import torch
         leg = self.felis.Leg(self.ctx, r.sysd, seed=r.seed, list_cap=r.list_cap or self.list_cap)
-        h = types.SimpleNamespace(leg=leg, req=r, k=0)     # first step builds every window's list
+        h = types.SimpleNamespace(leg=leg, req=r, k=0, attempts=0)   # first step builds every window's list
         W = leg.n_windows
         h.u = torch.empty((W, W * (r.n_steps // r.sample_every)), dtype=torch.float64, device=leg.x.device)
         return h
@@ -240,8 +245,13 @@ class FelisEngine:
     def sample(self, h):
         f = self.felis
         W = h.leg.n_windows
-        f.ukn(self.ctx, h.leg, h.leg.lambdas, h.leg.x, h.leg.y, h.leg.z, self.beta,
-              out=h.u[:, h.k * W:(h.k + 1) * W])
+        col = h.u[:, h.k * W:(h.k + 1) * W]
+        f.ukn(self.ctx, h.leg, h.leg.lambdas, h.leg.x, h.leg.y, h.leg.z, self.beta, out=col)
+        r = h.req
+        if r.exchange_every and ((h.k + 1) * r.sample_every) % r.exchange_every == 0:
+            # replica exchange from this sample's u[state][replica] (no host sync)
+            f.hrex(self.ctx, h.leg, col, h.attempts, r.seed, count=False)
+            h.attempts += 1
         try:
             self.ctx.device_check()
         except f.FelisError as e:

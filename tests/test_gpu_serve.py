@@ -42,6 +42,25 @@ def legs():
     return a, gen.sized_leg(3300, 20, 6), gen.sized_leg(4000, 42, 7)
 
 
+def test_step_repeatable_from_scratch(F, legs):
+    """A leg stepped from its initial state gives the same bits whatever ran
+    on the device before (clusters with padding slots included: 3298 atoms)."""
+    felis, ctx = F
+    _, B, C = legs
+
+    def run(sysd, steps):
+        leg = felis.Leg(ctx, sysd, seed=22)
+        felis.step(ctx, [leg], steps)
+        ctx.device_check()
+        return _state(leg)
+
+    first = run(B, 3)
+    run(C, 5)                                   # other kernels leave other LDS and cache contents
+    run(gen.config1(), 2)
+    again = run(B, 3)
+    assert all(torch.equal(p, q) for p, q in zip(first, again))
+
+
 def _state(leg):
     return [t.clone() for t in (leg.x, leg.y, leg.z, leg.vx, leg.vy, leg.vz, leg.fx, leg.fy, leg.fz)]
 
@@ -94,9 +113,9 @@ def _serve(ctx, reqs, **kw):
     return srv.serve(reqs)
 
 
-def _req(rid, sysd, t, seed, cap=0):
+def _req(rid, sysd, t, seed, cap=0, exchange_every=0):
     from paper_2603_22274_amd.serve import Request
-    return Request(rid, t, sysd, n_steps=40, sample_every=10, seed=seed, list_cap=cap)
+    return Request(rid, t, sysd, n_steps=40, sample_every=10, seed=seed, list_cap=cap, exchange_every=exchange_every)
 
 
 def test_served_dg_alone_equals_mixed(F, legs):
@@ -111,6 +130,20 @@ def test_served_dg_alone_equals_mixed(F, legs):
     assert a.dG == m.dG and a.mbar_iters == m.mbar_iters
     assert stats['completed'] == 3
     assert 0 < stats['latency_p50_s'] <= stats['latency_p99_s']
+
+
+def test_served_replica_exchange_alone_equals_mixed(F, legs):
+    """Replica exchange every two samples: the leg's swaps, and so its dG,
+    depend only on its own u_kn and seed, whatever runs beside it."""
+    felis, ctx = F
+    A, B, C = legs
+    alone, _ = _serve(ctx, [_req(0, A, 0.0, 21, exchange_every=20)])
+    mixed, _ = _serve(ctx, [_req(1, B, 0.0, 22, exchange_every=20), _req(0, A, 0.0, 21, exchange_every=20),
+                            _req(2, C, 0.02, 23)])
+    a = alone[0]
+    m = next(r for r in mixed if r.rid == 0)
+    assert a.status == 'ok' and m.status == 'ok' and a.dG is not None
+    assert a.dG == m.dG and a.mbar_iters == m.mbar_iters
 
 
 def test_capacity_retry_and_eviction_isolated(F, legs):

@@ -169,7 +169,7 @@ def test_capacity_failure_requeued_with_larger_list():
     assert [r.status for r in out] == ['ok'] * 3
     assert out[1].retries == 1
     retry = [e for e in srv.log if e['event'] == 'retry']
-    assert retry == [{'t': retry[0]['t'], 'event': 'retry', 'rid': 1, 'list_cap': 128}]
+    assert retry == [{'t': retry[0]['t'], 'event': 'retry', 'rid': 1, 'list_cap': 200}]
     assert out[1].steps == 200 and eng.samples[1] == 4       # counted afresh after the retry
     assert eng.live == {}
 
