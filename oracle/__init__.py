@@ -7,8 +7,9 @@ brute-force O(N^2) pair sums, direct Ewald, an independently written FP64
 smooth PME (numpy FFTs), bonded and Boresch terms, a Langevin-middle step with
 iterative SHAKE constraints and a Philox noise stream written from its
 published definition, the cross-lambda reduced potentials, a plain
-self-consistent MBAR and Metropolis replica exchange between neighbouring
-windows.
+self-consistent MBAR, Metropolis replica exchange between neighbouring
+windows, and the segmented free-energy assembly with the analytic restraint
+term.
 
 Citations name the paper's sections:
   * "Double annihilation protocol" -- Beutler softcore form, Lorentz-Berthelot
@@ -26,5 +27,6 @@ Pinned by tests in ``tests/test_oracle_*.py`` (Madelung and Wigner constants,
 alpha independence, lambda end points, finite differences, Newton's third
 law, NVE drift, harmonic-oscillator statistics, analytic harmonic free
 energies, BAR and EXP reductions, Philox known-answer vectors, the exact
-stationary distribution of replica exchange over permutations).
+stationary distribution of replica exchange over permutations, the analytic
+restraint term against quadrature of the restrained partition function).
 """
