@@ -49,10 +49,11 @@ def boresch_restraint_dg(g0, k, temperature=300.0, v0=V0):
 
 def segments(n_windows, n_segments):
     """Window index lists of n_segments overlapping segments covering
-    0..n_windows-1; neighbouring segments share their boundary window."""
+    0..n_windows-1; neighbouring segments share their boundary window, the
+    s-th boundary being window floor(s (n_windows - 1) / n_segments)."""
     if n_segments < 1 or n_windows < n_segments + 1:
         raise ValueError('need at least two windows per segment')
-    cuts = [round(s * (n_windows - 1) / n_segments) for s in range(n_segments + 1)]
+    cuts = [s * (n_windows - 1) // n_segments for s in range(n_segments + 1)]
     return [list(range(cuts[s], cuts[s + 1] + 1)) for s in range(n_segments)]
 
 
