@@ -233,6 +233,19 @@ int felis_hrex(felis_ctx* ctx, felis_leg* leg, const double* u, int64_t u_stride
  * Synchronises the stream. */
 int felis_leg_states(felis_ctx* ctx, const felis_leg* leg, int32_t* state_of_replica);
 
+/* Free energy (kcal/mol, written to *dg) of imposing the Boresch restraints
+ * on the decoupled ligand from the 1 mol/L standard state (V0 = 1660.539 A^3),
+ * the analytic term of dG_bind = dG_solvent - dG_complex + dG_restrain (figure 1,
+ * section "Restraints").  The paper's closed form is not printed; this is the
+ * harmonic-limit expression of Boresch et al. 2003:
+ *   kT ln[8 pi^2 V0 sqrt(k_r k_thA k_thB k_phA k_phB k_phC) / (r0^2 sin thA0 sin thB0 (2 pi kT)^3)]
+ * with the cosine dihedrals k[1 - cos] at their second-order limit.  g0, k
+ * (host) [6] in the leg's restraint order (distance, the angles at L1 and P1,
+ * the three dihedrals; A, rad, kcal/mol/A^2, kcal/mol/rad^2).  Host arithmetic
+ * only (no context, no device).  FELIS_E_INVAL unless every k > 0, r0 > 0,
+ * 0 < thA0, thB0 < pi and temperature > 0. */
+int felis_restraint_dg(const double* g0, const double* k, double temperature, double* dg);
+
 /* Kernel timing with HIP events recorded on the context's stream around the
  * launches of one stage inside felis_step / felis_ukn (the events bracket
  * exactly the stage's kernels, so their elapsed time is the stage's device

@@ -679,6 +679,22 @@ int felis_hrex(felis_ctx* c, felis_leg* leg, const double* u, int64_t u_stride, 
   return FELIS_OK;
 }
 
+int felis_restraint_dg(const double* g0, const double* k, double temperature, double* dg) {
+  if (!g0 || !k || !dg || !(temperature > 0) || !std::isfinite(temperature)) return FELIS_E_INVAL;
+  double prodk = 1.0;
+  for (int t = 0; t < 6; ++t) {
+    if (!(k[t] > 0) || !std::isfinite(k[t]) || !std::isfinite(g0[t])) return FELIS_E_INVAL;
+    prodk *= k[t];
+  }
+  if (!(g0[0] > 0) || !(g0[1] > 0 && g0[1] < M_PI) || !(g0[2] > 0 && g0[2] < M_PI)) return FELIS_E_INVAL;
+  const double kT = kKB * temperature;
+  const double v0 = 1660.5390;                       // A^3 per molecule at 1 mol/L
+  const double num = 8.0 * M_PI * M_PI * v0 * std::sqrt(prodk);
+  const double den = g0[0] * g0[0] * std::sin(g0[1]) * std::sin(g0[2]) * std::pow(2.0 * M_PI * kT, 3);
+  *dg = kT * std::log(num / den);
+  return FELIS_OK;
+}
+
 int felis_profile(felis_ctx* c, int enable) {
   if (!c) return FELIS_E_INVAL;
   c->prof = enable != 0;

@@ -75,6 +75,7 @@ def lib():
         'felis_build_nlist': (C.c_int, [vp, P(FelisLeg), C.c_int, C.c_int]),
         'felis_leg_rebuilds': (C.c_int, [vp, P(FelisLeg), vp]),
         'felis_leg_states': (C.c_int, [vp, P(FelisLeg), vp]),
+        'felis_restraint_dg': (C.c_int, [vp, vp, C.c_double, P(C.c_double)]),
         'felis_hrex': (C.c_int, [vp, P(FelisLeg), vp, C.c_int64, C.c_int64, C.c_uint64, vp]),
         'felis_nlist_export_pairs': (C.c_int, [vp, P(FelisLeg), C.c_int, C.c_double, vp, C.c_int64, P(C.c_int64)]),
         'felis_nonbonded': (C.c_int, [vp, P(FelisLeg), C.c_int, C.c_int]),
@@ -299,6 +300,21 @@ def leg_states(ctx, leg):
     out = np.zeros(leg.n_windows, np.int32)
     ctx.check(lib().felis_leg_states(ctx.h, C.byref(leg.s), out.ctypes.data_as(C.c_void_p)))
     return out
+
+
+def restraint_dg(g0, k, temperature=300.0):
+    """Free energy (kcal/mol) of imposing the Boresch restraints on the decoupled
+    ligand from the 1 mol/L standard state (host computation in the library)."""
+    g = np.ascontiguousarray(g0, np.float64)
+    kk = np.ascontiguousarray(k, np.float64)
+    if g.shape != (6,) or kk.shape != (6,):
+        raise ValueError('six restraint geometries and force constants')
+    out = C.c_double(0.0)
+    rc = lib().felis_restraint_dg(g.ctypes.data_as(C.c_void_p), kk.ctypes.data_as(C.c_void_p), float(temperature),
+                                  C.byref(out))
+    if rc:
+        raise FelisError(rc, 'restraint term: invalid geometry, force constants or temperature')
+    return out.value
 
 
 def hrex(ctx, leg, u, attempt, seed, count=True):

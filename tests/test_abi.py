@@ -149,3 +149,22 @@ extern "C" void settle_many(int n, const float* old, float* nw, float mO, float 
     # constraints met in FP32
     r = np.linalg.norm(got[0::3] - got[1::3], axis=1)
     assert np.max(np.abs(r - s.d_oh)) < 1e-5
+
+
+def test_restraint_term_matches_oracle_on_the_host():
+    """felis_restraint_dg is host arithmetic: it runs without a device."""
+    import math
+    from oracle import estimator as oest
+    from paper_2603_22274_amd import felis
+    rng = np.random.default_rng(8)
+    for _ in range(20):
+        g0 = np.array([rng.uniform(3, 9), rng.uniform(0.3, 2.8), rng.uniform(0.3, 2.8),
+                       rng.uniform(-3, 3), rng.uniform(-3, 3), rng.uniform(-3, 3)])
+        k = rng.uniform(1.0, 200.0, 6)
+        T = rng.uniform(250.0, 350.0)
+        assert math.isclose(felis.restraint_dg(g0, k, T), oest.boresch_restraint_dg(g0, k, T), rel_tol=1e-13)
+    good_g, good_k = np.array([5.0, 1.5, 1.5, 0, 0, 0]), np.full(6, 10.0)
+    for g, k, T in ((good_g, -good_k, 300.0), (np.array([0.0, 1.5, 1.5, 0, 0, 0]), good_k, 300.0),
+                    (np.array([5.0, 3.2, 1.5, 0, 0, 0]), good_k, 300.0), (good_g, good_k, 0.0)):
+        with pytest.raises(felis.FelisError):
+            felis.restraint_dg(g, k, T)

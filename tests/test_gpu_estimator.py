@@ -1,0 +1,59 @@
+"""Segmented free-energy assembly on the GPU against the oracle: the 42-window
+small complex leg run as three overlapping segments (each its own leg, all in
+one batch, boundary windows duplicated), each segment's u_kn at its own
+states from its own frames, MBAR per segment on the device; the segment sum
+and the binding assembly against the oracle's MBAR on the same u_kn."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import estimator as oest
+from paper_2603_22274_amd import gen
+
+pytestmark = pytest.mark.gpu
+
+KB = 0.0019872043
+T = 300.0
+BETA = 1.0 / (KB * T)
+
+
+@pytest.fixture(scope='module')
+def F():
+    if not torch.cuda.is_available():
+        pytest.skip('no HIP device')
+    from paper_2603_22274_amd import felis
+    ctx = felis.Context(0)
+    yield felis, ctx
+    torch.cuda.synchronize()
+    ctx.close()
+
+
+def test_segmented_dg_and_binding_assembly(F):
+    felis, ctx = F
+    from paper_2603_22274_amd import estimator
+    s = gen.small_complex()
+    segs = estimator.segments(s.n_windows, 3)
+    assert segs == oest.segments(s.n_windows, 3)
+    legs = [felis.Leg(ctx, s, windows=w, seed=40 + k) for k, w in enumerate(segs)]
+    felis.step(ctx, legs, 40, 0.002, T, 5.0)                      # settle the start
+    n_samples = 8
+    us = [torch.empty((len(w), len(w) * n_samples), dtype=torch.float64, device='cuda') for w in segs]
+    for t in range(n_samples):
+        felis.step(ctx, legs, 10, 0.002, T, 0.5)
+        for leg, w, u in zip(legs, segs, us):
+            W = len(w)
+            felis.ukn(ctx, leg, s.lambdas[w], leg.x, leg.y, leg.z, BETA, out=u[:, t * W:(t + 1) * W])
+    ctx.device_check()
+    nks = [np.full(len(w), n_samples) for w in segs]
+    got = estimator.segmented_dg(ctx, us, nks, T)
+    ref = oest.segmented_dg([u.cpu().numpy() for u in us], nks, T)
+    assert np.isfinite(got) and abs(got - ref) <= 1e-6, (got, ref)
+    # each segment on its own as well
+    for u, nk in zip(us, nks):
+        a = estimator.segment_dg(ctx, u, nk, T)
+        b = oest.segmented_dg([u.cpu().numpy()], [nk], T)
+        assert abs(a - b) <= 1e-6, (a, b)
+    dg_solv = 3.7
+    bind = estimator.binding_dg(dg_solv, got, s.restraint_g0, s.restraint_k, T)
+    ref_bind = oest.binding_dg(dg_solv, ref, oest.boresch_restraint_dg(s.restraint_g0, s.restraint_k, T))
+    assert abs(bind - ref_bind) <= 1e-6, (bind, ref_bind)
