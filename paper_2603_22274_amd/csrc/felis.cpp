@@ -181,9 +181,9 @@ int make_plan(felis_ctx* c, const felis_leg* L, Plan& P) {
   y.cgrid = put((size_t)h.npair * h.Ktot * 8);
   for (int d = 0; d < 3; ++d) { y.tw[d] = put(h.K[d] * 8); y.bmod[d] = put(h.K[d] * 4); }
   y.eacc = put(W * FELIS_NE * 8);
-  y.uacc = put((size_t)h.npair * (3 + kMaxLamV) * 8);
-  y.upart = put((size_t)h.npair * ((h.n + 255) / 256) * 4 * (1 + kMaxLamV) * 8);
-  y.lpart = put((size_t)h.npair * 4 * (1 + kMaxLamV) * 8);
+  y.uacc = put(2 * (size_t)h.npair * (3 + kMaxLamV) * 8);
+  y.upart = put(2 * (size_t)h.npair * ((h.n + 255) / 256) * (1 + kMaxLamV) * 8);
+  y.lpart = put(2 * (size_t)h.npair * (1 + kMaxLamV) * 8);
   y.ucst = put(8 * sizeof(double));
   y.total = o;
   return FELIS_OK;

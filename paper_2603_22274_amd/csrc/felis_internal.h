@@ -94,14 +94,14 @@ struct LegDev {
   unsigned* lent;                       // [W][nclus][2][cap]: list of the cluster's atoms 0-3 and of
                                         // atoms 4-7 (slot << 8 | 4-bit mask over the half's atoms)
   long long *frx, *fry, *frz;           // [W][n] reciprocal-space forces of the current MD step
-  long long* grid64;                    // [W][Ktot] fixed-point charge grids
+  long long* grid64;                    // [2 npair][Ktot] u_kn ligand charge grids, fixed point
   float2* cgrid;                        // [npair][Ktot] complex grids
   float2* tw[3];                        // [K] exp(-2 pi i k / K) per axis
   float* bmod[3];                       // [K] B-spline moduli factor per axis
   long long* eacc;                      // [W][FELIS_NE] fixed-point energies
-  long long* uacc;                      // [npair][3 + kMaxLamV] u_kn fixed-point sums (PME, restraint)
-  double* upart;                        // [npair][ceil(n/256)][4][1 + kMaxLamV] u_kn pair partials
-  double* lpart;                        // [npair][4][1 + kMaxLamV] ligand-ligand partials
+  long long* uacc;                      // [2 npair][3 + kMaxLamV] u_kn fixed-point sums (PME, restraint)
+  double* upart;                        // [2 npair][ceil(n/256)][1 + kMaxLamV] u_kn pair partials
+  double* lpart;                        // [2 npair][1 + kMaxLamV] ligand-ligand partials
   int* err;                             // context error word
   int* need;                            // context: largest list length seen
   int leg_index;                        // position of this leg in the launched batch

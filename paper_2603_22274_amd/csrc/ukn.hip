@@ -11,9 +11,14 @@
 //   E_sc: softcore LJ of every ligand pair (ligand-environment and
 //         non-excluded ligand-ligand) at lambda_ij = lam_v;
 //   U_B:  Boresch energy.
-// phi_E and phi_L come from one complex PME per frame: the environment's
-// charges spread into the real part, the ligand's into the imaginary part.
-// Sums run in FP64 per lane and combine in int64 fixed point.
+// The reciprocal parts need only the ligand's potential phi_L: the PME
+// reciprocal energy is a symmetric bilinear form of two spread charge grids,
+// so sum_{i in L} q_i phi_E(r_i) = sum_{j in E} q_j phi_L(r_j).  Each frame
+// spreads its few ligand charges, two frames share one complex FFT (real and
+// imaginary part), and phi_L is gathered at every atom: a read-only pass over
+// the environment instead of scattering all of its charges.  Pair sums run in
+// FP64 per lane; block partials combine in a fixed order (pair terms) or in
+// int64 fixed point (reciprocal terms).
 #include "felis_internal.h"
 #include "erfc_coeffs.h"
 #include "restraint.h"
@@ -64,36 +69,9 @@ __device__ __forceinline__ void acc_add(const LegDev& g, int f, int slot, double
             (unsigned long long)to_fixed(e, kEnergyScale, g.err, kSiteUkn, f));
 }
 
-// items: frame x atom, 16 lanes per atom; environment charges into grid 2f,
-// ligand charges into grid 2f+1 (unscaled charges)
+// items: frame x ligand atom, 16 lanes per atom: the ligand's unscaled
+// charges of frame f into int64 grid f
 __global__ __launch_bounds__(256) void k_ukn_spread(const LegDev* legs, UknArgs A) {
-  const LegDev& g = legs[0];
-  const long long local = (long long)blockIdx.x * 16 + (threadIdx.x >> 4);
-  if (local >= (long long)A.nf * g.n) return;
-  const int f = (int)(local / g.n);
-  const int a = (int)(local - (long long)f * g.n);
-  const int sub = threadIdx.x & 15, iy = sub & 3, iz = sub >> 2;
-  const size_t o = (size_t)(A.f0 + f) * A.stride + a;
-  float fxr, fyr, fzr, wx[4], wy[4], wz[4];
-  const int bx = grid_base(A.fx[o], g.invL[0], g.K[0], &fxr);
-  const int by = grid_base(A.fy[o], g.invL[1], g.K[1], &fyr);
-  const int bz = grid_base(A.fz[o], g.invL[2], g.K[2], &fzr);
-  bspline4(fxr, wx); bspline4(fyr, wy); bspline4(fzr, wz);
-  int gy = by - iy; if (gy < 0) gy += g.K[1];
-  int gz = bz - iz; if (gz < 0) gz += g.K[2];
-  const int which = 2 * f + (g.lig[a] ? 1 : 0);
-  long long* grid = g.grid64 + (size_t)which * g.Ktot + ((size_t)gz * g.K[1] + gy) * g.K[0];
-  const double qyz = (double)(g.q[a] * wy[iy] * wz[iz]);
-#pragma unroll
-  for (int ix = 0; ix < 4; ++ix) {
-    int gx = bx - ix; if (gx < 0) gx += g.K[0];
-    const long long v = __double2ll_rn(qyz * (double)wx[ix] * kGridScale);
-    if (v) atomicAdd((unsigned long long*)&grid[gx], (unsigned long long)v);
-  }
-}
-
-// items: frame x ligand atom, 16 lanes per atom: E_LE += q phi_E, E_LL += q phi_L / 2
-__global__ __launch_bounds__(256) void k_ukn_gather(const LegDev* legs, UknArgs A) {
   const LegDev& g = legs[0];
   const long long local = (long long)blockIdx.x * 16 + (threadIdx.x >> 4);
   if (local >= (long long)A.nf * g.nlig) return;
@@ -108,37 +86,95 @@ __global__ __launch_bounds__(256) void k_ukn_gather(const LegDev* legs, UknArgs 
   bspline4(fxr, wx); bspline4(fyr, wy); bspline4(fzr, wz);
   int gy = by - iy; if (gy < 0) gy += g.K[1];
   int gz = bz - iz; if (gz < 0) gz += g.K[2];
-  const float2* cg = g.cgrid + (size_t)f * g.Ktot + ((size_t)gz * g.K[1] + gy) * g.K[0];
-  float pe = 0.f, pl = 0.f;
+  long long* grid = g.grid64 + (size_t)f * g.Ktot + ((size_t)gz * g.K[1] + gy) * g.K[0];
+  const double qyz = (double)(g.q[a] * wy[iy] * wz[iz]);
 #pragma unroll
   for (int ix = 0; ix < 4; ++ix) {
     int gx = bx - ix; if (gx < 0) gx += g.K[0];
-    const float2 c = cg[gx];
-    pe = fmaf(wx[ix], c.x, pe);
-    pl = fmaf(wx[ix], c.y, pl);
-  }
-  const float wyz = wy[iy] * wz[iz];
-  pe *= wyz; pl *= wyz;
-  for (int off = 1; off < 16; off <<= 1) {
-    pe += __shfl_xor(pe, off, 64);
-    pl += __shfl_xor(pl, off, 64);
-  }
-  if (sub == 0) {
-    const double q = (double)g.q[a];
-    acc_add(g, f, 0, q * (double)pe);
-    acc_add(g, f, 1, 0.5 * q * (double)pl);
+    const long long v = __double2ll_rn(qyz * (double)wx[ix] * kGridScale);
+    if (v) atomicAdd((unsigned long long*)&grid[gx], (unsigned long long)v);
   }
 }
 
-// items: frame x block of 256 atoms: ligand-environment pairs within r_c
+// items: frame x block of 256 atoms, 16 lanes per atom, 16 atoms per pass:
+// phi_L of frame f (part f & 1 of complex grid f / 2) at every atom;
+// E_LE += q phi_L over environment atoms, E_LL += q phi_L / 2 over ligand atoms
+__global__ __launch_bounds__(256) void k_ukn_gather(const LegDev* legs, UknArgs A) {
+  const LegDev& g = legs[0];
+  const int nb = (g.n + 255) / 256;
+  const int f = blockIdx.x / nb;
+  const int a0 = (blockIdx.x - f * nb) * 256 + (threadIdx.x >> 4);
+  const int sub = threadIdx.x & 15, iy = sub & 3, iz = sub >> 2;
+  const float* cg = (const float*)(g.cgrid + (size_t)(f >> 1) * g.Ktot) + (f & 1);
+  const size_t fo = (size_t)(A.f0 + f) * A.stride;
+  double le = 0.0, ll = 0.0;
+  for (int t = 0; t < 16; ++t) {
+    const int a = a0 + 16 * t;
+    const bool valid = a < g.n;                      // uniform over the 16 lanes of an atom
+    const int ac = valid ? a : g.n - 1;
+    float fxr, fyr, fzr, wx[4], wy[4], wz[4];
+    const int bx = grid_base(A.fx[fo + ac], g.invL[0], g.K[0], &fxr);
+    const int by = grid_base(A.fy[fo + ac], g.invL[1], g.K[1], &fyr);
+    const int bz = grid_base(A.fz[fo + ac], g.invL[2], g.K[2], &fzr);
+    bspline4(fxr, wx); bspline4(fyr, wy); bspline4(fzr, wz);
+    int gy = by - iy; if (gy < 0) gy += g.K[1];
+    int gz = bz - iz; if (gz < 0) gz += g.K[2];
+    const float* row = cg + 2 * ((size_t)gz * g.K[1] + gy) * g.K[0];
+    float ph = 0.f;
+#pragma unroll
+    for (int ix = 0; ix < 4; ++ix) {
+      int gx = bx - ix; if (gx < 0) gx += g.K[0];
+      ph = fmaf(wx[ix], row[2 * gx], ph);
+    }
+    ph *= wy[iy] * wz[iz];
+    for (int off = 1; off < 16; off <<= 1) ph += __shfl_xor(ph, off, 64);
+    if (sub == 0 && valid) {
+      const double qp = (double)g.q[ac] * (double)ph;
+      if (g.lig[ac]) ll += 0.5 * qp;
+      else le += qp;
+    }
+  }
+  le = wave_sum(le);
+  ll = wave_sum(ll);
+  __shared__ double s_r[2][4];
+  const int wv = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) { s_r[0][wv] = le; s_r[1][wv] = ll; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    acc_add(g, f, 0, ((s_r[0][0] + s_r[0][1]) + s_r[0][2]) + s_r[0][3]);
+    acc_add(g, f, 1, ((s_r[1][0] + s_r[1][1]) + s_r[1][2]) + s_r[1][3]);
+  }
+}
+
+constexpr int kGV = 16;              // lambda_vdw values accumulated per lane at once
+
+// block partials of one frame: the 4 waves' sums in LDS, added in wave order
+__device__ __forceinline__ void block_partial(double* s_red, int slot, double v) {
+  v = wave_sum(v);
+  if ((threadIdx.x & 63) == 0) s_red[(threadIdx.x >> 6) * (1 + kMaxLamV) + slot] = v;
+}
+
+__device__ __forceinline__ void block_flush(const double* s_red, double* out, int nslot) {
+  __syncthreads();
+  for (int t = threadIdx.x; t < nslot; t += blockDim.x)
+    out[t] = ((s_red[t] + s_red[(1 + kMaxLamV) + t]) + s_red[2 * (1 + kMaxLamV) + t]) +
+             s_red[3 * (1 + kMaxLamV) + t];
+}
+
+// items: frame x block of 256 atoms: ligand-environment pairs within r_c.
+// Each lane keeps its own FP64 sums over the ligand atoms for kGV lambda_vdw
+// values at a time; one block partial per frame, block and slot (slot 0
+// Coulomb, 1 + kv softcore LJ at lamv[kv]), unbounded (a frame evaluated at a
+// state it was not sampled in may carry enormous overlap energies) and summed
+// in a fixed order by k_ukn_combine
 __global__ __launch_bounds__(256) void k_ukn_pairs(const LegDev* legs, UknArgs A) {
   const LegDev& g = legs[0];
   const int nb = (g.n + 255) / 256;
   const int f = blockIdx.x / nb;
   const int j = (blockIdx.x - f * nb) * 256 + threadIdx.x;
-  const int lane = threadIdx.x & 63;
   __shared__ float4 s_lx[kMaxLigand];     // x, y, z, q
   __shared__ float2 s_lp[kMaxLigand];     // sigma/2, 2 sqrt(eps)
+  __shared__ double s_red[4 * (1 + kMaxLamV)];
   const size_t fo = (size_t)(A.f0 + f) * A.stride;
   for (int t = threadIdx.x; t < g.nlig; t += blockDim.x) {
     const int a = g.lig_idx[t];
@@ -153,96 +189,115 @@ __global__ __launch_bounds__(256) void k_ukn_pairs(const LegDev* legs, UknArgs A
     qj = g.q[j]; hs = 0.5f * g.sig[j]; se = 2.0f * sqrtf(g.eps[j]);
   }
   const float c_ke = (float)kKE;
-  double ec = 0.0, esc = 0.0;
-  for (int li = 0; li < g.nlig; ++li) {
-    const float4 L = s_lx[li];
-    const float3 d = min_img(g, xj - L.x, yj - L.y, zj - L.z);
-    const float r2 = d.x * d.x + d.y * d.y + d.z * d.z;
-    const bool in = env && r2 < g.rc2;
-    if (__ballot(in) == 0ull) continue;
-    const float r2s = in ? r2 : 1.0f;
-    const float rinv = __builtin_amdgcn_rsqf(r2s);
-    float ex;
-    const float erfcv = erfc_fit(g.alpha * r2s * rinv, &ex);
-    if (in) ec += (double)(c_ke * L.w * qj * erfcv * rinv);
-    const float sg = s_lp[li].x + hs;
-    const float s2 = sg * sg;
-    const float s6 = s2 * s2 * s2;
-    const float r6 = r2s * r2s * r2s;
-    const float e4 = s_lp[li].y * se;
-    for (int kv = 0; kv < A.KV; ++kv) {
-      const float inv = __builtin_amdgcn_rcpf(fmaf(A.asc[kv], s6, r6));
-      const float u = s6 * inv;
-      const float e = in ? A.lamv[kv] * e4 * fmaf(u, u, -u) : 0.0f;
-      const double tot = wave_sum((double)e);
-      if (lane == kv) esc += tot;
+  double ec = 0.0;
+  for (int v0 = 0; v0 < A.KV; v0 += kGV) {
+    double esc[kGV];
+#pragma unroll
+    for (int t = 0; t < kGV; ++t) esc[t] = 0.0;
+    for (int li = 0; li < g.nlig; ++li) {
+      const float4 L = s_lx[li];
+      const float3 d = min_img(g, xj - L.x, yj - L.y, zj - L.z);
+      const float r2 = d.x * d.x + d.y * d.y + d.z * d.z;
+      const bool in = env && r2 < g.rc2;
+      if (__ballot(in) == 0ull) continue;
+      const float r2s = in ? r2 : 1.0f;
+      if (v0 == 0) {
+        const float rinv = __builtin_amdgcn_rsqf(r2s);
+        float ex;
+        const float erfcv = erfc_fit(g.alpha * r2s * rinv, &ex);
+        if (in) ec += (double)(c_ke * L.w * qj * erfcv * rinv);
+      }
+      const float sg = s_lp[li].x + hs;
+      const float s2 = sg * sg;
+      const float s6 = s2 * s2 * s2;
+      const float r6 = r2s * r2s * r2s;
+      const float e4 = in ? s_lp[li].y * se : 0.0f;
+#pragma unroll
+      for (int t = 0; t < kGV; ++t) {
+        if (v0 + t < A.KV) {
+          const float inv = __builtin_amdgcn_rcpf(fmaf(A.asc[v0 + t], s6, r6));
+          const float u = s6 * inv;
+          esc[t] += (double)(A.lamv[v0 + t] * e4 * fmaf(u, u, -u));
+        }
+      }
     }
+#pragma unroll
+    for (int t = 0; t < kGV; ++t)
+      if (v0 + t < A.KV) block_partial(s_red, 1 + v0 + t, esc[t]);
   }
-  // per-wave FP64 partials (unbounded: a frame evaluated at a state it was
-  // not sampled in may carry enormous overlap energies); summed in a fixed
-  // order by k_ukn_combine
-  ec = wave_sum(ec);
-  double* part = g.upart + ((size_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * (1 + kMaxLamV);
-  if (lane == 0) part[0] = ec;
-  if (lane < A.KV) part[1 + lane] = esc;
+  block_partial(s_red, 0, ec);
+  block_flush(s_red, g.upart + (size_t)blockIdx.x * (1 + kMaxLamV), 1 + A.KV);
 }
 
 // one block per frame: ligand-ligand pairs, excluded-pair corrections and the
-// Boresch energy
+// Boresch energy; one partial row per frame (slot 0 E_LL real space, 1 + kv
+// softcore LJ), the same per-lane accumulation as k_ukn_pairs
 __global__ __launch_bounds__(256) void k_ukn_ligand(const LegDev* legs, UknArgs A) {
   const LegDev& g = legs[0];
   const int f = blockIdx.x;
-  const int lane = threadIdx.x & 63;
   const size_t fo = (size_t)(A.f0 + f) * A.stride;
   const int nl = g.nlig;
   const int np = nl * (nl - 1) / 2;
   const float c_ke = (float)kKE;
-  double ell = 0.0, esc = 0.0;
-  for (int base = 0; base < np; base += blockDim.x) {
-    const int p = base + threadIdx.x;
-    bool in = false, exc = false;
-    float r2s = 1.0f, qq = 0.f, s6 = 0.f, e4 = 0.f;
-    if (p < np) {
-      // decode p -> (i, j), i < j, row-major over the upper triangle
-      int i = 0, rem = p;
-      while (rem >= nl - 1 - i) { rem -= nl - 1 - i; ++i; }
-      const int jl = i + 1 + rem;
-      const int a = g.lig_idx[i], b = g.lig_idx[jl];
-      for (int k = g.excl_ptr[a]; k < g.excl_ptr[a + 1]; ++k) exc |= (g.excl_idx[k] == b);
-      const float3 d = min_img(g, A.fx[fo + b] - A.fx[fo + a], A.fy[fo + b] - A.fy[fo + a],
-                               A.fz[fo + b] - A.fz[fo + a]);
-      const float r2 = d.x * d.x + d.y * d.y + d.z * d.z;
-      qq = c_ke * g.q[a] * g.q[b];
-      if (exc) {
-        const float r = sqrtf(r2);
-        ell -= (r > 1e-4f) ? (double)(qq * erff(g.alpha * r) / r)
-                           : (double)(qq * 2.0f * g.alpha * 0.56418958354775628f);
-      } else if (r2 < g.rc2) {
-        in = true;
-        r2s = r2;
-        const float rinv = __builtin_amdgcn_rsqf(r2);
-        float ex;
-        ell += (double)(qq * erfc_fit(g.alpha * r2 * rinv, &ex) * rinv);
-        const float sg = 0.5f * (g.sig[a] + g.sig[b]);
-        const float s2 = sg * sg;
-        s6 = s2 * s2 * s2;
-        e4 = 4.0f * sqrtf(g.eps[a] * g.eps[b]);
+  __shared__ double s_red[4 * (1 + kMaxLamV)];
+  double ell = 0.0;
+  for (int v0 = 0; v0 < A.KV; v0 += kGV) {
+    double esc[kGV];
+#pragma unroll
+    for (int t = 0; t < kGV; ++t) esc[t] = 0.0;
+    for (int base = 0; base < np; base += blockDim.x) {
+      const int p = base + threadIdx.x;
+      bool in = false;
+      float r2s = 1.0f, s6 = 0.f, e4 = 0.f;
+      if (p < np) {
+        // decode p -> (i, j), i < j, row-major over the upper triangle
+        int i = 0, rem = p;
+        while (rem >= nl - 1 - i) { rem -= nl - 1 - i; ++i; }
+        const int jl = i + 1 + rem;
+        const int a = g.lig_idx[i], b = g.lig_idx[jl];
+        bool exc = false;
+        for (int k = g.excl_ptr[a]; k < g.excl_ptr[a + 1]; ++k) exc |= (g.excl_idx[k] == b);
+        const float3 d = min_img(g, A.fx[fo + b] - A.fx[fo + a], A.fy[fo + b] - A.fy[fo + a],
+                                 A.fz[fo + b] - A.fz[fo + a]);
+        const float r2 = d.x * d.x + d.y * d.y + d.z * d.z;
+        const float qq = c_ke * g.q[a] * g.q[b];
+        if (exc) {
+          if (v0 == 0) {
+            const float r = sqrtf(r2);
+            ell -= (r > 1e-4f) ? (double)(qq * erff(g.alpha * r) / r)
+                               : (double)(qq * 2.0f * g.alpha * 0.56418958354775628f);
+          }
+        } else if (r2 < g.rc2) {
+          in = true;
+          r2s = r2;
+          if (v0 == 0) {
+            const float rinv = __builtin_amdgcn_rsqf(r2);
+            float ex;
+            ell += (double)(qq * erfc_fit(g.alpha * r2 * rinv, &ex) * rinv);
+          }
+          const float sg = 0.5f * (g.sig[a] + g.sig[b]);
+          const float s2 = sg * sg;
+          s6 = s2 * s2 * s2;
+          e4 = 4.0f * sqrtf(g.eps[a] * g.eps[b]);
+        }
+      }
+      if (__ballot(in) == 0ull) continue;
+      const float r6 = r2s * r2s * r2s;
+#pragma unroll
+      for (int t = 0; t < kGV; ++t) {
+        if (v0 + t < A.KV) {
+          const float inv = __builtin_amdgcn_rcpf(fmaf(A.asc[v0 + t], s6, r6));
+          const float u = s6 * inv;
+          esc[t] += (double)(in ? A.lamv[v0 + t] * e4 * fmaf(u, u, -u) : 0.0f);
+        }
       }
     }
-    if (__ballot(in) == 0ull) continue;
-    const float r6 = r2s * r2s * r2s;
-    for (int kv = 0; kv < A.KV; ++kv) {
-      const float inv = __builtin_amdgcn_rcpf(fmaf(A.asc[kv], s6, r6));
-      const float u = s6 * inv;
-      const float e = in ? A.lamv[kv] * e4 * fmaf(u, u, -u) : 0.0f;
-      const double tot = wave_sum((double)e);
-      if (lane == kv) esc += tot;
-    }
+#pragma unroll
+    for (int t = 0; t < kGV; ++t)
+      if (v0 + t < A.KV) block_partial(s_red, 1 + v0 + t, esc[t]);
   }
-  ell = wave_sum(ell);
-  double* part = g.lpart + ((size_t)f * 4 + (threadIdx.x >> 6)) * (1 + kMaxLamV);
-  if (lane == 0) part[0] = ell;
-  if (lane < A.KV) part[1 + lane] = esc;
+  block_partial(s_red, 0, ell);
+  block_flush(s_red, g.lpart + (size_t)f * (1 + kMaxLamV), 1 + A.KV);
   if (threadIdx.x == 0 && g.has_rest) {
     v3 p[6];
     const size_t o1 = fo + g.ranch[0];
@@ -283,34 +338,38 @@ struct CombineArgs {
   unsigned char kv[kMaxStates];
 };
 
-// items: frame x state
+// one block per frame: the pair partials of every block of k_ukn_pairs summed
+// per slot (one wave per slot, lanes over blocks, fixed tree), then u at every
+// state
 __global__ __launch_bounds__(256) void k_ukn_combine(const LegDev* legs, UknArgs A, CombineArgs C,
                                                      const double* cst, int K, double beta, double* u,
                                                      long long u_stride) {
   const LegDev& g = legs[0];
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= (long long)A.nf * K) return;
-  const int f = (int)(i / K), k = (int)(i - (long long)(i / K) * K);
+  const int f = blockIdx.x;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int nb = g.nlig > 0 ? (g.n + 255) / 256 : 0;     // no ligand: no pair partials
+  __shared__ double s_p[1 + kMaxLamV];
+  const double* pp = g.upart + (size_t)f * nb * (1 + kMaxLamV);
+  const double* lp = g.lpart + (size_t)f * (1 + kMaxLamV);
+  for (int slot = wv; slot < 1 + A.KV; slot += 4) {
+    double v = 0.0;
+    for (int t = lane; t < nb; t += 64) v += pp[(size_t)t * (1 + kMaxLamV) + slot];
+    v = wave_sum(v);
+    if (lane == 0) s_p[slot] = v;
+  }
+  __syncthreads();
   const long long* acc = g.uacc + (size_t)f * kNU;
   const double s = 1.0 / kEnergyScale;
-  const int kv = C.kv[k];
-  double ele = (double)acc[0] * s + cst[0];
-  double ell = (double)acc[1] * s + cst[1];
-  const double ub = (double)acc[2] * s;
-  double esc = 0.0;
-  const int nb = g.nlig > 0 ? (g.n + 255) / 256 : 0;     // no ligand: no pair partials
-  const double* pp = g.upart + (size_t)f * nb * 4 * (1 + kMaxLamV);
-  for (int t = 0; t < 4 * nb; ++t) {
-    ele += pp[(size_t)t * (1 + kMaxLamV)];
-    esc += pp[(size_t)t * (1 + kMaxLamV) + 1 + kv];
+  const bool has_l = g.nlig > 0;
+  for (int k = threadIdx.x; k < K; k += blockDim.x) {
+    const int kv = C.kv[k];
+    const double ele = (double)acc[0] * s + cst[0] + s_p[0];
+    const double ell = (double)acc[1] * s + cst[1] + (has_l ? lp[0] : 0.0);
+    const double ub = (double)acc[2] * s;
+    const double esc = s_p[1 + kv] + (has_l ? lp[1 + kv] : 0.0);
+    const double le = C.le[k], lr = C.lr[k];
+    u[(long long)k * u_stride + A.f0 + f] = beta * (le * ele + le * le * ell + esc + lr * ub);
   }
-  const double* lp = g.lpart + (size_t)f * 4 * (1 + kMaxLamV);
-  for (int t = 0; t < (g.nlig > 0 ? 4 : 0); ++t) {
-    ell += lp[t * (1 + kMaxLamV)];
-    esc += lp[t * (1 + kMaxLamV) + 1 + kv];
-  }
-  const double le = C.le[k], lr = C.lr[k];
-  u[(long long)k * u_stride + A.f0 + f] = beta * (le * ele + le * le * ell + esc + lr * ub);
 }
 
 }  // namespace
@@ -343,21 +402,23 @@ int launch_ukn(hipStream_t s, const LegDev* d, const LegHost& h, double sc_alpha
     C.lr[k] = lambdas[3 * k + 2];
   }
   hipLaunchKernelGGL(k_ukn_const, dim3(1), dim3(256), 0, s, d, cst);
-  const int F = h.npair;
+  // two frames per complex grid: 2 npair frames per pass
+  const int F = 2 * h.npair;
   for (long long f0 = 0; f0 < n_frames; f0 += F) {
     const int nf = (int)std::min<long long>(F, n_frames - f0);
+    const int nb = (h.n + 255) / 256;
     A.f0 = f0;
     A.nf = nf;
     launch_fill_i64(s, uacc, (size_t)nf * kNU);
-    hipLaunchKernelGGL(k_ukn_spread, dim3((unsigned)(((long long)nf * h.n + 15) / 16)), dim3(256), 0, s, d, A);
-    launch_pme_fft(s, d, &h, 1, true);
     if (h.nlig) {
-      hipLaunchKernelGGL(k_ukn_gather, dim3((unsigned)(((long long)nf * h.nlig + 15) / 16)), dim3(256), 0, s, d, A);
-      hipLaunchKernelGGL(k_ukn_pairs, dim3((unsigned)(nf * ((h.n + 255) / 256))), dim3(256), 0, s, d, A);
+      hipLaunchKernelGGL(k_ukn_spread, dim3((unsigned)(((long long)nf * h.nlig + 15) / 16)), dim3(256), 0, s, d, A);
+      launch_pme_fft(s, d, &h, 1, true);
+      hipLaunchKernelGGL(k_ukn_gather, dim3((unsigned)(nf * nb)), dim3(256), 0, s, d, A);
+      hipLaunchKernelGGL(k_ukn_pairs, dim3((unsigned)(nf * nb)), dim3(256), 0, s, d, A);
       hipLaunchKernelGGL(k_ukn_ligand, dim3(nf), dim3(256), 0, s, d, A);
     }
-    hipLaunchKernelGGL(k_ukn_combine, dim3((unsigned)(((long long)nf * K + 255) / 256)), dim3(256), 0, s, d,
-                       A, C, (const double*)cst, K, beta, u, u_stride);
+    hipLaunchKernelGGL(k_ukn_combine, dim3((unsigned)nf), dim3(256), 0, s, d, A, C, (const double*)cst, K, beta,
+                       u, u_stride);
   }
   return FELIS_OK;
 }
