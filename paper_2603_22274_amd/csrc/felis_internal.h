@@ -148,6 +148,17 @@ __device__ __forceinline__ long long to_fixed(double v, double scale, int* err, 
   return __double2ll_rn(s);
 }
 
+// A device pointer seen in the global address space: loads through it are
+// global (not flat) instructions, which count only against the vector-memory
+// counter, so a load issued early stays in flight across later work.
+template <typename T>
+using gptr = const T __attribute__((address_space(1)))*;
+template <typename T>
+__device__ __forceinline__ gptr<T> as_global(const T* p) { return (gptr<T>)p; }
+// float4 records read through a global pointer as a native 4-vector
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ gptr<f32x4> as_global4(const float4* p) { return (gptr<f32x4>)p; }
+
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);

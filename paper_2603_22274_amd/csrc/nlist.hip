@@ -283,7 +283,8 @@ __global__ __launch_bounds__(1024) void k_check_sort(const LegDev* legs, BlockMa
 bool sort_in_lds(const LegHost& h) { return h.ncell <= kSortCells && h.n <= kSortAtoms; }
 
 // One block per cluster: sweep the coarse blocks (aligned 2x2x2 fine cells)
-// within r_list of the cluster's box, 256 blocks per round, and list every
+// within r_list of the cluster's box, 256 blocks per round, each trimmed to
+// the Hilbert span of its fine cells within r_list, and list every
 // atom j with at least one i of the cluster in range.  The four waves take
 // consecutive quarters of each 256-candidate step and append in wave order,
 // so the list order is fixed (cells in sweep order, slots ascending) while a
@@ -337,6 +338,10 @@ __global__ __launch_bounds__(256) void k_build(const LegDev* legs, BlockMap map)
   }
   __syncthreads();
 
+  // box edges in scalar registers: read once, not again after every list store
+  const float Lf[3] = {scalar(g.Lf[0]), scalar(g.Lf[1]), scalar(g.Lf[2])};
+  const float iLf[3] = {scalar(g.invLf[0]), scalar(g.invLf[1]), scalar(g.invLf[2])};
+  const int cap = __builtin_amdgcn_readfirstlane(g.cap);
   const float4 lo4 = g.bblo[item], hi4 = g.bbhi[item];
   const float lo[3] = {lo4.x, lo4.y, lo4.z}, hi[3] = {hi4.x, hi4.y, hi4.z};
   const int nf = g.ncoarse;
@@ -348,11 +353,15 @@ __global__ __launch_bounds__(256) void k_build(const LegDev* legs, BlockMap map)
   for (int d = 0; d < 3; ++d) {
     cen[d] = 0.5f * (lo[d] + hi[d]);
     half[d] = 0.5f * (hi[d] - lo[d]);
-    if (!(half[d] >= 0.f && half[d] <= g.Lf[d])) { cen[d] = 0.f; half[d] = g.Lf[d]; }   // no valid atom
-    const float cs = g.Lf[d] / (float)nf;
+    if (!(half[d] >= 0.f && half[d] <= Lf[d])) { cen[d] = 0.f; half[d] = Lf[d]; }   // no valid atom
+    // nf is a power of two: exact cell edge; the range ends use its inverse
+    // (a rounding flip only adds or drops a cell whose nearest face lies
+    // pre - r_list - 0.01 = 0.04 A beyond the list radius)
+    const float cs = ldexpf(Lf[d], 1 - g.nbits);
+    const float ics = ldexpf(iLf[d], g.nbits - 1);
     csd[d] = cs;
-    const int a0 = (int)floorf((cen[d] - half[d] - pre) / cs);
-    const int a1 = (int)floorf((cen[d] + half[d] + pre) / cs);
+    const int a0 = (int)floorf((cen[d] - half[d] - pre) * ics);
+    const int a1 = (int)floorf((cen[d] + half[d] + pre) * ics);
     full[d] = a1 - a0 + 1 >= nf;               // the range wraps onto itself: every cell, no gap test
     r0[d] = full[d] ? 0 : a0;
     nC[d] = full[d] ? nf : a1 - a0 + 1;
@@ -370,14 +379,14 @@ __global__ __launch_bounds__(256) void k_build(const LegDev* legs, BlockMap map)
       xi[ii][d] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(s_xi[ii][d])));
       // position relative to the cluster's first atom (always a real atom), nearest image
       const float v = xi[ii][d] - xi[0][d];
-      ri[ii][d] = __fmaf_rn(-g.Lf[d], rintf(v * g.invLf[d]), v);
+      ri[ii][d] = __fmaf_rn(-Lf[d], rintf(v * iLf[d]), v);
       if (ai[ii] >= 0) ext[d] = fmaxf(ext[d], fabsf(ri[ii][d]));
     }
   }
   // one periodic image per candidate (taken against the first atom) is the
   // nearest image for every i whenever extent + r_list + margin < L/2
-  const bool shift = ext[0] + incl + 0.02f < 0.5f * g.Lf[0] && ext[1] + incl + 0.02f < 0.5f * g.Lf[1] &&
-                     ext[2] + incl + 0.02f < 0.5f * g.Lf[2];
+  const bool shift = ext[0] + incl + 0.02f < 0.5f * Lf[0] && ext[1] + incl + 0.02f < 0.5f * Lf[1] &&
+                     ext[2] + incl + 0.02f < 0.5f * Lf[2];
   // i-side terms of |r_j - r_i|^2 = |r_j|^2 - 2 r_i.r_j + |r_i|^2 in the
   // shifted frame (|r| < 25 A there, so the FP32 error of the expanded form
   // stays below 1e-3 A^2, far inside the 0.01 A margin), held in scalar
@@ -390,16 +399,17 @@ __global__ __launch_bounds__(256) void k_build(const LegDev* legs, BlockMap map)
                                  : -1.0e30f);
   }
   const int* cst = g.cellstart + (size_t)w * (g.ncell + 1);
-  unsigned* outL = g.lent + (size_t)item * 2 * g.cap;      // partners of atoms 0-3
-  unsigned* outH = outL + g.cap;                            // partners of atoms 4-7
+  unsigned* outL = g.lent + (size_t)item * 2 * cap;      // partners of atoms 0-3
+  unsigned* outH = outL + cap;                            // partners of atoms 4-7
   const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   const int ncells = nC[0] * nC[1] * nC[2];
   int countL = 0, countH = 0, par = 0;
   // block index ci -> (c0, c1, c2) by float-reciprocal quotients with one
-  // correction (exact for ci < 2^22); a block coordinate lies in (-nf, 2nf)
+  // correction (exact for ci < 2^22, with the hardware reciprocal too); a
+  // block coordinate lies in (-nf, 2nf)
   // (the range is narrower than the box unless full), so one wrap suffices
   const int n12 = nC[1] * nC[2];
-  const float inv12 = 1.0f / (float)n12, inv2 = 1.0f / (float)nC[2];
+  const float inv12 = __builtin_amdgcn_rcpf((float)n12), inv2 = __builtin_amdgcn_rcpf((float)nC[2]);
   auto wrapc = [nf](int c) { return c < 0 ? c + nf : (c >= nf ? c - nf : c); };
   for (int cb = 0; cb < ncells; cb += 256) {
     const int ci = cb + tid;
@@ -419,9 +429,32 @@ __global__ __launch_bounds__(256) void k_build(const LegDev* legs, BlockMap map)
         gap2 += gp * gp;
       }
       if (gap2 < pre2) {
-        const unsigned cc = g.hcoarse[(wrapc(C[0]) * nf + wrapc(C[1])) * nf + wrapc(C[2])];
-        s0 = cst[8 * cc];                        // fine cells 8cc .. 8cc+7 are contiguous
-        cnt = cst[8 * cc + 8] - s0;
+        // the block's 8 fine cells hold 8 consecutive Hilbert indices: take
+        // the span from the first to the last child that passes its own gap test
+        float g2c[3][2];
+        for (int d = 0; d < 3; ++d)
+          for (int hh = 0; hh < 2; ++hh) {
+            const float cf = 0.5f * csd[d];
+            const int F = 2 * C[d] + hh;
+            const float gp = fmaxf(0.f, fmaxf((float)F * cf - hi[d], lo[d] - (float)(F + 1) * cf));
+            g2c[d][hh] = full[d] ? 0.f : gp * gp;
+          }
+        const int nff = 2 * nf, W0 = 2 * wrapc(C[0]), W1 = 2 * wrapc(C[1]), W2 = 2 * wrapc(C[2]);
+        unsigned hc[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+          hc[k] = g.hcell[((W0 + (k >> 2)) * nff + W1 + ((k >> 1) & 1)) * nff + W2 + (k & 1)];
+        unsigned kmin = 0xffffffffu, kmax = 0u;
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+          if (g2c[0][k >> 2] + g2c[1][(k >> 1) & 1] + g2c[2][k & 1] < pre2) {
+            kmin = min(kmin, hc[k]);
+            kmax = max(kmax, hc[k]);
+          }
+        if (kmin <= kmax) {
+          s0 = cst[kmin];
+          cnt = cst[kmax + 1] - s0;
+        }
       }
     }
     int inc = cnt;
@@ -461,7 +494,7 @@ __global__ __launch_bounds__(256) void k_build(const LegDev* legs, BlockMap map)
             float rj3[3];
             for (int d = 0; d < 3; ++d) {
               const float v = xj[d] - xi[0][d];
-              rj3[d] = __fmaf_rn(-g.Lf[d], rintf(v * g.invLf[d]), v);
+              rj3[d] = __fmaf_rn(-Lf[d], rintf(v * iLf[d]), v);
             }
             // |r_j|^2 - 2 r_i.r_j - (r_list + 0.01)^2 < -|r_i|^2
             const float nthr = __fmaf_rn(rj3[0], rj3[0], __fmaf_rn(rj3[1], rj3[1], rj3[2] * rj3[2])) - inc2;
@@ -476,9 +509,9 @@ __global__ __launch_bounds__(256) void k_build(const LegDev* legs, BlockMap map)
 #pragma unroll 1
             for (int ii = 0; ii < kClus; ++ii) {
               float dx = xj[0] - s_xi[ii][0], dy = xj[1] - s_xi[ii][1], dz = xj[2] - s_xi[ii][2];
-              dx -= g.Lf[0] * rintf(dx * g.invLf[0]);
-              dy -= g.Lf[1] * rintf(dy * g.invLf[1]);
-              dz -= g.Lf[2] * rintf(dz * g.invLf[2]);
+              dx -= Lf[0] * rintf(dx * iLf[0]);
+              dy -= Lf[1] * rintf(dy * iLf[1]);
+              dz -= Lf[2] * rintf(dz * iLf[2]);
               const float d2 = (dx * dx + dy * dy) + dz * dz;
               if (d2 < inc2 && ai[ii] >= 0) mask |= 1u << ii;
             }
@@ -505,11 +538,11 @@ __global__ __launch_bounds__(256) void k_build(const LegDev* legs, BlockMap map)
       countH += s_wc[par][1][0] + s_wc[par][1][1] + s_wc[par][1][2] + s_wc[par][1][3];
       if (mL) {
         const int pos = offL + __popcll(bL & lt);
-        if (pos < g.cap) outL[pos] = ((unsigned)s << 8) | mL;
+        if (pos < cap) outL[pos] = ((unsigned)s << 8) | mL;
       }
       if (mH) {
         const int pos = offH + __popcll(bH & lt);
-        if (pos < g.cap) outH[pos] = ((unsigned)s << 8) | mH;
+        if (pos < cap) outH[pos] = ((unsigned)s << 8) | mH;
       }
       par ^= 1;
     }
@@ -518,15 +551,15 @@ __global__ __launch_bounds__(256) void k_build(const LegDev* legs, BlockMap map)
     __syncthreads();                            // the round's tables are rewritten next
   }
   const int count = max(countL, countH);
-  if (count > g.cap) {
+  if (count > cap) {
     if (tid == 0) {
       latch(g.err, kErrListCap, kSiteList, (w << 20) | max(s_ai[0], 0), g.leg_index);
       atomicMax(g.need, count);
     }
   }
   if (tid == 0) {
-    g.lcount[2 * item] = min(countL, g.cap);
-    g.lcount[2 * item + 1] = min(countH, g.cap);
+    g.lcount[2 * item] = min(countL, cap);
+    g.lcount[2 * item + 1] = min(countH, cap);
   }
 }
 

@@ -97,8 +97,8 @@ __device__ __forceinline__ float uniform(float v) {
 // cluster's first atom (exact when r_c + cluster extent < L/2 on every axis);
 // otherwise every (i, j) takes its own minimum image.
 template <bool ENERGY, bool SHIFT, int HALF>
-__device__ __forceinline__ void sweep(const LegDev& g, const ICluster& I, const unsigned* __restrict__ ent, int cnt,
-                                      const float4* __restrict__ xq, const float4* __restrict__ pr, int lane,
+__device__ __forceinline__ void sweep(const LegDev& g, const ICluster& I, gptr<unsigned> ent, int cnt,
+                                      gptr<f32x4> xq, gptr<f32x4> pr, int lane,
                                       float lam_v, float a_sc, bool soft_window, float (&fx)[4],
                                       float (&fy)[4], float (&fz)[4], double& ec, double& el) {
   const float Lx = g.Lf[0], Ly = g.Lf[1], Lz = g.Lf[2];
@@ -113,8 +113,8 @@ __device__ __forceinline__ void sweep(const LegDev& g, const ICluster& I, const 
     const int nidx = it + 64 + lane;
     e_next = nidx < cnt ? ent[nidx] : 0u;                  // in flight during this iteration
     const int s = (int)(e >> 8);
-    const float4 xj = xq[s];
-    const float4 pj = pr[s];
+    const f32x4 xj = xq[s];
+    const f32x4 pj = pr[s];
     float jx = xj.x, jy = xj.y, jz = xj.z;
     if (SHIFT) {
       jx = fmaf(-Lx, rintf((jx - I.x[0]) * iLx), jx);
@@ -195,8 +195,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
   if (item >= (long long)g.W * g.nclus) return;
   const int w = (int)(item / g.nclus);
   const int c = (int)(item - (long long)w * g.nclus);
-  const float4* __restrict__ xq = g.xyzq + (size_t)w * g.npad;
-  const float4* __restrict__ pr = g.prm + (size_t)w * g.npad;
+  const gptr<f32x4> xq = as_global4(g.xyzq + (size_t)w * g.npad);
+  const gptr<f32x4> pr = as_global4(g.prm + (size_t)w * g.npad);
   const float lam_v = g.lam[4 * w + 1];
   const float a_sc = g.lam[4 * w + 3];
   const bool soft_window = lam_v < 1.0f;
@@ -207,8 +207,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
   float ext[3] = {0.f, 0.f, 0.f};
 #pragma unroll
   for (int ii = 0; ii < kClus; ++ii) {
-    const float4 a = xq[c * kClus + ii];
-    const float4 p = pr[c * kClus + ii];
+    const f32x4 a = xq[c * kClus + ii];
+    const f32x4 p = pr[c * kClus + ii];
     float v[3] = {uniform(a.x), uniform(a.y), uniform(a.z)};
     if (ii > 0) {
       const float r0[3] = {I.x[0], I.y[0], I.z[0]};
@@ -227,13 +227,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
   const bool shift = rc + ext[0] < 0.5f * g.Lf[0] && rc + ext[1] < 0.5f * g.Lf[1] && rc + ext[2] < 0.5f * g.Lf[2];
   // the two half-cluster lists (partners of atoms 0-3, then of atoms 4-7);
   // each half's forces are reduced over the wave before the next half
-  const unsigned* __restrict__ ent = g.lent + (size_t)item * 2 * g.cap;
+  const gptr<unsigned> ent = as_global(g.lent + (size_t)item * 2 * g.cap);
   double ec = 0.0, el = 0.0;
   __shared__ float s_f[4][kClus][3];                  // per wave: the 8 atoms' pair forces
 #pragma unroll
   for (int half = 0; half < 2; ++half) {
     float fx[4] = {0.f, 0.f, 0.f, 0.f}, fy[4] = {0.f, 0.f, 0.f, 0.f}, fz[4] = {0.f, 0.f, 0.f, 0.f};
-    const unsigned* __restrict__ eh = ent + half * g.cap;
+    const gptr<unsigned> eh = ent + half * g.cap;
     const int cnt = g.lcount[2 * item + half];
     if (half == 0) {
       if (shift) sweep<ENERGY, true, 0>(g, I, eh, cnt, xq, pr, lane, lam_v, a_sc, soft_window, fx, fy, fz, ec, el);
