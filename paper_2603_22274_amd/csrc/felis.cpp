@@ -18,7 +18,7 @@ using namespace felis;
 namespace {
 
 struct Layout {
-  size_t lam, lamS, rstate, free_atoms, lig_idx, xr, yr, zr, flag, nbuild, maxdisp, wmax, hcell, hcoarse, perm, cellcode, cellstart, cursor, xyzq, prm, bblo,
+  size_t lam, lamS, rstate, free_atoms, lig_idx, xr, yr, zr, flag, nbuild, maxdisp, wmax, hcell, perm, cellcode, cellstart, cursor, xyzq, prm, bblo,
       bbhi, gsten, lcount, lent, frx, fry, frz, grid64, cgrid, tw[3], bmod[3], eacc, uacc, upart, lpart, ucst, total;
 };
 
@@ -159,7 +159,6 @@ int make_plan(felis_ctx* c, const felis_leg* L, Plan& P) {
   y.free_atoms = put(n * 4);
   y.lig_idx = put(n * 4);
   y.hcell = put((size_t)h.ncell * 4);            // filled once at set-up (outside every cleared range)
-  y.hcoarse = put((size_t)(h.ncell / 8) * 4);
   y.xr = put(W * n * 4); y.yr = put(W * n * 4); y.zr = put(W * n * 4);
   y.flag = put(W * 4);
   y.nbuild = put(W * 8);
@@ -247,7 +246,6 @@ LegDev make_dev(const felis_ctx* c, const felis_leg* L, const Plan& p, const Met
   g.wmax = (unsigned*)(w + y.wmax);
   g.units = p.h.nwat + p.h.nfree;
   g.hcell = (const unsigned*)(w + y.hcell);
-  g.hcoarse = (const unsigned*)(w + y.hcoarse);
   g.perm = (int*)(w + y.perm);
   g.cellcode = (int*)(w + y.cellcode);
   g.cellstart = (int*)(w + y.cellstart);
@@ -483,17 +481,13 @@ int felis_leg_init(felis_ctx* c, felis_leg* L) {
   if (!freeat.empty()) ok &= hipMemcpy(w + y.free_atoms, freeat.data(), freeat.size() * 4, hipMemcpyHostToDevice) == hipSuccess;
   if (!ligi.empty()) ok &= hipMemcpy(w + y.lig_idx, ligi.data(), ligi.size() * 4, hipMemcpyHostToDevice) == hipSuccess;
   {
-    // Hilbert indices of the fine cells and of the coarse (2x2x2) blocks
-    const int nb = p.nbits, nf = 1 << nb, nfc = nf / 2;
-    std::vector<unsigned> hc((size_t)h.ncell), hq((size_t)h.ncell / 8);
+    // Hilbert indices of the fine cells
+    const int nb = p.nbits, nf = 1 << nb;
+    std::vector<unsigned> hc((size_t)h.ncell);
     for (int x = 0; x < nf; ++x)
       for (int yy = 0; yy < nf; ++yy)
         for (int z = 0; z < nf; ++z) hc[((size_t)x * nf + yy) * nf + z] = hilbert3(x, yy, z, nb);
-    for (int x = 0; x < nfc; ++x)
-      for (int yy = 0; yy < nfc; ++yy)
-        for (int z = 0; z < nfc; ++z) hq[((size_t)x * nfc + yy) * nfc + z] = hilbert3(2 * x, 2 * yy, 2 * z, nb) >> 3;
     ok &= hipMemcpy(w + y.hcell, hc.data(), hc.size() * 4, hipMemcpyHostToDevice) == hipSuccess;
-    ok &= hipMemcpy(w + y.hcoarse, hq.data(), hq.size() * 4, hipMemcpyHostToDevice) == hipSuccess;
   }
   for (int d = 0; d < 3; ++d) {
     const int K = h.K[d];

@@ -80,7 +80,6 @@ struct LegDev {
                                         // its first and in its second window (float bits)
   int units;                            // integration units per window (rigid waters + other atoms)
   const unsigned* hcell;                // [ncell] Hilbert index of fine cell (x * 2^nbits + y) * 2^nbits + z
-  const unsigned* hcoarse;              // [ncell / 8] Hilbert index / 8 of coarse block (x, y, z), same order
   int* perm;                            // [W][npad] sorted slot -> atom (-1 = padding)
   int* cellcode;                        // [W][n]
   int* cellstart;                       // [W][ncell + 1]
