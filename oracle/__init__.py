@@ -8,8 +8,8 @@ smooth PME (numpy FFTs), bonded and Boresch terms, a Langevin-middle step with
 iterative SHAKE constraints and a Philox noise stream written from its
 published definition, the cross-lambda reduced potentials, a plain
 self-consistent MBAR, Metropolis replica exchange between neighbouring
-windows, and the segmented free-energy assembly with the analytic restraint
-term.
+windows, the segmented free-energy assembly with the analytic restraint
+term, and the Monte Carlo barostat's volume move.
 
 Citations name the paper's sections:
   * "Double annihilation protocol" -- Beutler softcore form, Lorentz-Berthelot
@@ -28,5 +28,7 @@ alpha independence, lambda end points, finite differences, Newton's third
 law, NVE drift, harmonic-oscillator statistics, analytic harmonic free
 energies, BAR and EXP reductions, Philox known-answer vectors, the exact
 stationary distribution of replica exchange over permutations, the analytic
-restraint term against quadrature of the restrained partition function).
+restraint term against quadrature of the restrained partition function, the
+ideal-gas isothermal-isobaric volume law and the gas constant at standard
+conditions for the barostat).
 """
