@@ -113,6 +113,10 @@ typedef struct felis_leg {
   uint64_t seed;                 /* noise key of this leg */
   int64_t step;                  /* index of the next MD step (advanced by felis_step) */
   int32_t list_cap;              /* list entries per 8-atom cluster; 0 = sized from density */
+  double pressure_bar;           /* > 0: NPT; a Monte Carlo barostat at this pressure gives each
+                                    window its own box (section "Simulation protocol"); 0: every
+                                    window keeps `box` */
+  int32_t barostat_every;        /* MD steps between volume moves (with pressure_bar > 0) */
   void* work;                    /* (dev) library scratch of work_bytes */
   size_t work_bytes;
 } felis_leg;
@@ -203,14 +207,50 @@ int felis_step(felis_ctx* ctx, felis_leg* legs, int n_legs, int n_steps, double 
                double temperature, double gamma);
 
 /* Reduced potentials of n_frames frames of one leg at K lambda states:
- * u[k * u_stride + f] = beta [lam_e E_LE + lam_e^2 E_LL + E_sc(lam_v) + lam_r U_B]
- * (lambda-independent terms dropped; MBAR is invariant to them).  Frame f's
- * coordinates are fx/fy/fz + f * frame_stride (dev, float, n_atoms each).
- * lambdas (host) [K][3].  Uses the leg's scratch (call felis_leg_init first);
- * at most 64 distinct lambda_vdw values and 256 ligand atoms. */
+ * u[k * u_stride + f] = beta [lam_e E_LE + lam_e^2 E_LL + E_sc(lam_v) + lam_r U_B + P V_f]
+ * (lambda-independent terms dropped; MBAR is invariant to them; the P V term
+ * only for legs with pressure_bar > 0).  Frame f's coordinates are
+ * fx/fy/fz + f * frame_stride (dev, float, n_atoms each); frame_box (dev,
+ * [n_frames][3] edges in A, or NULL: every frame in the leg's `box`) gives
+ * each frame's periodic box (NPT frames).  lambdas (host) [K][3].  Uses the
+ * leg's scratch (call felis_leg_init first); at most 64 distinct lambda_vdw
+ * values and 256 ligand atoms. */
 int felis_ukn(felis_ctx* ctx, felis_leg* leg, const double* lambdas, int K, const float* fx,
               const float* fy, const float* fz, int64_t frame_stride, int64_t n_frames,
-              double beta, double* u, int64_t u_stride);
+              const double* frame_box, double beta, double* u, int64_t u_stride);
+
+/* Monte Carlo barostat ("Simulation protocol": NPT at 1.01325 bar, a volume
+ * move every 25 steps) for legs with pressure_bar > 0.  Each window (replica)
+ * has its own box and moves on its own: V' = V + dV_max (2 u1 - 1), box edges
+ * scaled by s = (V'/V)^(1/3), every molecule (bonded component, rigid waters
+ * joined) translated rigidly so that the mean of its atom positions scales
+ * by s; accepted when w = U' - U + P (V' - V) - N_mol kT ln(V'/V) <= 0 or
+ * u2 < exp(-w/kT), otherwise positions and box are restored (velocities are
+ * never scaled).  U is the window's total energy (all FELIS_NE components,
+ * computed by the library before and after the move).  dV_max starts at
+ * 0.01 V and is divided by 1.1 after a block of 10 attempts with fewer than
+ * a quarter accepted, multiplied by 1.1 (at most 0.3 V) with more than three
+ * quarters.  u1, u2 from Philox4x32-10 on counter (window, 0x4241524F,
+ * attempt) with the leg's seed as key: u1 = ((w0 >> 5) 2^26 + (w1 >> 6))
+ * 2^-53, u2 the same from (w2, w3).
+ * felis_step makes the move before every step whose index is a positive
+ * multiple of barostat_every (attempt = step / barostat_every);
+ * felis_barostat makes one now for every leg of the batch with a pressure
+ * (others are evaluated but unchanged), at the given attempt index, and
+ * leaves every window's lists valid for its positions and box.
+ * FELIS_E_INVAL if no leg of the batch has a pressure. */
+int felis_barostat(felis_ctx* ctx, felis_leg* legs, int n_legs, double temperature, int64_t attempt);
+
+/* Each window's current box edges, edges (host) [n_windows][3].  Synchronises. */
+int felis_leg_boxes(felis_ctx* ctx, const felis_leg* leg, double* edges);
+
+/* Barostat state of each window after the last move, out (host)
+ * [n_windows][FELIS_BARO_NS]: U before, U after the trial move (kcal/mol),
+ * w (kcal/mol), V, V' (A^3), s, accepted (0/1), dV_max (A^3), attempts and
+ * acceptances so far.  Synchronises.  FELIS_E_INVAL for a leg without a
+ * pressure. */
+#define FELIS_BARO_NS 10
+int felis_barostat_stats(felis_ctx* ctx, const felis_leg* leg, double* out);
 
 /* Hamiltonian replica exchange among the windows of one leg (simulation
  * details: exchanges among one GPU's windows every 5 ps).  The leg's windows
@@ -260,7 +300,8 @@ enum {
   FELIS_PROF_NLIST = 2,     /* displacement check and list rebuild */
   FELIS_PROF_INTEGRATE = 3, /* Langevin-middle update with SETTLE */
   FELIS_PROF_UKN = 4,       /* one felis_ukn call */
-  FELIS_PROF_N = 5
+  FELIS_PROF_BARO = 5,      /* one volume move (two energy evaluations, move, test) */
+  FELIS_PROF_N = 6
 };
 int felis_profile(felis_ctx* ctx, int enable);
 int felis_profile_read(felis_ctx* ctx, int which, double* total_ms, int64_t* launches);

@@ -31,6 +31,7 @@ UNITS = {
     'ukn.hip': [],
     'mbar.hip': [],
     'hrex.hip': [],
+    'barostat.hip': [],
     'felis.cpp': [],
 }
 

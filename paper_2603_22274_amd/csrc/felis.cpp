@@ -18,7 +18,7 @@ using namespace felis;
 namespace {
 
 struct Layout {
-  size_t lam, lamS, rstate, free_atoms, lig_idx, xr, yr, zr, flag, nbuild, maxdisp, wmax, hcell, perm, cellcode, cellstart, cursor, xyzq, prm, bblo,
+  size_t lam, lamS, rstate, free_atoms, lig_idx, xr, yr, zr, flag, nbuild, maxdisp, wmax, hcell, box, ubox, rbforce, mol_ptr, mol_atoms, baro, boxb, xb, yb, zb, perm, cellcode, cellstart, cursor, xyzq, prm, bblo,
       bbhi, gsten, lcount, lent, frx, fry, frz, grid64, cgrid, tw[3], bmod[3], eacc, uacc, upart, lpart, ucst, total;
 };
 
@@ -31,6 +31,7 @@ struct Plan {
 
 struct Meta {          // facts read from the topology at felis_leg_init
   int nfree, nlig;
+  int nmol;            // molecules (legs with a barostat; 0 otherwise)
   size_t work_bytes;
 };
 
@@ -90,6 +91,8 @@ int make_plan(felis_ctx* c, const felis_leg* L, Plan& P) {
   const double lmin = std::min(L->box[0], std::min(L->box[1], L->box[2]));
   if (!(L->r_cut + L->skin < 0.5 * lmin)) return fail(c, FELIS_E_BOX, "r_cut + skin must be below half the box");
   if (L->sc_p != 1) return fail(c, FELIS_E_UNSUPPORTED, "softcore p must be 1");
+  if (!(L->pressure_bar >= 0) || !(L->pressure_bar < 1e6) || (L->pressure_bar > 0 && L->barostat_every < 1))
+    return fail(c, FELIS_E_INVAL, "pressure_bar >= 0 and, with a barostat, barostat_every >= 1");
   if (L->spline_order != 4) return fail(c, FELIS_E_UNSUPPORTED, "PME spline order must be 4");
   if (!(L->sc_alpha >= 0)) return fail(c, FELIS_E_INVAL, "sc_alpha");
   // the real-space erfc is a fit on [0, 3.5] (Ewald tolerances down to ~4e-7)
@@ -132,7 +135,8 @@ int make_plan(felis_ctx* c, const felis_leg* L, Plan& P) {
     h.K[d] = K;
   }
   h.Ktot = h.K[0] * h.K[1] * h.K[2];
-  h.npair = (h.W + 1) / 2;
+  // a barostat gives every window its own box: one window per complex grid
+  h.npair = L->pressure_bar > 0 ? h.W : (h.W + 1) / 2;
   int nbits = (int)std::floor(std::log2(lmin / 2.4));
   nbits = std::max(1, std::min(7, nbits));
   p.nbits = nbits;
@@ -159,6 +163,18 @@ int make_plan(felis_ctx* c, const felis_leg* L, Plan& P) {
   y.free_atoms = put(n * 4);
   y.lig_idx = put(n * 4);
   y.hcell = put((size_t)h.ncell * 4);            // filled once at set-up (outside every cleared range)
+  y.box = put(W * sizeof(BoxW));                  // set at set-up, changed only by the barostat
+  y.ubox = put(2 * (size_t)h.npair * sizeof(BoxW));
+  y.rbforce = put(W * 4);
+  {
+    // barostat: molecule table, per-window state, positions before a move
+    const bool npt = L->pressure_bar > 0;
+    y.mol_ptr = put(npt ? (n + 1) * 4 : 0);
+    y.mol_atoms = put(npt ? n * 4 : 0);
+    y.baro = put(npt ? W * sizeof(BaroW) : 0);
+    y.boxb = put(npt ? W * sizeof(BoxW) : 0);
+    y.xb = put(npt ? W * n * 4 : 0); y.yb = put(npt ? W * n * 4 : 0); y.zb = put(npt ? W * n * 4 : 0);
+  }
   y.xr = put(W * n * 4); y.yr = put(W * n * 4); y.zr = put(W * n * 4);
   y.flag = put(W * 4);
   y.nbuild = put(W * 8);
@@ -207,13 +223,10 @@ LegDev make_dev(const felis_ctx* c, const felis_leg* L, const Plan& p, const Met
     g.rg0[t] = (float)L->restraint_g0[t];
     g.rk[t] = (float)L->restraint_k[t];
   }
-  for (int d = 0; d < 3; ++d) {
-    g.L[d] = L->box[d];
-    g.invL[d] = 1.0 / L->box[d];
-    g.Lf[d] = (float)L->box[d];
-    g.invLf[d] = (float)(1.0 / L->box[d]);
-  }
+  g.box0 = make_box(L->box, L->ewald_alpha);
+  g.pack = L->pressure_bar > 0 ? 0 : 1;
   g.rc2 = (float)(L->r_cut * L->r_cut);
+  g.rc2d = L->r_cut * L->r_cut;
   g.alpha = (float)L->ewald_alpha;
   g.sc_alpha = (float)L->sc_alpha;
   g.skin_half2 = (float)(0.25 * L->skin * L->skin);
@@ -221,10 +234,7 @@ LegDev make_dev(const felis_ctx* c, const felis_leg* L, const Plan& p, const Met
   g.rlist2 = g.rlist * g.rlist;
   g.d_oh = (float)L->d_oh;
   g.d_hh = (float)L->d_hh;
-  const double V = L->box[0] * L->box[1] * L->box[2];
-  g.pme_pref = (float)(kKE / (M_PI * V));
   g.self_pref = (float)(kKE * L->ewald_alpha / std::sqrt(M_PI));
-  g.bg_pref = kKE * M_PI / (2.0 * V * L->ewald_alpha * L->ewald_alpha);
   g.q = L->charge; g.sig = L->sigma; g.eps = L->epsilon; g.mass = L->mass; g.lig = L->is_ligand;
   g.excl_ij = L->excl_ij; g.excl_ptr = L->excl_ptr; g.excl_idx = L->excl_idx;
   g.bond_ij = L->bond_ij; g.bond_k = L->bond_k; g.bond_r0 = L->bond_r0;
@@ -246,6 +256,17 @@ LegDev make_dev(const felis_ctx* c, const felis_leg* L, const Plan& p, const Met
   g.wmax = (unsigned*)(w + y.wmax);
   g.units = p.h.nwat + p.h.nfree;
   g.hcell = (const unsigned*)(w + y.hcell);
+  g.box = (BoxW*)(w + y.box);
+  g.ubox = (BoxW*)(w + y.ubox);
+  g.rbforce = (int*)(w + y.rbforce);
+  g.nmol = m.nmol;
+  if (m.nmol) {
+    g.mol_ptr = (const int*)(w + y.mol_ptr);
+    g.mol_atoms = (const int*)(w + y.mol_atoms);
+    g.baro = (BaroW*)(w + y.baro);
+    g.boxb = (BoxW*)(w + y.boxb);
+    g.xb = (float*)(w + y.xb); g.yb = (float*)(w + y.yb); g.zb = (float*)(w + y.zb);
+  }
   g.perm = (int*)(w + y.perm);
   g.cellcode = (int*)(w + y.cellcode);
   g.cellstart = (int*)(w + y.cellstart);
@@ -286,6 +307,7 @@ int prepare(felis_ctx* c, const felis_leg* legs, int n_legs, std::vector<LegHost
     if (!legs[i].work || legs[i].work_bytes < p.lay.total) return fail(c, FELIS_E_INVAL, "leg work buffer too small");
     p.h.nfree = it->second.nfree;
     p.h.nlig = it->second.nlig;
+    p.h.nmol = it->second.nmol;
     hs[i] = p.h;
     devs[i] = make_dev(c, &legs[i], p, it->second, i);
   }
@@ -489,6 +511,10 @@ int felis_leg_init(felis_ctx* c, felis_leg* L) {
         for (int z = 0; z < nf; ++z) hc[((size_t)x * nf + yy) * nf + z] = hilbert3(x, yy, z, nb);
     ok &= hipMemcpy(w + y.hcell, hc.data(), hc.size() * 4, hipMemcpyHostToDevice) == hipSuccess;
   }
+  {
+    const std::vector<BoxW> bw((size_t)h.W, make_box(L->box, L->ewald_alpha));
+    ok &= hipMemcpy(w + y.box, bw.data(), bw.size() * sizeof(BoxW), hipMemcpyHostToDevice) == hipSuccess;
+  }
   for (int d = 0; d < 3; ++d) {
     const int K = h.K[d];
     std::vector<float> tw(2 * (size_t)K), bm(K);
@@ -511,6 +537,7 @@ int felis_leg_init(felis_ctx* c, felis_leg* L) {
   ok &= hipMemsetAsync(w + y.nbuild, 0, h.W * 8, c->stream) == hipSuccess;
   ok &= hipMemsetAsync(w + y.maxdisp, 0, h.W * 4, c->stream) == hipSuccess;
   ok &= hipMemsetAsync(w + y.wmax, 0, y.perm - y.wmax, c->stream) == hipSuccess;
+  ok &= hipMemsetAsync(w + y.rbforce, 0, h.W * 4, c->stream) == hipSuccess;
   ok &= hipMemsetAsync(w + y.lcount, 0, (size_t)h.W * h.nclus * 2 * 4, c->stream) == hipSuccess;
   ok &= hipMemsetAsync(w + y.grid64, 0, y.cgrid - y.grid64, c->stream) == hipSuccess;
   ok &= hipMemsetAsync(w + y.eacc, 0, y.ucst - y.eacc, c->stream) == hipSuccess;
@@ -519,6 +546,47 @@ int felis_leg_init(felis_ctx* c, felis_leg* L) {
   Meta m;
   m.nfree = (int)freeat.size();
   m.nlig = (int)ligi.size();
+  m.nmol = 0;
+  if (L->pressure_bar > 0) {
+    // molecules: connected components of the bonds with each rigid water's
+    // atoms joined (union-find), numbered by their lowest atom
+    std::vector<int> bij(2 * (size_t)h.nbonds);
+    if (h.nbonds && hipMemcpy(bij.data(), L->bond_ij, bij.size() * 4, hipMemcpyDeviceToHost) != hipSuccess)
+      return fail(c, FELIS_E_DEVICE, "bond copy failed");
+    std::vector<int> parent(h.n);
+    for (int a = 0; a < h.n; ++a) parent[a] = a;
+    auto find = [&](int a) {
+      while (parent[a] != a) { parent[a] = parent[parent[a]]; a = parent[a]; }
+      return a;
+    };
+    auto join = [&](int a, int b) {
+      if (a < 0 || b < 0 || a >= h.n || b >= h.n) return false;
+      const int ra = find(a), rb = find(b);
+      if (ra != rb) parent[std::max(ra, rb)] = std::min(ra, rb);
+      return true;
+    };
+    for (int k = 0; k < h.nbonds; ++k)
+      if (!join(bij[2 * k], bij[2 * k + 1])) return fail(c, FELIS_E_INVAL, "bond atom out of range");
+    for (int k = 0; k < h.nwat; ++k) { join(wat[3 * k], wat[3 * k + 1]); join(wat[3 * k], wat[3 * k + 2]); }
+    std::vector<int> id(h.n, -1), cnt;
+    for (int a = 0; a < h.n; ++a) {
+      const int r = find(a);
+      if (id[r] < 0) { id[r] = (int)cnt.size(); cnt.push_back(0); }
+      ++cnt[id[r]];
+    }
+    m.nmol = (int)cnt.size();
+    std::vector<int> ptr(m.nmol + 1, 0), atoms(h.n), fill;
+    for (int t = 0; t < m.nmol; ++t) ptr[t + 1] = ptr[t] + cnt[t];
+    fill.assign(ptr.begin(), ptr.end() - 1);
+    for (int a = 0; a < h.n; ++a) atoms[fill[id[find(a)]]++] = a;
+    std::vector<BaroW> bw((size_t)h.W);
+    std::memset(bw.data(), 0, bw.size() * sizeof(BaroW));
+    for (auto& b : bw) b.dv_max = 0.01 * L->box[0] * L->box[1] * L->box[2];
+    ok &= hipMemcpy(w + y.mol_ptr, ptr.data(), ptr.size() * 4, hipMemcpyHostToDevice) == hipSuccess;
+    ok &= hipMemcpy(w + y.mol_atoms, atoms.data(), atoms.size() * 4, hipMemcpyHostToDevice) == hipSuccess;
+    ok &= hipMemcpy(w + y.baro, bw.data(), bw.size() * sizeof(BaroW), hipMemcpyHostToDevice) == hipSuccess;
+    if (!ok) return fail(c, FELIS_E_DEVICE, "barostat tables");
+  }
   m.work_bytes = L->work_bytes;
   c->meta[L->work] = m;
   c->cache.clear();
@@ -591,6 +659,35 @@ int felis_bonded(felis_ctx* c, felis_leg* legs, int n_legs, int flags) {
   return launched(c);
 }
 
+// Every energy component of every window of the batch (lists brought up to
+// date first); the window totals land in each leg's energy array.
+void energy_pass(felis_ctx* c, const std::vector<LegHost>& hs, int n_legs, bool from_word) {
+  const LegHost* h = hs.data();
+  launch_zero_energy(c->stream, c->d_legs, h, n_legs, 0, FELIS_E_TOTAL);
+  launch_check(c->stream, c->d_legs, h, n_legs, 0, from_word);
+  launch_sort_pack(c->stream, c->d_legs, h, n_legs);
+  launch_lists(c->stream, c->d_legs, h, n_legs);
+  launch_pairs(c->stream, c->d_legs, h, n_legs, true);
+  launch_corrections(c->stream, c->d_legs, h, n_legs, true);
+  launch_bonded(c->stream, c->d_legs, h, n_legs, true);
+  launch_pme(c->stream, c->d_legs, h, n_legs, true, false);
+  launch_finish_energy(c->stream, c->d_legs, h, n_legs, 0, FELIS_E_TOTAL);
+}
+
+// One volume move of every window of the due legs: energies, trial move
+// (box, molecule centres), energies in the trial boxes, Metropolis test and
+// restore of rejected windows.  Windows of other legs are evaluated too
+// (their state is unchanged).
+void baro_attempt(felis_ctx* c, const std::vector<LegHost>& hs, int n_legs, const BaroArgs& A, bool from_word) {
+  mark(c, FELIS_PROF_BARO, false);
+  energy_pass(c, hs, n_legs, from_word);
+  launch_baro_keep_u0(c->stream, c->d_legs, hs.data(), n_legs);
+  launch_baro_propose(c->stream, c->d_legs, hs.data(), n_legs, A);
+  energy_pass(c, hs, n_legs, false);
+  launch_baro_accept(c->stream, c->d_legs, hs.data(), n_legs, A);
+  mark(c, FELIS_PROF_BARO, true);
+}
+
 int felis_step(felis_ctx* c, felis_leg* legs, int n_legs, int n_steps, double dt, double temperature,
                double gamma) {
   std::vector<LegHost> hs;
@@ -600,12 +697,29 @@ int felis_step(felis_ctx* c, felis_leg* legs, int n_legs, int n_steps, double dt
     return fail(c, FELIS_E_INVAL, "n_steps, dt, temperature, gamma");
   std::vector<long long> step(n_legs);
   std::vector<unsigned long long> seed(n_legs);
+  BaroArgs A;
+  std::memset(&A, 0, sizeof(A));
+  A.kT = kKB * temperature;
   for (int s = 0; s < n_steps; ++s) {
-    for (int i = 0; i < n_legs; ++i) { step[i] = legs[i].step + s; seed[i] = legs[i].seed; }
+    bool baro = false;
+    for (int i = 0; i < n_legs; ++i) {
+      step[i] = legs[i].step + s;
+      seed[i] = legs[i].seed;
+      // volume moves before the steps whose index is a positive multiple of
+      // barostat_every
+      const bool due = legs[i].pressure_bar > 0 && step[i] > 0 && step[i] % legs[i].barostat_every == 0;
+      A.due[i] = due ? 1 : 0;
+      A.attempt[i] = due ? step[i] / legs[i].barostat_every : 0;
+      A.seed[i] = legs[i].seed;
+      A.pressure[i] = legs[i].pressure_bar * kBar;
+      baro |= due;
+    }
+    if (baro) baro_attempt(c, hs, n_legs, A, s > 0);
     mark(c, FELIS_PROF_NLIST, false);
     // the first step scans positions; later steps read the largest
-    // displacement the previous step's integrator recorded
-    launch_check(c->stream, c->d_legs, hs.data(), n_legs, 0, s > 0);
+    // displacement the previous step's integrator recorded (after a volume
+    // move: scan again)
+    launch_check(c->stream, c->d_legs, hs.data(), n_legs, 0, s > 0 && !baro);
     launch_sort_pack(c->stream, c->d_legs, hs.data(), n_legs);
     // reciprocal space needs only the cell sort and the packed coordinates
     // and parameters: it runs on the side stream beside the list build, the
@@ -633,8 +747,72 @@ int felis_step(felis_ctx* c, felis_leg* legs, int n_legs, int n_steps, double dt
   return launched(c);
 }
 
+int felis_barostat(felis_ctx* c, felis_leg* legs, int n_legs, double temperature, int64_t attempt) {
+  std::vector<LegHost> hs;
+  int rc = prepare(c, legs, n_legs, hs);
+  if (rc) return rc;
+  if (!(temperature > 0) || attempt < 0) return fail(c, FELIS_E_INVAL, "temperature > 0, attempt >= 0");
+  BaroArgs A;
+  std::memset(&A, 0, sizeof(A));
+  A.kT = kKB * temperature;
+  bool any = false;
+  for (int i = 0; i < n_legs; ++i) {
+    A.due[i] = legs[i].pressure_bar > 0 ? 1 : 0;
+    A.attempt[i] = attempt;
+    A.seed[i] = legs[i].seed;
+    A.pressure[i] = legs[i].pressure_bar * kBar;
+    any |= A.due[i] != 0;
+  }
+  if (!any) return fail(c, FELIS_E_INVAL, "no leg of the batch has a pressure");
+  baro_attempt(c, hs, n_legs, A, false);
+  // lists of rejected windows were built for the trial move: rebuild them now
+  launch_check(c->stream, c->d_legs, hs.data(), n_legs, 0, false);
+  launch_build(c->stream, c->d_legs, hs.data(), n_legs);
+  return launched(c);
+}
+
+int felis_leg_boxes(felis_ctx* c, const felis_leg* L, double* edges) {
+  std::vector<LegHost> hs;
+  int rc = prepare(c, L, 1, hs);
+  if (rc) return rc;
+  if (!edges) return fail(c, FELIS_E_INVAL, "null output");
+  Plan p;
+  make_plan(c, L, p);
+  std::vector<BoxW> b((size_t)L->n_windows);
+  if (hipMemcpyAsync(b.data(), (char*)L->work + p.lay.box, b.size() * sizeof(BoxW), hipMemcpyDeviceToHost,
+                     c->stream) != hipSuccess ||
+      hipStreamSynchronize(c->stream) != hipSuccess)
+    return fail(c, FELIS_E_DEVICE, "box copy failed");
+  for (int w = 0; w < L->n_windows; ++w)
+    for (int d = 0; d < 3; ++d) edges[3 * w + d] = b[w].L[d];
+  return FELIS_OK;
+}
+
+int felis_barostat_stats(felis_ctx* c, const felis_leg* L, double* out) {
+  std::vector<LegHost> hs;
+  int rc = prepare(c, L, 1, hs);
+  if (rc) return rc;
+  if (!out) return fail(c, FELIS_E_INVAL, "null output");
+  if (!(L->pressure_bar > 0)) return fail(c, FELIS_E_INVAL, "the leg has no barostat");
+  Plan p;
+  make_plan(c, L, p);
+  std::vector<BaroW> b((size_t)L->n_windows);
+  if (hipMemcpyAsync(b.data(), (char*)L->work + p.lay.baro, b.size() * sizeof(BaroW), hipMemcpyDeviceToHost,
+                     c->stream) != hipSuccess ||
+      hipStreamSynchronize(c->stream) != hipSuccess)
+    return fail(c, FELIS_E_DEVICE, "barostat state copy failed");
+  for (int w = 0; w < L->n_windows; ++w) {
+    double* o = out + (size_t)FELIS_BARO_NS * w;
+    o[0] = b[w].u0; o[1] = b[w].u1; o[2] = b[w].work; o[3] = b[w].vol_old; o[4] = b[w].vol_new;
+    o[5] = b[w].scale; o[6] = b[w].accepted; o[7] = b[w].dv_max; o[8] = (double)b[w].total_att;
+    o[9] = (double)b[w].total_acc;
+  }
+  return FELIS_OK;
+}
+
 int felis_ukn(felis_ctx* c, felis_leg* leg, const double* lambdas, int K, const float* fx, const float* fy,
-              const float* fz, int64_t frame_stride, int64_t n_frames, double beta, double* u, int64_t u_stride) {
+              const float* fz, int64_t frame_stride, int64_t n_frames, const double* frame_box, double beta,
+              double* u, int64_t u_stride) {
   std::vector<LegHost> hs;
   int rc = prepare(c, leg, 1, hs);
   if (rc) return rc;
@@ -648,8 +826,9 @@ int felis_ukn(felis_ctx* c, felis_leg* leg, const double* lambdas, int K, const 
   make_plan(c, leg, p);
   char* w = (char*)leg->work;
   mark(c, FELIS_PROF_UKN, false);
-  rc = launch_ukn(c->stream, c->d_legs, hs[0], leg->sc_alpha, lambdas, K, fx, fy, fz, frame_stride, n_frames, beta,
-                  u, u_stride, (long long*)(w + p.lay.uacc), (double*)(w + p.lay.ucst));
+  rc = launch_ukn(c->stream, c->d_legs, hs[0], leg->sc_alpha, lambdas, K, fx, fy, fz, frame_stride, n_frames,
+                  frame_box, leg->pressure_bar * kBar, beta, u, u_stride, (long long*)(w + p.lay.uacc),
+                  (double*)(w + p.lay.ucst));
   mark(c, FELIS_PROF_UKN, true);
   if (rc) return fail(c, rc, "u_kn: more than 128 states, 64 distinct lambda_vdw or 256 ligand atoms");
   return launched(c);

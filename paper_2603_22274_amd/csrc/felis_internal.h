@@ -21,6 +21,7 @@ constexpr int kMaxFFT = 128;        // largest PME grid dimension (bases pack in
 constexpr int kClus = 8;            // atoms per i-cluster (pair kernel)
 
 constexpr double kKE = 332.06371;                 // kcal A / (mol e^2)
+constexpr double kBar = 1.0e-25 * 6.02214076e23 / 4184.0;   // 1 bar in kcal / (mol A^3)
 constexpr double kKB = 0.0019872043;              // kcal / (mol K)
 constexpr double kAccel = 418.4;                  // (kcal/mol/A/amu) -> A/ps^2
 constexpr double kForceScale = 4294967296.0;      // 2^32 int64 units per kcal/mol/A
@@ -35,6 +36,41 @@ enum : int {
   kErrBox = 8,           // cutoff or list radius inconsistent with the box
 };
 
+// One window's periodic box.  Every window starts in the leg's box; with a
+// barostat each window's box changes on its own.
+struct BoxW {
+  float Lf[3], invLf[3];
+  float pme_pref;                       // KE / (pi V)
+  float pad_;
+  double L[3], invL[3];
+  double bg_pref;                       // KE pi / (2 V alpha^2)
+  double vol;
+};
+
+__host__ __device__ inline BoxW make_box(const double* L, double alpha) {
+  BoxW b;
+  for (int d = 0; d < 3; ++d) {
+    b.L[d] = L[d];
+    b.invL[d] = 1.0 / L[d];
+    b.Lf[d] = (float)L[d];
+    b.invLf[d] = (float)(1.0 / L[d]);
+  }
+  b.vol = L[0] * L[1] * L[2];
+  b.pme_pref = (float)(kKE / (3.14159265358979323846 * b.vol));
+  b.bg_pref = kKE * 3.14159265358979323846 / (2.0 * b.vol * alpha * alpha);
+  b.pad_ = 0.f;
+  return b;
+}
+
+// Barostat state of one window
+struct BaroW {
+  double dv_max;                        // half-width of the volume proposal, A^3
+  double u0, u1;                        // window energy before / after the trial move
+  double vol_old, vol_new, scale, work;
+  int due, accepted, n_att, n_acc;      // this attempt; attempts and acceptances in the block of 10
+  long long total_att, total_acc;
+};
+
 // Per-leg device descriptor: sizes, parameters, and pointers into the
 // caller's state and the leg's private workspace.
 struct LegDev {
@@ -45,14 +81,14 @@ struct LegDev {
   int nrad[3], rad[3][kMaxRadix];       // FFT radix plan per axis
   int has_rest, ranch[6];
   float rg0[6], rk[6];
-  double L[3], invL[3];
-  float Lf[3], invLf[3];
+  BoxW box0;                            // the leg's box at set-up (u_kn frames given without boxes)
+  int pack;                             // 1: windows 2p, 2p+1 share complex grid p (equal boxes);
+                                        // 0: one window per grid (each window its own box)
   float rc2, alpha, sc_alpha, skin_half2;
+  double rc2d;                          // r_cut^2 in FP64 (u_kn distance test)
   double rlist, rlist2;
   float d_oh, d_hh;
-  float pme_pref;                       // KE / (pi V)
   float self_pref;                      // KE alpha / sqrt(pi)
-  double bg_pref;                       // KE pi / (2 V alpha^2)
   // topology (caller-owned)
   const float *q, *sig, *eps, *mass;
   const uint8_t* lig;
@@ -65,6 +101,16 @@ struct LegDev {
   long long *fx, *fy, *fz;
   double* energy;                       // [W][FELIS_NE]
   // workspace (library-owned layout)
+  BoxW* box;                            // [W] each window's box
+  BoxW* ubox;                           // [2 npair] boxes of the u_kn frames of one pass
+  int* rbforce;                         // [W] 1: rebuild the window's lists at the next check
+  // barostat (legs with a pressure; nmol = 0 otherwise)
+  int nmol;                             // molecules: bonded components, rigid waters joined
+  const int* mol_ptr;                   // [nmol + 1] CSR over mol_atoms
+  const int* mol_atoms;                 // [n]
+  BaroW* baro;                          // [W]
+  BoxW* boxb;                           // [W] box before the trial move
+  float *xb, *yb, *zb;                  // [W][n] positions before the trial move
   float* lam;                           // [W][4] per replica: elec, vdw, restraint, sc_alpha*(1-vdw) of
                                         // the state it holds
   const float* lamS;                    // [W][4] the same rows in state order (the leg's lambda table)
@@ -256,6 +302,17 @@ inline int make_map(BlockMap& m, int n_legs, F blocks_of) {
 struct LegHost {
   int n, W, npad, nclus, cap, nexcl, nbonds, nwat, nfree, nlig, K[3], Ktot, npair, ncell;
   int has_rest;
+  int nmol;                             // > 0 only for legs with a barostat
+};
+
+// One barostat attempt for a batch: which legs move, their attempt index,
+// noise key and pressure (kcal / (mol A^3))
+struct BaroArgs {
+  int due[kMaxLegs];
+  long long attempt[kMaxLegs];
+  unsigned long long seed[kMaxLegs];
+  double pressure[kMaxLegs];
+  double kT;
 };
 
 // ---- launchers (one per translation unit) ----
@@ -280,13 +337,20 @@ void launch_integrate(hipStream_t s, const LegDev* d, const LegHost* h, int nl,
 void launch_zero_energy(hipStream_t s, const LegDev* d, const LegHost* h, int nl, int c0, int c1);
 void launch_finish_energy(hipStream_t s, const LegDev* d, const LegHost* h, int nl, int c0, int c1);
 void launch_fill_i64(hipStream_t s, long long* p, size_t n);
-void launch_pme_fft(hipStream_t s, const LegDev* d, const LegHost* h, int nl, bool from_int64);
+// ukn_mode: 0 the MD grids; u_kn int64 grids of 1 two frames per complex grid
+// or 2 one frame per grid (boxes from ubox)
+void launch_pme_fft(hipStream_t s, const LegDev* d, const LegHost* h, int nl, int ukn_mode);
 void launch_hrex(hipStream_t s, const LegDev* d, const LegHost& h, const double* u, long long u_stride,
                  long long attempt, unsigned long long seed, int* accepted);
 int launch_ukn(hipStream_t s, const LegDev* d, const LegHost& h, double sc_alpha, const double* lambdas,
                int K, const float* fx, const float* fy, const float* fz, long long frame_stride,
-               long long n_frames, double beta, double* u, long long u_stride, long long* uacc,
-               double* cst);
+               long long n_frames, const double* frame_box, double pressure, double beta, double* u,
+               long long u_stride, long long* uacc, double* cst);
+// barostat: proposal, box change and molecule move of the due windows; the
+// energy before the move; Metropolis test, restore of rejected moves
+void launch_baro_propose(hipStream_t s, const LegDev* d, const LegHost* h, int nl, const BaroArgs& A);
+void launch_baro_keep_u0(hipStream_t s, const LegDev* d, const LegHost* h, int nl);
+void launch_baro_accept(hipStream_t s, const LegDev* d, const LegHost* h, int nl, const BaroArgs& A);
 int launch_mbar(hipStream_t s, const double* u, const int* N_k, int K, long long Ntot, double tol,
                 int max_iter, double* f_out, int* iters, void* work, size_t work_bytes);
 size_t mbar_work_bytes(int K, long long Ntot);

@@ -40,6 +40,7 @@ __global__ __launch_bounds__(256) void k_check(const LegDev* legs, BlockMap map,
   __shared__ float red[256];
   __shared__ int s_flag;
   float m = 0.f;
+  force |= g.rbforce[w];                         // a box change (barostat) since the last build
   if (FROM_WORD) {
     if (g.units < 64) {
       if (threadIdx.x == 0) m = __uint_as_float(g.maxdisp[w]);
@@ -69,6 +70,7 @@ __global__ __launch_bounds__(256) void k_check(const LegDev* legs, BlockMap map,
     g.flag[w] = f;
     g.nbuild[w] += f;
     g.maxdisp[w] = 0u;
+    g.rbforce[w] = 0;
     s_flag = f;
   }
   __syncthreads();
@@ -85,9 +87,10 @@ __global__ __launch_bounds__(256) void k_cells_count(const LegDev* legs, BlockMa
   const int w = (int)(i / g.n);
   if (!g.flag[w]) return;
   const int nf = 1 << g.nbits;
+  const BoxW& B = g.box[w];
   const float x = g.x[i], y = g.y[i], z = g.z[i];
-  const unsigned c = g.hcell[(cell_of(x, g.Lf[0], g.invLf[0], nf) * nf + cell_of(y, g.Lf[1], g.invLf[1], nf)) * nf +
-                            cell_of(z, g.Lf[2], g.invLf[2], nf)];
+  const unsigned c = g.hcell[(cell_of(x, B.Lf[0], B.invLf[0], nf) * nf + cell_of(y, B.Lf[1], B.invLf[1], nf)) * nf +
+                            cell_of(z, B.Lf[2], B.invLf[2], nf)];
   g.cellcode[i] = (int)c;
   atomicAdd(&g.cursor[(size_t)w * g.ncell + c], 1);
   g.xr[i] = x; g.yr[i] = y; g.zr[i] = z;
@@ -185,6 +188,7 @@ __global__ __launch_bounds__(1024) void k_check_sort(const LegDev* legs, BlockMa
   __shared__ int s_flag;
   const size_t o = (size_t)w * g.n;
   float m = 0.f;
+  force |= g.rbforce[w];                         // a box change (barostat) since the last build
   if (FROM_WORD) {
     if (g.units < 64) {
       if (tid == 0) m = __uint_as_float(g.maxdisp[w]);
@@ -211,12 +215,15 @@ __global__ __launch_bounds__(1024) void k_check_sort(const LegDev* legs, BlockMa
     g.flag[w] = f;
     g.nbuild[w] += f;
     g.maxdisp[w] = 0u;
+    g.rbforce[w] = 0;
     s_flag = f;
   }
   __syncthreads();
   if (!s_flag) return;                            // uniform over the block
 
   const int nc = g.ncell, n = g.n, nf = 1 << g.nbits;
+  const float bL[3] = {g.box[w].Lf[0], g.box[w].Lf[1], g.box[w].Lf[2]};
+  const float biL[3] = {g.box[w].invLf[0], g.box[w].invLf[1], g.box[w].invLf[2]};
   for (int c = tid; c < nc; c += blockDim.x) s_cur[c] = 0;
   // every position this thread sorts is loaded before any is used (at most
   // kSortAtoms / 1024 per thread), so the loads overlap
@@ -232,8 +239,8 @@ __global__ __launch_bounds__(1024) void k_check_sort(const LegDev* legs, BlockMa
   for (int k = 0; k < kPer; ++k) {
     const int a = tid + k * 1024;
     if (a < n) {
-      const unsigned c = g.hcell[(cell_of(px[k], g.Lf[0], g.invLf[0], nf) * nf + cell_of(py[k], g.Lf[1], g.invLf[1], nf)) *
-                                     nf + cell_of(pz[k], g.Lf[2], g.invLf[2], nf)];
+      const unsigned c = g.hcell[(cell_of(px[k], bL[0], biL[0], nf) * nf + cell_of(py[k], bL[1], biL[1], nf)) *
+                                     nf + cell_of(pz[k], bL[2], biL[2], nf)];
       s_code[a] = (unsigned short)c;
       atomicAdd(&s_cur[c], 1);
       g.xr[o + a] = px[k]; g.yr[o + a] = py[k]; g.zr[o + a] = pz[k];
@@ -339,8 +346,9 @@ __global__ __launch_bounds__(256) void k_build(const LegDev* legs, BlockMap map)
   __syncthreads();
 
   // box edges in scalar registers: read once, not again after every list store
-  const float Lf[3] = {scalar(g.Lf[0]), scalar(g.Lf[1]), scalar(g.Lf[2])};
-  const float iLf[3] = {scalar(g.invLf[0]), scalar(g.invLf[1]), scalar(g.invLf[2])};
+  const BoxW& B = g.box[w];
+  const float Lf[3] = {scalar(B.Lf[0]), scalar(B.Lf[1]), scalar(B.Lf[2])};
+  const float iLf[3] = {scalar(B.invLf[0]), scalar(B.invLf[1]), scalar(B.invLf[2])};
   const int cap = __builtin_amdgcn_readfirstlane(g.cap);
   const float4 lo4 = g.bblo[item], hi4 = g.bbhi[item];
   const float lo[3] = {lo4.x, lo4.y, lo4.z}, hi[3] = {hi4.x, hi4.y, hi4.z};
@@ -589,9 +597,10 @@ __global__ __launch_bounds__(256) void k_export(const LegDev* legs, int leg, int
         double dx = (double)g.x[o + aj] - (double)g.x[o + ai];
         double dy = (double)g.y[o + aj] - (double)g.y[o + ai];
         double dz = (double)g.z[o + aj] - (double)g.z[o + ai];
-        dx = dx - g.L[0] * rint(dx * g.invL[0]);
-        dy = dy - g.L[1] * rint(dy * g.invL[1]);
-        dz = dz - g.L[2] * rint(dz * g.invL[2]);
+        const BoxW& B = g.box[w];
+        dx = dx - B.L[0] * rint(dx * B.invL[0]);
+        dy = dy - B.L[1] * rint(dy * B.invL[1]);
+        dz = dz - B.L[2] * rint(dz * B.invL[2]);
         const double d2 = (dx * dx + dy * dy) + dz * dz;
         if (!(d2 < r2)) continue;
         const unsigned long long k2 = atomicAdd(count, 1ull);

@@ -46,9 +46,10 @@ __global__ __launch_bounds__(256) void k_pack(const LegDev* legs, BlockMap map) 
     g.xyzq[i] = v;
     // PME stencil of the slot (read by spreading and the gather)
     float f[3];
-    const int bx = grid_base(v.x, g.invL[0], g.K[0], &f[0]);
-    const int by = grid_base(v.y, g.invL[1], g.K[1], &f[1]);
-    const int bz = grid_base(v.z, g.invL[2], g.K[2], &f[2]);
+    const BoxW& B = g.box[w];
+    const int bx = grid_base(v.x, B.invL[0], g.K[0], &f[0]);
+    const int by = grid_base(v.y, B.invL[1], g.K[1], &f[1]);
+    const int bz = grid_base(v.z, B.invL[2], g.K[2], &f[2]);
     g.gsten[i] = make_float4(f[0], f[1], f[2], pack_bases(bx, by, bz));
   }
   if (REBUILD) {
@@ -60,8 +61,9 @@ __global__ __launch_bounds__(256) void k_pack(const LegDev* legs, BlockMap map) 
     }
     float lo[3] = {3.0e38f, 3.0e38f, 3.0e38f}, hi[3] = {-3.0e38f, -3.0e38f, -3.0e38f};
     if (a >= 0) {
-      const float r[3] = {wrapf(v.x, g.Lf[0], g.invLf[0]), wrapf(v.y, g.Lf[1], g.invLf[1]),
-                          wrapf(v.z, g.Lf[2], g.invLf[2])};
+      const BoxW& B = g.box[w];
+      const float r[3] = {wrapf(v.x, B.Lf[0], B.invLf[0]), wrapf(v.y, B.Lf[1], B.invLf[1]),
+                          wrapf(v.z, B.Lf[2], B.invLf[2])};
       for (int d = 0; d < 3; ++d) { lo[d] = r[d]; hi[d] = r[d]; }
     }
     for (int k = 1; k < kClus; k <<= 1)
@@ -76,10 +78,10 @@ __global__ __launch_bounds__(256) void k_pack(const LegDev* legs, BlockMap map) 
   }
 }
 
-__device__ __forceinline__ float3 min_img(const LegDev& g, float dx, float dy, float dz) {
-  dx = fmaf(-g.Lf[0], rintf(dx * g.invLf[0]), dx);
-  dy = fmaf(-g.Lf[1], rintf(dy * g.invLf[1]), dy);
-  dz = fmaf(-g.Lf[2], rintf(dz * g.invLf[2]), dz);
+__device__ __forceinline__ float3 min_img(const BoxW& B, float dx, float dy, float dz) {
+  dx = fmaf(-B.Lf[0], rintf(dx * B.invLf[0]), dx);
+  dy = fmaf(-B.Lf[1], rintf(dy * B.invLf[1]), dy);
+  dz = fmaf(-B.Lf[2], rintf(dz * B.invLf[2]), dz);
   return make_float3(dx, dy, dz);
 }
 
@@ -92,17 +94,28 @@ __device__ __forceinline__ float uniform(float v) {
   return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
 }
 
+// a window's box edges held in scalar registers for a whole kernel
+struct BoxF {
+  float L[3], iL[3];
+};
+
+__device__ __forceinline__ BoxF box_f(const BoxW& B) {
+  BoxF b;
+  for (int d = 0; d < 3; ++d) { b.L[d] = uniform(B.Lf[d]); b.iL[d] = uniform(B.invLf[d]); }
+  return b;
+}
+
 // Sweep a cluster's j-list: lane = listed j, unrolled loop over the cluster's
 // i-atoms.  SHIFT: the periodic image of j is chosen once against the
 // cluster's first atom (exact when r_c + cluster extent < L/2 on every axis);
 // otherwise every (i, j) takes its own minimum image.
 template <bool ENERGY, bool SHIFT, int HALF>
-__device__ __forceinline__ void sweep(const LegDev& g, const ICluster& I, gptr<unsigned> ent, int cnt,
+__device__ __forceinline__ void sweep(const LegDev& g, const BoxF B, const ICluster& I, gptr<unsigned> ent, int cnt,
                                       gptr<f32x4> xq, gptr<f32x4> pr, int lane,
                                       float lam_v, float a_sc, bool soft_window, float (&fx)[4],
                                       float (&fy)[4], float (&fz)[4], double& ec, double& el) {
-  const float Lx = g.Lf[0], Ly = g.Lf[1], Lz = g.Lf[2];
-  const float iLx = g.invLf[0], iLy = g.invLf[1], iLz = g.invLf[2];
+  const float Lx = B.L[0], Ly = B.L[1], Lz = B.L[2];
+  const float iLx = B.iL[0], iLy = B.iL[1], iLz = B.iL[2];
   const float rc2 = g.rc2, alpha = g.alpha;
   const float c2a = 2.0f * alpha * 0.56418958354775628f;   // 2 alpha / sqrt(pi)
   const float pa = FELIS_ERFC_P * alpha;                    // fit variable t = 1 / (1 + P alpha r)
@@ -197,6 +210,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
   const int c = (int)(item - (long long)w * g.nclus);
   const gptr<f32x4> xq = as_global4(g.xyzq + (size_t)w * g.npad);
   const gptr<f32x4> pr = as_global4(g.prm + (size_t)w * g.npad);
+  const BoxF B = box_f(g.box[w]);
   const float lam_v = g.lam[4 * w + 1];
   const float a_sc = g.lam[4 * w + 3];
   const bool soft_window = lam_v < 1.0f;
@@ -213,7 +227,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
     if (ii > 0) {
       const float r0[3] = {I.x[0], I.y[0], I.z[0]};
       for (int d = 0; d < 3; ++d) {
-        v[d] = fmaf(-g.Lf[d], rintf((v[d] - r0[d]) * g.invLf[d]), v[d]);
+        v[d] = fmaf(-B.L[d], rintf((v[d] - r0[d]) * B.iL[d]), v[d]);
         if (c * kClus + ii < g.n) ext[d] = fmaxf(ext[d], fabsf(v[d] - r0[d]));
       }
     }
@@ -224,7 +238,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
     I.lig[ii] = uniform(p.z);
   }
   const float rc = sqrtf(g.rc2) + 0.01f;
-  const bool shift = rc + ext[0] < 0.5f * g.Lf[0] && rc + ext[1] < 0.5f * g.Lf[1] && rc + ext[2] < 0.5f * g.Lf[2];
+  const bool shift = rc + ext[0] < 0.5f * B.L[0] && rc + ext[1] < 0.5f * B.L[1] && rc + ext[2] < 0.5f * B.L[2];
   // the two half-cluster lists (partners of atoms 0-3, then of atoms 4-7);
   // each half's forces are reduced over the wave before the next half
   const gptr<unsigned> ent = as_global(g.lent + (size_t)item * 2 * g.cap);
@@ -236,11 +250,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
     const gptr<unsigned> eh = ent + half * g.cap;
     const int cnt = g.lcount[2 * item + half];
     if (half == 0) {
-      if (shift) sweep<ENERGY, true, 0>(g, I, eh, cnt, xq, pr, lane, lam_v, a_sc, soft_window, fx, fy, fz, ec, el);
-      else sweep<ENERGY, false, 0>(g, I, eh, cnt, xq, pr, lane, lam_v, a_sc, soft_window, fx, fy, fz, ec, el);
+      if (shift) sweep<ENERGY, true, 0>(g, B, I, eh, cnt, xq, pr, lane, lam_v, a_sc, soft_window, fx, fy, fz, ec, el);
+      else sweep<ENERGY, false, 0>(g, B, I, eh, cnt, xq, pr, lane, lam_v, a_sc, soft_window, fx, fy, fz, ec, el);
     } else {
-      if (shift) sweep<ENERGY, true, 1>(g, I, eh, cnt, xq, pr, lane, lam_v, a_sc, soft_window, fx, fy, fz, ec, el);
-      else sweep<ENERGY, false, 1>(g, I, eh, cnt, xq, pr, lane, lam_v, a_sc, soft_window, fx, fy, fz, ec, el);
+      if (shift) sweep<ENERGY, true, 1>(g, B, I, eh, cnt, xq, pr, lane, lam_v, a_sc, soft_window, fx, fy, fz, ec, el);
+      else sweep<ENERGY, false, 1>(g, B, I, eh, cnt, xq, pr, lane, lam_v, a_sc, soft_window, fx, fy, fz, ec, el);
     }
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
@@ -269,7 +283,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
       const float le = g.lam[4 * w];
       const float qa = g.q[ai] * (g.lig[ai] ? le : 1.f), qb = g.q[b] * (g.lig[b] ? le : 1.f);
       const size_t oa = (size_t)w * g.n + ai, ob = (size_t)w * g.n + b;
-      const float3 d = min_img(g, g.x[ob] - g.x[oa], g.y[ob] - g.y[oa], g.z[ob] - g.z[oa]);
+      float3 d = make_float3(g.x[ob] - g.x[oa], g.y[ob] - g.y[oa], g.z[ob] - g.z[oa]);
+      d.x = fmaf(-B.L[0], rintf(d.x * B.iL[0]), d.x);
+      d.y = fmaf(-B.L[1], rintf(d.y * B.iL[1]), d.y);
+      d.z = fmaf(-B.L[2], rintf(d.z * B.iL[2]), d.z);
       const float r2 = d.x * d.x + d.y * d.y + d.z * d.z;
       const float qq = (float)kKE * qa * qb;
       const float c2a = 2.0f * g.alpha * 0.56418958354775628f;
@@ -354,14 +371,14 @@ __global__ __launch_bounds__(256) void k_self(const LegDev* legs, BlockMap map) 
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    const double e = -(double)g.self_pref * r2[0] - g.bg_pref * r1[0] * r1[0];
+    const double e = -(double)g.self_pref * r2[0] - g.box[w].bg_pref * r1[0] * r1[0];
     atomicAdd((unsigned long long*)&g.eacc[(size_t)w * FELIS_NE + FELIS_E_SELF],
               (unsigned long long)to_fixed(e, kEnergyScale, g.err));
   }
 }
 
-__device__ __forceinline__ float3 vec(const LegDev& g, size_t ofrom, size_t oto) {
-  return min_img(g, g.x[oto] - g.x[ofrom], g.y[oto] - g.y[ofrom], g.z[oto] - g.z[ofrom]);
+__device__ __forceinline__ float3 vec(const LegDev& g, const BoxW& B, size_t ofrom, size_t oto) {
+  return min_img(B, g.x[oto] - g.x[ofrom], g.y[oto] - g.y[ofrom], g.z[oto] - g.z[ofrom]);
 }
 
 // items: window x (bonds + 1): harmonic bonds; the last item of a window is
@@ -381,7 +398,7 @@ __global__ __launch_bounds__(256) void k_bonded(const LegDev* legs, BlockMap map
     const size_t base = (size_t)w * g.n;
     if (k < g.nbonds) {
       const int a = g.bond_ij[2 * k], b = g.bond_ij[2 * k + 1];
-      const float3 d = vec(g, base + b, base + a);          // r_a - r_b
+      const float3 d = vec(g, g.box[w], base + b, base + a);          // r_a - r_b
       const float r = sqrtf(d.x * d.x + d.y * d.y + d.z * d.z);
       const float dr = r - g.bond_r0[k];
       const float fs = -g.bond_k[k] * dr / r;                // F_a = fs (r_a - r_b)
@@ -394,7 +411,7 @@ __global__ __launch_bounds__(256) void k_bonded(const LegDev* legs, BlockMap map
       const size_t o1 = base + g.ranch[0];
       for (int t = 0; t < 6; ++t) {
         const size_t ot = base + g.ranch[t];
-        const float3 d = min_img(g, g.x[ot] - g.x[o1], g.y[ot] - g.y[o1], g.z[ot] - g.z[o1]);
+        const float3 d = min_img(g.box[w], g.x[ot] - g.x[o1], g.y[ot] - g.y[o1], g.z[ot] - g.z[o1]);
         p[t] = mk(d.x, d.y, d.z);
       }
       er = (double)lr * boresch_eval(p, g.rg0, g.rk, F);

@@ -132,7 +132,7 @@ __device__ __forceinline__ float2* fft_lines(float2* src, float2* dst, int n, co
 // MODE: 0 forward, 1 inverse, 2 forward from the int64 grids (x axis),
 //       3 forward * G * inverse (z axis)
 template <int AXIS, int MODE>
-__global__ __launch_bounds__(256) void k_fft(const LegDev* legs, BlockMap map) {
+__global__ __launch_bounds__(256) void k_fft(const LegDev* legs, BlockMap map, int ukn) {
   const int leg = find_leg(map, blockIdx.x);
   const LegDev& g = legs[leg];
   const int Kx = g.K[0], Ky = g.K[1], Kz = g.K[2];
@@ -185,19 +185,21 @@ __global__ __launch_bounds__(256) void k_fft(const LegDev* legs, BlockMap map) {
   __syncthreads();
   float2* res = fft_lines(bufA, bufB, n, g.rad[AXIS], g.nrad[AXIS], tw);
   if (MODE == 3) {
-    // multiply by G(kx, ky, kz): element e = kz of line (ky = o, kx = ch*kLines + b)
+    // multiply by G(kx, ky, kz): element e = kz of line (ky = o, kx = ch*kLines + b),
+    // in the box of the grid's window (u_kn: of its frame)
+    const BoxW& B = ukn ? g.ubox[ukn == 1 ? 2 * p : p] : g.box[g.pack ? 2 * p : p];
     const float a2 = g.alpha * g.alpha;
     for (int idx = threadIdx.x; idx < n * kLines; idx += blockDim.x) {
       const int e = idx / kLines, b = idx - e * kLines;
       const int kx = ch * kLines + b, ky = o, kz = e;
       float G = 0.f;
       if (kx < Kx) {
-        const float mx = (float)(kx <= Kx / 2 ? kx : kx - Kx) * g.invLf[0];
-        const float my = (float)(ky <= Ky / 2 ? ky : ky - Ky) * g.invLf[1];
-        const float mz = (float)(kz <= Kz / 2 ? kz : kz - Kz) * g.invLf[2];
+        const float mx = (float)(kx <= Kx / 2 ? kx : kx - Kx) * B.invLf[0];
+        const float my = (float)(ky <= Ky / 2 ? ky : ky - Ky) * B.invLf[1];
+        const float mz = (float)(kz <= Kz / 2 ? kz : kz - Kz) * B.invLf[2];
         const float m2 = mx * mx + my * my + mz * mz;
         if (m2 > 0.f)
-          G = g.pme_pref * __expf(-9.8696044010893586f * m2 / a2) / m2 * g.bmod[0][kx] * g.bmod[1][ky] *
+          G = B.pme_pref * __expf(-9.8696044010893586f * m2 / a2) / m2 * g.bmod[0][kx] * g.bmod[1][ky] *
               g.bmod[2][kz];
       }
       const float2 v = res[idx];
@@ -381,7 +383,7 @@ __global__ __launch_bounds__(256) void k_spread(const LegDev* legs, BlockMap map
   const float margin = sqrtf(g.skin_half2) + 0.05f;
   int c0[3], nspan[3];
   for (int d = 0; d < 3; ++d) {
-    const float Lc = g.Lf[d] / (float)nc, hgrid = g.Lf[d] / (float)g.K[d];
+    const float Lc = g.box[w].Lf[d] / (float)nc, hgrid = g.box[w].Lf[d] / (float)g.K[d];
     const int a0 = (int)floorf(((float)P0[d] * hgrid - margin) / Lc);
     const int a1 = (int)floorf(((float)(P1[d] + 3) * hgrid + margin) / Lc);
     const bool full = a1 - a0 + 1 >= nc;
@@ -484,10 +486,10 @@ __global__ __launch_bounds__(256) void k_spread(const LegDev* legs, BlockMap map
     __syncthreads();                              // the round's tables are rewritten next
   }
   // this window's component of the pair's complex grid; an unpaired last
-  // window also clears the imaginary part
-  float* cg = reinterpret_cast<float*>(g.cgrid + (size_t)(w >> 1) * g.Ktot);
-  const int comp = w & 1;
-  const bool clear_im = comp == 0 && w + 1 >= g.W;
+  // window, or a window with a grid of its own, also clears the imaginary part
+  float* cg = reinterpret_cast<float*>(g.cgrid + (size_t)(g.pack ? w >> 1 : w) * g.Ktot);
+  const int comp = g.pack ? (w & 1) : 0;
+  const bool clear_im = comp == 0 && (!g.pack || w + 1 >= g.W);
   for (int e = tid; e < kBrick * kBrick * kBrick; e += 256) {
     const int lx = e % kBrick, ly = (e / kBrick) % kBrick, lz = e / (kBrick * kBrick);
     const int x = P0[0] + lx, y = P0[1] + ly, z = P0[2] + lz;
@@ -529,8 +531,8 @@ __global__ __launch_bounds__(256) void k_gather(const LegDev* legs, BlockMap map
   int gxv[4];
 #pragma unroll
   for (int ix = 0; ix < 4; ++ix) { gxv[ix] = bx - ix; if (gxv[ix] < 0) gxv[ix] += g.K[0]; }
-  const float2* plane = g.cgrid + (size_t)(w >> 1) * g.Ktot + (size_t)gz * g.K[1] * g.K[0];
-  const bool im = w & 1;
+  const float2* plane = g.cgrid + (size_t)(g.pack ? w >> 1 : w) * g.Ktot + (size_t)gz * g.K[1] * g.K[0];
+  const bool im = g.pack && (w & 1);
   float p0 = 0.f, px = 0.f, py = 0.f;          // sum w phi, sum dwx phi, sum dwy phi over the plane
 #pragma unroll
   for (int iy = 0; iy < 4; ++iy) {
@@ -557,9 +559,10 @@ __global__ __launch_bounds__(256) void k_gather(const LegDev* legs, BlockMap map
   }
   const int sub = iz;
   if (valid && sub == 0) {
-    const float fx = -q * gxs * (float)g.K[0] * g.invLf[0];
-    const float fy = -q * gys * (float)g.K[1] * g.invLf[1];
-    const float fz = -q * gzs * (float)g.K[2] * g.invLf[2];
+    const BoxW& B = g.box[w];
+    const float fx = -q * gxs * (float)g.K[0] * B.invLf[0];
+    const float fy = -q * gys * (float)g.K[1] * B.invLf[1];
+    const float fz = -q * gzs * (float)g.K[2] * B.invLf[2];
     const int where = (w << 20) | a;
     const long long ix = to_fixed((double)fx, kForceScale, g.err, kSiteGather, where, g.leg_index);
     const long long iy = to_fixed((double)fy, kForceScale, g.err, kSiteGather, where, g.leg_index);
@@ -594,7 +597,7 @@ __global__ __launch_bounds__(256) void k_gather(const LegDev* legs, BlockMap map
 inline int blocks_for(long long items, int per) { return (int)((items + per - 1) / per); }
 
 template <int AXIS, int MODE>
-void fft_pass(hipStream_t s, const LegDev* d, const LegHost* h, int nl) {
+void fft_pass(hipStream_t s, const LegDev* d, const LegHost* h, int nl, int ukn) {
   BlockMap m;
   int nmax = 0;
   const int nb = make_map(m, nl, [&](int i) {
@@ -604,12 +607,13 @@ void fft_pass(hipStream_t s, const LegDev* d, const LegHost* h, int nl) {
     return h[i].npair * outer * ((inner + kLines - 1) / kLines);
   });
   const size_t lds = (2 * (size_t)nmax * kLines + nmax) * sizeof(float2);
-  if (nb) hipLaunchKernelGGL((k_fft<AXIS, MODE>), dim3(nb), dim3(256), lds, s, d, m);
+  if (nb) hipLaunchKernelGGL((k_fft<AXIS, MODE>), dim3(nb), dim3(256), lds, s, d, m, ukn);
 }
 
 }  // namespace
 
-void launch_pme_fft(hipStream_t s, const LegDev* d, const LegHost* h, int nl, bool from_int64) {
+void launch_pme_fft(hipStream_t s, const LegDev* d, const LegHost* h, int nl, int ukn_mode) {
+  const bool from_int64 = ukn_mode != 0;
   int plane = 0, kxy = 0;
   for (int i = 0; i < nl; ++i) {
     plane = std::max(plane, h[i].K[0] * h[i].K[1]);
@@ -620,16 +624,16 @@ void launch_pme_fft(hipStream_t s, const LegDev* d, const LegHost* h, int nl, bo
     const int nb = make_map(m, nl, [&](int i) { return h[i].npair * h[i].K[2]; });
     const size_t lds = (2 * (size_t)plane + kxy) * sizeof(float2);
     if (nb) hipLaunchKernelGGL(k_fft_xy<false>, dim3(nb), dim3(kXYThreads), lds, s, d, m);
-    fft_pass<2, 3>(s, d, h, nl);
+    fft_pass<2, 3>(s, d, h, nl, ukn_mode);
     if (nb) hipLaunchKernelGGL(k_fft_xy<true>, dim3(nb), dim3(kXYThreads), lds, s, d, m);
     return;
   }
-  if (from_int64) fft_pass<0, 2>(s, d, h, nl);
-  else fft_pass<0, 0>(s, d, h, nl);
-  fft_pass<1, 0>(s, d, h, nl);
-  fft_pass<2, 3>(s, d, h, nl);
-  fft_pass<1, 1>(s, d, h, nl);
-  fft_pass<0, 1>(s, d, h, nl);
+  if (from_int64) fft_pass<0, 2>(s, d, h, nl, 0);
+  else fft_pass<0, 0>(s, d, h, nl, 0);
+  fft_pass<1, 0>(s, d, h, nl, 0);
+  fft_pass<2, 3>(s, d, h, nl, ukn_mode);
+  fft_pass<1, 1>(s, d, h, nl, 0);
+  fft_pass<0, 1>(s, d, h, nl, 0);
 }
 
 void launch_pme(hipStream_t s, const LegDev* d, const LegHost* h, int nl, bool energy, bool step_forces) {
@@ -641,7 +645,7 @@ void launch_pme(hipStream_t s, const LegDev* d, const LegHost* h, int nl, bool e
   });
   if (!nb) return;
   hipLaunchKernelGGL(k_spread, dim3(nb), dim3(256), 0, s, d, m);
-  launch_pme_fft(s, d, h, nl, false);
+  launch_pme_fft(s, d, h, nl, 0);
   nb = make_map(m, nl, [&](int i) { return blocks_for((long long)h[i].W * h[i].npad, 64); });
   if (energy) hipLaunchKernelGGL((k_gather<true, false>), dim3(nb), dim3(256), 0, s, d, m);
   else if (step_forces) hipLaunchKernelGGL((k_gather<false, true>), dim3(nb), dim3(256), 0, s, d, m);

@@ -16,9 +16,12 @@
 // so sum_{i in L} q_i phi_E(r_i) = sum_{j in E} q_j phi_L(r_j).  Each frame
 // spreads its few ligand charges, two frames share one complex FFT (real and
 // imaginary part), and phi_L is gathered at every atom: a read-only pass over
-// the environment instead of scattering all of its charges.  Pair sums run in
-// FP64 per lane; block partials combine in a fixed order (pair terms) or in
-// int64 fixed point (reciprocal terms).
+// the environment instead of scattering all of its charges.  Pair distances
+// and the softcore LJ are FP64 (a frame evaluated at a state it was not
+// sampled in can hold r^-12 overlaps of 1e6 kT), the erfc Coulomb FP32; pair
+// sums run in FP64 per lane; block partials combine in a fixed order (pair
+// terms) or in int64 fixed point (reciprocal terms).  Frames may each have
+// their own box (NPT); with a pressure, u gains beta P V of the frame.
 #include "felis_internal.h"
 #include "erfc_coeffs.h"
 #include "restraint.h"
@@ -32,6 +35,7 @@ struct UknArgs {
   const float *fx, *fy, *fz;
   long long stride, f0;
   int nf, KV;
+  int upk;                             // 1: one frame per complex grid (frames in their own boxes)
   float lamv[kMaxLamV];
   float asc[kMaxLamV];
 };
@@ -57,10 +61,10 @@ __device__ __forceinline__ void bspline4(float f, float* w) {
 }
 
 
-__device__ __forceinline__ float3 min_img(const LegDev& g, float dx, float dy, float dz) {
-  dx = fmaf(-g.Lf[0], rintf(dx * g.invLf[0]), dx);
-  dy = fmaf(-g.Lf[1], rintf(dy * g.invLf[1]), dy);
-  dz = fmaf(-g.Lf[2], rintf(dz * g.invLf[2]), dz);
+__device__ __forceinline__ float3 min_img(const BoxW& B, float dx, float dy, float dz) {
+  dx = fmaf(-B.Lf[0], rintf(dx * B.invLf[0]), dx);
+  dy = fmaf(-B.Lf[1], rintf(dy * B.invLf[1]), dy);
+  dz = fmaf(-B.Lf[2], rintf(dz * B.invLf[2]), dz);
   return make_float3(dx, dy, dz);
 }
 
@@ -80,13 +84,17 @@ __global__ __launch_bounds__(256) void k_ukn_spread(const LegDev* legs, UknArgs 
   const int sub = threadIdx.x & 15, iy = sub & 3, iz = sub >> 2;
   const size_t o = (size_t)(A.f0 + f) * A.stride + a;
   float fxr, fyr, fzr, wx[4], wy[4], wz[4];
-  const int bx = grid_base(A.fx[o], g.invL[0], g.K[0], &fxr);
-  const int by = grid_base(A.fy[o], g.invL[1], g.K[1], &fyr);
-  const int bz = grid_base(A.fz[o], g.invL[2], g.K[2], &fzr);
+  const BoxW& B = g.ubox[f];
+  const int bx = grid_base(A.fx[o], B.invL[0], g.K[0], &fxr);
+  const int by = grid_base(A.fy[o], B.invL[1], g.K[1], &fyr);
+  const int bz = grid_base(A.fz[o], B.invL[2], g.K[2], &fzr);
   bspline4(fxr, wx); bspline4(fyr, wy); bspline4(fzr, wz);
   int gy = by - iy; if (gy < 0) gy += g.K[1];
   int gz = bz - iz; if (gz < 0) gz += g.K[2];
-  long long* grid = g.grid64 + (size_t)f * g.Ktot + ((size_t)gz * g.K[1] + gy) * g.K[0];
+  // int64 grids 2p, 2p+1 become the real and imaginary parts of complex grid
+  // p: frame f takes grid f, or grid 2f (imaginary part left zero) when
+  // every frame has a grid of its own
+  long long* grid = g.grid64 + (size_t)(A.upk ? 2 * f : f) * g.Ktot + ((size_t)gz * g.K[1] + gy) * g.K[0];
   const double qyz = (double)(g.q[a] * wy[iy] * wz[iz]);
 #pragma unroll
   for (int ix = 0; ix < 4; ++ix) {
@@ -105,7 +113,9 @@ __global__ __launch_bounds__(256) void k_ukn_gather(const LegDev* legs, UknArgs 
   const int f = blockIdx.x / nb;
   const int a0 = (blockIdx.x - f * nb) * 256 + (threadIdx.x >> 4);
   const int sub = threadIdx.x & 15, iy = sub & 3, iz = sub >> 2;
-  const float* cg = (const float*)(g.cgrid + (size_t)(f >> 1) * g.Ktot) + (f & 1);
+  const float* cg = A.upk ? (const float*)(g.cgrid + (size_t)f * g.Ktot)
+                          : (const float*)(g.cgrid + (size_t)(f >> 1) * g.Ktot) + (f & 1);
+  const BoxW& B = g.ubox[f];
   const size_t fo = (size_t)(A.f0 + f) * A.stride;
   double le = 0.0, ll = 0.0;
   for (int t = 0; t < 16; ++t) {
@@ -113,9 +123,9 @@ __global__ __launch_bounds__(256) void k_ukn_gather(const LegDev* legs, UknArgs 
     const bool valid = a < g.n;                      // uniform over the 16 lanes of an atom
     const int ac = valid ? a : g.n - 1;
     float fxr, fyr, fzr, wx[4], wy[4], wz[4];
-    const int bx = grid_base(A.fx[fo + ac], g.invL[0], g.K[0], &fxr);
-    const int by = grid_base(A.fy[fo + ac], g.invL[1], g.K[1], &fyr);
-    const int bz = grid_base(A.fz[fo + ac], g.invL[2], g.K[2], &fzr);
+    const int bx = grid_base(A.fx[fo + ac], B.invL[0], g.K[0], &fxr);
+    const int by = grid_base(A.fy[fo + ac], B.invL[1], g.K[1], &fyr);
+    const int bz = grid_base(A.fz[fo + ac], B.invL[2], g.K[2], &fzr);
     bspline4(fxr, wx); bspline4(fyr, wy); bspline4(fzr, wz);
     int gy = by - iy; if (gy < 0) gy += g.K[1];
     int gz = bz - iz; if (gz < 0) gz += g.K[2];
@@ -173,21 +183,24 @@ __global__ __launch_bounds__(256) void k_ukn_pairs(const LegDev* legs, UknArgs A
   const int f = blockIdx.x / nb;
   const int j = (blockIdx.x - f * nb) * 256 + threadIdx.x;
   __shared__ float4 s_lx[kMaxLigand];     // x, y, z, q
-  __shared__ float2 s_lp[kMaxLigand];     // sigma/2, 2 sqrt(eps)
+  __shared__ float2 s_lp[kMaxLigand];     // sigma/2, eps
   __shared__ double s_red[4 * (1 + kMaxLamV)];
   const size_t fo = (size_t)(A.f0 + f) * A.stride;
+  const BoxW& B = g.ubox[f];
   for (int t = threadIdx.x; t < g.nlig; t += blockDim.x) {
     const int a = g.lig_idx[t];
     s_lx[t] = make_float4(A.fx[fo + a], A.fy[fo + a], A.fz[fo + a], g.q[a]);
-    s_lp[t] = make_float2(0.5f * g.sig[a], 2.0f * sqrtf(g.eps[a]));
+    s_lp[t] = make_float2(0.5f * g.sig[a], g.eps[a]);
   }
   __syncthreads();
   const bool env = j < g.n && !g.lig[j];
-  float xj = 0.f, yj = 0.f, zj = 0.f, qj = 0.f, hs = 0.f, se = 0.f;
+  float xj = 0.f, yj = 0.f, zj = 0.f, qj = 0.f;
+  double hs = 0.0, epsj = 0.0;
   if (env) {
     xj = A.fx[fo + j]; yj = A.fy[fo + j]; zj = A.fz[fo + j];
-    qj = g.q[j]; hs = 0.5f * g.sig[j]; se = 2.0f * sqrtf(g.eps[j]);
+    qj = g.q[j]; hs = 0.5 * (double)g.sig[j]; epsj = (double)g.eps[j];
   }
+  const double Lx = B.L[0], Ly = B.L[1], Lz = B.L[2], iLx = B.invL[0], iLy = B.invL[1], iLz = B.invL[2];
   const float c_ke = (float)kKE;
   double ec = 0.0;
   for (int v0 = 0; v0 < A.KV; v0 += kGV) {
@@ -196,28 +209,34 @@ __global__ __launch_bounds__(256) void k_ukn_pairs(const LegDev* legs, UknArgs A
     for (int t = 0; t < kGV; ++t) esc[t] = 0.0;
     for (int li = 0; li < g.nlig; ++li) {
       const float4 L = s_lx[li];
-      const float3 d = min_img(g, xj - L.x, yj - L.y, zj - L.z);
-      const float r2 = d.x * d.x + d.y * d.y + d.z * d.z;
-      const bool in = env && r2 < g.rc2;
+      // the distance in FP64 (minimum image included): a frame evaluated at a
+      // state it was not sampled in can hold r^-12 overlaps of 1e6 kT, where
+      // FP32 distances would lose six digits
+      double dx = (double)xj - (double)L.x, dy = (double)yj - (double)L.y, dz = (double)zj - (double)L.z;
+      dx = fma(-Lx, rint(dx * iLx), dx);
+      dy = fma(-Ly, rint(dy * iLy), dy);
+      dz = fma(-Lz, rint(dz * iLz), dz);
+      const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+      const bool in = env && r2 < g.rc2d;
       if (__ballot(in) == 0ull) continue;
-      const float r2s = in ? r2 : 1.0f;
+      const double r2s = in ? r2 : 1.0;
       if (v0 == 0) {
-        const float rinv = __builtin_amdgcn_rsqf(r2s);
+        const float r2f = (float)r2s;
+        const float rinv = __builtin_amdgcn_rsqf(r2f);
         float ex;
-        const float erfcv = erfc_fit(g.alpha * r2s * rinv, &ex);
+        const float erfcv = erfc_fit(g.alpha * r2f * rinv, &ex);
         if (in) ec += (double)(c_ke * L.w * qj * erfcv * rinv);
       }
-      const float sg = s_lp[li].x + hs;
-      const float s2 = sg * sg;
-      const float s6 = s2 * s2 * s2;
-      const float r6 = r2s * r2s * r2s;
-      const float e4 = in ? s_lp[li].y * se : 0.0f;
+      const double sg = (double)s_lp[li].x + hs;
+      const double s2 = sg * sg;
+      const double s6 = s2 * s2 * s2;
+      const double r6 = r2s * r2s * r2s;
+      const double e4 = in ? 4.0 * sqrt((double)s_lp[li].y * epsj) : 0.0;
 #pragma unroll
       for (int t = 0; t < kGV; ++t) {
         if (v0 + t < A.KV) {
-          const float inv = __builtin_amdgcn_rcpf(fmaf(A.asc[v0 + t], s6, r6));
-          const float u = s6 * inv;
-          esc[t] += (double)(A.lamv[v0 + t] * e4 * fmaf(u, u, -u));
+          const double u = s6 / fma((double)A.asc[v0 + t], s6, r6);
+          esc[t] += (double)A.lamv[v0 + t] * e4 * fma(u, u, -u);
         }
       }
     }
@@ -248,7 +267,7 @@ __global__ __launch_bounds__(256) void k_ukn_ligand(const LegDev* legs, UknArgs 
     for (int base = 0; base < np; base += blockDim.x) {
       const int p = base + threadIdx.x;
       bool in = false;
-      float r2s = 1.0f, s6 = 0.f, e4 = 0.f;
+      double r2s = 1.0, s6 = 0.0, e4 = 0.0;
       if (p < np) {
         // decode p -> (i, j), i < j, row-major over the upper triangle
         int i = 0, rem = p;
@@ -257,9 +276,15 @@ __global__ __launch_bounds__(256) void k_ukn_ligand(const LegDev* legs, UknArgs 
         const int a = g.lig_idx[i], b = g.lig_idx[jl];
         bool exc = false;
         for (int k = g.excl_ptr[a]; k < g.excl_ptr[a + 1]; ++k) exc |= (g.excl_idx[k] == b);
-        const float3 d = min_img(g, A.fx[fo + b] - A.fx[fo + a], A.fy[fo + b] - A.fy[fo + a],
-                                 A.fz[fo + b] - A.fz[fo + a]);
-        const float r2 = d.x * d.x + d.y * d.y + d.z * d.z;
+        const BoxW& B = g.ubox[f];
+        double dxd = (double)A.fx[fo + b] - (double)A.fx[fo + a];
+        double dyd = (double)A.fy[fo + b] - (double)A.fy[fo + a];
+        double dzd = (double)A.fz[fo + b] - (double)A.fz[fo + a];
+        dxd = fma(-B.L[0], rint(dxd * B.invL[0]), dxd);
+        dyd = fma(-B.L[1], rint(dyd * B.invL[1]), dyd);
+        dzd = fma(-B.L[2], rint(dzd * B.invL[2]), dzd);
+        const double r2d = fma(dxd, dxd, fma(dyd, dyd, dzd * dzd));
+        const float r2 = (float)r2d;
         const float qq = c_ke * g.q[a] * g.q[b];
         if (exc) {
           if (v0 == 0) {
@@ -267,28 +292,27 @@ __global__ __launch_bounds__(256) void k_ukn_ligand(const LegDev* legs, UknArgs 
             ell -= (r > 1e-4f) ? (double)(qq * erff(g.alpha * r) / r)
                                : (double)(qq * 2.0f * g.alpha * 0.56418958354775628f);
           }
-        } else if (r2 < g.rc2) {
+        } else if (r2d < g.rc2d) {
           in = true;
-          r2s = r2;
+          r2s = r2d;
           if (v0 == 0) {
             const float rinv = __builtin_amdgcn_rsqf(r2);
             float ex;
             ell += (double)(qq * erfc_fit(g.alpha * r2 * rinv, &ex) * rinv);
           }
-          const float sg = 0.5f * (g.sig[a] + g.sig[b]);
-          const float s2 = sg * sg;
+          const double sg = 0.5 * ((double)g.sig[a] + (double)g.sig[b]);
+          const double s2 = sg * sg;
           s6 = s2 * s2 * s2;
-          e4 = 4.0f * sqrtf(g.eps[a] * g.eps[b]);
+          e4 = 4.0 * sqrt((double)g.eps[a] * (double)g.eps[b]);
         }
       }
       if (__ballot(in) == 0ull) continue;
-      const float r6 = r2s * r2s * r2s;
+      const double r6 = r2s * r2s * r2s;
 #pragma unroll
       for (int t = 0; t < kGV; ++t) {
         if (v0 + t < A.KV) {
-          const float inv = __builtin_amdgcn_rcpf(fmaf(A.asc[v0 + t], s6, r6));
-          const float u = s6 * inv;
-          esc[t] += (double)(in ? A.lamv[v0 + t] * e4 * fmaf(u, u, -u) : 0.0f);
+          const double u = s6 / fma((double)A.asc[v0 + t], s6, r6);
+          esc[t] += in ? (double)A.lamv[v0 + t] * e4 * fma(u, u, -u) : 0.0;
         }
       }
     }
@@ -303,7 +327,7 @@ __global__ __launch_bounds__(256) void k_ukn_ligand(const LegDev* legs, UknArgs 
     const size_t o1 = fo + g.ranch[0];
     for (int t = 0; t < 6; ++t) {
       const size_t ot = fo + g.ranch[t];
-      const float3 d = min_img(g, A.fx[ot] - A.fx[o1], A.fy[ot] - A.fy[o1], A.fz[ot] - A.fz[o1]);
+      const float3 d = min_img(g.ubox[f], A.fx[ot] - A.fx[o1], A.fy[ot] - A.fy[o1], A.fz[ot] - A.fz[o1]);
       p[t] = mk(d.x, d.y, d.z);
     }
     acc_add(g, f, 2, boresch_eval(p, g.rg0, g.rk, nullptr));
@@ -328,15 +352,24 @@ __global__ __launch_bounds__(256) void k_ukn_const(const LegDev* legs, double* o
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    out[0] = -g.bg_pref * 2.0 * r[0][0] * r[1][0];                          // E_LE background
-    out[1] = -(double)g.self_pref * r[2][0] - g.bg_pref * r[1][0] * r[1][0];  // E_LL self + background
+    out[0] = 2.0 * r[0][0] * r[1][0];             // E_LE background / (-bg_pref)
+    out[1] = r[1][0] * r[1][0];                   // E_LL background / (-bg_pref)
+    out[2] = -(double)g.self_pref * r[2][0];      // E_LL self term
   }
 }
 
 struct CombineArgs {
   double le[kMaxStates], lr[kMaxStates];
   unsigned char kv[kMaxStates];
+  double pressure;                     // kcal/(mol A^3): u gains beta P V of the frame's box (NPT)
 };
+
+// one block: the box of every frame of the pass (given edges, or the leg's box)
+__global__ __launch_bounds__(256) void k_ukn_boxes(const LegDev* legs, UknArgs A, const double* fbox) {
+  const LegDev& g = legs[0];
+  for (int f = threadIdx.x; f < 2 * g.npair; f += blockDim.x)      // unused entries: the leg's box
+    g.ubox[f] = (fbox && f < A.nf) ? make_box(fbox + 3 * (A.f0 + f), (double)g.alpha) : g.box0;
+}
 
 // one block per frame: the pair partials of every block of k_ukn_pairs summed
 // per slot (one wave per slot, lanes over blocks, fixed tree), then u at every
@@ -361,14 +394,16 @@ __global__ __launch_bounds__(256) void k_ukn_combine(const LegDev* legs, UknArgs
   const long long* acc = g.uacc + (size_t)f * kNU;
   const double s = 1.0 / kEnergyScale;
   const bool has_l = g.nlig > 0;
+  const double bg = g.ubox[f].bg_pref;
+  const double pv = C.pressure * g.ubox[f].vol;
   for (int k = threadIdx.x; k < K; k += blockDim.x) {
     const int kv = C.kv[k];
-    const double ele = (double)acc[0] * s + cst[0] + s_p[0];
-    const double ell = (double)acc[1] * s + cst[1] + (has_l ? lp[0] : 0.0);
+    const double ele = (double)acc[0] * s - bg * cst[0] + s_p[0];
+    const double ell = (double)acc[1] * s + cst[2] - bg * cst[1] + (has_l ? lp[0] : 0.0);
     const double ub = (double)acc[2] * s;
     const double esc = s_p[1 + kv] + (has_l ? lp[1 + kv] : 0.0);
     const double le = C.le[k], lr = C.lr[k];
-    u[(long long)k * u_stride + A.f0 + f] = beta * (le * ele + le * le * ell + esc + lr * ub);
+    u[(long long)k * u_stride + A.f0 + f] = beta * (le * ele + le * le * ell + esc + lr * ub + pv);
   }
 }
 
@@ -376,8 +411,8 @@ __global__ __launch_bounds__(256) void k_ukn_combine(const LegDev* legs, UknArgs
 
 int launch_ukn(hipStream_t s, const LegDev* d, const LegHost& h, double sc_alpha, const double* lambdas,
                int K, const float* fx, const float* fy, const float* fz, long long frame_stride,
-               long long n_frames, double beta, double* u, long long u_stride, long long* uacc,
-               double* cst) {
+               long long n_frames, const double* frame_box, double pressure, double beta, double* u,
+               long long u_stride, long long* uacc, double* cst) {
   if (K < 1 || K > kMaxStates) return FELIS_E_UNSUPPORTED;
   if (h.nlig > kMaxLigand) return FELIS_E_UNSUPPORTED;
   UknArgs A;
@@ -401,18 +436,22 @@ int launch_ukn(hipStream_t s, const LegDev* d, const LegHost& h, double sc_alpha
     C.le[k] = lambdas[3 * k];
     C.lr[k] = lambdas[3 * k + 2];
   }
+  C.pressure = pressure;
   hipLaunchKernelGGL(k_ukn_const, dim3(1), dim3(256), 0, s, d, cst);
-  // two frames per complex grid: 2 npair frames per pass
-  const int F = 2 * h.npair;
+  // two frames per complex grid (2 npair frames per pass) when they share the
+  // leg's box; frames with boxes of their own take a grid each
+  A.upk = frame_box ? 1 : 0;
+  const int F = frame_box ? h.npair : 2 * h.npair;
   for (long long f0 = 0; f0 < n_frames; f0 += F) {
     const int nf = (int)std::min<long long>(F, n_frames - f0);
     const int nb = (h.n + 255) / 256;
     A.f0 = f0;
     A.nf = nf;
     launch_fill_i64(s, uacc, (size_t)nf * kNU);
+    hipLaunchKernelGGL(k_ukn_boxes, dim3(1), dim3(256), 0, s, d, A, frame_box);
     if (h.nlig) {
       hipLaunchKernelGGL(k_ukn_spread, dim3((unsigned)(((long long)nf * h.nlig + 15) / 16)), dim3(256), 0, s, d, A);
-      launch_pme_fft(s, d, &h, 1, true);
+      launch_pme_fft(s, d, &h, 1, frame_box ? 2 : 1);
       hipLaunchKernelGGL(k_ukn_gather, dim3((unsigned)(nf * nb)), dim3(256), 0, s, d, A);
       hipLaunchKernelGGL(k_ukn_pairs, dim3((unsigned)(nf * nb)), dim3(256), 0, s, d, A);
       hipLaunchKernelGGL(k_ukn_ligand, dim3(nf), dim3(256), 0, s, d, A);

@@ -22,7 +22,8 @@ FORCE_SCALE = 4294967296.0
 NE = 8
 COMPONENTS = ('coul_real', 'lj', 'excl', 'self', 'recip', 'bond', 'restraint', 'total')
 ENERGY = 1
-PROF_PAIRS, PROF_PME, PROF_NLIST, PROF_INTEGRATE, PROF_UKN = 0, 1, 2, 3, 4
+PROF_PAIRS, PROF_PME, PROF_NLIST, PROF_INTEGRATE, PROF_UKN, PROF_BARO = 0, 1, 2, 3, 4, 5
+BARO_NS = 10                 # values per window from barostat_stats
 
 vp = C.c_void_p
 
@@ -42,6 +43,7 @@ class FelisLeg(C.Structure):
         ('x', vp), ('y', vp), ('z', vp), ('vx', vp), ('vy', vp), ('vz', vp),
         ('fx', vp), ('fy', vp), ('fz', vp), ('energy', vp),
         ('seed', C.c_uint64), ('step', C.c_int64), ('list_cap', C.c_int32),
+        ('pressure_bar', C.c_double), ('barostat_every', C.c_int32),
         ('work', vp), ('work_bytes', C.c_size_t),
     ]
 
@@ -77,13 +79,16 @@ def lib():
         'felis_leg_states': (C.c_int, [vp, P(FelisLeg), vp]),
         'felis_restraint_dg': (C.c_int, [vp, vp, C.c_double, P(C.c_double)]),
         'felis_hrex': (C.c_int, [vp, P(FelisLeg), vp, C.c_int64, C.c_int64, C.c_uint64, vp]),
+        'felis_barostat': (C.c_int, [vp, P(FelisLeg), C.c_int, C.c_double, C.c_int64]),
+        'felis_leg_boxes': (C.c_int, [vp, P(FelisLeg), vp]),
+        'felis_barostat_stats': (C.c_int, [vp, P(FelisLeg), vp]),
         'felis_nlist_export_pairs': (C.c_int, [vp, P(FelisLeg), C.c_int, C.c_double, vp, C.c_int64, P(C.c_int64)]),
         'felis_nonbonded': (C.c_int, [vp, P(FelisLeg), C.c_int, C.c_int]),
         'felis_pme': (C.c_int, [vp, P(FelisLeg), C.c_int, C.c_int]),
         'felis_bonded': (C.c_int, [vp, P(FelisLeg), C.c_int, C.c_int]),
         'felis_step': (C.c_int, [vp, P(FelisLeg), C.c_int, C.c_int, C.c_double, C.c_double, C.c_double]),
-        'felis_ukn': (C.c_int, [vp, P(FelisLeg), vp, C.c_int, vp, vp, vp, C.c_int64, C.c_int64, C.c_double,
-                                vp, C.c_int64]),
+        'felis_ukn': (C.c_int, [vp, P(FelisLeg), vp, C.c_int, vp, vp, vp, C.c_int64, C.c_int64, vp,
+                                C.c_double, vp, C.c_int64]),
         'felis_profile': (C.c_int, [vp, C.c_int]),
         'felis_profile_read': (C.c_int, [vp, C.c_int, P(C.c_double), P(C.c_int64)]),
         'felis_mbar_work_size': (C.c_int, [C.c_int, C.c_int64, P(C.c_size_t)]),
@@ -142,7 +147,8 @@ class Leg:
     """Device-resident leg: topology, per-window state and library scratch for
     a synthetic system (``paper_2603_22274_amd.gen.System``)."""
 
-    def __init__(self, ctx: Context, sysd, windows=None, seed=1234, device='cuda', list_cap=0, positions=None):
+    def __init__(self, ctx: Context, sysd, windows=None, seed=1234, device='cuda', list_cap=0, positions=None,
+                 pressure_bar=0.0, barostat_every=25):
         self.sys = sysd
         self.ctx = ctx
         lam = sysd.lambdas if windows is None else sysd.lambdas[windows]
@@ -209,6 +215,7 @@ class Leg:
         s.seed = seed
         s.step = 0
         s.list_cap = list_cap
+        s.pressure_bar, s.barostat_every = float(pressure_bar), int(barostat_every)
         nbytes = C.c_size_t(0)
         ctx.check(lib().felis_leg_work_size(C.byref(s), C.byref(nbytes)))
         self.work = torch.empty(int(nbytes.value), dtype=torch.uint8, device=dev)
@@ -317,6 +324,31 @@ def restraint_dg(g0, k, temperature=300.0):
     return out.value
 
 
+def barostat(ctx, legs, temperature, attempt):
+    """One Monte Carlo volume move now for every leg of ``legs`` that has a
+    pressure (the others are evaluated but unchanged)."""
+    legs = legs if isinstance(legs, (list, tuple)) else [legs]
+    arr = _batch(legs)
+    ctx.check(lib().felis_barostat(ctx.h, arr, len(legs), float(temperature), int(attempt)))
+    _sync_back(legs, arr)
+
+
+def leg_boxes(ctx, leg):
+    """(W, 3) numpy float64: each window's current box edges (synchronises)."""
+    out = np.zeros((leg.n_windows, 3), np.float64)
+    ctx.check(lib().felis_leg_boxes(ctx.h, C.byref(leg.s), out.ctypes.data_as(C.c_void_p)))
+    return out
+
+
+def barostat_stats(ctx, leg):
+    """(W, 10) numpy float64 per window after the last volume move: U before,
+    U after the trial move, w, V, V', s, accepted, dV_max, attempts,
+    acceptances (synchronises)."""
+    out = np.zeros((leg.n_windows, BARO_NS), np.float64)
+    ctx.check(lib().felis_barostat_stats(ctx.h, C.byref(leg.s), out.ctypes.data_as(C.c_void_p)))
+    return out
+
+
 def hrex(ctx, leg, u, attempt, seed, count=True):
     """One replica-exchange attempt among the leg's windows from u[state][replica]
     (device float64, at least n_windows columns).  Returns the number of swaps
@@ -368,16 +400,22 @@ def step(ctx, legs, n_steps, dt=0.002, temperature=300.0, gamma=0.5):
     _sync_back(legs, arr)
 
 
-def ukn(ctx, leg, lambdas, x, y, z, beta, out=None):
+def ukn(ctx, leg, lambdas, x, y, z, beta, out=None, boxes=None):
     """Reduced potentials [K, n_frames] (device float64) of frames given as
-    (n_frames, N) float32 device tensors."""
+    (n_frames, N) float32 device tensors; ``boxes``: (n_frames, 3) float64
+    device tensor of each frame's box edges (None: the leg's box)."""
     lam = np.ascontiguousarray(lambdas, np.float64)
     K = len(lam)
     nf = x.shape[0]
     stride = x.stride(0)
     u = out if out is not None else torch.empty((K, nf), dtype=torch.float64, device=x.device)
+    fb = None
+    if boxes is not None:
+        fb = torch.as_tensor(boxes, dtype=torch.float64, device=x.device).contiguous()
+        if fb.shape != (nf, 3):
+            raise ValueError('boxes must be (n_frames, 3)')
     ctx.check(lib().felis_ukn(ctx.h, C.byref(leg.s), lam.ctypes.data_as(C.c_void_p), K, _ptr(x), _ptr(y), _ptr(z),
-                              stride, nf, beta, _ptr(u), u.stride(0)))
+                              stride, nf, _ptr(fb) if fb is not None else None, beta, _ptr(u), u.stride(0)))
     return u
 
 
