@@ -108,6 +108,7 @@ def main():
     ap.add_argument('--hrex-every', type=int, default=2500,
                     help='MD steps between replica-exchange attempts among the windows (0: none); 5 ps as in the paper')
     ap.add_argument('--serve-legs', type=int, default=8, help='legs in the served mixed workload (0: skip)')
+    ap.add_argument('--no-npt', action='store_true', help='skip the NPT (Monte Carlo barostat) line')
     ap.add_argument('--copy-calibration', action='store_true',
                     help='run a plain 256 MiB device copy first (reference for traffic counters)')
     args = ap.parse_args()
@@ -222,6 +223,36 @@ def main():
                       "form": "one window per leg and launch chain (same kernels), MD only",
                       "md_steps_per_window": nrep}
 
+    npt = None
+    if not args.no_npt:
+        # the same leg in the paper's ensemble: NPT at 1.01325 bar, a volume
+        # move of every window every 25 steps (two energy evaluations each)
+        every = 25
+        nl = felis.Leg(ctx, sysd, seed=22274, positions=leg.positions().cpu().numpy(), pressure_bar=1.01325,
+                       barostat_every=every)
+        felis.build_nlist(ctx, [nl], force=True)
+        felis.step(ctx, [nl], 4 * every, DT, 300.0, 0.5)
+        torch.cuda.synchronize()
+        n_npt = 8 * every
+        felis.profile(ctx, True)
+        for which in range(felis.PROF_BARO + 1):
+            felis.profile_read(ctx, which)
+        tc = time.perf_counter()
+        felis.step(ctx, [nl], n_npt, DT, 300.0, 0.5)
+        torch.cuda.synchronize()
+        td = time.perf_counter()
+        baro_ms, baro_n = felis.profile_read(ctx, felis.PROF_BARO)
+        felis.profile(ctx, False)
+        st = felis.barostat_stats(ctx, nl)
+        vols = np.prod(felis.leg_boxes(ctx, nl), axis=1)
+        ctx.device_check()
+        npt = {"value": n_npt * DT * W / 1000.0 / ((td - tc) / 86400.0), "unit": "ns·windows/day",
+               "pressure_bar": 1.01325, "move_every_md_steps": every, "md_steps": n_npt,
+               "move_ms": baro_ms / max(baro_n, 1), "moves": int(baro_n),
+               "acceptance": float(st[:, 9].sum() / max(st[:, 8].sum(), 1)),
+               "volume_over_start": [float(v / np.prod(sysd.box)) for v in (vols.min(), vols.mean(), vols.max())],
+               "note": "every window its own box and complex PME grid; MD + volume moves, no u_kn"}
+
     served = None
     if args.serve_legs > 0:
         served = serve_mix(ctx, args.serve_legs, not args.no_per_window)
@@ -246,6 +277,7 @@ def main():
                      "avg_launch_ms": avg_pairs_s * 1000.0, "launches": pairs_n},
         "cpu_baseline": cpu,
         "per_window_form": per_window,
+        "npt": npt,
         "stage_ms_per_md_step": {k: v[0] / max(v[1], 1) for k, v in prof.items() if k != 'ukn'},
         "ukn_ms_per_call": prof['ukn'][0] / max(prof['ukn'][1], 1),
         "replica_exchange": {"every_md_steps": args.hrex_every, "attempts_in_timed_region": timed_attempts,

@@ -243,6 +243,10 @@ int felis_barostat(felis_ctx* ctx, felis_leg* legs, int n_legs, double temperatu
 
 /* Each window's current box edges, edges (host) [n_windows][3].  Synchronises. */
 int felis_leg_boxes(felis_ctx* ctx, const felis_leg* leg, double* edges);
+/* The same into device memory edges (dev) [n_windows][3], enqueued on the
+ * context's stream (e.g. the frame boxes of a felis_ukn sample of the leg's
+ * current coordinates). */
+int felis_leg_boxes_async(felis_ctx* ctx, const felis_leg* leg, double* edges);
 
 /* Barostat state of each window after the last move, out (host)
  * [n_windows][FELIS_BARO_NS]: U before, U after the trial move (kcal/mol),

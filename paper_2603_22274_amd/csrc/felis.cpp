@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstddef>
 #include <cstring>
 #include <string>
 #include <unordered_map>
@@ -785,6 +786,20 @@ int felis_leg_boxes(felis_ctx* c, const felis_leg* L, double* edges) {
     return fail(c, FELIS_E_DEVICE, "box copy failed");
   for (int w = 0; w < L->n_windows; ++w)
     for (int d = 0; d < 3; ++d) edges[3 * w + d] = b[w].L[d];
+  return FELIS_OK;
+}
+
+int felis_leg_boxes_async(felis_ctx* c, const felis_leg* L, double* edges) {
+  std::vector<LegHost> hs;
+  int rc = prepare(c, L, 1, hs);
+  if (rc) return rc;
+  if (!edges) return fail(c, FELIS_E_INVAL, "null output");
+  Plan p;
+  make_plan(c, L, p);
+  const char* src = (const char*)L->work + p.lay.box + offsetof(BoxW, L);
+  if (hipMemcpy2DAsync(edges, 3 * sizeof(double), src, sizeof(BoxW), 3 * sizeof(double), L->n_windows,
+                       hipMemcpyDeviceToDevice, c->stream) != hipSuccess)
+    return fail(c, FELIS_E_DEVICE, "box copy failed");
   return FELIS_OK;
 }
 

@@ -81,6 +81,7 @@ def lib():
         'felis_hrex': (C.c_int, [vp, P(FelisLeg), vp, C.c_int64, C.c_int64, C.c_uint64, vp]),
         'felis_barostat': (C.c_int, [vp, P(FelisLeg), C.c_int, C.c_double, C.c_int64]),
         'felis_leg_boxes': (C.c_int, [vp, P(FelisLeg), vp]),
+        'felis_leg_boxes_async': (C.c_int, [vp, P(FelisLeg), vp]),
         'felis_barostat_stats': (C.c_int, [vp, P(FelisLeg), vp]),
         'felis_nlist_export_pairs': (C.c_int, [vp, P(FelisLeg), C.c_int, C.c_double, vp, C.c_int64, P(C.c_int64)]),
         'felis_nonbonded': (C.c_int, [vp, P(FelisLeg), C.c_int, C.c_int]),
@@ -250,7 +251,7 @@ class Leg:
         return sum(t.numel() * t.element_size() for t in tens)
 
 
-def leg_footprint(sysd, n_windows=None, list_cap=0):
+def leg_footprint(sysd, n_windows=None, list_cap=0, pressure_bar=0.0):
     """Device bytes a ``Leg`` of ``sysd`` holds (library scratch + state and
     topology tensors), computed without allocating anything."""
     W, N = (sysd.n_windows if n_windows is None else n_windows), sysd.n_atoms
@@ -262,6 +263,7 @@ def leg_footprint(sysd, n_windows=None, list_cap=0):
     s.grid = (C.c_int32 * 3)(*sysd.grid)
     s.spline_order = sysd.spline_order
     s.list_cap = list_cap
+    s.pressure_bar, s.barostat_every = float(pressure_bar), 25
     s.n_excl, s.n_bonds, s.n_waters = len(sysd.excl), len(sysd.bonds), len(sysd.waters)
     # felis_leg_work_size validates but never dereferences the arrays
     fake = C.c_void_p(256)
@@ -337,6 +339,14 @@ def leg_boxes(ctx, leg):
     """(W, 3) numpy float64: each window's current box edges (synchronises)."""
     out = np.zeros((leg.n_windows, 3), np.float64)
     ctx.check(lib().felis_leg_boxes(ctx.h, C.byref(leg.s), out.ctypes.data_as(C.c_void_p)))
+    return out
+
+
+def leg_boxes_device(ctx, leg, out=None):
+    """(W, 3) device float64 tensor of each window's box edges, enqueued on
+    the context's stream (no host synchronisation)."""
+    out = out if out is not None else torch.empty((leg.n_windows, 3), dtype=torch.float64, device=leg.x.device)
+    ctx.check(lib().felis_leg_boxes_async(ctx.h, C.byref(leg.s), _ptr(out)))
     return out
 
 

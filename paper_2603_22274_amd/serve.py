@@ -44,6 +44,8 @@ class Request:
     list_cap: int = 0         # neighbour-list capacity per cluster (0: library default)
     exchange_every: int = 0   # MD steps between replica-exchange attempts among the leg's windows
                               # (a multiple of sample_every; 0: none; the paper uses 5 ps)
+    pressure_bar: float = 0.0  # > 0: NPT, a Monte Carlo volume move of every window every
+    barostat_every: int = 25   # barostat_every MD steps (the paper: 1.01325 bar, 25 steps)
 
 
 @dataclasses.dataclass
@@ -217,13 +219,18 @@ class FelisEngine:
         its u_kn sample matrix."""
         W = r.sysd.n_windows
         samples = r.n_steps // r.sample_every
-        return self.felis.leg_footprint(r.sysd, list_cap=r.list_cap or self.list_cap) + W * W * samples * 8
+        return (self.felis.leg_footprint(r.sysd, list_cap=r.list_cap or self.list_cap, pressure_bar=r.pressure_bar)
+                + W * W * samples * 8)
 
     def admit(self, r):
         import torch
-        leg = self.felis.Leg(self.ctx, r.sysd, seed=r.seed, list_cap=r.list_cap or self.list_cap)
+        leg = self.felis.Leg(self.ctx, r.sysd, seed=r.seed, list_cap=r.list_cap or self.list_cap,
+                             pressure_bar=r.pressure_bar, barostat_every=r.barostat_every)
         h = types.SimpleNamespace(leg=leg, req=r, k=0, attempts=0)   # first step builds every window's list
         W = leg.n_windows
+        # NPT: each sample's frames in their windows' current boxes
+        h.boxes = (torch.empty((W, 3), dtype=torch.float64, device=leg.x.device) if r.pressure_bar > 0
+                   else None)
         h.u = torch.empty((W, W * (r.n_steps // r.sample_every)), dtype=torch.float64, device=leg.x.device)
         return h
 
@@ -246,7 +253,8 @@ class FelisEngine:
         f = self.felis
         W = h.leg.n_windows
         col = h.u[:, h.k * W:(h.k + 1) * W]
-        f.ukn(self.ctx, h.leg, h.leg.lambdas, h.leg.x, h.leg.y, h.leg.z, self.beta, out=col)
+        boxes = f.leg_boxes_device(self.ctx, h.leg, h.boxes) if h.boxes is not None else None
+        f.ukn(self.ctx, h.leg, h.leg.lambdas, h.leg.x, h.leg.y, h.leg.z, self.beta, out=col, boxes=boxes)
         r = h.req
         if r.exchange_every and ((h.k + 1) * r.sample_every) % r.exchange_every == 0:
             # replica exchange from this sample's u[state][replica] (no host sync)
@@ -273,6 +281,7 @@ class FelisEngine:
     def release(self, h):
         h.leg = None
         h.u = None
+        h.boxes = None
 
 
 def relax_start(ctx, sysd, steps=400, seed=7, dt=0.002, temperature=300.0):

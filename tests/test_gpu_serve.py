@@ -113,9 +113,10 @@ def _serve(ctx, reqs, **kw):
     return srv.serve(reqs)
 
 
-def _req(rid, sysd, t, seed, cap=0, exchange_every=0):
+def _req(rid, sysd, t, seed, cap=0, exchange_every=0, pressure_bar=0.0):
     from paper_2603_22274_amd.serve import Request
-    return Request(rid, t, sysd, n_steps=40, sample_every=10, seed=seed, list_cap=cap, exchange_every=exchange_every)
+    return Request(rid, t, sysd, n_steps=40, sample_every=10, seed=seed, list_cap=cap, exchange_every=exchange_every,
+                   pressure_bar=pressure_bar, barostat_every=10)
 
 
 def test_served_dg_alone_equals_mixed(F, legs):
@@ -143,6 +144,20 @@ def test_served_replica_exchange_alone_equals_mixed(F, legs):
     a = alone[0]
     m = next(r for r in mixed if r.rid == 0)
     assert a.status == 'ok' and m.status == 'ok' and a.dG is not None
+    assert a.dG == m.dG and a.mbar_iters == m.mbar_iters
+
+
+def test_served_npt_leg_alone_equals_mixed(F, legs):
+    """A leg with a barostat (a volume move of every window every 10 steps, u_kn
+    of each sample in its windows' boxes) gives the same dG alone and served
+    beside fixed-box legs."""
+    felis, ctx = F
+    A, B, C = legs
+    alone, _ = _serve(ctx, [_req(0, A, 0.0, 21, pressure_bar=1.01325)])
+    mixed, _ = _serve(ctx, [_req(1, B, 0.0, 22), _req(0, A, 0.0, 21, pressure_bar=1.01325), _req(2, C, 0.02, 23)])
+    a = alone[0]
+    m = next(r for r in mixed if r.rid == 0)
+    assert a.status == 'ok' and m.status == 'ok' and a.dG is not None and np.isfinite(a.dG)
     assert a.dG == m.dG and a.mbar_iters == m.mbar_iters
 
 
