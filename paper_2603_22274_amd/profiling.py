@@ -92,7 +92,7 @@ def counters(pmc_dir, kernels):
 _CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), 'csrc')
 PAIR_SOURCES = ('nonbonded.hip', 'erfc_coeffs.h', 'felis_internal.h')
 _BENCH = ("python -u <repo>/bench.py --steps 2 --warmup 0 --md 10 --equil 20 --no-cpu-baseline "
-          "--no-per-window --serve-legs 0 --copy-calibration")
+          "--no-per-window --serve-legs 0 --no-npt --copy-calibration")
 _PASSES = {
     'A': 'SQ_WAVES SQ_WAVE_CYCLES SQ_BUSY_CYCLES SQ_WAIT_ANY SQ_WAIT_INST_ANY SQ_ACTIVE_INST_VALU '
          'SQ_ACTIVE_INST_LDS SQ_ACTIVE_INST_VMEM',
