@@ -51,12 +51,13 @@ __global__ __launch_bounds__(64) void k_baro_propose(const LegDev* legs, BlockMa
     const double L[3] = {b.scale * old.L[0], b.scale * old.L[1], b.scale * old.L[2]};
     g.box[w] = make_box(L, (double)g.alpha);
   }
-  g.rbforce[w] = 1;                              // lists and cells follow the new box
+  b.used_old = g.skin_used[w];
 }
 
 // items: leg x window x molecule, one wave each: the molecule's centre in FP64
 // (lanes over its atoms, fixed reduction tree), then every atom saved and
-// moved by (s - 1) c
+// moved by (s - 1) c, its list reference position with it (the displacement
+// since the last build is unchanged), and the molecule's radius recorded
 __global__ __launch_bounds__(256) void k_baro_scale(const LegDev* legs, BlockMap map) {
   const int leg = find_leg(map, blockIdx.x);
   const LegDev& g = legs[leg];
@@ -75,15 +76,46 @@ __global__ __launch_bounds__(256) void k_baro_scale(const LegDev* legs, BlockMap
     cx += (double)g.x[o + a]; cy += (double)g.y[o + a]; cz += (double)g.z[o + a];
   }
   cx = wave_sum(cx); cy = wave_sum(cy); cz = wave_sum(cz);
-  const double f = (b.scale - 1.0) / (double)(a1 - a0);
+  const double inv_n = 1.0 / (double)(a1 - a0);
+  const double f = (b.scale - 1.0) * inv_n;
   const double dx = f * cx, dy = f * cy, dz = f * cz;
+  const double mx = cx * inv_n, my = cy * inv_n, mz = cz * inv_n;
+  float rm = 0.f;
   for (int k = a0 + lane; k < a1; k += 64) {
     const int a = g.mol_atoms[k];
     const float x = g.x[o + a], y = g.y[o + a], z = g.z[o + a];
+    const double ex = (double)x - mx, ey = (double)y - my, ez = (double)z - mz;
+    rm = fmaxf(rm, (float)sqrt(ex * ex + ey * ey + ez * ez));
     g.xb[o + a] = x; g.yb[o + a] = y; g.zb[o + a] = z;
     g.x[o + a] = (float)((double)x + dx);
     g.y[o + a] = (float)((double)y + dy);
     g.z[o + a] = (float)((double)z + dz);
+    g.xr[o + a] = (float)((double)g.xr[o + a] + dx);
+    g.yr[o + a] = (float)((double)g.yr[o + a] + dy);
+    g.zr[o + a] = (float)((double)g.zr[o + a] + dz);
+  }
+  for (int off = 32; off > 0; off >>= 1) rm = fmaxf(rm, __shfl_xor(rm, off, 64));
+  if (lane == 0) g.molr[item] = rm;
+}
+
+// one block per (leg, window): skin used by the trial move, |s - 1| (r_list +
+// 2 r_mol + skin), r_mol the largest molecule radius (the bound that keeps
+// the lists and cells of the last build valid)
+__global__ __launch_bounds__(256) void k_baro_budget(const LegDev* legs, BlockMap map) {
+  const int leg = find_leg(map, blockIdx.x);
+  const LegDev& g = legs[leg];
+  const int w = blockIdx.x - map.start[leg];
+  const BaroW& b = g.baro[w];
+  if (!b.due) return;                            // uniform over the block
+  float rm = 0.f;
+  for (int m = threadIdx.x; m < g.nmol; m += blockDim.x) rm = fmaxf(rm, g.molr[(size_t)w * g.nmol + m]);
+  for (int off = 32; off > 0; off >>= 1) rm = fmaxf(rm, __shfl_xor(rm, off, 64));
+  __shared__ float s_m[4];
+  if ((threadIdx.x & 63) == 0) s_m[threadIdx.x >> 6] = rm;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double rmol = (double)fmaxf(fmaxf(s_m[0], s_m[1]), fmaxf(s_m[2], s_m[3])) * 1.0001 + 1e-4;
+    g.skin_used[w] += (float)(fabs(b.scale - 1.0) * (g.rlist + 2.0 * rmol + (double)g.skin) * 1.001);
   }
 }
 
@@ -122,9 +154,14 @@ __global__ __launch_bounds__(64) void k_baro_accept(const LegDev* legs, BlockMap
   b.total_acc += ok ? 1 : 0;
   b.n_att += 1;
   b.n_acc += ok ? 1 : 0;
+  // lists rebuilt for the trial state (the check of the second energy
+  // evaluation found the skin used up) are rebuilt again after a rejection;
+  // otherwise the restored state is the one before the move, skin included
+  b.rebuilt = g.flag[w];
   if (!ok) {
     g.box[w] = g.boxb[w];
-    g.rbforce[w] = 1;
+    if (b.rebuilt) g.rbforce[w] = 1;
+    else g.skin_used[w] = b.used_old;
   }
   if (b.n_att >= 10) {
     const double vol = g.box[w].vol;
@@ -144,6 +181,9 @@ __global__ __launch_bounds__(256) void k_baro_restore(const LegDev* legs, BlockM
   const int w = (int)(i / g.n);
   const BaroW& b = g.baro[w];
   if (!b.due || b.accepted) return;
+  if (!b.rebuilt) {                              // the reference moved with the atom: move it back
+    g.xr[i] -= g.x[i] - g.xb[i]; g.yr[i] -= g.y[i] - g.yb[i]; g.zr[i] -= g.z[i] - g.zb[i];
+  }
   g.x[i] = g.xb[i]; g.y[i] = g.yb[i]; g.z[i] = g.zb[i];
 }
 
@@ -157,6 +197,8 @@ void launch_baro_propose(hipStream_t s, const LegDev* d, const LegHost* h, int n
   if (nb) hipLaunchKernelGGL(k_baro_propose, dim3(nb), dim3(64), 0, s, d, m, A);
   const int nb2 = make_map(m, nl, [&](int i) { return h[i].nmol ? blocks_for((long long)h[i].W * h[i].nmol, 4) : 0; });
   if (nb2) hipLaunchKernelGGL(k_baro_scale, dim3(nb2), dim3(256), 0, s, d, m);
+  const int nb3 = make_map(m, nl, [&](int i) { return h[i].nmol ? h[i].W : 0; });
+  if (nb3) hipLaunchKernelGGL(k_baro_budget, dim3(nb3), dim3(256), 0, s, d, m);
 }
 
 void launch_baro_keep_u0(hipStream_t s, const LegDev* d, const LegHost* h, int nl) {

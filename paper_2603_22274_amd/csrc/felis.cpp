@@ -19,7 +19,7 @@ using namespace felis;
 namespace {
 
 struct Layout {
-  size_t lam, lamS, rstate, free_atoms, lig_idx, xr, yr, zr, flag, nbuild, maxdisp, wmax, hcell, box, ubox, rbforce, mol_ptr, mol_atoms, baro, boxb, xb, yb, zb, perm, cellcode, cellstart, cursor, xyzq, prm, bblo,
+  size_t lam, lamS, rstate, free_atoms, lig_idx, xr, yr, zr, flag, nbuild, maxdisp, wmax, hcell, box, ubox, rbforce, skin_used, mol_ptr, mol_atoms, baro, boxb, xb, yb, zb, molr, perm, cellcode, cellstart, cursor, xyzq, prm, bblo,
       bbhi, gsten, lcount, lent, frx, fry, frz, grid64, cgrid, tw[3], bmod[3], eacc, uacc, upart, lpart, ucst, total;
 };
 
@@ -167,6 +167,7 @@ int make_plan(felis_ctx* c, const felis_leg* L, Plan& P) {
   y.box = put(W * sizeof(BoxW));                  // set at set-up, changed only by the barostat
   y.ubox = put(2 * (size_t)h.npair * sizeof(BoxW));
   y.rbforce = put(W * 4);
+  y.skin_used = put(W * 4);
   {
     // barostat: molecule table, per-window state, positions before a move
     const bool npt = L->pressure_bar > 0;
@@ -175,6 +176,7 @@ int make_plan(felis_ctx* c, const felis_leg* L, Plan& P) {
     y.baro = put(npt ? W * sizeof(BaroW) : 0);
     y.boxb = put(npt ? W * sizeof(BoxW) : 0);
     y.xb = put(npt ? W * n * 4 : 0); y.yb = put(npt ? W * n * 4 : 0); y.zb = put(npt ? W * n * 4 : 0);
+    y.molr = put(npt ? W * n * 4 : 0);
   }
   y.xr = put(W * n * 4); y.yr = put(W * n * 4); y.zr = put(W * n * 4);
   y.flag = put(W * 4);
@@ -231,6 +233,7 @@ LegDev make_dev(const felis_ctx* c, const felis_leg* L, const Plan& p, const Met
   g.alpha = (float)L->ewald_alpha;
   g.sc_alpha = (float)L->sc_alpha;
   g.skin_half2 = (float)(0.25 * L->skin * L->skin);
+  g.skin = (float)L->skin;
   g.rlist = L->r_cut + L->skin;
   g.rlist2 = g.rlist * g.rlist;
   g.d_oh = (float)L->d_oh;
@@ -260,6 +263,7 @@ LegDev make_dev(const felis_ctx* c, const felis_leg* L, const Plan& p, const Met
   g.box = (BoxW*)(w + y.box);
   g.ubox = (BoxW*)(w + y.ubox);
   g.rbforce = (int*)(w + y.rbforce);
+  g.skin_used = (float*)(w + y.skin_used);
   g.nmol = m.nmol;
   if (m.nmol) {
     g.mol_ptr = (const int*)(w + y.mol_ptr);
@@ -267,6 +271,7 @@ LegDev make_dev(const felis_ctx* c, const felis_leg* L, const Plan& p, const Met
     g.baro = (BaroW*)(w + y.baro);
     g.boxb = (BoxW*)(w + y.boxb);
     g.xb = (float*)(w + y.xb); g.yb = (float*)(w + y.yb); g.zb = (float*)(w + y.zb);
+    g.molr = (float*)(w + y.molr);
   }
   g.perm = (int*)(w + y.perm);
   g.cellcode = (int*)(w + y.cellcode);
@@ -539,6 +544,7 @@ int felis_leg_init(felis_ctx* c, felis_leg* L) {
   ok &= hipMemsetAsync(w + y.maxdisp, 0, h.W * 4, c->stream) == hipSuccess;
   ok &= hipMemsetAsync(w + y.wmax, 0, y.perm - y.wmax, c->stream) == hipSuccess;
   ok &= hipMemsetAsync(w + y.rbforce, 0, h.W * 4, c->stream) == hipSuccess;
+  ok &= hipMemsetAsync(w + y.skin_used, 0, h.W * 4, c->stream) == hipSuccess;
   ok &= hipMemsetAsync(w + y.lcount, 0, (size_t)h.W * h.nclus * 2 * 4, c->stream) == hipSuccess;
   ok &= hipMemsetAsync(w + y.grid64, 0, y.cgrid - y.grid64, c->stream) == hipSuccess;
   ok &= hipMemsetAsync(w + y.eacc, 0, y.ucst - y.eacc, c->stream) == hipSuccess;

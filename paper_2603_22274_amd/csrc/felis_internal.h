@@ -68,6 +68,9 @@ struct BaroW {
   double u0, u1;                        // window energy before / after the trial move
   double vol_old, vol_new, scale, work;
   int due, accepted, n_att, n_acc;      // this attempt; attempts and acceptances in the block of 10
+  float used_old;                       // skin_used before the trial move
+  int pad2_;
+  int rebuilt, pad_;                    // lists rebuilt for the trial move
   long long total_att, total_acc;
 };
 
@@ -84,7 +87,7 @@ struct LegDev {
   BoxW box0;                            // the leg's box at set-up (u_kn frames given without boxes)
   int pack;                             // 1: windows 2p, 2p+1 share complex grid p (equal boxes);
                                         // 0: one window per grid (each window its own box)
-  float rc2, alpha, sc_alpha, skin_half2;
+  float rc2, alpha, sc_alpha, skin_half2, skin;
   double rc2d;                          // r_cut^2 in FP64 (u_kn distance test)
   double rlist, rlist2;
   float d_oh, d_hh;
@@ -104,6 +107,7 @@ struct LegDev {
   BoxW* box;                            // [W] each window's box
   BoxW* ubox;                           // [2 npair] boxes of the u_kn frames of one pass
   int* rbforce;                         // [W] 1: rebuild the window's lists at the next check
+  float* skin_used;                     // [W] list skin consumed by volume moves since the last build (A)
   // barostat (legs with a pressure; nmol = 0 otherwise)
   int nmol;                             // molecules: bonded components, rigid waters joined
   const int* mol_ptr;                   // [nmol + 1] CSR over mol_atoms
@@ -111,6 +115,7 @@ struct LegDev {
   BaroW* baro;                          // [W]
   BoxW* boxb;                           // [W] box before the trial move
   float *xb, *yb, *zb;                  // [W][n] positions before the trial move
+  float* molr;                          // [W][nmol] largest atom distance from its molecule's centre
   float* lam;                           // [W][4] per replica: elec, vdw, restraint, sc_alpha*(1-vdw) of
                                         // the state it holds
   const float* lamS;                    // [W][4] the same rows in state order (the leg's lambda table)

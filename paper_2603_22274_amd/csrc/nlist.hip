@@ -27,6 +27,18 @@ __device__ __forceinline__ int cell_of(float v, float L, float invL, int n) {
   return c < 0 ? 0 : (c >= n ? n - 1 : c);
 }
 
+// Largest squared displacement since the last build that keeps a window's
+// lists and cells valid: (skin/2)^2, less what volume moves have used (a
+// move by s changes a pair distance r by at most |s - 1| (r + 2 r_mol) and
+// an atom's place in the scaled cell grid by |s - 1| (r_mol + drift)).
+__device__ __forceinline__ float skin_threshold2(const LegDev& g, int w) {
+  const float used = g.skin_used[w];
+  if (used == 0.f) return g.skin_half2;
+  if (!(used < g.skin)) return -1.f;             // nothing left: rebuild
+  const float t = 0.5f * (g.skin - used);
+  return t * t;
+}
+
 // One block per window: rebuild flag = force || max displacement > skin/2;
 // a window being rebuilt gets its per-cell counters zeroed.  FROM_WORD: the
 // largest squared displacement was recorded by the previous step's
@@ -66,11 +78,12 @@ __global__ __launch_bounds__(256) void k_check(const LegDev* legs, BlockMap map,
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    const int f = (force || !(red[0] <= g.skin_half2)) ? 1 : 0;
+    const int f = (force || !(red[0] <= skin_threshold2(g, w))) ? 1 : 0;
     g.flag[w] = f;
     g.nbuild[w] += f;
     g.maxdisp[w] = 0u;
     g.rbforce[w] = 0;
+    if (f) g.skin_used[w] = 0.f;
     s_flag = f;
   }
   __syncthreads();
@@ -211,11 +224,12 @@ __global__ __launch_bounds__(1024) void k_check_sort(const LegDev* legs, BlockMa
   if (tid == 0) {
     float r = s_red[0];
     for (int k = 1; k < (int)(blockDim.x >> 6); ++k) r = fmaxf(r, s_red[k]);
-    const int f = (force || !(r <= g.skin_half2)) ? 1 : 0;
+    const int f = (force || !(r <= skin_threshold2(g, w))) ? 1 : 0;
     g.flag[w] = f;
     g.nbuild[w] += f;
     g.maxdisp[w] = 0u;
     g.rbforce[w] = 0;
+    if (f) g.skin_used[w] = 0.f;
     s_flag = f;
   }
   __syncthreads();
