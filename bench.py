@@ -161,13 +161,16 @@ def main():
         bench_step(0, False)
     torch.cuda.synchronize()
     ctx.device_check()
-    felis.profile(ctx, True)
-    for which in range(5):
+    # live timing of the pair kernel and of u_kn only: every recorded event is
+    # a queue packet between two kernels (the stage breakdown is taken after)
+    felis.profile(ctx, True, stages=(felis.PROF_PAIRS, felis.PROF_UKN))
+    for which in range(felis.PROF_BARO + 1):
         felis.profile_read(ctx, which)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
         bench_step(k, True)
+    timed_attempts = attempts[0]
     N_k = np.full(W, n_samples)
     mbar_ok = True
     try:
@@ -181,6 +184,13 @@ def main():
     felis.profile(ctx, False)
     prof = {name: felis.profile_read(ctx, i) for i, name in enumerate(('pairs', 'pme', 'nlist', 'integrate', 'ukn'))}
     ctx.device_check()
+    # stage breakdown (untimed): two more bench steps with every stage bracketed
+    felis.profile(ctx, True)
+    for k in range(2):
+        bench_step(0, False)
+    torch.cuda.synchronize()
+    felis.profile(ctx, False)
+    stages = {name: felis.profile_read(ctx, i) for i, name in enumerate(('pairs', 'pme', 'nlist', 'integrate'))}
     wall = t1 - t0
     md_steps = args.steps * args.md
     ns_windows = md_steps * DT * W / 1000.0
@@ -191,7 +201,6 @@ def main():
     achieved = flops / avg_pairs_s / 1e12
     traffic = _traffic()
     dg = float((f[-1] - f[0]) / beta) if f is not None else None
-    timed_attempts = attempts[0]
     # device time of one replica-exchange attempt (its u_kn is the sample's)
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     ucol = u[:, :W]
@@ -234,7 +243,7 @@ def main():
         felis.step(ctx, [nl], 4 * every, DT, 300.0, 0.5)
         torch.cuda.synchronize()
         n_npt = 8 * every
-        felis.profile(ctx, True)
+        felis.profile(ctx, True, stages=(felis.PROF_BARO,))
         for which in range(felis.PROF_BARO + 1):
             felis.profile_read(ctx, which)
         tc = time.perf_counter()
@@ -278,7 +287,7 @@ def main():
         "cpu_baseline": cpu,
         "per_window_form": per_window,
         "npt": npt,
-        "stage_ms_per_md_step": {k: v[0] / max(v[1], 1) for k, v in prof.items() if k != 'ukn'},
+        "stage_ms_per_md_step": {k: v[0] / max(v[1], 1) for k, v in stages.items()},
         "ukn_ms_per_call": prof['ukn'][0] / max(prof['ukn'][1], 1),
         "replica_exchange": {"every_md_steps": args.hrex_every, "attempts_in_timed_region": timed_attempts,
                              "attempt_us": hrex_us,

@@ -293,9 +293,13 @@ int felis_restraint_dg(const double* g0, const double* k, double temperature, do
 /* Kernel timing with HIP events recorded on the context's stream around the
  * launches of one stage inside felis_step / felis_ukn (the events bracket
  * exactly the stage's kernels, so their elapsed time is the stage's device
- * time).  felis_profile(ctx, 1) starts recording; felis_profile_read
- * synchronises, returns the summed milliseconds and the number of bracketed
- * launches for stage `which` since the last read, and resets it. */
+ * time).  felis_profile(ctx, 1) starts recording every stage, felis_profile(ctx,
+ * FELIS_PROF_MASK | m) only the stages whose bit (1 << FELIS_PROF_x) is set in
+ * m (each recorded event adds a queue packet between two kernels), 0 stops;
+ * felis_profile_read synchronises, returns the summed milliseconds and the
+ * number of bracketed launches for stage `which` since the last read, and
+ * resets it. */
+#define FELIS_PROF_MASK 0x40000000
 enum {
   FELIS_PROF_PAIRS = 0,     /* the real-space pair kernel */
   FELIS_PROF_PME = 1,       /* spreading, FFT passes, gather (in felis_step on the context's

@@ -58,7 +58,7 @@ struct felis_ctx {
   unsigned long long* d_count = nullptr;
   std::unordered_map<const void*, Meta> meta;
   std::string last_error;
-  bool prof = false;
+  int prof = 0;                     // bit t: record events around stage t
   Timer timers[FELIS_PROF_N];
 };
 
@@ -329,7 +329,7 @@ int prepare(felis_ctx* c, const felis_leg* legs, int n_legs, std::vector<LegHost
 
 // Records an event for timer t when profiling is on (start when stop == false).
 void mark(felis_ctx* c, int t, bool stop, hipStream_t s) {
-  if (!c->prof) return;
+  if (!((c->prof >> t) & 1)) return;
   Timer& T = c->timers[t];
   if (!stop && T.used + 2 > T.ev.size()) {
     for (int k = 0; k < 2; ++k) {
@@ -891,7 +891,7 @@ int felis_restraint_dg(const double* g0, const double* k, double temperature, do
 
 int felis_profile(felis_ctx* c, int enable) {
   if (!c) return FELIS_E_INVAL;
-  c->prof = enable != 0;
+  c->prof = enable == 1 ? (1 << FELIS_PROF_N) - 1 : (enable & ((1 << FELIS_PROF_N) - 1));
   return FELIS_OK;
 }
 

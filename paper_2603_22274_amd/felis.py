@@ -444,8 +444,16 @@ def mbar(ctx, u, N_k, tol=1e-10, max_iter=100000):
     return f, it.value
 
 
-def profile(ctx, enable=True):
-    ctx.check(lib().felis_profile(ctx.h, 1 if enable else 0))
+def profile(ctx, enable=True, stages=None):
+    """Record HIP events around every stage (``stages`` None) or only around
+    the given PROF_* stages; ``enable`` False stops recording."""
+    if not enable:
+        v = 0
+    elif stages is None:
+        v = 1
+    else:
+        v = 0x40000000 | sum(1 << int(t) for t in stages)
+    ctx.check(lib().felis_profile(ctx.h, v))
 
 
 def profile_read(ctx, which):
