@@ -36,6 +36,7 @@ DT = 0.002                      # ps
 PEAK_FP32 = 157.3               # TFLOP/s, MI355X FP32 vector (published; counts packed FP32)
 ISSUE_FP32 = 78.6               # TFLOP/s, non-packed FP32 issue: 256 CU x 4 SIMD x 16 lanes x 2 x 2.4 GHz
 FLOP_PER_PAIR = 75              # FP32 flops per in-cutoff pair (FMA = 2)
+PAIR_SAMPLE = 5                 # the timed region brackets every 5th pair-kernel launch with HIP events
 TRAFFIC_FILE = os.path.join(ROOT, 'profiles', 'pairs_traffic_solvent20.json')
 
 
@@ -161,9 +162,10 @@ def main():
         bench_step(0, False)
     torch.cuda.synchronize()
     ctx.device_check()
-    # live timing of the pair kernel and of u_kn only: every recorded event is
-    # a queue packet between two kernels (the stage breakdown is taken after)
-    felis.profile(ctx, True, stages=(felis.PROF_PAIRS, felis.PROF_UKN))
+    # live timing of the pair kernel (every PAIR_SAMPLE-th launch) and of u_kn:
+    # every recorded event is a queue packet between two kernels, ~6 us of
+    # idle queue each (the stage breakdown is taken after the timed region)
+    felis.profile(ctx, True, stages=(felis.PROF_PAIRS, felis.PROF_UKN), every=PAIR_SAMPLE)
     for which in range(felis.PROF_BARO + 1):
         felis.profile_read(ctx, which)
     torch.cuda.synchronize()
@@ -185,7 +187,7 @@ def main():
     prof = {name: felis.profile_read(ctx, i) for i, name in enumerate(('pairs', 'pme', 'nlist', 'integrate', 'ukn'))}
     ctx.device_check()
     # stage breakdown (untimed): two more bench steps with every stage bracketed
-    felis.profile(ctx, True)
+    felis.profile(ctx, True, every=1)
     for k in range(2):
         bench_step(0, False)
     torch.cuda.synchronize()
@@ -283,7 +285,8 @@ def main():
                      "traffic_gb_per_s": (traffic / avg_pairs_s / 1e9) if traffic else None,
                      "kernel": f"k_pairs (real-space pair kernel, all {W} windows per launch)",
                      "pairs_in_cutoff_per_launch": int(npairs_cut), "flop_per_pair": FLOP_PER_PAIR,
-                     "avg_launch_ms": avg_pairs_s * 1000.0, "launches": pairs_n},
+                     "avg_launch_ms": avg_pairs_s * 1000.0, "launches": pairs_n,
+                     "launches_timed_of": args.steps * args.md},
         "cpu_baseline": cpu,
         "per_window_form": per_window,
         "npt": npt,

@@ -312,6 +312,9 @@ enum {
   FELIS_PROF_N = 6
 };
 int felis_profile(felis_ctx* ctx, int enable);
+/* Bracket only every `every`-th occurrence of each recorded stage (1: all;
+ * counted from the last felis_profile call).  FELIS_E_INVAL if every < 1. */
+int felis_profile_every(felis_ctx* ctx, int every);
 int felis_profile_read(felis_ctx* ctx, int which, double* total_ms, int64_t* launches);
 
 /* Scratch bytes for felis_mbar: about (K + 1) n_total + K^2 (n_total/4096 + 1)

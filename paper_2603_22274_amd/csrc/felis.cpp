@@ -40,6 +40,8 @@ struct Meta {          // facts read from the topology at felis_leg_init
 struct Timer {
   std::vector<hipEvent_t> ev;     // start, stop, start, stop ...
   size_t used = 0;
+  long long seen = 0;             // stage occurrences since profiling was switched on
+  bool skip = false;              // the current occurrence is not bracketed
 };
 
 }  // namespace
@@ -59,6 +61,7 @@ struct felis_ctx {
   std::unordered_map<const void*, Meta> meta;
   std::string last_error;
   int prof = 0;                     // bit t: record events around stage t
+  int prof_every = 1;               // bracket every prof_every-th occurrence of a stage
   Timer timers[FELIS_PROF_N];
 };
 
@@ -331,6 +334,8 @@ int prepare(felis_ctx* c, const felis_leg* legs, int n_legs, std::vector<LegHost
 void mark(felis_ctx* c, int t, bool stop, hipStream_t s) {
   if (!((c->prof >> t) & 1)) return;
   Timer& T = c->timers[t];
+  if (!stop) T.skip = (T.seen++ % c->prof_every) != 0;
+  if (T.skip) return;
   if (!stop && T.used + 2 > T.ev.size()) {
     for (int k = 0; k < 2; ++k) {
       hipEvent_t e;
@@ -892,6 +897,13 @@ int felis_restraint_dg(const double* g0, const double* k, double temperature, do
 int felis_profile(felis_ctx* c, int enable) {
   if (!c) return FELIS_E_INVAL;
   c->prof = enable == 1 ? (1 << FELIS_PROF_N) - 1 : (enable & ((1 << FELIS_PROF_N) - 1));
+  for (auto& T : c->timers) { T.seen = 0; T.skip = false; }
+  return FELIS_OK;
+}
+
+int felis_profile_every(felis_ctx* c, int every) {
+  if (!c || every < 1) return FELIS_E_INVAL;
+  c->prof_every = every;
   return FELIS_OK;
 }
 

@@ -91,6 +91,7 @@ def lib():
         'felis_ukn': (C.c_int, [vp, P(FelisLeg), vp, C.c_int, vp, vp, vp, C.c_int64, C.c_int64, vp,
                                 C.c_double, vp, C.c_int64]),
         'felis_profile': (C.c_int, [vp, C.c_int]),
+        'felis_profile_every': (C.c_int, [vp, C.c_int]),
         'felis_profile_read': (C.c_int, [vp, C.c_int, P(C.c_double), P(C.c_int64)]),
         'felis_mbar_work_size': (C.c_int, [C.c_int, C.c_int64, P(C.c_size_t)]),
         'felis_mbar': (C.c_int, [vp, vp, vp, C.c_int, C.c_int64, C.c_double, C.c_int, vp, P(C.c_int), vp,
@@ -444,9 +445,11 @@ def mbar(ctx, u, N_k, tol=1e-10, max_iter=100000):
     return f, it.value
 
 
-def profile(ctx, enable=True, stages=None):
+def profile(ctx, enable=True, stages=None, every=1):
     """Record HIP events around every stage (``stages`` None) or only around
-    the given PROF_* stages; ``enable`` False stops recording."""
+    the given PROF_* stages, bracketing every ``every``-th occurrence of each;
+    ``enable`` False stops recording."""
+    ctx.check(lib().felis_profile_every(ctx.h, int(every)))
     if not enable:
         v = 0
     elif stages is None:
