@@ -19,7 +19,7 @@ using namespace felis;
 namespace {
 
 struct Layout {
-  size_t lam, lamS, rstate, free_atoms, lig_idx, xr, yr, zr, flag, nbuild, maxdisp, wmax, hcell, box, ubox, rbforce, skin_used, mol_ptr, mol_atoms, baro, boxb, xb, yb, zb, molr, perm, cellcode, cellstart, cursor, xyzq, prm, bblo,
+  size_t lam, lamS, rstate, free_atoms, lig_idx, xr, yr, zr, flag, nbuild, maxdisp, wmax, hcell, box, ubox, rbforce, skin_used, bptr, bnb, bid, mol_ptr, mol_atoms, baro, boxb, xb, yb, zb, molr, perm, cellcode, cellstart, cursor, xyzq, prm, bblo,
       bbhi, gsten, lcount, lent, frx, fry, frz, grid64, cgrid, tw[3], bmod[3], eacc, uacc, upart, lpart, ucst, total;
 };
 
@@ -171,6 +171,9 @@ int make_plan(felis_ctx* c, const felis_leg* L, Plan& P) {
   y.ubox = put(2 * (size_t)h.npair * sizeof(BoxW));
   y.rbforce = put(W * 4);
   y.skin_used = put(W * 4);
+  y.bptr = put((n + 1) * 4);                      // per-atom bond table (filled at set-up)
+  y.bnb = put(2 * (size_t)std::max(h.nbonds, 1) * 4);
+  y.bid = put(2 * (size_t)std::max(h.nbonds, 1) * 4);
   {
     // barostat: molecule table, per-window state, positions before a move
     const bool npt = L->pressure_bar > 0;
@@ -267,6 +270,9 @@ LegDev make_dev(const felis_ctx* c, const felis_leg* L, const Plan& p, const Met
   g.ubox = (BoxW*)(w + y.ubox);
   g.rbforce = (int*)(w + y.rbforce);
   g.skin_used = (float*)(w + y.skin_used);
+  g.bptr = (const int*)(w + y.bptr);
+  g.bnb = (const int*)(w + y.bnb);
+  g.bid = (const int*)(w + y.bid);
   g.nmol = m.nmol;
   if (m.nmol) {
     g.mol_ptr = (const int*)(w + y.mol_ptr);
@@ -559,12 +565,33 @@ int felis_leg_init(felis_ctx* c, felis_leg* L) {
   m.nfree = (int)freeat.size();
   m.nlig = (int)ligi.size();
   m.nmol = 0;
+  std::vector<int> bij(2 * (size_t)h.nbonds);
+  if (h.nbonds && hipMemcpy(bij.data(), L->bond_ij, bij.size() * 4, hipMemcpyDeviceToHost) != hipSuccess)
+    return fail(c, FELIS_E_DEVICE, "bond copy failed");
+  {
+    // per-atom bond table for the integrator: for atom a, its partners and
+    // bond indices in bond order
+    std::vector<int> ptr(h.n + 1, 0), nb(std::max(2 * h.nbonds, 2)), id(std::max(2 * h.nbonds, 2));
+    for (int k = 0; k < h.nbonds; ++k) {
+      const int a = bij[2 * k], b = bij[2 * k + 1];
+      if (a < 0 || b < 0 || a >= h.n || b >= h.n) return fail(c, FELIS_E_INVAL, "bond atom out of range");
+      ++ptr[a + 1]; ++ptr[b + 1];
+    }
+    for (int a = 0; a < h.n; ++a) ptr[a + 1] += ptr[a];
+    std::vector<int> fill(ptr.begin(), ptr.end() - 1);
+    for (int k = 0; k < h.nbonds; ++k) {
+      const int a = bij[2 * k], b = bij[2 * k + 1];
+      nb[fill[a]] = b; id[fill[a]++] = k;
+      nb[fill[b]] = a; id[fill[b]++] = k;
+    }
+    ok &= hipMemcpy(w + y.bptr, ptr.data(), ptr.size() * 4, hipMemcpyHostToDevice) == hipSuccess;
+    ok &= hipMemcpy(w + y.bnb, nb.data(), nb.size() * 4, hipMemcpyHostToDevice) == hipSuccess;
+    ok &= hipMemcpy(w + y.bid, id.data(), id.size() * 4, hipMemcpyHostToDevice) == hipSuccess;
+    if (!ok) return fail(c, FELIS_E_DEVICE, "bond table");
+  }
   if (L->pressure_bar > 0) {
     // molecules: connected components of the bonds with each rigid water's
     // atoms joined (union-find), numbered by their lowest atom
-    std::vector<int> bij(2 * (size_t)h.nbonds);
-    if (h.nbonds && hipMemcpy(bij.data(), L->bond_ij, bij.size() * 4, hipMemcpyDeviceToHost) != hipSuccess)
-      return fail(c, FELIS_E_DEVICE, "bond copy failed");
     std::vector<int> parent(h.n);
     for (int a = 0; a < h.n; ++a) parent[a] = a;
     auto find = [&](int a) {
@@ -747,8 +774,7 @@ int felis_step(felis_ctx* c, felis_leg* legs, int n_legs, int n_steps, double dt
     mark(c, FELIS_PROF_PAIRS, false);
     launch_pairs(c->stream, c->d_legs, hs.data(), n_legs, false);
     mark(c, FELIS_PROF_PAIRS, true);
-    launch_corrections(c->stream, c->d_legs, hs.data(), n_legs, false);
-    launch_bonded(c->stream, c->d_legs, hs.data(), n_legs, false);
+    // bonded and restraint forces are summed by the integrator itself
     (void)hipStreamWaitEvent(c->stream, c->ev_join, 0);
     mark(c, FELIS_PROF_INTEGRATE, false);
     launch_integrate(c->stream, c->d_legs, hs.data(), n_legs, step.data(), seed.data(), (float)dt,

@@ -99,6 +99,7 @@ struct LegDev {
   const int* bond_ij;
   const float *bond_k, *bond_r0;
   const int* water;
+  const int *bptr, *bnb, *bid;          // per-atom bonds: CSR [n + 1] over (partner atom, bond index)
   // state (caller-owned) [W][n]
   float *x, *y, *z, *vx, *vy, *vz;
   long long *fx, *fy, *fz;

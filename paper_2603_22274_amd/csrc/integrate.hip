@@ -9,6 +9,7 @@
 // Box-Muller: (sqrt(-2 ln u0) cos 2pi u1, sqrt(-2 ln u0) sin 2pi u1,
 // sqrt(-2 ln u2) cos 2pi u3).
 #include "felis_internal.h"
+#include "restraint.h"
 #include "settle.h"
 
 namespace felis {
@@ -35,6 +36,61 @@ struct StepArgs {
   float dt, kT, gamma;
 };
 
+// Anchor `anchor`'s share of the lambda_r-scaled Boresch restraint force in
+// window w (out of line: six atoms per window take this path, and its arrays
+// stay out of the integrator's registers)
+__device__ __attribute__((noinline)) v3 restraint_share(const LegDev& g, int w, int anchor) {
+  const BoxW& B = g.box[w];
+  const size_t base = (size_t)w * g.n;
+  const size_t o1 = base + g.ranch[0];
+  v3 p[6], Fr[6];
+  for (int t = 0; t < 6; ++t) {
+    const size_t ot = base + g.ranch[t];
+    float dx = g.x[ot] - g.x[o1], dy = g.y[ot] - g.y[o1], dz = g.z[ot] - g.z[o1];
+    dx = fmaf(-B.Lf[0], rintf(dx * B.invLf[0]), dx);
+    dy = fmaf(-B.Lf[1], rintf(dy * B.invLf[1]), dy);
+    dz = fmaf(-B.Lf[2], rintf(dz * B.invLf[2]), dz);
+    p[t] = mk(dx, dy, dz);
+  }
+  boresch_eval(p, g.rg0, g.rk, Fr);
+  const float lr = g.lam[4 * w + 2];
+  v3 F = mk(0.f, 0.f, 0.f);
+  for (int t = 0; t < 6; ++t)
+    if (g.ranch[t] == g.ranch[anchor]) F = vadd(F, vmul(Fr[t], lr));
+  return F;
+}
+
+// The bonded terms of atom a in window w: its harmonic bonds (each atom sums
+// its own, from the per-atom bond table, in bond order) and, for a Boresch
+// anchor, its share of the lambda_r-scaled restraint -- the forces of
+// k_bonded, computed where they are used instead of added by atomics.
+__device__ __forceinline__ v3 bonded_force(const LegDev& g, int w, int a) {
+  v3 F = mk(0.f, 0.f, 0.f);
+  const int k0 = g.bptr[a], k1 = g.bptr[a + 1];
+  int anchor = -1;
+  if (g.has_rest && g.lam[4 * w + 2] != 0.0f)
+    for (int t = 0; t < 6; ++t) anchor = (g.ranch[t] == a) ? t : anchor;
+  if (k0 == k1 && anchor < 0) return F;
+  const BoxW& B = g.box[w];
+  const size_t base = (size_t)w * g.n;
+  auto img = [&](size_t from, size_t to) {        // r_to - r_from, nearest image
+    float dx = g.x[to] - g.x[from], dy = g.y[to] - g.y[from], dz = g.z[to] - g.z[from];
+    dx = fmaf(-B.Lf[0], rintf(dx * B.invLf[0]), dx);
+    dy = fmaf(-B.Lf[1], rintf(dy * B.invLf[1]), dy);
+    dz = fmaf(-B.Lf[2], rintf(dz * B.invLf[2]), dz);
+    return mk(dx, dy, dz);
+  };
+  for (int k = k0; k < k1; ++k) {
+    const int b = g.bnb[k], id = g.bid[k];
+    const v3 d = img(base + b, base + a);           // r_a - r_b
+    const float r = sqrtf(d.x * d.x + d.y * d.y + d.z * d.z);
+    const float fs = -g.bond_k[id] * (r - g.bond_r0[id]) / r;
+    F = vadd(F, vmul(d, fs));
+  }
+  if (anchor >= 0) F = vadd(F, restraint_share(g, w, anchor));
+  return F;
+}
+
 // kick, half drift, O step, half drift for one atom: returns the total
 // displacement and the post-O velocity
 __device__ __forceinline__ void advance(const LegDev& g, const StepArgs& S, int leg, int w, int a,
@@ -43,10 +99,17 @@ __device__ __forceinline__ void advance(const LegDev& g, const StepArgs& S, int 
   const float m = g.mass[a];
   const float dt = S.dt;
   const float acc = (float)kAccel / m;
-  // total force: real-space, bonded and restraint terms in fx/fy/fz plus this
-  // step's reciprocal-space term; the sum is stored back so that fx/fy/fz
-  // hold the whole force of the step after the call
-  const long long tx = g.fx[o] + g.frx[o], ty = g.fy[o] + g.fry[o], tz = g.fz[o] + g.frz[o];
+  // total force: real-space terms in fx/fy/fz, this step's reciprocal-space
+  // term and the bonded terms; the sum is stored back so that fx/fy/fz hold
+  // the whole force of the step after the call
+  long long tx = g.fx[o] + g.frx[o], ty = g.fy[o] + g.fry[o], tz = g.fz[o] + g.frz[o];
+  const v3 fb = bonded_force(g, w, a);
+  if (fb.x != 0.f || fb.y != 0.f || fb.z != 0.f) {
+    const int where = (w << 20) | a;
+    tx += to_fixed((double)fb.x, kForceScale, g.err, kSiteBonded, where, g.leg_index);
+    ty += to_fixed((double)fb.y, kForceScale, g.err, kSiteBonded, where, g.leg_index);
+    tz += to_fixed((double)fb.z, kForceScale, g.err, kSiteBonded, where, g.leg_index);
+  }
   g.fx[o] = tx; g.fy[o] = ty; g.fz[o] = tz;
   const float F[3] = {(float)((double)tx * (1.0 / kForceScale)), (float)((double)ty * (1.0 / kForceScale)),
                       (float)((double)tz * (1.0 / kForceScale))};
