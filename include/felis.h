@@ -236,7 +236,7 @@ int felis_ukn(felis_ctx* ctx, felis_leg* leg, const double* lambdas, int K, cons
  * felis_step makes the move before every step whose index is a positive
  * multiple of barostat_every (attempt = step / barostat_every);
  * felis_barostat makes one now for every leg of the batch with a pressure
- * (others are evaluated but unchanged), at the given attempt index, and
+ * (others are left untouched), at the given attempt index, and
  * leaves every window's lists valid for its positions and box.
  * FELIS_E_INVAL if no leg of the batch has a pressure. */
 int felis_barostat(felis_ctx* ctx, felis_leg* legs, int n_legs, double temperature, int64_t attempt);

@@ -715,15 +715,19 @@ void energy_pass(felis_ctx* c, const std::vector<LegHost>& hs, int n_legs, bool 
 
 // One volume move of every window of the due legs: energies, trial move
 // (box, molecule centres), energies in the trial boxes, Metropolis test and
-// restore of rejected windows.  Windows of other legs are evaluated too
-// (their state is unchanged).
+// restore of rejected windows.
 void baro_attempt(felis_ctx* c, const std::vector<LegHost>& hs, int n_legs, const BaroArgs& A, bool from_word) {
+  // every launcher sizes its grid from the window (and grid) counts: legs
+  // that make no move get no workgroups and are left exactly as they are
+  std::vector<LegHost> hd(hs);
+  for (int i = 0; i < n_legs; ++i)
+    if (!A.due[i]) { hd[i].W = 0; hd[i].npair = 0; hd[i].nmol = 0; }
   mark(c, FELIS_PROF_BARO, false);
-  energy_pass(c, hs, n_legs, from_word);
-  launch_baro_keep_u0(c->stream, c->d_legs, hs.data(), n_legs);
-  launch_baro_propose(c->stream, c->d_legs, hs.data(), n_legs, A);
-  energy_pass(c, hs, n_legs, false);
-  launch_baro_accept(c->stream, c->d_legs, hs.data(), n_legs, A);
+  energy_pass(c, hd, n_legs, from_word);
+  launch_baro_keep_u0(c->stream, c->d_legs, hd.data(), n_legs);
+  launch_baro_propose(c->stream, c->d_legs, hd.data(), n_legs, A);
+  energy_pass(c, hd, n_legs, false);
+  launch_baro_accept(c->stream, c->d_legs, hd.data(), n_legs, A);
   mark(c, FELIS_PROF_BARO, true);
 }
 
