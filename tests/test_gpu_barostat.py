@@ -48,9 +48,14 @@ def _energy(sysd, x, box, lam):
     return e['total'], sum(abs(v) for k, v in e.items() if k != 'total')
 
 
-def test_volume_move_matches_oracle(F):
+@pytest.mark.parametrize('name', ['config0', 'small_complex'])
+def test_volume_move_matches_oracle(F, name):
+    """One move of every window; the complex leg has a chain 'protein' as one
+    molecule, ions, and the Boresch restraint across two molecules."""
     felis, ctx = F
-    s = _sys([0, 3, 6, 11])
+    base = getattr(gen, name)()
+    pick = [0, 3, 6, 11] if name == 'config0' else [0, 12, 25, 41]
+    s = dataclasses.replace(base, lambdas=base.lambdas[pick])
     seed = 9
     leg = felis.Leg(ctx, s, seed=seed, pressure_bar=P_BAR, barostat_every=1000)
     felis.step(ctx, [leg], 20, 0.002, T, 5.0)
