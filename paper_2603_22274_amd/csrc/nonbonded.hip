@@ -147,7 +147,9 @@ __device__ __forceinline__ void sweep(const LegDev& g, const BoxF B, const IClus
       }
       const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
       const bool in = ((e >> k) & 1u) && (r2 < rc2);
-      const float r2s = in ? r2 : 1.0f;
+      // lanes outside (in == false) may compute inf or NaN below: every
+      // result they feed is dropped by the selects on `in`
+      const float r2s = r2;
       const float rinv = __builtin_amdgcn_rsqf(r2s);
       const float rinv2 = rinv * rinv;
       const float r = r2s * rinv;
