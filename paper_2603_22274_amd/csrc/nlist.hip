@@ -15,6 +15,8 @@ namespace felis {
 namespace {
 
 constexpr int kCellOf = 4096;                 // candidates per table window in k_build
+constexpr int kBuildWaves = 2;                // waves per list-build workgroup
+constexpr int kBuildThreads = 64 * kBuildWaves;
 
 // a wave-uniform float moved to a scalar register
 __device__ __forceinline__ float scalar(float v) {
@@ -303,14 +305,16 @@ __global__ __launch_bounds__(1024) void k_check_sort(const LegDev* legs, BlockMa
 
 bool sort_in_lds(const LegHost& h) { return h.ncell <= kSortCells && h.n <= kSortAtoms; }
 
-// One block per cluster: sweep the coarse blocks (aligned 2x2x2 fine cells)
-// within r_list of the cluster's box, 256 blocks per round, each trimmed to
-// the Hilbert span of its fine cells within r_list, and list every
-// atom j with at least one i of the cluster in range.  The four waves take
-// consecutive quarters of each 256-candidate step and append in wave order,
-// so the list order is fixed (cells in sweep order, slots ascending) while a
-// cluster's candidates are spread over 256 lanes.
-__global__ __launch_bounds__(256) void k_build(const LegDev* legs, BlockMap map) {
+// One workgroup per cluster: sweep the coarse blocks (aligned 2x2x2 fine
+// cells) within r_list of the cluster's box, kBuildThreads blocks per round,
+// each trimmed to the Hilbert span of its fine cells within r_list, and list
+// every atom j with at least one i of the cluster in range.  The waves take
+// consecutive 64-candidate parts of each step and append in wave order, so
+// the list order is fixed (cells in sweep order, slots ascending).  Two waves
+// per workgroup: every wave repeats the cluster's set-up (~700 instructions),
+// so four waves spent 15 % more and one wave pays the per-round scan and
+// table work twice as often.
+__global__ __launch_bounds__(kBuildThreads) void k_build(const LegDev* legs, BlockMap map) {
   const int leg = find_leg(map, blockIdx.x);
   const LegDev& g = legs[leg];
   const long long item = (long long)blockIdx.x - map.start[leg];
@@ -324,10 +328,10 @@ __global__ __launch_bounds__(256) void k_build(const LegDev* legs, BlockMap map)
   __shared__ int s_ex[kClus][kMaxExcl];
   __shared__ int s_nex[kClus];
   __shared__ unsigned s_bloom[64];              // 2048-bit filter of excluded atoms
-  __shared__ int s_start[256];                  // first sorted slot of each block in the round
-  __shared__ int s_pre[256];                    // exclusive prefix of candidate counts
-  __shared__ int s_wsum[4];
-  __shared__ int s_wc[2][2][4];
+  __shared__ int s_start[kBuildThreads];        // first sorted slot of each block in the round
+  __shared__ int s_pre[kBuildThreads];          // exclusive prefix of candidate counts
+  __shared__ int s_wsum[kBuildWaves];
+  __shared__ int s_wc[2][2][kBuildWaves];
   __shared__ unsigned char s_cellof[kCellOf];   // candidate -> block of the round, one window at a time
   const size_t o = (size_t)w * g.n;
   const int* perm = g.perm + (size_t)w * g.npad;
@@ -433,7 +437,7 @@ __global__ __launch_bounds__(256) void k_build(const LegDev* legs, BlockMap map)
   const int n12 = nC[1] * nC[2];
   const float inv12 = __builtin_amdgcn_rcpf((float)n12), inv2 = __builtin_amdgcn_rcpf((float)nC[2]);
   auto wrapc = [nf](int c) { return c < 0 ? c + nf : (c >= nf ? c - nf : c); };
-  for (int cb = 0; cb < ncells; cb += 256) {
+  for (int cb = 0; cb < ncells; cb += kBuildThreads) {
     const int ci = cb + tid;
     int s0 = 0, cnt = 0;
     if (ci < ncells) {
@@ -489,7 +493,8 @@ __global__ __launch_bounds__(256) void k_build(const LegDev* legs, BlockMap map)
     __syncthreads();
     int woff = 0;
     for (int k = 0; k < wave; ++k) woff += s_wsum[k];
-    const int total = s_wsum[0] + s_wsum[1] + s_wsum[2] + s_wsum[3];
+    int total = 0;
+    for (int k = 0; k < kBuildWaves; ++k) total += s_wsum[k];
     const int pre_t = woff + inc - cnt;
     s_pre[tid] = pre_t;
     // candidates are taken kCellOf at a time: each block writes its index over
@@ -501,7 +506,7 @@ __global__ __launch_bounds__(256) void k_build(const LegDev* legs, BlockMap map)
     }
     __syncthreads();
     const int T1 = min(total, T0 + kCellOf);
-    for (int t0 = T0; t0 < T1; t0 += 256) {
+    for (int t0 = T0; t0 < T1; t0 += kBuildThreads) {
       const int t = t0 + tid;
       unsigned mask = 0;
       int s = 0;
@@ -556,8 +561,7 @@ __global__ __launch_bounds__(256) void k_build(const LegDev* legs, BlockMap map)
       __syncthreads();
       int offL = countL, offH = countH;
       for (int k = 0; k < wave; ++k) { offL += s_wc[par][0][k]; offH += s_wc[par][1][k]; }
-      countL += s_wc[par][0][0] + s_wc[par][0][1] + s_wc[par][0][2] + s_wc[par][0][3];
-      countH += s_wc[par][1][0] + s_wc[par][1][1] + s_wc[par][1][2] + s_wc[par][1][3];
+      for (int k = 0; k < kBuildWaves; ++k) { countL += s_wc[par][0][k]; countH += s_wc[par][1][k]; }
       if (mL) {
         const int pos = offL + __popcll(bL & lt);
         if (pos < cap) outL[pos] = ((unsigned)s << 8) | mL;
@@ -663,7 +667,7 @@ void launch_sort_pack(hipStream_t s, const LegDev* d, const LegHost* h, int nl) 
 void launch_lists(hipStream_t s, const LegDev* d, const LegHost* h, int nl) {
   BlockMap m;
   const int nb = make_map(m, nl, [&](int i) { return h[i].W * h[i].nclus; });
-  if (nb) hipLaunchKernelGGL(k_build, dim3(nb), dim3(256), 0, s, d, m);
+  if (nb) hipLaunchKernelGGL(k_build, dim3(nb), dim3(kBuildThreads), 0, s, d, m);
 }
 
 void launch_build(hipStream_t s, const LegDev* d, const LegHost* h, int nl) {
