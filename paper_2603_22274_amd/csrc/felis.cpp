@@ -705,11 +705,18 @@ void energy_pass(felis_ctx* c, const std::vector<LegHost>& hs, int n_legs, bool 
   launch_zero_energy(c->stream, c->d_legs, h, n_legs, 0, FELIS_E_TOTAL);
   launch_check(c->stream, c->d_legs, h, n_legs, 0, from_word);
   launch_sort_pack(c->stream, c->d_legs, h, n_legs);
+  // reciprocal space beside the list build and the pair kernel, as in a step;
+  // its forces go to frx.. (the pair kernel stores fx.. meanwhile), and the
+  // next step overwrites both: only the energy is wanted here
+  (void)hipEventRecord(c->ev_fork, c->stream);
+  (void)hipStreamWaitEvent(c->side, c->ev_fork, 0);
+  launch_pme(c->side, c->d_legs, h, n_legs, true, true);
+  (void)hipEventRecord(c->ev_join, c->side);
   launch_lists(c->stream, c->d_legs, h, n_legs);
   launch_pairs(c->stream, c->d_legs, h, n_legs, true);
   launch_corrections(c->stream, c->d_legs, h, n_legs, true);
   launch_bonded(c->stream, c->d_legs, h, n_legs, true);
-  launch_pme(c->stream, c->d_legs, h, n_legs, true, false);
+  (void)hipStreamWaitEvent(c->stream, c->ev_join, 0);
   launch_finish_energy(c->stream, c->d_legs, h, n_legs, 0, FELIS_E_TOTAL);
 }
 

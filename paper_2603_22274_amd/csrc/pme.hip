@@ -647,7 +647,8 @@ void launch_pme(hipStream_t s, const LegDev* d, const LegHost* h, int nl, bool e
   hipLaunchKernelGGL(k_spread, dim3(nb), dim3(256), 0, s, d, m);
   launch_pme_fft(s, d, h, nl, 0);
   nb = make_map(m, nl, [&](int i) { return blocks_for((long long)h[i].W * h[i].npad, 64); });
-  if (energy) hipLaunchKernelGGL((k_gather<true, false>), dim3(nb), dim3(256), 0, s, d, m);
+  if (energy && step_forces) hipLaunchKernelGGL((k_gather<true, true>), dim3(nb), dim3(256), 0, s, d, m);
+  else if (energy) hipLaunchKernelGGL((k_gather<true, false>), dim3(nb), dim3(256), 0, s, d, m);
   else if (step_forces) hipLaunchKernelGGL((k_gather<false, true>), dim3(nb), dim3(256), 0, s, d, m);
   else hipLaunchKernelGGL((k_gather<false, false>), dim3(nb), dim3(256), 0, s, d, m);
 }
