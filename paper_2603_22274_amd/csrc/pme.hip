@@ -326,7 +326,8 @@ __device__ __forceinline__ void bspline4(float f, float* w, float* dw) {
 
 
 constexpr int kBrick = 8;                      // brick edge in grid points
-constexpr int kSpreadCellOf = 2048;            // candidates per table window in spreading
+constexpr int kSpreadCellOf = 1024;            // candidates per table window in spreading
+constexpr int kSpreadChunk = 128;              // atoms per compact task list in spreading
 
 // Grid points of axis d that an atom with base index b touches, as a 4-bit
 // mask over the stencil offsets (point b - k, k = 0..3, periodic) that fall in
@@ -373,8 +374,10 @@ __global__ __launch_bounds__(256) void k_spread(const LegDev* legs, BlockMap map
   __shared__ unsigned char s_cellof[kSpreadCellOf];   // candidate -> cell of the round
   __shared__ int s_n;
   __shared__ float s_q[256], s_w[256][12];
-  __shared__ int s_b[256][3];
+  __shared__ int s_b[256];                       // packed bases (7 bits per axis)
   __shared__ unsigned s_m[256];
+  __shared__ unsigned short s_task[16 * kSpreadChunk];  // (atom << 4 | ix << 2 | iy) of the chunk
+  __shared__ int s_tw[4];
   for (int e = tid; e < kBrick * kBrick * kBrick; e += 256) tile[e] = 0;
   if (tid == 0) s_n = 0;
 
@@ -456,27 +459,55 @@ __global__ __launch_bounds__(256) void k_spread(const LegDev* legs, BlockMap map
             bspline4(fr[0], &s_w[k][0], nullptr);
             bspline4(fr[1], &s_w[k][4], nullptr);
             bspline4(fr[2], &s_w[k][8], nullptr);
-            s_b[k][0] = b0; s_b[k][1] = b1; s_b[k][2] = b2;
+            s_b[k] = __float_as_int(st.w);
             s_m[k] = mx | (my << 4) | (mz << 8);
           }
         }
         __syncthreads();
         const int na = s_n;
-        for (int task = tid; task < 16 * na; task += 256) {   // (atom, ix, iy), loop over iz
-          const int k = task >> 4, ix = task & 3, iy = (task >> 2) & 3;
-          const unsigned m = s_m[k];
-          if (!((m >> ix) & 1u) || !((m >> (4 + iy)) & 1u)) continue;
-          int px = s_b[k][0] - ix; if (px < 0) px += g.K[0];
-          int py = s_b[k][1] - iy; if (py < 0) py += g.K[1];
-          const double qxy = (double)(s_q[k] * s_w[k][ix] * s_w[k][4 + iy]);
-          const int row = ((py - P0[1]) * kBrick + (px - P0[0]));
-#pragma unroll
-          for (int iz = 0; iz < 4; ++iz) {
-            if (!((m >> (8 + iz)) & 1u)) continue;
-            int pz = s_b[k][2] - iz; if (pz < 0) pz += g.K[2];
-            const long long v = __double2ll_rn(qxy * (double)s_w[k][8 + iz] * kGridScale);
-            atomicAdd((unsigned long long*)&tile[(pz - P0[2]) * kBrick * kBrick + row], (unsigned long long)v);
+        // compact task lists, kSpreadChunk atoms at a time: one (atom, ix, iy)
+        // per stencil column inside the brick (about half of the 16 columns
+        // of an atom near a brick face)
+        for (int a0 = 0; a0 < na; a0 += kSpreadChunk) {
+          {
+            const unsigned m = (tid < kSpreadChunk && a0 + tid < na) ? s_m[a0 + tid] : 0u;
+            const int nt = __popc(m & 0xFu) * __popc((m >> 4) & 0xFu);
+            int inc = nt;
+            for (int k = 1; k < 64; k <<= 1) {
+              const int v = __shfl_up(inc, k, 64);
+              if (lane >= k) inc += v;
+            }
+            if (lane == 63) s_tw[wave] = inc;
+            __syncthreads();
+            int pos = inc - nt;
+            for (int k = 0; k < wave; ++k) pos += s_tw[k];
+            for (int ix = 0; ix < 4; ++ix) {
+              if (!((m >> ix) & 1u)) continue;
+              for (int iy = 0; iy < 4; ++iy)
+                if ((m >> (4 + iy)) & 1u) s_task[pos++] = (unsigned short)((tid << 4) | (ix << 2) | iy);
+            }
           }
+          __syncthreads();
+          const int ntask = s_tw[0] + s_tw[1] + s_tw[2] + s_tw[3];
+          for (int task = tid; task < ntask; task += 256) {   // (atom, ix, iy), loop over iz
+            const unsigned word = s_task[task];
+            const int k = a0 + (int)(word >> 4), ix = (int)((word >> 2) & 3u), iy = (int)(word & 3u);
+            const unsigned m = s_m[k];
+            int bb[3];
+            unpack_bases(__int_as_float(s_b[k]), bb);
+            int px = bb[0] - ix; if (px < 0) px += g.K[0];
+            int py = bb[1] - iy; if (py < 0) py += g.K[1];
+            const double qxy = (double)(s_q[k] * s_w[k][ix] * s_w[k][4 + iy]);
+            const int row = ((py - P0[1]) * kBrick + (px - P0[0]));
+#pragma unroll
+            for (int iz = 0; iz < 4; ++iz) {
+              if (!((m >> (8 + iz)) & 1u)) continue;
+              int pz = bb[2] - iz; if (pz < 0) pz += g.K[2];
+              const long long v = __double2ll_rn(qxy * (double)s_w[k][8 + iz] * kGridScale);
+              atomicAdd((unsigned long long*)&tile[(pz - P0[2]) * kBrick * kBrick + row], (unsigned long long)v);
+            }
+          }
+          __syncthreads();                          // s_task and s_tw are rewritten next
         }
         __syncthreads();
         if (tid == 0) s_n = 0;
