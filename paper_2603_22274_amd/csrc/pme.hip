@@ -356,9 +356,12 @@ __device__ __forceinline__ unsigned brick_mask(int b, int K, int P0, int P1) {
 __global__ __launch_bounds__(256) void k_spread(const LegDev* legs, BlockMap map) {
   const int leg = find_leg(map, blockIdx.x);
   const LegDev& g = legs[leg];
+  // grid sizes in scalar registers (otherwise reloaded from memory inside the loops)
+  const int K[3] = {__builtin_amdgcn_readfirstlane(g.K[0]), __builtin_amdgcn_readfirstlane(g.K[1]),
+                    __builtin_amdgcn_readfirstlane(g.K[2])};
   const int tid = threadIdx.x;
-  const int nbx = (g.K[0] + kBrick - 1) / kBrick, nby = (g.K[1] + kBrick - 1) / kBrick;
-  const int nbz = (g.K[2] + kBrick - 1) / kBrick;
+  const int nbx = (K[0] + kBrick - 1) / kBrick, nby = (K[1] + kBrick - 1) / kBrick;
+  const int nbz = (K[2] + kBrick - 1) / kBrick;
   const int bl = blockIdx.x - map.start[leg];
   const int per = nbx * nby * nbz;
   const int w = bl / per;
@@ -367,7 +370,7 @@ __global__ __launch_bounds__(256) void k_spread(const LegDev* legs, BlockMap map
   r -= bz * nbx * nby;
   const int by = r / nbx, bx = r - by * nbx;
   const int P0[3] = {bx * kBrick, by * kBrick, bz * kBrick};
-  const int P1[3] = {min(P0[0] + kBrick, g.K[0]), min(P0[1] + kBrick, g.K[1]), min(P0[2] + kBrick, g.K[2])};
+  const int P1[3] = {min(P0[0] + kBrick, K[0]), min(P0[1] + kBrick, K[1]), min(P0[2] + kBrick, K[2])};
 
   __shared__ long long tile[kBrick * kBrick * kBrick];
   __shared__ int s_start[256], s_pre[256], s_wsum[4];
@@ -386,7 +389,7 @@ __global__ __launch_bounds__(256) void k_spread(const LegDev* legs, BlockMap map
   const float margin = sqrtf(g.skin_half2) + 0.05f;
   int c0[3], nspan[3];
   for (int d = 0; d < 3; ++d) {
-    const float Lc = g.box[w].Lf[d] / (float)nc, hgrid = g.box[w].Lf[d] / (float)g.K[d];
+    const float Lc = g.box[w].Lf[d] / (float)nc, hgrid = g.box[w].Lf[d] / (float)K[d];
     const int a0 = (int)floorf(((float)P0[d] * hgrid - margin) / Lc);
     const int a1 = (int)floorf(((float)(P1[d] + 3) * hgrid + margin) / Lc);
     const bool full = a1 - a0 + 1 >= nc;
@@ -449,9 +452,9 @@ __global__ __launch_bounds__(256) void k_spread(const LegDev* legs, BlockMap map
           unpack_bases(st.w, bb);
           const int b0 = bb[0], b1 = bb[1], b2 = bb[2];
           const float fr[3] = {st.x, st.y, st.z};
-          const unsigned mx = brick_mask(b0, g.K[0], P0[0], P1[0]);
-          const unsigned my = brick_mask(b1, g.K[1], P0[1], P1[1]);
-          const unsigned mz = brick_mask(b2, g.K[2], P0[2], P1[2]);
+          const unsigned mx = brick_mask(b0, K[0], P0[0], P1[0]);
+          const unsigned my = brick_mask(b1, K[1], P0[1], P1[1]);
+          const unsigned mz = brick_mask(b2, K[2], P0[2], P1[2]);
           if (mx && my && mz) {
             const float4 pa = pr[s];                 // sorted parameters: .z ligand flag, .w charge
             const int k = atomicAdd(&s_n, 1);
@@ -495,14 +498,14 @@ __global__ __launch_bounds__(256) void k_spread(const LegDev* legs, BlockMap map
             const unsigned m = s_m[k];
             int bb[3];
             unpack_bases(__int_as_float(s_b[k]), bb);
-            int px = bb[0] - ix; if (px < 0) px += g.K[0];
-            int py = bb[1] - iy; if (py < 0) py += g.K[1];
+            int px = bb[0] - ix; if (px < 0) px += K[0];
+            int py = bb[1] - iy; if (py < 0) py += K[1];
             const double qxy = (double)(s_q[k] * s_w[k][ix] * s_w[k][4 + iy]);
             const int row = ((py - P0[1]) * kBrick + (px - P0[0]));
 #pragma unroll
             for (int iz = 0; iz < 4; ++iz) {
               if (!((m >> (8 + iz)) & 1u)) continue;
-              int pz = bb[2] - iz; if (pz < 0) pz += g.K[2];
+              int pz = bb[2] - iz; if (pz < 0) pz += K[2];
               const long long v = __double2ll_rn(qxy * (double)s_w[k][8 + iz] * kGridScale);
               atomicAdd((unsigned long long*)&tile[(pz - P0[2]) * kBrick * kBrick + row], (unsigned long long)v);
             }
@@ -525,7 +528,7 @@ __global__ __launch_bounds__(256) void k_spread(const LegDev* legs, BlockMap map
     const int lx = e % kBrick, ly = (e / kBrick) % kBrick, lz = e / (kBrick * kBrick);
     const int x = P0[0] + lx, y = P0[1] + ly, z = P0[2] + lz;
     if (x >= P1[0] || y >= P1[1] || z >= P1[2]) continue;
-    const size_t off = ((size_t)z * g.K[1] + y) * g.K[0] + x;
+    const size_t off = ((size_t)z * K[1] + y) * K[0] + x;
     cg[2 * off + comp] = (float)((double)tile[e] * (1.0 / kGridScale));
     if (clear_im) cg[2 * off + 1] = 0.f;
   }
@@ -537,6 +540,9 @@ template <bool ENERGY, bool STEP>
 __global__ __launch_bounds__(256) void k_gather(const LegDev* legs, BlockMap map) {
   const int leg = find_leg(map, blockIdx.x);
   const LegDev& g = legs[leg];
+  // grid sizes in scalar registers (otherwise reloaded from memory inside the loops)
+  const int K[3] = {__builtin_amdgcn_readfirstlane(g.K[0]), __builtin_amdgcn_readfirstlane(g.K[1]),
+                    __builtin_amdgcn_readfirstlane(g.K[2])};
   // atoms in the neighbour-list sort order (spatially coherent); 4 lanes per
   // atom, lane iz sums the 16 stencil points of plane z = bz - iz
   const int local = (blockIdx.x - map.start[leg]) * 64 + (threadIdx.x >> 2);   // W N_pad < 2^31
@@ -558,17 +564,17 @@ __global__ __launch_bounds__(256) void k_gather(const LegDev* legs, BlockMap map
   bspline4(st.x, wx, dx);
   bspline4(st.y, wy, dy);
   bspline4(st.z, wz, dz);
-  int gz = bz - iz; if (gz < 0) gz += g.K[2];
+  int gz = bz - iz; if (gz < 0) gz += K[2];
   int gxv[4];
 #pragma unroll
-  for (int ix = 0; ix < 4; ++ix) { gxv[ix] = bx - ix; if (gxv[ix] < 0) gxv[ix] += g.K[0]; }
-  const float2* plane = g.cgrid + (size_t)(g.pack ? w >> 1 : w) * g.Ktot + (size_t)gz * g.K[1] * g.K[0];
+  for (int ix = 0; ix < 4; ++ix) { gxv[ix] = bx - ix; if (gxv[ix] < 0) gxv[ix] += K[0]; }
+  const float2* plane = g.cgrid + (size_t)(g.pack ? w >> 1 : w) * g.Ktot + (size_t)gz * K[1] * K[0];
   const bool im = g.pack && (w & 1);
   float p0 = 0.f, px = 0.f, py = 0.f;          // sum w phi, sum dwx phi, sum dwy phi over the plane
 #pragma unroll
   for (int iy = 0; iy < 4; ++iy) {
-    int gy = by - iy; if (gy < 0) gy += g.K[1];
-    const float2* row = plane + (size_t)gy * g.K[0];
+    int gy = by - iy; if (gy < 0) gy += K[1];
+    const float2* row = plane + (size_t)gy * K[0];
     float s0 = 0.f, s1 = 0.f;
 #pragma unroll
     for (int ix = 0; ix < 4; ++ix) {
@@ -591,9 +597,9 @@ __global__ __launch_bounds__(256) void k_gather(const LegDev* legs, BlockMap map
   const int sub = iz;
   if (valid && sub == 0) {
     const BoxW& B = g.box[w];
-    const float fx = -q * gxs * (float)g.K[0] * B.invLf[0];
-    const float fy = -q * gys * (float)g.K[1] * B.invLf[1];
-    const float fz = -q * gzs * (float)g.K[2] * B.invLf[2];
+    const float fx = -q * gxs * (float)K[0] * B.invLf[0];
+    const float fy = -q * gys * (float)K[1] * B.invLf[1];
+    const float fz = -q * gzs * (float)K[2] * B.invLf[2];
     const int where = (w << 20) | a;
     const long long ix = to_fixed((double)fx, kForceScale, g.err, kSiteGather, where, g.leg_index);
     const long long iy = to_fixed((double)fy, kForceScale, g.err, kSiteGather, where, g.leg_index);
