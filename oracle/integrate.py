@@ -3,6 +3,7 @@
 Section "Simulation protocol": LangevinMiddleIntegrator (Zhang et al. 2019),
 2 fs step, friction 0.5/ps, rigid TIP3P water.  One step, in order:
   v <- v + dt F(x)/m                    (kick)
+  v <- v + M^-1 G^T mu, G v = 0         (velocity constraint of rigid waters)
   x' <- x + dt/2 v                      (half drift)
   v <- a v + sqrt((1 - a^2) kT / m) xi  (Ornstein-Uhlenbeck, a = exp(-gamma dt))
   x' <- x' + dt/2 v                     (half drift)
@@ -86,11 +87,42 @@ def shake_waters(x_old, x_new, waters, mass, d_oh, d_hh, box, tol=1e-12, max_ite
     raise RuntimeError("SHAKE did not converge")
 
 
+def constrain_velocities(x, v, waters, mass, box):
+    """Velocity part of the rigid-water constraints (the RATTLE condition
+    d/dt |r_a - r_b|^2 = 0 for the three distances of every water): each
+    constraint k = (a, b) moves v_a by mu_k r_ab / m_a and v_b by
+    -mu_k r_ab / m_b along its bond vector r_ab = x_a - x_b, with the three
+    multipliers of a water solved exactly from the 3x3 linear system
+    r_k . (v'_a - v'_b) = 0.  The result is the mass-weighted projection of v
+    onto the velocities the rigid molecules allow."""
+    from .pairs import min_image
+    v = np.array(v, np.float64, copy=True)
+    if len(waters) == 0:
+        return v
+    invm = 1.0 / np.asarray(mass, np.float64)
+    cons = [(waters[:, 0], waters[:, 1]), (waters[:, 0], waters[:, 2]), (waters[:, 1], waters[:, 2])]
+    r = [min_image(x[a] - x[b], box) for a, b in cons]                 # (nw, 3) each
+    c = np.stack([(r[k] * (v[a] - v[b])).sum(1) for k, (a, b) in enumerate(cons)], 1)
+    A = np.empty((len(waters), 3, 3))
+    for k, (ak, bk) in enumerate(cons):
+        for l, (al, bl) in enumerate(cons):
+            # rate of constraint k per unit mu_l: r_k . (dv_ak - dv_bk)
+            wa = np.where(ak == al, invm[ak], 0.0) - np.where(ak == bl, invm[ak], 0.0)
+            wb = np.where(bk == al, invm[bk], 0.0) - np.where(bk == bl, invm[bk], 0.0)
+            A[:, k, l] = (r[k] * r[l]).sum(1) * (wa - wb)
+    mu = np.linalg.solve(A, -c[:, :, None])[:, :, 0]
+    for k, (a, b) in enumerate(cons):
+        v[a] += (mu[:, k] * invm[a])[:, None] * r[k]
+        v[b] -= (mu[:, k] * invm[b])[:, None] * r[k]
+    return v
+
+
 def langevin_middle_step(sysd, x, v, force_fn, dt, temperature, gamma, seed, window, step):
     """One step; ``force_fn(x)`` returns (N,3) forces in kcal/mol/A."""
     m = sysd.mass.astype(np.float64)[:, None]
     F = force_fn(x)
     v = v + dt * F * ACCEL / m
+    v = constrain_velocities(x, v, sysd.waters, sysd.mass, sysd.box)
     x1 = x + 0.5 * dt * v
     a = math.exp(-gamma * dt)
     sd = np.sqrt((1.0 - a * a) * KB * temperature * ACCEL / m)
