@@ -1,6 +1,7 @@
 // Langevin-middle step with SETTLE rigid water (section "Simulation protocol":
 // LangevinMiddleIntegrator, rigid TIP3P).  Per window and atom, FP32:
-//   v += dt F/m;  dx = dt/2 v;  v = a v + sqrt((1 - a^2) kT/m) xi;  dx += dt/2 v;
+//   v += dt F/m;  waters: v projected on the molecule's rigid-body motions;
+//   dx = dt/2 v;  v = a v + sqrt((1 - a^2) kT/m) xi;  dx += dt/2 v;
 //   waters: SETTLE on (old, old + dx);  v += (dx_constrained - dx)/dt;  x += dx.
 // Displacements are kept relative to the old positions, so the constraint
 // solve runs on O(1 A) numbers at full FP32 precision.
@@ -91,17 +92,13 @@ __device__ __forceinline__ v3 bonded_force(const LegDev& g, int w, int a) {
   return F;
 }
 
-// kick, half drift, O step, half drift for one atom: returns the total
-// displacement and the post-O velocity
-__device__ __forceinline__ void advance(const LegDev& g, const StepArgs& S, int leg, int w, int a,
-                                        v3& dx, v3& vel) {
+// kick for one atom: returns v + dt F/m.  The total force (real-space terms
+// in fx/fy/fz, this step's reciprocal-space term and the bonded terms) is
+// stored back, so that fx/fy/fz hold the whole force of the step after the
+// call.
+__device__ __forceinline__ v3 kick(const LegDev& g, const StepArgs& S, int w, int a) {
   const size_t o = (size_t)w * g.n + a;
-  const float m = g.mass[a];
-  const float dt = S.dt;
-  const float acc = (float)kAccel / m;
-  // total force: real-space terms in fx/fy/fz, this step's reciprocal-space
-  // term and the bonded terms; the sum is stored back so that fx/fy/fz hold
-  // the whole force of the step after the call
+  const float acc = (float)kAccel / g.mass[a];
   long long tx = g.fx[o] + g.frx[o], ty = g.fy[o] + g.fry[o], tz = g.fz[o] + g.frz[o];
   const v3 fb = bonded_force(g, w, a);
   if (fb.x != 0.f || fb.y != 0.f || fb.z != 0.f) {
@@ -113,7 +110,16 @@ __device__ __forceinline__ void advance(const LegDev& g, const StepArgs& S, int 
   g.fx[o] = tx; g.fy[o] = ty; g.fz[o] = tz;
   const float F[3] = {(float)((double)tx * (1.0 / kForceScale)), (float)((double)ty * (1.0 / kForceScale)),
                       (float)((double)tz * (1.0 / kForceScale))};
-  v3 v = mk(g.vx[o] + dt * F[0] * acc, g.vy[o] + dt * F[1] * acc, g.vz[o] + dt * F[2] * acc);
+  const float dt = S.dt;
+  return mk(g.vx[o] + dt * F[0] * acc, g.vy[o] + dt * F[1] * acc, g.vz[o] + dt * F[2] * acc);
+}
+
+// half drift, O step, half drift from the post-kick velocity v: returns the
+// total displacement and the post-O velocity
+__device__ __forceinline__ void drift_o(const LegDev& g, const StepArgs& S, int leg, int w, int a, v3 v, v3& dx,
+                                        v3& vel) {
+  const float acc = (float)kAccel / g.mass[a];
+  const float dt = S.dt;
   const float hd = 0.5f * dt;
   dx = vmul(v, hd);
   const float ea = expf(-S.gamma * dt);
@@ -122,6 +128,11 @@ __device__ __forceinline__ void advance(const LegDev& g, const StepArgs& S, int 
   v = vadd(vmul(v, ea), vmul(xi, sd));
   dx = vadd(dx, vmul(v, hd));
   vel = v;
+}
+
+__device__ __forceinline__ void advance(const LegDev& g, const StepArgs& S, int leg, int w, int a, v3& dx,
+                                        v3& vel) {
+  drift_o(g, S, leg, w, a, kick(g, S, w, a), dx, vel);
 }
 
 // writes the new position and velocity; returns the squared displacement
@@ -146,14 +157,16 @@ __device__ __forceinline__ float unit_step(const LegDev& g, const StepArgs& S, i
     return store(g, w, a, dx, v);
   }
   const int ao = g.water[3 * u], ah1 = g.water[3 * u + 1], ah2 = g.water[3 * u + 2];
-  v3 dO, dH1, dH2, vO, vH1, vH2;
-  advance(g, S, leg, w, ao, dO, vO);
-  advance(g, S, leg, w, ah1, dH1, vH1);
-  advance(g, S, leg, w, ah2, dH2, vH2);
   const size_t base = (size_t)w * g.n;
   const v3 xo = mk(g.x[base + ao], g.y[base + ao], g.z[base + ao]);
   const v3 b0 = vsub(mk(g.x[base + ah1], g.y[base + ah1], g.z[base + ah1]), xo);
   const v3 c0 = vsub(mk(g.x[base + ah2], g.y[base + ah2], g.z[base + ah2]), xo);
+  v3 kO = kick(g, S, w, ao), kH1 = kick(g, S, w, ah1), kH2 = kick(g, S, w, ah2);
+  rigid_velocity(b0, c0, g.mass[ao], g.mass[ah1], kO, kH1, kH2);
+  v3 dO, dH1, dH2, vO, vH1, vH2;
+  drift_o(g, S, leg, w, ao, kO, dO, vO);
+  drift_o(g, S, leg, w, ah1, kH1, dH1, vH1);
+  drift_o(g, S, leg, w, ah2, kH2, dH2, vH2);
   v3 a1 = dO, b1 = vadd(b0, dH1), c1 = vadd(c0, dH2);
   const v3 a1u = a1, b1u = b1, c1u = c1;
   settle(b0, c0, a1, b1, c1, g.mass[ao], g.mass[ah1], g.d_oh, g.d_hh);

@@ -84,4 +84,41 @@ FELIS_HD inline void settle(v3 b0, v3 c0, v3& a1, v3& b1, v3& c1, float mO, floa
   c1 = vadd(com, vadd(vadd(vmul(ex, xc3), vmul(ey, yc3)), vmul(ez, zc1)));
 }
 
+// Velocity constraint of a rigid water after the kick: the mass-weighted
+// projection of (vO, vH1, vH2) on the molecule's rigid-body motions,
+// v_i = V + omega x r_i with V the centre-of-mass velocity, r_i taken from
+// the centre of mass and I omega = L (inertia tensor and angular momentum
+// about the centre of mass), which is the velocity that keeps all three
+// distances fixed to first order.  b0, c0: H1, H2 relative to O.
+FELIS_HD inline void rigid_velocity(v3 b0, v3 c0, float mO, float mH, v3& vO, v3& vH1, v3& vH2) {
+  const float M = mO + 2.0f * mH;
+  const v3 com = vmul(vadd(b0, c0), mH / M);
+  const v3 rO = vmul(com, -1.0f), r1 = vsub(b0, com), r2 = vsub(c0, com);
+  const v3 V = vmul(vadd(vmul(vO, mO), vmul(vadd(vH1, vH2), mH)), 1.0f / M);
+  const v3 L = vadd(vmul(vcross(rO, vO), mO), vmul(vadd(vcross(r1, vH1), vcross(r2, vH2)), mH));
+  // inertia tensor about the centre of mass
+  float xx = 0.f, yy = 0.f, zz = 0.f, xy = 0.f, xz = 0.f, yz = 0.f;
+  const v3 rr[3] = {rO, r1, r2};
+  const float mm[3] = {mO, mH, mH};
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const v3 r = rr[k];
+    xx += mm[k] * (r.y * r.y + r.z * r.z);
+    yy += mm[k] * (r.x * r.x + r.z * r.z);
+    zz += mm[k] * (r.x * r.x + r.y * r.y);
+    xy -= mm[k] * r.x * r.y;
+    xz -= mm[k] * r.x * r.z;
+    yz -= mm[k] * r.y * r.z;
+  }
+  // omega = I^-1 L by the adjugate of the symmetric tensor
+  const float c00 = yy * zz - yz * yz, c01 = xz * yz - xy * zz, c02 = xy * yz - xz * yy;
+  const float c11 = xx * zz - xz * xz, c12 = xy * xz - xx * yz, c22 = xx * yy - xy * xy;
+  const float idet = 1.0f / (xx * c00 + xy * c01 + xz * c02);
+  const v3 om = mk((c00 * L.x + c01 * L.y + c02 * L.z) * idet, (c01 * L.x + c11 * L.y + c12 * L.z) * idet,
+                   (c02 * L.x + c12 * L.y + c22 * L.z) * idet);
+  vO = vadd(V, vcross(om, rO));
+  vH1 = vadd(V, vcross(om, r1));
+  vH2 = vadd(V, vcross(om, r2));
+}
+
 }  // namespace felis

@@ -151,6 +151,48 @@ extern "C" void settle_many(int n, const float* old, float* nw, float mO, float 
     assert np.max(np.abs(r - s.d_oh)) < 1e-5
 
 
+def test_rigid_velocity_matches_oracle_constraint():
+    """The integrator's velocity constraint of a rigid water (rigid-body
+    projection, FP32, compiled for the host) against the oracle's RATTLE
+    multipliers solved in FP64."""
+    from oracle.integrate import constrain_velocities
+    from paper_2603_22274_amd import gen
+    shim = r'''
+#include "settle.h"
+extern "C" void project_many(int n, const float* x, float* v, float mO, float mH) {
+  for (int i = 0; i < n; ++i) {
+    const float* o = x + 9 * i; float* p = v + 9 * i;
+    felis::v3 b0 = felis::mk(o[3] - o[0], o[4] - o[1], o[5] - o[2]);
+    felis::v3 c0 = felis::mk(o[6] - o[0], o[7] - o[1], o[8] - o[2]);
+    felis::v3 a = felis::mk(p[0], p[1], p[2]), b = felis::mk(p[3], p[4], p[5]), c = felis::mk(p[6], p[7], p[8]);
+    felis::rigid_velocity(b0, c0, mO, mH, a, b, c);
+    p[0] = a.x; p[1] = a.y; p[2] = a.z; p[3] = b.x; p[4] = b.y; p[5] = b.z; p[6] = c.x; p[7] = c.y; p[8] = c.z;
+  }
+}
+'''
+    s = gen.config0()
+    rng = np.random.default_rng(1)
+    W = s.waters[:64]
+    x = np.ascontiguousarray(s.pos[W], np.float32)              # (64, 3, 3)
+    v = np.ascontiguousarray(rng.normal(0, 8.0, x.shape), np.float32)
+    with tempfile.TemporaryDirectory() as d:
+        cpp = os.path.join(d, 'p.cpp')
+        open(cpp, 'w').write(shim)
+        so = os.path.join(d, 'p.so')
+        subprocess.run(['g++', '-O2', '-shared', '-fPIC', '-I',
+                        os.path.join(ROOT, 'paper_2603_22274_amd', 'csrc'), cpp, '-o', so], check=True)
+        lib = C.CDLL(so)
+        got = v.copy()
+        lib.project_many(len(W), x.ctypes.data_as(C.c_void_p), got.ctypes.data_as(C.c_void_p),
+                         C.c_float(s.mass[W[0, 0]]), C.c_float(s.mass[W[0, 1]]))
+    wat = np.arange(3 * len(W)).reshape(-1, 3)
+    mass = np.tile(s.mass[W[0]], len(W))
+    ref = constrain_velocities(x.reshape(-1, 3).astype(np.float64), v.reshape(-1, 3).astype(np.float64), wat,
+                               mass, np.array([1e4] * 3))
+    err = np.abs(got.reshape(-1, 3) - ref).max() / np.abs(ref).max()
+    assert err < 2e-6, err
+
+
 def test_restraint_term_matches_oracle_on_the_host():
     """felis_restraint_dg is host arithmetic: it runs without a device."""
     import math
