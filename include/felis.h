@@ -155,9 +155,14 @@ int felis_leg_init(felis_ctx* ctx, felis_leg* leg);
 /* Neighbour lists (appendix B cutoffs; list radius r_cut + skin).  Per window,
  * atoms are sorted along a Hilbert curve of fine cells and grouped into
  * 8-atom clusters; each cluster lists every atom j with, for each of its atoms
- * i, a bit: |d_ij| < r_cut + skin in FP64 minimum image, j != i, (i, j) not
- * excluded.  With force = 0 only windows whose atoms moved more than skin/2
- * since their last build are rebuilt; force = 1 rebuilds all. */
+ * i, a bit that is set when j != i, (i, j) is not excluded and the FP32
+ * minimum-image distance is below r_cut + skin + 0.01 A.  The 0.01 A margin
+ * is far above the FP32 error of the distance, so the listed pairs are a
+ * superset of the exact set {|d_ij| < r_cut + skin in FP64}; the pair kernel
+ * applies the cutoff r_cut itself, and felis_nlist_export_pairs applies the
+ * FP64 test to give the exact set.  With force = 0 only windows whose atoms
+ * moved more than skin/2 since their last build are rebuilt; force = 1
+ * rebuilds all. */
 int felis_build_nlist(felis_ctx* ctx, felis_leg* legs, int n_legs, int force);
 
 /* Neighbour-list builds of each window since felis_leg_init (forced builds
@@ -165,10 +170,13 @@ int felis_build_nlist(felis_ctx* ctx, felis_leg* legs, int n_legs, int force);
 int felis_leg_rebuilds(felis_ctx* ctx, const felis_leg* leg, int64_t* counts);
 
 /* Test/diagnostic export of window `window`'s list: every pair (i < j) whose
- * list bit is set and whose FP64 minimum-image distance is < r (pass
- * r >= r_cut + skin for the whole list) is written to pairs[2 k], pairs[2 k + 1]
- * (dev, capacity `cap` pairs, unordered); *n_pairs receives the count (also
- * when it exceeds cap, then FELIS_E_CAPACITY).  Synchronises. */
+ * list bit is set and whose FP64 minimum-image distance (dx = x_j - x_i,
+ * dx -= L rint(dx / L) as a separate multiply and subtract, d^2 = (dx^2 +
+ * dy^2) + dz^2, no contraction) is < r is written to pairs[2 k],
+ * pairs[2 k + 1] (dev, capacity `cap` pairs, unordered).  With r = r_cut +
+ * skin the result is the exact FP64 list.  *n_pairs receives the count (also
+ * when it exceeds cap, then FELIS_E_CAPACITY; cap = 0 with pairs = NULL only
+ * counts).  Synchronises. */
 int felis_nlist_export_pairs(felis_ctx* ctx, const felis_leg* leg, int window, double r,
                              int32_t* pairs, int64_t cap, int64_t* n_pairs);
 
@@ -180,8 +188,14 @@ int felis_nlist_export_pairs(felis_ctx* ctx, const felis_leg* leg, int window, d
  * components COUL_REAL, LJ, EXCL, SELF and TOTAL are written. */
 int felis_nonbonded(felis_ctx* ctx, felis_leg* legs, int n_legs, int flags);
 
-/* PME reciprocal space (order-4 B-spline spreading, 3D FFT, influence function,
- * gather); forces are ADDED; with FELIS_ENERGY writes RECIP and TOTAL.
+/* PME reciprocal space, the long-range part of the electrostatics that
+ * appendix B cuts at 1 nm in real space (the paper names PME and prints no
+ * formula; this is smooth PME of Essmann et al. 1995): charges (ligand ones
+ * scaled by lambda_elec, section "Double annihilation protocol") spread with
+ * order-4 cardinal B-splines, 3D FFT, the influence function
+ * exp(-pi^2 m^2 / alpha^2) / (pi V m^2) times the B-spline moduli, inverse FFT
+ * and gather; E_rec = (KE / 2) sum_m G(m) |F(Q)(m)|^2.  Forces are ADDED;
+ * with FELIS_ENERGY writes RECIP and TOTAL.
  * Spreading locates atoms through the neighbour-list cell sort, so this call
  * first rebuilds the lists of windows that moved more than skin/2 (as
  * felis_build_nlist with force = 0 does). */
@@ -206,7 +220,12 @@ int felis_bonded(felis_ctx* ctx, felis_leg* legs, int n_legs, int flags);
 int felis_step(felis_ctx* ctx, felis_leg* legs, int n_legs, int n_steps, double dt,
                double temperature, double gamma);
 
-/* Reduced potentials of n_frames frames of one leg at K lambda states:
+/* Reduced potentials of n_frames frames of one leg at K lambda states, the
+ * input MBAR needs for each segment's free energy (section "Simulation
+ * protocol"); the lambda dependence follows section "Double annihilation
+ * protocol" (charges scaled by lambda_elec, so ligand-environment terms scale
+ * as lambda_elec and ligand-ligand terms as lambda_elec^2; softcore LJ at
+ * lambda_vdw) and section "Restraints" (Boresch energy x lambda_restraint):
  * u[k * u_stride + f] = beta [lam_e E_LE + lam_e^2 E_LL + E_sc(lam_v) + lam_r U_B + P V_f]
  * (lambda-independent terms dropped; MBAR is invariant to them; the P V term
  * only for legs with pressure_bar > 0).  Frame f's coordinates are
@@ -290,6 +309,31 @@ int felis_leg_states(felis_ctx* ctx, const felis_leg* leg, int32_t* state_of_rep
  * 0 < thA0, thB0 < pi and temperature > 0. */
 int felis_restraint_dg(const double* g0, const double* k, double temperature, double* dg);
 
+/* A leg's (or segment's) free-energy difference from MBAR's dimensionless
+ * free energies (section "Simulation protocol"): *dg = kT (f[K-1] - f[0])
+ * kcal/mol, the decoupling direction when the leg's windows run from the
+ * coupled to the decoupled state.  f (host) [K].  Host arithmetic only.
+ * FELIS_E_INVAL unless K >= 2, temperature > 0 and f is finite. */
+int felis_delta_g(const double* f, int K, double temperature, double* dg);
+
+/* Boundary windows of n_segments overlapping segments of a leg of n_windows
+ * windows (section "Simulation protocol": each GPU runs a segment of the
+ * path, neighbouring segments duplicate their boundary window): segment s
+ * spans windows first[s] .. first[s + 1], first[s] = floor(s (n_windows - 1)
+ * / n_segments); first (host) [n_segments + 1].  FELIS_E_INVAL unless every
+ * segment gets at least two windows. */
+int felis_segment_bounds(int n_windows, int n_segments, int32_t* first);
+
+/* Binding free energy (figure 1, section "Restraints"): the leg free
+ * energies are the sums of their segments' differences (host arrays of
+ * n_solvent and n_complex values, each from felis_delta_g), and
+ *   dG_bind = dG_solvent - dG_complex + dG_restrain,
+ * with dG_restrain from felis_restraint_dg(g0, k, temperature).  Host
+ * arithmetic only; errors as felis_restraint_dg, FELIS_E_INVAL for empty
+ * segment lists or non-finite values. */
+int felis_binding_dg(const double* dg_solvent_segments, int n_solvent, const double* dg_complex_segments,
+                     int n_complex, const double* g0, const double* k, double temperature, double* dg_bind);
+
 /* Kernel timing with HIP events recorded on the context's stream around the
  * launches of one stage inside felis_step / felis_ukn (the events bracket
  * exactly the stage's kernels, so their elapsed time is the stage's device
@@ -326,7 +370,8 @@ int felis_mbar_work_size(int K, int64_t n_total, size_t* bytes);
  * and N_k (host, samples drawn from each state; only the counts matter, not
  * the column order).  Solves the MBAR equations by Newton's method on their
  * convex objective (self-consistent steps where the Newton system is
- * singular) until the last step satisfies max|df| <= rel_tol * max(1, max|f|);
+ * singular, a backtracking line search while steps are large) until the full
+ * (undamped) step of an iteration satisfies max|df| <= rel_tol * max(1, max|f|);
  * states with N_k = 0 follow from the converged denominators.  f_out (host)
  * [K] dimensionless free energies, gauge f_0 = 0; *iters the Newton
  * iterations used.  FELIS_E_NOCONV at max_iter or on a non-finite result.

@@ -931,6 +931,33 @@ int felis_restraint_dg(const double* g0, const double* k, double temperature, do
   return FELIS_OK;
 }
 
+int felis_delta_g(const double* f, int K, double temperature, double* dg) {
+  if (!f || !dg || K < 2 || !(temperature > 0) || !std::isfinite(temperature)) return FELIS_E_INVAL;
+  if (!std::isfinite(f[0]) || !std::isfinite(f[K - 1])) return FELIS_E_INVAL;
+  *dg = kKB * temperature * (f[K - 1] - f[0]);
+  return FELIS_OK;
+}
+
+int felis_segment_bounds(int n_windows, int n_segments, int32_t* first) {
+  if (!first || n_segments < 1 || n_windows < n_segments + 1) return FELIS_E_INVAL;
+  for (int s = 0; s <= n_segments; ++s) first[s] = (int32_t)(((long long)s * (n_windows - 1)) / n_segments);
+  return FELIS_OK;
+}
+
+int felis_binding_dg(const double* dg_solvent_segments, int n_solvent, const double* dg_complex_segments,
+                     int n_complex, const double* g0, const double* k, double temperature, double* dg_bind) {
+  if (!dg_solvent_segments || !dg_complex_segments || !dg_bind || n_solvent < 1 || n_complex < 1)
+    return FELIS_E_INVAL;
+  double solv = 0.0, cplx = 0.0, rest = 0.0;
+  for (int i = 0; i < n_solvent; ++i) solv += dg_solvent_segments[i];
+  for (int i = 0; i < n_complex; ++i) cplx += dg_complex_segments[i];
+  if (!std::isfinite(solv) || !std::isfinite(cplx)) return FELIS_E_INVAL;
+  const int rc = felis_restraint_dg(g0, k, temperature, &rest);
+  if (rc) return rc;
+  *dg_bind = solv - cplx + rest;
+  return FELIS_OK;
+}
+
 int felis_profile(felis_ctx* c, int enable) {
   if (!c) return FELIS_E_INVAL;
   c->prof = enable == 1 ? (1 << FELIS_PROF_N) - 1 : (enable & ((1 << FELIS_PROF_N) - 1));

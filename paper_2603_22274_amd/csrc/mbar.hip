@@ -299,7 +299,9 @@ int launch_mbar(hipStream_t s, const double* u, const int* N_k, int K, long long
       f[k] += t * step[k];
       fmaxv = std::fmax(fmaxv, std::fabs(f[k]));
     }
-    if (t * smax <= tol * std::fmax(1.0, fmaxv)) { done = true; break; }
+    // converged only when the full (undamped) step is within the tolerance:
+    // a step the line search cut short says nothing about the distance left
+    if (smax <= tol * std::fmax(1.0, fmaxv)) { done = true; break; }
   }
   // unsampled states from the final denominators, then the gauge f_0 = 0
   int rc = evaluate(s, u, w, K, N, f, Nk, true, ev);

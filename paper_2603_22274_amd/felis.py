@@ -78,6 +78,9 @@ def lib():
         'felis_leg_rebuilds': (C.c_int, [vp, P(FelisLeg), vp]),
         'felis_leg_states': (C.c_int, [vp, P(FelisLeg), vp]),
         'felis_restraint_dg': (C.c_int, [vp, vp, C.c_double, P(C.c_double)]),
+        'felis_delta_g': (C.c_int, [vp, C.c_int, C.c_double, P(C.c_double)]),
+        'felis_segment_bounds': (C.c_int, [C.c_int, C.c_int, vp]),
+        'felis_binding_dg': (C.c_int, [vp, C.c_int, vp, C.c_int, vp, vp, C.c_double, P(C.c_double)]),
         'felis_hrex': (C.c_int, [vp, P(FelisLeg), vp, C.c_int64, C.c_int64, C.c_uint64, vp]),
         'felis_barostat': (C.c_int, [vp, P(FelisLeg), C.c_int, C.c_double, C.c_int64]),
         'felis_leg_boxes': (C.c_int, [vp, P(FelisLeg), vp]),
@@ -327,6 +330,42 @@ def restraint_dg(g0, k, temperature=300.0):
     return out.value
 
 
+def delta_g(f, temperature=300.0):
+    """kT (f[-1] - f[0]) in kcal/mol from MBAR's free energies (library arithmetic)."""
+    ff = np.ascontiguousarray(f, np.float64)
+    out = C.c_double(0.0)
+    rc = lib().felis_delta_g(ff.ctypes.data_as(C.c_void_p), len(ff), float(temperature), C.byref(out))
+    if rc:
+        raise FelisError(rc, 'delta_g: at least two finite free energies and a positive temperature')
+    return out.value
+
+
+def segment_bounds(n_windows, n_segments):
+    """First window of each segment and the last window of the leg (numpy int32, n_segments + 1)."""
+    out = np.zeros(n_segments + 1, np.int32)
+    rc = lib().felis_segment_bounds(int(n_windows), int(n_segments), out.ctypes.data_as(C.c_void_p))
+    if rc:
+        raise FelisError(rc, 'every segment needs at least two windows')
+    return out
+
+
+def binding_dg(dg_solvent_segments, dg_complex_segments, g0, k, temperature=300.0):
+    """dG_bind = sum(solvent segments) - sum(complex segments) + dG_restrain (library arithmetic)."""
+    a = np.ascontiguousarray(np.atleast_1d(dg_solvent_segments), np.float64)
+    b = np.ascontiguousarray(np.atleast_1d(dg_complex_segments), np.float64)
+    g = np.ascontiguousarray(g0, np.float64)
+    kk = np.ascontiguousarray(k, np.float64)
+    if g.shape != (6,) or kk.shape != (6,):
+        raise ValueError('six restraint geometries and force constants')
+    out = C.c_double(0.0)
+    rc = lib().felis_binding_dg(a.ctypes.data_as(C.c_void_p), len(a), b.ctypes.data_as(C.c_void_p), len(b),
+                                g.ctypes.data_as(C.c_void_p), kk.ctypes.data_as(C.c_void_p), float(temperature),
+                                C.byref(out))
+    if rc:
+        raise FelisError(rc, 'binding_dg: invalid segment values, restraint geometry or temperature')
+    return out.value
+
+
 def barostat(ctx, legs, temperature, attempt):
     """One Monte Carlo volume move now for every leg of ``legs`` that has a
     pressure (the others are evaluated but unchanged)."""
@@ -380,6 +419,16 @@ def nlist_export_pairs(ctx, leg, window, r=None, cap=None):
     p = buf[: n.value].cpu().numpy().astype(np.int64)
     order = np.lexsort((p[:, 1], p[:, 0]))
     return p[order]
+
+
+def nlist_count_pairs(ctx, leg, window, r=None):
+    """Number of listed pairs (i < j) with FP64 distance < r (nothing is copied)."""
+    r = leg.sys.r_list if r is None else r
+    n = C.c_int64(0)
+    rc = lib().felis_nlist_export_pairs(ctx.h, C.byref(leg.s), window, r, None, 0, C.byref(n))
+    if rc not in (OK, E_CAPACITY):
+        ctx.check(rc)
+    return int(n.value)
 
 
 def nonbonded(ctx, legs, energy=True):

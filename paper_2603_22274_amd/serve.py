@@ -272,7 +272,7 @@ class FelisEngine:
         u = h.u[:, :h.k * W]
         try:
             fe, it = f.mbar(self.ctx, u, np.full(W, h.k), tol=self.tol, max_iter=self.max_iter)
-            return float((fe[-1] - fe[0]) / self.beta), it, True
+            return f.delta_g(fe, self.T), it, True
         except f.FelisError as e:
             if e.code != f.E_NOCONV:
                 raise LegFailed(str(e))

@@ -193,6 +193,30 @@ extern "C" void project_many(int n, const float* x, float* v, float mO, float mH
     assert err < 2e-6, err
 
 
+def test_free_energy_assembly_on_the_host():
+    """felis_delta_g, felis_segment_bounds and felis_binding_dg (host
+    arithmetic, no device) against the oracle's estimator."""
+    import math
+    from oracle import estimator as oest
+    from paper_2603_22274_amd import felis
+    rng = np.random.default_rng(9)
+    f = rng.normal(0, 20, 11)
+    assert math.isclose(felis.delta_g(f, 310.0), oest.KB * 310.0 * (f[-1] - f[0]), rel_tol=1e-15)
+    for W, n in ((42, 3), (73, 8), (12, 1), (80, 79)):
+        b = felis.segment_bounds(W, n)
+        segs = [list(range(int(b[s]), int(b[s + 1]) + 1)) for s in range(n)]
+        assert segs == oest.segments(W, n)
+    g0, k = np.array([6.0, 1.4, 1.7, 0.3, -1.0, 2.0]), np.array([10.0, 100, 100, 100, 100, 100])
+    sol, cpx = [1.5, -2.25, 0.5], [3.0, 4.5]
+    got = felis.binding_dg(sol, cpx, g0, k, 300.0)
+    ref = oest.binding_dg(sum(sol), sum(cpx), oest.boresch_restraint_dg(g0, k, 300.0))
+    assert math.isclose(got, ref, rel_tol=1e-13)
+    for bad in (lambda: felis.delta_g([1.0], 300.0), lambda: felis.segment_bounds(3, 3),
+                lambda: felis.binding_dg([], cpx, g0, k), lambda: felis.delta_g([0.0, np.nan], 300.0)):
+        with pytest.raises(felis.FelisError):
+            bad()
+
+
 def test_restraint_term_matches_oracle_on_the_host():
     """felis_restraint_dg is host arithmetic: it runs without a device."""
     import math

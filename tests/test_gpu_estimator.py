@@ -45,7 +45,8 @@ def test_segmented_dg_and_binding_assembly(F):
             felis.ukn(ctx, leg, s.lambdas[w], leg.x, leg.y, leg.z, BETA, out=u[:, t * W:(t + 1) * W])
     ctx.device_check()
     nks = [np.full(len(w), n_samples) for w in segs]
-    got = estimator.segmented_dg(ctx, us, nks, T)
+    seg_dgs = estimator.segment_dgs(ctx, us, nks, T)
+    got = sum(seg_dgs)
     ref = oest.segmented_dg([u.cpu().numpy() for u in us], nks, T)
     assert np.isfinite(got) and abs(got - ref) <= 1e-6, (got, ref)
     # each segment on its own as well
@@ -54,6 +55,6 @@ def test_segmented_dg_and_binding_assembly(F):
         b = oest.segmented_dg([u.cpu().numpy()], [nk], T)
         assert abs(a - b) <= 1e-6, (a, b)
     dg_solv = 3.7
-    bind = estimator.binding_dg(dg_solv, got, s.restraint_g0, s.restraint_k, T)
+    bind = estimator.binding_dg([dg_solv], seg_dgs, s.restraint_g0, s.restraint_k, T)
     ref_bind = oest.binding_dg(dg_solv, ref, oest.boresch_restraint_dg(s.restraint_g0, s.restraint_k, T))
     assert abs(bind - ref_bind) <= 1e-6, (bind, ref_bind)
