@@ -7,6 +7,9 @@ P2-P1-L1-L2, P1-L1-L2-L3 and L1-P1-P2-P3.  Distance and angle terms use
 by lambda_restraint (appendix B schedules).
 
 Harmonic chain bonds use (k/2)(r - r0)^2 (the same harmonic convention).
+Rotatable ligand torsions (section "Double annihilation protocol": periodic
+torsions of rotatable bonds scaled linearly by the alchemical parameter, here
+lambda_vdw) use lambda_vdw k [1 + cos(n phi - delta)].
 Dihedral: phi(a,b,c,d) = atan2(|b2| b1.(b2 x b3), (b1 x b2).(b2 x b3)) with
 b1 = b - a, b2 = c - b, b3 = d - c.  All vectors use the minimum image.
 """
@@ -96,3 +99,24 @@ def boresch(pos, sysd, lam_rest):
         for i, gg in zip(quad, (ga, gb, gc, gd)):
             f[i] -= dE * gg
     return lam_rest * e, lam_rest * f
+
+
+def torsions(pos, sysd, lam_vdw):
+    """lambda_vdw * sum_t k_t [1 + cos(n_t phi_t - delta_t)] over the leg's
+    rotatable torsions, and its forces (zero when the leg has none)."""
+    x = np.asarray(pos, dtype=np.float64)
+    f = np.zeros_like(x)
+    if sysd.torsions is None or len(sysd.torsions) == 0 or lam_vdw == 0.0:
+        return 0.0, f
+    e = 0.0
+    for t, quad in enumerate(sysd.torsions):
+        quad = [int(a) for a in quad]
+        k = float(sysd.torsion_k[t])
+        n = float(sysd.torsion_n[t])
+        dl = float(sysd.torsion_phase[t])
+        phi, ga, gb, gc, gd = _dihedral_grad(*(x[i] for i in quad), sysd.box)
+        e += k * (1.0 + np.cos(n * phi - dl))
+        dE = -k * n * np.sin(n * phi - dl)
+        for i, gg in zip(quad, (ga, gb, gc, gd)):
+            f[i] -= dE * gg
+    return lam_vdw * e, lam_vdw * f

@@ -38,8 +38,9 @@ def window_energy(sysd, pos, lam, recip='pme', pme=None):
     e['recip'] = er
     f = f + fr
     eb, fb = bonded.bonds(x, sysd)
-    e['bond'] = eb
-    f = f + fb
+    et, ft = bonded.torsions(x, sysd, lam[1])
+    e['bond'] = eb + et                  # bonded: harmonic bonds + lambda-scaled rotatable torsions
+    f = f + fb + ft
     erest, frest = bonded.boresch(x, sysd, lam[2])
     e['restraint'] = erest
     f = f + frest

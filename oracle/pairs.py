@@ -29,8 +29,16 @@ def min_image(d, box):
 
 
 def scaled_charges(sysd, lam_elec):
+    """Charges of a window: ligand charges times lambda_elec (section "Double
+    annihilation protocol"); the oxygens of the alchemical waters take up
+    (1 - lambda_elec) of their offset, which keeps the net charge of every
+    window that of the coupled state (same section)."""
     q = sysd.charge.astype(np.float64)
-    return np.where(sysd.is_ligand.astype(bool), q * lam_elec, q)
+    q = np.where(sysd.is_ligand.astype(bool), q * lam_elec, q)
+    off = getattr(sysd, 'alch_offset', None)
+    if off is not None:
+        q = q + (1.0 - lam_elec) * off.astype(np.float64)
+    return q
 
 
 def _excl_keys(sysd):
@@ -61,6 +69,30 @@ def neighbor_pairs(pos, box, sysd, r):
         keep = ~np.isin(k, keys)
         out.append(np.stack([ii[keep], jj[keep]], 1))
     p = np.concatenate(out) if out else np.zeros((0, 2), np.int64)
+    order = np.lexsort((p[:, 1], p[:, 0]))
+    return p[order].astype(np.int64)
+
+
+def neighbor_pairs_tree(pos, box, sysd, r, margin=1e-3):
+    """The canonical list of ``neighbor_pairs`` for large systems: candidate
+    pairs within r + margin from a periodic k-d tree (a library search over
+    the coordinates wrapped into the box), then exactly the same FP64
+    inclusion test, exclusion filter and ordering as the brute force."""
+    from scipy.spatial import cKDTree
+    x = np.asarray(pos, dtype=np.float64)
+    n = len(x)
+    box = np.asarray(box, np.float64)
+    wrapped = np.mod(x, box)
+    wrapped[wrapped >= box] = 0.0
+    cand = cKDTree(wrapped, boxsize=box).query_pairs(r + margin, output_type='ndarray').astype(np.int64)
+    ii = np.minimum(cand[:, 0], cand[:, 1])
+    jj = np.maximum(cand[:, 0], cand[:, 1])
+    d = min_image(x[jj] - x[ii], box)
+    d2 = (d[:, 0] * d[:, 0] + d[:, 1] * d[:, 1]) + d[:, 2] * d[:, 2]
+    m = d2 < r * r
+    ii, jj = ii[m], jj[m]
+    keep = ~np.isin(ii * n + jj, _excl_keys(sysd))
+    p = np.stack([ii[keep], jj[keep]], 1)
     order = np.lexsort((p[:, 1], p[:, 0]))
     return p[order].astype(np.int64)
 

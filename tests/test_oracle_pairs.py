@@ -77,6 +77,17 @@ def test_neighbor_list_matches_kdtree():
         assert {tuple(p) for p in got.tolist()} == ref
 
 
+def test_tree_list_equals_brute_force():
+    """The k-d tree candidate form of the canonical list is the brute-force
+    list itself (identical FP64 test), on jittered coordinates of two systems."""
+    for s in (gen.config0(), gen.small_complex()):
+        rng = np.random.default_rng(4)
+        x = (s.pos + rng.normal(0, 0.05, s.pos.shape)).astype(np.float32)
+        a = pairs.neighbor_pairs(x, s.box, s, s.r_list)
+        b = pairs.neighbor_pairs_tree(x, s.box, s, s.r_list)
+        assert a.shape == b.shape and np.array_equal(a, b)
+
+
 def test_sampled_atoms_match_full_sum():
     s = gen.config0()
     lam = s.lambdas[7]
