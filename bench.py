@@ -1,25 +1,37 @@
 """Throughput of the alchemical-window hot path on one MI355X.
 
-Workload: the 20-window solvent leg (2,500 seeded-orientation 3-site waters in
-a 42 A box plus a 40-atom ligand; cutoff 10 A, skin 1 A, PME 48^3 order 4;
-8 electrostatic then 12 vdW windows), all windows batched in every launch.
+Headline workload: the 42-window complex leg (a 5,000-atom chain protein, a
+50-atom ligand held by a Boresch restraint, 4 Na+/4 Cl- and 21,823 waters in
+an 88 A box: 70,527 atoms; cutoff 10 A, skin 1 A, PME 96^3 order 4; 12
+restraint, 10 electrostatic and 20 vdW windows), every window batched in
+every launch.  The smaller 20-window solvent leg is available with
+``--workload solvent20``.
 
-One bench step = one pass of the whole hot path over the batch: `--md` Langevin
--middle steps of 2 fs for every window (list check/rebuild, real-space pair
-kernel, PME, bonded terms, integrator with SETTLE), then the reduced
-potentials u_kn of every window's current frame at all 20 states.  After the
-timed steps, MBAR solves the collected u_kn (inside the timed region).
+One bench step = one pass of the whole hot path over the batch: ``--md``
+Langevin-middle steps of 2 fs for every window (list check/rebuild, real-space
+pair kernel, PME, bonded and restraint terms, integrator with SETTLE), then
+the reduced potentials u_kn of every window's current frame at all states.
+After the timed steps MBAR solves the collected u_kn (inside the timed
+region).
+
+The throughput counts only if the run's free energy is right: after the timed
+region, the frames that a segment of neighbouring windows produced are handed
+to the FP64 oracle (its own u_kn and MBAR, on the host cores), and |ddG|
+between the GPU's segment Delta G (GPU u_kn + GPU MBAR on the same frames) and
+the oracle's must be <= 0.01 kcal/mol, else ``value`` is reported as 0.
 
 Prints one JSON line: aggregate ns.windows/day, the pair kernel's roofline
-(FP32 ALU bound; algorithmic flops from in-cutoff pairs; duration from HIP
-events recorded around the kernel inside the timed region), the FP64 oracle
-timed on the host as the CPU baseline, and the unbatched per-window form of
-the same leg for comparison.
+(FP32 ALU bound; algorithmic flops = unique in-cutoff pairs x 60; duration
+from HIP events recorded around the kernel inside the timed region), the FP64
+oracle timed on the host as the CPU baseline, the plain per-window form of
+the same leg, and a served stream of uneven legs with its p50/p99 latency.
 """
 from __future__ import annotations
 
 import argparse
 import json
+import math
+import multiprocessing as mp
 import os
 import sys
 import time
@@ -35,15 +47,26 @@ KB = 0.0019872043
 DT = 0.002                      # ps
 PEAK_FP32 = 157.3               # TFLOP/s, MI355X FP32 vector (published; counts packed FP32)
 ISSUE_FP32 = 78.6               # TFLOP/s, non-packed FP32 issue: 256 CU x 4 SIMD x 16 lanes x 2 x 2.4 GHz
-FLOP_PER_PAIR = 75              # FP32 flops per in-cutoff pair (FMA = 2)
+FLOP_PER_PAIR = 60              # FP32 flops per unique in-cutoff pair (FMA = 2)
+PAIR_BYTES_PER_ATOM = 56        # algorithmic HBM bytes per atom-window of one pair launch:
+                                # coordinates + charge (16) and parameters (16) read, 3 int64 forces written
 PAIR_SAMPLE = 5                 # the timed region brackets every 5th pair-kernel launch with HIP events
-TRAFFIC_FILE = os.path.join(ROOT, 'profiles', 'pairs_traffic_solvent20.json')
+DDG_TOL = 0.01                  # kcal/mol
+TRAFFIC_FILES = {'complex42': os.path.join(ROOT, 'profiles', 'pairs_traffic_complex42.json'),
+                 'solvent20': os.path.join(ROOT, 'profiles', 'pairs_traffic_solvent20.json')}
 
 
-def _traffic():
+def _workers():
+    """Host worker processes for the oracle: the machine's CPU share (at most 15
+    besides this process)."""
+    n = len(os.sched_getaffinity(0)) if hasattr(os, 'sched_getaffinity') else (os.cpu_count() or 1)
+    return max(1, min(15, n - 1))
+
+
+def _traffic(workload):
     try:
-        t = json.load(open(TRAFFIC_FILE))
-    except (OSError, ValueError):
+        t = json.load(open(TRAFFIC_FILES[workload]))
+    except (OSError, ValueError, KeyError):
         return None
     from paper_2603_22274_amd.profiling import src_digest
     if t.get('kernel_digest') != src_digest():
@@ -51,52 +74,130 @@ def _traffic():
     return t.get('bytes_per_launch')
 
 
-def cpu_baseline(sysd, windows=(0, 5, 9, 14, 19)):
-    """Window-steps of the FP64 oracle (forces by brute force + PME, one
-    Langevin-middle step) on one host thread (library thread pools limited to
-    one), a bounded sample of ~10 s; scaled to ns.windows/day."""
+# ---- host workers (spawned processes; they import numpy, scipy and the oracle only)
+
+_W = {}
+
+
+def _init_worker(sysd):
+    os.environ['OMP_NUM_THREADS'] = '1'
     from threadpoolctl import threadpool_limits
-    from oracle import energy as oenergy, integrate as ointeg
     from oracle.ewald import PME
-    pme = PME(sysd.box, sysd.grid, sysd.ewald_alpha)
+    _W['limit'] = threadpool_limits(limits=1)
+    _W['sys'] = sysd
+    _W['pme'] = PME(sysd.box, sysd.grid, sysd.ewald_alpha)
+
+
+def _ukn_task(args):
+    pos, lambdas, beta = args
+    from oracle import ukn as oukn
+    return oukn.ukn_frame(_W['sys'], pos.astype(np.float64), lambdas, beta, _W['pme'])
+
+
+def _rsa_task(args):
+    pos, lam, atoms = args
+    from oracle import pairs as opairs
+    t0 = time.perf_counter()
+    opairs.real_space_atoms(pos.astype(np.float64), _W['sys'], lam, atoms)
+    return time.perf_counter() - t0
+
+
+def _gen_task(spec):
+    from paper_2603_22274_amd import gen
+    n, w, seed = spec
+    return gen.sized_leg(n, w, seed)
+
+
+def _pool(sysd, n):
+    return mp.get_context('spawn').Pool(n, initializer=_init_worker, initargs=(sysd,))
+
+
+def ddg_check(sysd, frames, states, seg, u_gpu, beta, ctx, felis, nproc):
+    """|ddG| of the segment ``seg`` (consecutive window indices) between
+    GPU u_kn + GPU MBAR and oracle u_kn + oracle MBAR on the same frames.
+    frames: (n, N, 3) float32 host array; states: the state each frame was
+    sampled in; u_gpu: (K_all, n) device tensor of the frames' GPU u_kn."""
+    import torch
+    from oracle import mbar as ombar
+    lam = sysd.lambdas[seg]
+    t0 = time.perf_counter()
+    with _pool(sysd, nproc) as p:
+        ref = np.stack(p.map(_ukn_task, [(f, lam, beta) for f in frames], chunksize=1), 1)
+    t_or = time.perf_counter() - t0
+    N_k = np.array([(states == s).sum() for s in seg])
+    ug = u_gpu[seg].contiguous()
+    f_gpu, it_gpu = felis.mbar(ctx, ug, N_k, tol=1e-12, max_iter=20000)
+    f_ref, it_ref = ombar.mbar(ref, N_k, tol=1e-12, max_iter=2000000)
+    dg_gpu = felis.delta_g(f_gpu, 300.0)
+    dg_ref = float((f_ref[-1] - f_ref[0]) / beta)
+    du = (ug.cpu().numpy() - ug.cpu().numpy()[0]) - (ref - ref[0])
+    return {"segment_windows": [int(s) for s in seg], "frames": int(len(frames)),
+            "lambdas": [[float(v) for v in r] for r in lam],
+            "dG_gpu_kcal_per_mol": dg_gpu, "dG_oracle_kcal_per_mol": dg_ref, "abs_ddG": abs(dg_gpu - dg_ref),
+            "tolerance": DDG_TOL, "passed": bool(abs(dg_gpu - dg_ref) <= DDG_TOL),
+            "max_abs_du_kT": float(np.abs(du).max()), "mbar_iterations_gpu_oracle": [int(it_gpu), int(it_ref)],
+            "oracle_s": round(t_or, 1), "oracle_processes": nproc}
+
+
+def cpu_baseline(sysd, lam_index, nproc, n_atoms_sample):
+    """One window-step of the FP64 oracle on the host cores, as a bounded
+    sample: real-space forces of ``n_atoms_sample`` atoms by the oracle's
+    per-atom brute force spread over worker processes, scaled to every atom,
+    plus (in this process) one FP64 PME, the exclusion, bonded and restraint
+    terms and one Langevin-middle step with SHAKE; scaled to ns.windows/day."""
+    from threadpoolctl import threadpool_limits
+    from oracle import bonded as obonded, integrate as ointeg, pairs as opairs
+    from oracle.ewald import PME
+    lam = sysd.lambdas[lam_index]
     x = sysd.pos.astype(np.float64)
-    v = np.zeros_like(x)
+    rng = np.random.default_rng(22274)
+    atoms = np.sort(rng.choice(sysd.n_atoms, n_atoms_sample, replace=False))
+    chunks = np.array_split(atoms, nproc)
+    t0 = time.perf_counter()
+    with _pool(sysd, nproc) as p:
+        cpu_s = p.map(_rsa_task, [(sysd.pos, lam, c) for c in chunks], chunksize=1)
+    wall_rs = time.perf_counter() - t0
+    rs_cpu = float(np.sum(cpu_s))                   # CPU seconds for the sampled atoms
     with threadpool_limits(limits=1):
-        t0 = time.perf_counter()
-        for w in windows:
-            lam = sysd.lambdas[w]
-            force = lambda y, lam=lam: oenergy.window_energy(sysd, y, lam, pme=pme)[1]
-            ointeg.langevin_middle_step(sysd, x, v, force, DT, 300.0, 0.5, 1, w, 0)
-        t = (time.perf_counter() - t0) / len(windows)
-    return {"value": DT * 1e-3 / t * 86400.0, "unit": "ns·windows/day", "cores": 1, "kind": "oracle",
-            "sample": f"{len(windows)} window-steps (windows {list(windows)}) of the {sysd.n_atoms}-atom leg: "
-                      f"brute-force FP64 pair sums, FP64 PME 48^3, one Langevin-middle step with SHAKE each; "
-                      f"{t * len(windows):.1f} s on one thread (thread pools limited to 1) of "
-                      f"{os.cpu_count()} host cores"}
+        t1 = time.perf_counter()
+        pme = PME(sysd.box, sysd.grid, sysd.ewald_alpha)
+        er, fr = pme.energy_forces(x, opairs.scaled_charges(sysd, lam[0]))
+        ex, fx = opairs.exclusion_correction(x, sysd, lam)
+        eb, fb = obonded.bonds(x, sysd)
+        erst, frst = obonded.boresch(x, sysd, lam[2])
+        f_rest = fr + fx + fb + frst
+        v = np.zeros_like(x)
+        ointeg.langevin_middle_step(sysd, x, v, lambda y: f_rest, DT, 300.0, 0.5, 1, lam_index, 0)
+        t_rest = time.perf_counter() - t1
+    # CPU seconds of one whole window-step, and its wall time on nproc + 1 cores
+    cpu_step = rs_cpu * sysd.n_atoms / n_atoms_sample + t_rest
+    wall_step = cpu_step / (nproc + 1)
+    return {"value": DT * 1e-3 / wall_step * 86400.0, "unit": "ns·windows/day", "cores": nproc + 1,
+            "kind": "oracle",
+            "sample": f"window {lam_index} of the {sysd.n_atoms}-atom leg: FP64 real-space forces of "
+                      f"{n_atoms_sample} sampled atoms by the oracle's per-atom brute force ({rs_cpu:.1f} CPU-s "
+                      f"over {nproc} processes, {wall_rs:.1f} s wall), scaled to all atoms, plus one FP64 PME "
+                      f"{'x'.join(map(str, sysd.grid))}, exclusion/bond/restraint terms and one Langevin-middle "
+                      f"step with SHAKE ({t_rest:.1f} s); one window-step = {cpu_step:.0f} CPU-s, "
+                      f"{wall_step:.1f} s on {nproc + 1} cores"}
 
 
-def serve_mix(ctx, n_legs, per_window):
-    """A seeded stream of uneven legs (4,000-12,000 atoms; 12, 20 or 42
-    windows; 400 steps, u_kn every 50; Poisson arrivals at 8 legs/s, so the
-    stream arrives faster than the GPU finishes it) served with continuous
-    batching, then the same stream one leg and one window at a time.
-    Latency = arrival to Delta G."""
+def served_stream(ctx, systems, specs, n_steps, sample_every, rate):
+    """The served form: a seeded Poisson stream of uneven legs, admitted by
+    device memory and stepped together with continuous batching; latency is
+    arrival -> Delta G of each leg."""
     from paper_2603_22274_amd import serve
-    reqs = serve.served_workload(n_legs=n_legs, rate=8.0, seed=22274, atoms=(4000, 12000), n_steps=400,
-                                 sample_every=50)
-    for r in reqs:                      # relaxed starting coordinates (input preparation, untimed)
-        serve.relax_start(ctx, r.sysd)
+    reqs = serve.poisson_requests(len(systems), rate, 22274, lambda i: systems[i], n_steps, sample_every)
     eng = serve.FelisEngine(ctx, mbar_max_iter=5000)
-    srv = serve.Server(eng, hbm_budget=64 << 30, epoch_steps=50)
+    srv = serve.Server(eng, hbm_budget=200 << 30, epoch_steps=50)
     out, stats = srv.serve(reqs)
     stats = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in stats.items()}
-    stats["workload"] = (f"{n_legs} legs, atoms {sorted(r.sysd.n_atoms for r in reqs)}, windows "
-                         f"{[r.sysd.n_windows for r in reqs]}, 400 steps each, u_kn every 50, Poisson 8 legs/s, "
-                         f"starts relaxed by 400 high-friction steps of the coupled state")
+    stats["workload"] = (f"{len(systems)} legs, atoms {[s.n_atoms for s in systems]}, windows "
+                         f"{[s.n_windows for s in systems]}, {n_steps} steps per window, u_kn every "
+                         f"{sample_every}, Poisson arrivals at {rate} legs/s, HBM budget 200 GiB, starts relaxed by "
+                         f"400 high-friction steps of the coupled state")
     stats["mbar_converged"] = sum(1 for r in out if r.status == 'ok')
-    if per_window:
-        seq = serve.run_sequential_per_window(ctx, reqs)
-        stats["per_window_sequential"] = {k: round(v, 4) for k, v in seq.items()}
+    stats["latencies_s"] = [round(r.latency, 3) for r in out]
     return stats
 
 
@@ -106,15 +207,22 @@ def main():
     ap.add_argument('--steps', type=int, default=20)
     ap.add_argument('--warmup', type=int, default=3)
     ap.add_argument('--md', type=int, default=50, help='MD steps per bench step (u_kn sample interval)')
+    ap.add_argument('--workload', choices=('complex42', 'solvent20'), default='complex42')
+    ap.add_argument('--equil', type=int, default=200, help='untimed equilibration MD steps of every window')
+    ap.add_argument('--ddg-segment', type=str, default='16:23',
+                    help="neighbouring windows a:b whose frames the oracle re-evaluates (ddG gate); '' to skip")
     ap.add_argument('--no-cpu-baseline', action='store_true')
+    ap.add_argument('--cpu-atoms', type=int, default=6000, help='atoms of the CPU-baseline sample')
     ap.add_argument('--no-per-window', action='store_true')
-    ap.add_argument('--equil', type=int, default=200, help='untimed equilibration MD steps')
-    ap.add_argument('--schedule', choices=('bench', 'paper'), default='bench',
-                    help="'paper': the 73-window production solvent schedule of appendix B on the same system")
     ap.add_argument('--hrex-every', type=int, default=2500,
                     help='MD steps between replica-exchange attempts among the windows (0: none); 5 ps as in the paper')
-    ap.add_argument('--serve-legs', type=int, default=8, help='legs in the served mixed workload (0: skip)')
-    ap.add_argument('--no-npt', action='store_true', help='skip the NPT (Monte Carlo barostat) line')
+    ap.add_argument('--serve-legs', type=int, default=16, help='legs in the served stream (0: skip)')
+    ap.add_argument('--serve-steps', type=int, default=400, help='MD steps per window of a served leg')
+    ap.add_argument('--schedule', choices=('bench', 'paper'), default='bench',
+                    help="'paper': the production schedule of appendix B on the same system (80 complex or "
+                         "73 solvent windows)")
+    ap.add_argument('--npt', action='store_true',
+                    help='also measure the leg in NPT (Monte Carlo barostat, a volume move every 25 steps)')
     ap.add_argument('--copy-calibration', action='store_true',
                     help='run a plain 256 MiB device copy first (reference for traffic counters)')
     args = ap.parse_args()
@@ -123,8 +231,28 @@ def main():
               "legs and window segments shard across GPUs without exchange (see DESIGN.md).", file=sys.stderr)
         sys.exit(2)
 
+    from paper_2603_22274_amd import gen
+    nproc = _workers()
+    # inputs first, before anything touches the GPU: the headline leg and the
+    # served stream's legs (atoms ~ U[5k, 80k], windows ~ {12, 20, 42})
+    t_gen = time.perf_counter()
+    sysd = gen.config2() if args.workload == 'complex42' else gen.config1()
+    if args.schedule == 'paper':
+        import dataclasses
+        sysd = dataclasses.replace(sysd, lambdas=gen.schedule('paper_complex' if args.workload == 'complex42'
+                                                              else 'paper_solvent'))
+    specs = []
+    if args.serve_legs > 0:
+        rng = np.random.default_rng([22274, 4])
+        specs = [(int(rng.integers(5000, 80001)), int(rng.choice([12, 20, 42])), 22274 + i)
+                 for i in range(args.serve_legs)]
+        with mp.get_context('spawn').Pool(nproc) as p:
+            served_systems = p.map(_gen_task, specs, chunksize=1)
+    t_gen = time.perf_counter() - t_gen
+    print(f"# inputs generated in {t_gen:.1f} s ({nproc} processes)", file=sys.stderr, flush=True)
+
     import torch
-    from paper_2603_22274_amd import felis, gen
+    from paper_2603_22274_amd import felis, serve
 
     if args.copy_calibration:
         src = torch.empty(256 << 20, dtype=torch.uint8, device='cuda')
@@ -132,25 +260,30 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    sysd = gen.config1()
-    if args.schedule == 'paper':
-        import dataclasses
-        sysd = dataclasses.replace(sysd, lambdas=gen.schedule('paper_solvent'))
     ctx = felis.Context(0)
+    # relaxed start of the coupled state (input preparation, untimed)
+    serve.relax_start(ctx, sysd)
     leg = felis.Leg(ctx, sysd, seed=22274)
-    W = leg.n_windows
+    W, N = leg.n_windows, leg.n_atoms
     beta = 1.0 / (KB * 300.0)
     felis.build_nlist(ctx, [leg], force=True)
-    # settle the lattice start before anything is measured
     felis.step(ctx, [leg], args.equil, DT, 300.0, 5.0)
     ctx.device_check()
+    print(f"# {args.workload}: {N} atoms, {W} windows equilibrated", file=sys.stderr, flush=True)
     # algorithmic work: unique pairs within r_c per window (FP64 distances)
     felis.build_nlist(ctx, [leg])
-    npairs_cut = sum(len(felis.nlist_export_pairs(ctx, leg, w, sysd.r_cut)) for w in range(W))
+    npairs_cut = sum(felis.nlist_count_pairs(ctx, leg, w, sysd.r_cut) for w in range(W))
 
+    seg = []
+    if args.ddg_segment:
+        a, b = (int(v) for v in args.ddg_segment.split(':'))
+        seg = list(range(max(0, a), min(W, b)))
     n_samples = args.steps
     u = torch.empty((W, W * n_samples), dtype=torch.float64, device='cuda')
-
+    frames = torch.empty((n_samples, len(seg), N, 3), dtype=torch.float32, device='cuda') if seg else None
+    seg_idx = torch.as_tensor(seg, dtype=torch.long, device='cuda') if seg else None
+    state_of = np.arange(W)                  # replica -> state held (changes only at an exchange)
+    sample_states = []
     md_done = [0]
     attempts = [0]
 
@@ -158,10 +291,16 @@ def main():
         felis.step(ctx, [leg], args.md, DT, 300.0, 0.5)
         col = u[:, k * W:(k + 1) * W] if timed else None
         col = felis.ukn(ctx, leg, sysd.lambdas, leg.x, leg.y, leg.z, beta, out=col)
+        if timed and seg:
+            frames[k, :, :, 0].copy_(leg.x.index_select(0, seg_idx))
+            frames[k, :, :, 1].copy_(leg.y.index_select(0, seg_idx))
+            frames[k, :, :, 2].copy_(leg.z.index_select(0, seg_idx))
+            sample_states.append(state_of.copy())
         md_done[0] += args.md
         if args.hrex_every and md_done[0] % args.hrex_every == 0:
             felis.hrex(ctx, leg, col, attempts[0], 22274, count=False)   # from this sample's u_kn
             attempts[0] += 1
+            state_of[:] = felis.leg_states(ctx, leg)
 
     for k in range(args.warmup):
         bench_step(0, False)
@@ -173,6 +312,7 @@ def main():
     felis.profile(ctx, True, stages=(felis.PROF_PAIRS, felis.PROF_UKN), every=PAIR_SAMPLE)
     for which in range(felis.PROF_BARO + 1):
         felis.profile_read(ctx, which)
+    sample_states.clear()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
@@ -191,6 +331,7 @@ def main():
     felis.profile(ctx, False)
     prof = {name: felis.profile_read(ctx, i) for i, name in enumerate(('pairs', 'pme', 'nlist', 'integrate', 'ukn'))}
     ctx.device_check()
+    print(f"# timed region {t1 - t0:.2f} s", file=sys.stderr, flush=True)
     # stage breakdown (untimed): two more bench steps with every stage bracketed
     felis.profile(ctx, True, every=1)
     for k in range(2):
@@ -201,13 +342,13 @@ def main():
     wall = t1 - t0
     md_steps = args.steps * args.md
     ns_windows = md_steps * DT * W / 1000.0
-    value = ns_windows / (wall / 86400.0)
+    rate = ns_windows / (wall / 86400.0)
     pairs_ms, pairs_n = prof['pairs']
     avg_pairs_s = pairs_ms / max(pairs_n, 1) / 1000.0
-    flops = npairs_cut * FLOP_PER_PAIR
-    achieved = flops / avg_pairs_s / 1e12
-    traffic = _traffic()
-    dg = float((f[-1] - f[0]) / beta) if f is not None else None
+    achieved = npairs_cut * FLOP_PER_PAIR / avg_pairs_s / 1e12
+    alg_bytes = PAIR_BYTES_PER_ATOM * N * W
+    traffic = _traffic(args.workload)
+    dg = felis.delta_g(f, 300.0) if f is not None else None
     # device time of one replica-exchange attempt (its u_kn is the sample's)
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     ucol = u[:, :W]
@@ -219,14 +360,30 @@ def main():
     torch.cuda.synchronize()
     hrex_us = ev0.elapsed_time(ev1) / 10 * 1000.0
 
+    ddg = None
+    if seg:
+        # frames of the segment's windows, grouped by the state each was sampled in
+        fr = frames.reshape(n_samples * len(seg), N, 3).cpu().numpy()
+        st = np.concatenate([np.asarray(s)[seg] for s in sample_states])
+        cols = np.concatenate([k * W + np.asarray(seg) for k in range(n_samples)])
+        keep = np.isin(st, seg)                  # a replica may hold a state outside the segment after an exchange
+        fr, st, cols = fr[keep], st[keep], cols[keep]
+        ucols = u[:, torch.as_tensor(cols, device='cuda')]
+        ddg = ddg_check(sysd, fr, st, seg, ucols, beta, ctx, felis, nproc)
+        print(f"# ddG check {ddg['abs_ddG']:.2e} kcal/mol ({ddg['oracle_s']} s)", file=sys.stderr, flush=True)
+        del fr
+    del frames
+    value = rate if (ddg is None or ddg['passed']) else 0.0
+
     per_window = None
     if not args.no_per_window:
-        # the same leg as 20 one-window legs, each launched on its own
+        # the same leg as one-window legs, each launched on its own
+        wins = list(range(W))
         legs1 = [felis.Leg(ctx, sysd, windows=[w], seed=22274, positions=leg.positions()[w].cpu().numpy())
-                 for w in range(W)]
+                 for w in wins]
         for l in legs1:
             felis.build_nlist(ctx, [l], force=True)
-        nrep = max(1, args.md // 2)
+        nrep = 10
         for l in legs1:
             felis.step(ctx, [l], 5, DT, 300.0, 0.5)
         torch.cuda.synchronize()
@@ -235,21 +392,24 @@ def main():
             felis.step(ctx, [l], nrep, DT, 300.0, 0.5)
         torch.cuda.synchronize()
         tb = time.perf_counter()
-        per_window = {"value": nrep * DT * W / 1000.0 / ((tb - ta) / 86400.0), "unit": "ns·windows/day",
+        ctx.device_check()
+        per_window = {"value": nrep * DT * len(wins) / 1000.0 / ((tb - ta) / 86400.0), "unit": "ns·windows/day",
                       "form": "one window per leg and launch chain (same kernels), MD only",
-                      "md_steps_per_window": nrep}
+                      "md_steps_per_window": nrep, "windows": len(wins)}
+        del legs1
+        torch.cuda.empty_cache()
 
     npt = None
-    if not args.no_npt:
+    if args.npt:
         # the same leg in the paper's ensemble: NPT at 1.01325 bar, a volume
         # move of every window every 25 steps (two energy evaluations each)
         every = 25
         nl = felis.Leg(ctx, sysd, seed=22274, positions=leg.positions().cpu().numpy(), pressure_bar=1.01325,
                        barostat_every=every)
         felis.build_nlist(ctx, [nl], force=True)
-        felis.step(ctx, [nl], 4 * every, DT, 300.0, 0.5)
+        felis.step(ctx, [nl], 2 * every, DT, 300.0, 0.5)
         torch.cuda.synchronize()
-        n_npt = 8 * every
+        n_npt = 4 * every
         felis.profile(ctx, True, stages=(felis.PROF_BARO,))
         for which in range(felis.PROF_BARO + 1):
             felis.profile_read(ctx, which)
@@ -268,26 +428,40 @@ def main():
                "acceptance": float(st[:, 9].sum() / max(st[:, 8].sum(), 1)),
                "volume_over_start": [float(v / np.prod(sysd.box)) for v in (vols.min(), vols.mean(), vols.max())],
                "note": "every window its own box and complex PME grid; MD + volume moves, no u_kn"}
+        del nl
+        torch.cuda.empty_cache()
 
     served = None
     if args.serve_legs > 0:
-        served = serve_mix(ctx, args.serve_legs, not args.no_per_window)
+        del leg
+        torch.cuda.empty_cache()
+        for s in served_systems:                # relaxed starting coordinates (input preparation, untimed)
+            serve.relax_start(ctx, s)
+        served = served_stream(ctx, served_systems, specs, args.serve_steps, 50, 2.0)
+        print(f"# served {served['completed']}/{served['legs']} legs in {served['wall_s']} s", file=sys.stderr,
+              flush=True)
 
-    cpu = None if args.no_cpu_baseline else cpu_baseline(sysd)
+    cpu = None if args.no_cpu_baseline else cpu_baseline(sysd, min(W - 1, 30), nproc, args.cpu_atoms)
+    work = ("complex leg, 42 windows (12 restraint, 10 electrostatic, 20 vdW), 70527 atoms (5,000-atom chain "
+            "protein, 50-atom Boresch-restrained ligand, 4 Na+/4 Cl-, 21,823 TIP3P-geometry waters), 88 A box, "
+            "r_c 10 A, skin 1 A, PME 96^3 order 4, 2 fs, 300 K" if args.workload == 'complex42' else
+            "solvent leg, 20 windows, 7540 atoms (2500 TIP3P-geometry waters + 40-atom ligand), 42 A box, "
+            "r_c 10 A, skin 1 A, PME 48^3 order 4, 2 fs, 300 K")
+    if args.schedule == 'paper':
+        work += f"; the production schedule of appendix B ({W} windows)"
     out = {
         "metric": METRIC, "value": value, "unit": "ns·windows/day", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": wall / args.steps * 1000.0, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "fp32", "data": "synthetic",
-        "config": {"workload": f"solvent leg, {W} windows" + (" (the paper's 73-window production schedule)"
-                                                             if args.schedule == 'paper' else "") +
-                               ", 7540 atoms (2500 TIP3P-geometry waters + 40-atom "
-                               "ligand), 42 A box, r_c 10 A, skin 1 A, PME 48^3 order 4, 2 fs, 300 K",
-                   "md_steps_per_step": args.md, "windows": W, "atoms": sysd.n_atoms,
-                   "ukn_states": W, "mbar_samples": int(W * n_samples)},
+        "config": {"workload": work, "md_steps_per_step": args.md, "windows": W, "atoms": N, "ukn_states": W,
+                   "mbar_samples": int(W * n_samples)},
+        "throughput_before_gate": rate,
+        "ddg_check": ddg,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32, "traffic": traffic,
                      "nonpacked_issue_peak": ISSUE_FP32, "frac_of_nonpacked_peak": achieved / ISSUE_FP32,
-                     "traffic_gb_per_s": (traffic / avg_pairs_s / 1e9) if traffic else None,
+                     "algorithmic_bytes_per_launch": alg_bytes,
+                     "traffic_over_algorithmic": (traffic / alg_bytes) if traffic else None,
                      "kernel": f"k_pairs (real-space pair kernel, all {W} windows per launch)",
                      "pairs_in_cutoff_per_launch": int(npairs_cut), "flop_per_pair": FLOP_PER_PAIR,
                      "avg_launch_ms": avg_pairs_s * 1000.0, "launches": pairs_n,
@@ -301,8 +475,9 @@ def main():
                              "attempt_us": hrex_us,
                              "note": "neighbour swaps from the sample-time u_kn; one single-workgroup kernel"},
         "mbar": {"converged": mbar_ok, "iterations": iters, "dG_kcal_per_mol": dg},
-        "leg_latency_s": {"p50": wall, "p99": wall, "legs": 1,
-                          "note": "one leg in this workload; the served mixed batch reports its own"},
+        "leg_latency_s": ({"p50": served["latency_p50_s"], "p99": served["latency_p99_s"],
+                           "legs": served["completed"], "from": "served stream, arrival to Delta G"}
+                          if served else None),
         "served": served,
     }
     print(json.dumps(out))

@@ -61,7 +61,7 @@ enum {
   FELIS_E_EXCL = 2,      /* -KE q_i q_j erf(alpha r)/r over excluded pairs */
   FELIS_E_SELF = 3,      /* Ewald self term + neutralising-background term */
   FELIS_E_RECIP = 4,     /* PME reciprocal energy */
-  FELIS_E_BOND = 5,      /* harmonic bonds (k/2)(r - r0)^2 */
+  FELIS_E_BOND = 5,      /* bonded: harmonic bonds (k/2)(r - r0)^2 + lambda_vdw x rotatable torsions */
   FELIS_E_RESTRAINT = 6, /* lambda_restraint x Boresch energy */
   FELIS_E_TOTAL = 7
 };
@@ -117,6 +117,21 @@ typedef struct felis_leg {
                                     window its own box (section "Simulation protocol"); 0: every
                                     window keeps `box` */
   int32_t barostat_every;        /* MD steps between volume moves (with pressure_bar > 0) */
+  int32_t n_torsions;            /* rotatable ligand torsions, scaled linearly with lambda_vdw
+                                    (section "Double annihilation protocol"); 0 = none */
+  const int32_t* torsion_ijkl;   /* (dev) [n_torsions][4] atoms a, b, c, d (rotatable bond b-c) */
+  const float* torsion_k;        /* (dev) [n_torsions] kcal/mol: energy lambda_vdw k [1 + cos(n phi - delta)] */
+  const int32_t* torsion_n;      /* (dev) [n_torsions] periodicity n >= 1 */
+  const float* torsion_phase;    /* (dev) [n_torsions] delta, rad */
+  const float* alch_offset;      /* (dev) [n_atoms] or NULL: alchemical waters (section "Double
+                                    annihilation protocol": charged ligands): atom i's charge in a
+                                    window is q_i (x lambda_elec for ligand atoms) + (1 - lambda_elec)
+                                    alch_offset[i], nonzero on the designated waters only, so the net
+                                    charge is the same in every window */
+  int32_t plain_fp64;            /* 1: the plain form, for comparison only: inside felis_step the pair
+                                    and reciprocal-space forces are accumulated with FP64 atomics
+                                    (order-dependent, not bitwise reproducible) instead of int64 fixed
+                                    point; 0: the default fixed-point accumulation */
   void* work;                    /* (dev) library scratch of work_bytes */
   size_t work_bytes;
 } felis_leg;
@@ -201,9 +216,10 @@ int felis_nonbonded(felis_ctx* ctx, felis_leg* legs, int n_legs, int flags);
  * felis_build_nlist with force = 0 does). */
 int felis_pme(felis_ctx* ctx, felis_leg* legs, int n_legs, int flags);
 
-/* Harmonic bonds and lambda_restraint-scaled Boresch restraint (section
- * "Restraints"); forces are ADDED; with FELIS_ENERGY writes BOND, RESTRAINT
- * and TOTAL. */
+/* Harmonic bonds, lambda_vdw-scaled rotatable torsions (section "Double
+ * annihilation protocol") and the lambda_restraint-scaled Boresch restraint
+ * (section "Restraints"); forces are ADDED; with FELIS_ENERGY writes BOND
+ * (bonds and torsions), RESTRAINT and TOTAL. */
 int felis_bonded(felis_ctx* ctx, felis_leg* legs, int n_legs, int flags);
 
 /* n_steps Langevin-middle steps ("Simulation protocol") for every window:
@@ -226,7 +242,8 @@ int felis_step(felis_ctx* ctx, felis_leg* legs, int n_legs, int n_steps, double 
  * protocol" (charges scaled by lambda_elec, so ligand-environment terms scale
  * as lambda_elec and ligand-ligand terms as lambda_elec^2; softcore LJ at
  * lambda_vdw) and section "Restraints" (Boresch energy x lambda_restraint):
- * u[k * u_stride + f] = beta [lam_e E_LE + lam_e^2 E_LL + E_sc(lam_v) + lam_r U_B + P V_f]
+ * u[k * u_stride + f] = beta [lam_e E_LE + lam_e^2 E_LL + E_sc(lam_v) + lam_v U_T + lam_r U_B + P V_f]
+ * (U_T: the rotatable torsions, unscaled)
  * (lambda-independent terms dropped; MBAR is invariant to them; the P V term
  * only for legs with pressure_bar > 0).  Frame f's coordinates are
  * fx/fy/fz + f * frame_stride (dev, float, n_atoms each); frame_box (dev,

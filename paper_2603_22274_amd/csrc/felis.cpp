@@ -19,7 +19,7 @@ using namespace felis;
 namespace {
 
 struct Layout {
-  size_t lam, lamS, rstate, free_atoms, lig_idx, xr, yr, zr, flag, nbuild, maxdisp, wmax, hcell, box, ubox, rbforce, skin_used, bptr, bnb, bid, mol_ptr, mol_atoms, baro, boxb, xb, yb, zb, molr, perm, cellcode, cellstart, cursor, xyzq, prm, bblo,
+  size_t lam, lamS, rstate, free_atoms, lig_idx, aw_idx, fd, xr, yr, zr, flag, nbuild, maxdisp, wmax, hcell, box, ubox, rbforce, skin_used, bptr, bnb, bid, tptr, tid, mol_ptr, mol_atoms, baro, boxb, xb, yb, zb, molr, perm, cellcode, cellstart, cursor, xyzq, prm, bblo,
       bbhi, gsten, lcount, lent, frx, fry, frz, grid64, cgrid, tw[3], bmod[3], eacc, uacc, upart, lpart, ucst, total;
 };
 
@@ -32,6 +32,7 @@ struct Plan {
 
 struct Meta {          // facts read from the topology at felis_leg_init
   int nfree, nlig;
+  int naw;             // alchemical-water atoms
   int nmol;            // molecules (legs with a barostat; 0 otherwise)
   size_t work_bytes;
 };
@@ -98,6 +99,8 @@ int make_plan(felis_ctx* c, const felis_leg* L, Plan& P) {
   if (!(L->pressure_bar >= 0) || !(L->pressure_bar < 1e6) || (L->pressure_bar > 0 && L->barostat_every < 1))
     return fail(c, FELIS_E_INVAL, "pressure_bar >= 0 and, with a barostat, barostat_every >= 1");
   if (L->spline_order != 4) return fail(c, FELIS_E_UNSUPPORTED, "PME spline order must be 4");
+  if (L->plain_fp64 && L->pressure_bar > 0)
+    return fail(c, FELIS_E_UNSUPPORTED, "the plain (FP64-atomic) form runs at fixed box only");
   if (!(L->sc_alpha >= 0)) return fail(c, FELIS_E_INVAL, "sc_alpha");
   // the real-space erfc is a fit on [0, 3.5] (Ewald tolerances down to ~4e-7)
   if (!(L->ewald_alpha * L->r_cut <= 3.5))
@@ -114,6 +117,9 @@ int make_plan(felis_ctx* c, const felis_leg* L, Plan& P) {
     return fail(c, FELIS_E_INVAL, "bonds");
   if (L->n_waters < 0 || 3LL * L->n_waters > L->n_atoms || (L->n_waters > 0 && !L->water_ohh))
     return fail(c, FELIS_E_INVAL, "waters");
+  if (L->n_torsions < 0 || (L->n_torsions > 0 && (!L->torsion_ijkl || !L->torsion_k || !L->torsion_n ||
+                                                   !L->torsion_phase)))
+    return fail(c, FELIS_E_INVAL, "torsions");
   if (L->has_restraint)
     for (int t = 0; t < 6; ++t)
       if (L->restraint_atoms[t] < 0 || L->restraint_atoms[t] >= L->n_atoms)
@@ -132,6 +138,7 @@ int make_plan(felis_ctx* c, const felis_leg* L, Plan& P) {
   h.nwat = L->n_waters;
   h.nfree = h.n - 3 * h.nwat;
   h.has_rest = L->has_restraint ? 1 : 0;
+  h.ntors = L->n_torsions;
   for (int d = 0; d < 3; ++d) {
     const int K = L->grid[d];
     if (K < 4 || K > kMaxFFT || !factor_plan(K, p.rad[d], &p.nrad[d]))
@@ -166,6 +173,8 @@ int make_plan(felis_ctx* c, const felis_leg* L, Plan& P) {
   y.rstate = put(W * 4);
   y.free_atoms = put(n * 4);
   y.lig_idx = put(n * 4);
+  y.aw_idx = put(3 * n * 4);
+  y.fd = put(L->plain_fp64 ? 3 * W * n * 8 : 0);
   y.hcell = put((size_t)h.ncell * 4);            // filled once at set-up (outside every cleared range)
   y.box = put(W * sizeof(BoxW));                  // set at set-up, changed only by the barostat
   y.ubox = put(2 * (size_t)h.npair * sizeof(BoxW));
@@ -174,6 +183,8 @@ int make_plan(felis_ctx* c, const felis_leg* L, Plan& P) {
   y.bptr = put((n + 1) * 4);                      // per-atom bond table (filled at set-up)
   y.bnb = put(2 * (size_t)std::max(h.nbonds, 1) * 4);
   y.bid = put(2 * (size_t)std::max(h.nbonds, 1) * 4);
+  y.tptr = put((n + 1) * 4);                      // per-atom torsion table (filled at set-up)
+  y.tid = put(4 * (size_t)std::max(h.ntors, 1) * 4);
   {
     // barostat: molecule table, per-window state, positions before a move
     const bool npt = L->pressure_bar > 0;
@@ -236,6 +247,10 @@ LegDev make_dev(const felis_ctx* c, const felis_leg* L, const Plan& p, const Met
   g.pack = L->pressure_bar > 0 ? 0 : 1;
   g.rc2 = (float)(L->r_cut * L->r_cut);
   g.rc2d = L->r_cut * L->r_cut;
+  g.rcd = L->r_cut;
+  g.alphad = L->ewald_alpha;
+  g.sc_alphad = L->sc_alpha;
+  for (int t = 0; t < 6; ++t) { g.rg0d[t] = L->restraint_g0[t]; g.rkd[t] = L->restraint_k[t]; }
   g.alpha = (float)L->ewald_alpha;
   g.sc_alpha = (float)L->sc_alpha;
   g.skin_half2 = (float)(0.25 * L->skin * L->skin);
@@ -244,7 +259,7 @@ LegDev make_dev(const felis_ctx* c, const felis_leg* L, const Plan& p, const Met
   g.rlist2 = g.rlist * g.rlist;
   g.d_oh = (float)L->d_oh;
   g.d_hh = (float)L->d_hh;
-  g.self_pref = (float)(kKE * L->ewald_alpha / std::sqrt(M_PI));
+  g.self_pref = kKE * L->ewald_alpha / std::sqrt(M_PI);
   g.q = L->charge; g.sig = L->sigma; g.eps = L->epsilon; g.mass = L->mass; g.lig = L->is_ligand;
   g.excl_ij = L->excl_ij; g.excl_ptr = L->excl_ptr; g.excl_idx = L->excl_idx;
   g.bond_ij = L->bond_ij; g.bond_k = L->bond_k; g.bond_r0 = L->bond_r0;
@@ -259,6 +274,11 @@ LegDev make_dev(const felis_ctx* c, const felis_leg* L, const Plan& p, const Met
   g.rstate = (int*)(w + y.rstate);
   g.free_atoms = (int*)(w + y.free_atoms);
   g.lig_idx = (int*)(w + y.lig_idx);
+  g.aoff = L->alch_offset;
+  g.naw = m.naw;
+  g.aw_idx = (int*)(w + y.aw_idx);
+  g.plain = L->plain_fp64 ? 1 : 0;
+  g.fd = (double*)(w + y.fd);
   g.xr = (float*)(w + y.xr); g.yr = (float*)(w + y.yr); g.zr = (float*)(w + y.zr);
   g.flag = (int*)(w + y.flag);
   g.nbuild = (long long*)(w + y.nbuild);
@@ -273,6 +293,10 @@ LegDev make_dev(const felis_ctx* c, const felis_leg* L, const Plan& p, const Met
   g.bptr = (const int*)(w + y.bptr);
   g.bnb = (const int*)(w + y.bnb);
   g.bid = (const int*)(w + y.bid);
+  g.ntors = h.ntors;
+  g.tors = L->torsion_ijkl; g.tors_k = L->torsion_k; g.tors_n = L->torsion_n; g.tors_phase = L->torsion_phase;
+  g.tptr = (const int*)(w + y.tptr);
+  g.tid = (const int*)(w + y.tid);
   g.nmol = m.nmol;
   if (m.nmol) {
     g.mol_ptr = (const int*)(w + y.mol_ptr);
@@ -322,6 +346,7 @@ int prepare(felis_ctx* c, const felis_leg* legs, int n_legs, std::vector<LegHost
     if (!legs[i].work || legs[i].work_bytes < p.lay.total) return fail(c, FELIS_E_INVAL, "leg work buffer too small");
     p.h.nfree = it->second.nfree;
     p.h.nlig = it->second.nlig;
+    p.h.naw = it->second.naw;
     p.h.nmol = it->second.nmol;
     hs[i] = p.h;
     devs[i] = make_dev(c, &legs[i], p, it->second, i);
@@ -555,6 +580,7 @@ int felis_leg_init(felis_ctx* c, felis_leg* L) {
   ok &= hipMemsetAsync(w + y.maxdisp, 0, h.W * 4, c->stream) == hipSuccess;
   ok &= hipMemsetAsync(w + y.wmax, 0, y.perm - y.wmax, c->stream) == hipSuccess;
   ok &= hipMemsetAsync(w + y.rbforce, 0, h.W * 4, c->stream) == hipSuccess;
+  if (L->plain_fp64) ok &= hipMemsetAsync(w + y.fd, 0, 3 * (size_t)h.W * h.n * 8, c->stream) == hipSuccess;
   ok &= hipMemsetAsync(w + y.skin_used, 0, h.W * 4, c->stream) == hipSuccess;
   ok &= hipMemsetAsync(w + y.lcount, 0, (size_t)h.W * h.nclus * 2 * 4, c->stream) == hipSuccess;
   ok &= hipMemsetAsync(w + y.grid64, 0, y.cgrid - y.grid64, c->stream) == hipSuccess;
@@ -564,6 +590,34 @@ int felis_leg_init(felis_ctx* c, felis_leg* L) {
   Meta m;
   m.nfree = (int)freeat.size();
   m.nlig = (int)ligi.size();
+  m.naw = 0;
+  if (L->alch_offset) {
+    // alchemical-water atoms (nonzero offset, never ligand atoms) and their
+    // two exclusion partners each (the other atoms of the rigid water)
+    std::vector<float> off(h.n);
+    std::vector<int> ep(h.n + 1), ei;
+    if (hipMemcpy(off.data(), L->alch_offset, h.n * 4, hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(ep.data(), L->excl_ptr, (h.n + 1) * 4, hipMemcpyDeviceToHost) != hipSuccess)
+      return fail(c, FELIS_E_DEVICE, "alchemical offset copy failed");
+    ei.resize(std::max(ep[h.n], 1));
+    if (ep[h.n] && hipMemcpy(ei.data(), L->excl_idx, ep[h.n] * 4, hipMemcpyDeviceToHost) != hipSuccess)
+      return fail(c, FELIS_E_DEVICE, "exclusion copy failed");
+    std::vector<int> aw, part;
+    for (int a = 0; a < h.n; ++a) {
+      if (off[a] == 0.0f) continue;
+      if (lig[a]) return fail(c, FELIS_E_INVAL, "an alchemical offset on a ligand atom");
+      if (ep[a + 1] - ep[a] != 2) return fail(c, FELIS_E_INVAL, "an alchemical-water atom needs two exclusions");
+      aw.push_back(a);
+      part.push_back(ei[ep[a]]);
+      part.push_back(ei[ep[a] + 1]);
+    }
+    m.naw = (int)aw.size();
+    if (m.nlig + m.naw > kMaxLigand)
+      return fail(c, FELIS_E_UNSUPPORTED, "more than 256 ligand and alchemical-water atoms");
+    aw.insert(aw.end(), part.begin(), part.end());
+    if (!aw.empty() && hipMemcpy(w + y.aw_idx, aw.data(), aw.size() * 4, hipMemcpyHostToDevice) != hipSuccess)
+      return fail(c, FELIS_E_DEVICE, "alchemical water table");
+  }
   m.nmol = 0;
   std::vector<int> bij(2 * (size_t)h.nbonds);
   if (h.nbonds && hipMemcpy(bij.data(), L->bond_ij, bij.size() * 4, hipMemcpyDeviceToHost) != hipSuccess)
@@ -588,6 +642,24 @@ int felis_leg_init(felis_ctx* c, felis_leg* L) {
     ok &= hipMemcpy(w + y.bnb, nb.data(), nb.size() * 4, hipMemcpyHostToDevice) == hipSuccess;
     ok &= hipMemcpy(w + y.bid, id.data(), id.size() * 4, hipMemcpyHostToDevice) == hipSuccess;
     if (!ok) return fail(c, FELIS_E_DEVICE, "bond table");
+  }
+  {
+    // per-atom torsion table for the integrator: for atom a, entries 4 t + s
+    // (torsion t, a is its s-th atom) in torsion order
+    std::vector<int> tq(4 * (size_t)h.ntors);
+    if (h.ntors && hipMemcpy(tq.data(), L->torsion_ijkl, tq.size() * 4, hipMemcpyDeviceToHost) != hipSuccess)
+      return fail(c, FELIS_E_DEVICE, "torsion copy failed");
+    std::vector<int> ptr(h.n + 1, 0), id(std::max(4 * h.ntors, 1));
+    for (size_t e = 0; e < tq.size(); ++e) {
+      if (tq[e] < 0 || tq[e] >= h.n) return fail(c, FELIS_E_INVAL, "torsion atom out of range");
+      ++ptr[tq[e] + 1];
+    }
+    for (int a = 0; a < h.n; ++a) ptr[a + 1] += ptr[a];
+    std::vector<int> fill(ptr.begin(), ptr.end() - 1);
+    for (size_t e = 0; e < tq.size(); ++e) id[fill[tq[e]]++] = (int)e;
+    ok &= hipMemcpy(w + y.tptr, ptr.data(), ptr.size() * 4, hipMemcpyHostToDevice) == hipSuccess;
+    ok &= hipMemcpy(w + y.tid, id.data(), id.size() * 4, hipMemcpyHostToDevice) == hipSuccess;
+    if (!ok) return fail(c, FELIS_E_DEVICE, "torsion table");
   }
   if (L->pressure_bar > 0) {
     // molecules: connected components of the bonds with each rigid water's
@@ -666,7 +738,7 @@ int felis_nonbonded(felis_ctx* c, felis_leg* legs, int n_legs, int flags) {
   const bool en = flags & FELIS_ENERGY;
   if (en) launch_zero_energy(c->stream, c->d_legs, hs.data(), n_legs, FELIS_E_COUL_REAL, FELIS_E_SELF + 1);
   launch_pack(c->stream, c->d_legs, hs.data(), n_legs, false);
-  launch_pairs(c->stream, c->d_legs, hs.data(), n_legs, en);
+  launch_pairs(c->stream, c->d_legs, hs.data(), n_legs, en ? 2 : 0);
   launch_corrections(c->stream, c->d_legs, hs.data(), n_legs, en);
   if (en) launch_finish_energy(c->stream, c->d_legs, hs.data(), n_legs, FELIS_E_COUL_REAL, FELIS_E_SELF + 1);
   return launched(c);
@@ -693,7 +765,7 @@ int felis_bonded(felis_ctx* c, felis_leg* legs, int n_legs, int flags) {
   if (rc) return rc;
   const bool en = flags & FELIS_ENERGY;
   if (en) launch_zero_energy(c->stream, c->d_legs, hs.data(), n_legs, FELIS_E_BOND, FELIS_E_RESTRAINT + 1);
-  launch_bonded(c->stream, c->d_legs, hs.data(), n_legs, en);
+  launch_bonded(c->stream, c->d_legs, hs.data(), n_legs, en ? 2 : 0);
   if (en) launch_finish_energy(c->stream, c->d_legs, hs.data(), n_legs, FELIS_E_BOND, FELIS_E_RESTRAINT + 1);
   return launched(c);
 }
@@ -713,9 +785,10 @@ void energy_pass(felis_ctx* c, const std::vector<LegHost>& hs, int n_legs, bool 
   launch_pme(c->side, c->d_legs, h, n_legs, true, true);
   (void)hipEventRecord(c->ev_join, c->side);
   launch_lists(c->stream, c->d_legs, h, n_legs);
-  launch_pairs(c->stream, c->d_legs, h, n_legs, true);
+  // the Metropolis test needs energy differences: FP32 pair terms summed in FP64
+  launch_pairs(c->stream, c->d_legs, h, n_legs, 1);
   launch_corrections(c->stream, c->d_legs, h, n_legs, true);
-  launch_bonded(c->stream, c->d_legs, h, n_legs, true);
+  launch_bonded(c->stream, c->d_legs, h, n_legs, 1);
   (void)hipStreamWaitEvent(c->stream, c->ev_join, 0);
   launch_finish_energy(c->stream, c->d_legs, h, n_legs, 0, FELIS_E_TOTAL);
 }
@@ -783,7 +856,7 @@ int felis_step(felis_ctx* c, felis_leg* legs, int n_legs, int n_steps, double dt
     launch_lists(c->stream, c->d_legs, hs.data(), n_legs);
     mark(c, FELIS_PROF_NLIST, true);       // the build stage also packs the sorted coordinates
     mark(c, FELIS_PROF_PAIRS, false);
-    launch_pairs(c->stream, c->d_legs, hs.data(), n_legs, false);
+    launch_pairs(c->stream, c->d_legs, hs.data(), n_legs, 0, true);
     mark(c, FELIS_PROF_PAIRS, true);
     // bonded and restraint forces are summed by the integrator itself
     (void)hipStreamWaitEvent(c->stream, c->ev_join, 0);

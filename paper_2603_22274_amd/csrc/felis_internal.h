@@ -89,9 +89,11 @@ struct LegDev {
                                         // 0: one window per grid (each window its own box)
   float rc2, alpha, sc_alpha, skin_half2, skin;
   double rc2d;                          // r_cut^2 in FP64 (u_kn distance test)
+  double rcd, alphad, sc_alphad;        // r_cut, Ewald alpha and softcore alpha in FP64 (energy terms)
+  double rg0d[6], rkd[6];               // restraint reference geometry and force constants in FP64
   double rlist, rlist2;
   float d_oh, d_hh;
-  float self_pref;                      // KE alpha / sqrt(pi)
+  double self_pref;                     // KE alpha / sqrt(pi)
   // topology (caller-owned)
   const float *q, *sig, *eps, *mass;
   const uint8_t* lig;
@@ -100,6 +102,16 @@ struct LegDev {
   const float *bond_k, *bond_r0;
   const int* water;
   const int *bptr, *bnb, *bid;          // per-atom bonds: CSR [n + 1] over (partner atom, bond index)
+  int ntors;                            // rotatable torsions (scaled by lambda_vdw)
+  const int* tors;                      // [ntors][4] atoms
+  const float *tors_k, *tors_phase;     // [ntors]
+  const int* tors_n;                    // [ntors]
+  const int *tptr, *tid;                // per-atom torsions: CSR [n + 1] over 4 t + (the atom's place in t)
+  const float* aoff;                    // [n] alchemical-water charge offsets (NULL: none)
+  int naw;                              // alchemical-water atoms (nonzero offset)
+  int* aw_idx;                          // [naw] those atoms, then their two exclusion partners each [2 naw]
+  int plain;                            // 1: felis_step accumulates pair and reciprocal forces in fd
+  double* fd;                           // [3][W][n] FP64 force sums of the plain form (cleared by the integrator)
   // state (caller-owned) [W][n]
   float *x, *y, *z, *vx, *vy, *vz;
   long long *fx, *fy, *fz;
@@ -163,6 +175,18 @@ struct BlockMap {
   int n_legs;
   int start[kMaxLegs + 1];
 };
+
+// Charge of atom a in a window with lambda_elec le (section "Double
+// annihilation protocol"): ligand charges scaled by le; alchemical-water
+// atoms take up (1 - le) of their offset.
+__device__ __forceinline__ float window_charge(const LegDev& g, int a, float le) {
+  const float q = g.q[a] * (g.lig[a] ? le : 1.0f);
+  return g.aoff ? fmaf(1.0f - le, g.aoff[a], q) : q;
+}
+__device__ __forceinline__ double window_charge_fp64(const LegDev& g, int a, double le) {
+  const double q = (double)g.q[a] * (g.lig[a] ? le : 1.0);
+  return g.aoff ? q + (1.0 - le) * (double)g.aoff[a] : q;
+}
 
 __device__ __forceinline__ int find_leg(const BlockMap& m, int b) {
   int lo = 0, hi = m.n_legs - 1;
@@ -306,7 +330,7 @@ inline int make_map(BlockMap& m, int n_legs, F blocks_of) {
 
 // Host-side mirror of the sizes each launcher needs.
 struct LegHost {
-  int n, W, npad, nclus, cap, nexcl, nbonds, nwat, nfree, nlig, K[3], Ktot, npair, ncell;
+  int n, W, npad, nclus, cap, nexcl, nbonds, nwat, nfree, nlig, K[3], Ktot, npair, ncell, ntors, naw;
   int has_rest;
   int nmol;                             // > 0 only for legs with a barostat
 };
@@ -331,9 +355,12 @@ void launch_lists(hipStream_t s, const LegDev* d, const LegHost* h, int nl);
 void launch_export(hipStream_t s, const LegDev* d, const LegHost& h, int window, double r,
                    int* pairs, long long cap, unsigned long long* count);
 void launch_pack(hipStream_t s, const LegDev* d, const LegHost* h, int nl, bool rebuild);
-void launch_pairs(hipStream_t s, const LegDev* d, const LegHost* h, int nl, bool energy);
+// energy: 0 forces only; 1 also energies from the FP32 pair terms (summed in
+// FP64); 2 also energies with every term evaluated in FP64
+// step: inside felis_step (legs in the plain form accumulate in fd)
+void launch_pairs(hipStream_t s, const LegDev* d, const LegHost* h, int nl, int energy, bool step = false);
 void launch_corrections(hipStream_t s, const LegDev* d, const LegHost* h, int nl, bool energy);
-void launch_bonded(hipStream_t s, const LegDev* d, const LegHost* h, int nl, bool energy);
+void launch_bonded(hipStream_t s, const LegDev* d, const LegHost* h, int nl, int energy);
 // step_forces: the gather stores each atom's force in frx/fry/frz (read by the
 // integrator) instead of adding it to fx/fy/fz
 void launch_pme(hipStream_t s, const LegDev* d, const LegHost* h, int nl, bool energy, bool step_forces = false);

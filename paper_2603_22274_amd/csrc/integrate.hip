@@ -61,17 +61,38 @@ __device__ __attribute__((noinline)) v3 restraint_share(const LegDev& g, int w, 
   return F;
 }
 
+// Atom `slot` of torsion t's share of its lambda_vdw-scaled force in window w
+// (out of line, like the restraint share)
+__device__ __attribute__((noinline)) v3 torsion_share(const LegDev& g, int w, int t, int slot) {
+  const BoxW& B = g.box[w];
+  const size_t base = (size_t)w * g.n;
+  const size_t o0 = base + g.tors[4 * t];
+  v3 p[4], F[4];
+  for (int s = 0; s < 4; ++s) {
+    const size_t os = base + g.tors[4 * t + s];
+    float dx = g.x[os] - g.x[o0], dy = g.y[os] - g.y[o0], dz = g.z[os] - g.z[o0];
+    dx = fmaf(-B.Lf[0], rintf(dx * B.invLf[0]), dx);
+    dy = fmaf(-B.Lf[1], rintf(dy * B.invLf[1]), dy);
+    dz = fmaf(-B.Lf[2], rintf(dz * B.invLf[2]), dz);
+    p[s] = mk(dx, dy, dz);
+  }
+  torsion_eval(p, g.tors_k[t], g.tors_n[t], g.tors_phase[t], F);
+  return vmul(F[slot], g.lam[4 * w + 1]);
+}
+
 // The bonded terms of atom a in window w: its harmonic bonds (each atom sums
-// its own, from the per-atom bond table, in bond order) and, for a Boresch
+// its own, from the per-atom bond table, in bond order), its lambda_vdw-scaled
+// rotatable torsions (per-atom torsion table) and, for a Boresch
 // anchor, its share of the lambda_r-scaled restraint -- the forces of
 // k_bonded, computed where they are used instead of added by atomics.
 __device__ __forceinline__ v3 bonded_force(const LegDev& g, int w, int a) {
   v3 F = mk(0.f, 0.f, 0.f);
   const int k0 = g.bptr[a], k1 = g.bptr[a + 1];
+  const int t0 = g.tptr[a], t1 = g.lam[4 * w + 1] != 0.0f ? g.tptr[a + 1] : t0;
   int anchor = -1;
   if (g.has_rest && g.lam[4 * w + 2] != 0.0f)
     for (int t = 0; t < 6; ++t) anchor = (g.ranch[t] == a) ? t : anchor;
-  if (k0 == k1 && anchor < 0) return F;
+  if (k0 == k1 && anchor < 0 && t0 == t1) return F;
   const BoxW& B = g.box[w];
   const size_t base = (size_t)w * g.n;
   auto img = [&](size_t from, size_t to) {        // r_to - r_from, nearest image
@@ -88,6 +109,10 @@ __device__ __forceinline__ v3 bonded_force(const LegDev& g, int w, int a) {
     const float fs = -g.bond_k[id] * (r - g.bond_r0[id]) / r;
     F = vadd(F, vmul(d, fs));
   }
+  for (int e = t0; e < t1; ++e) {
+    const int te = g.tid[e];
+    F = vadd(F, torsion_share(g, w, te >> 2, te & 3));
+  }
   if (anchor >= 0) F = vadd(F, restraint_share(g, w, anchor));
   return F;
 }
@@ -99,8 +124,21 @@ __device__ __forceinline__ v3 bonded_force(const LegDev& g, int w, int a) {
 __device__ __forceinline__ v3 kick(const LegDev& g, const StepArgs& S, int w, int a) {
   const size_t o = (size_t)w * g.n + a;
   const float acc = (float)kAccel / g.mass[a];
-  long long tx = g.fx[o] + g.frx[o], ty = g.fy[o] + g.fry[o], tz = g.fz[o] + g.frz[o];
   const v3 fb = bonded_force(g, w, a);
+  if (g.plain) {
+    // the plain form: the step's pair and reciprocal forces were summed by
+    // FP64 atomics; read them, clear the sums for the next step
+    const size_t wn = (size_t)g.W * g.n;
+    const double sx = g.fd[o] + (double)fb.x, sy = g.fd[wn + o] + (double)fb.y, sz = g.fd[2 * wn + o] + (double)fb.z;
+    g.fd[o] = 0.0; g.fd[wn + o] = 0.0; g.fd[2 * wn + o] = 0.0;
+    const int where = (w << 20) | a;
+    g.fx[o] = to_fixed(sx, kForceScale, g.err, kSiteBonded, where, g.leg_index);
+    g.fy[o] = to_fixed(sy, kForceScale, g.err, kSiteBonded, where, g.leg_index);
+    g.fz[o] = to_fixed(sz, kForceScale, g.err, kSiteBonded, where, g.leg_index);
+    const float dt = S.dt;
+    return mk(g.vx[o] + dt * (float)sx * acc, g.vy[o] + dt * (float)sy * acc, g.vz[o] + dt * (float)sz * acc);
+  }
+  long long tx = g.fx[o] + g.frx[o], ty = g.fy[o] + g.fry[o], tz = g.fz[o] + g.frz[o];
   if (fb.x != 0.f || fb.y != 0.f || fb.z != 0.f) {
     const int where = (w << 20) | a;
     tx += to_fixed((double)fb.x, kForceScale, g.err, kSiteBonded, where, g.leg_index);

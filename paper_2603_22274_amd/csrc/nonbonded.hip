@@ -39,7 +39,7 @@ __global__ __launch_bounds__(256) void k_pack(const LegDev* legs, BlockMap map) 
   float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
   if (a >= 0) {
     const size_t o = (size_t)w * g.n + a;
-    const float q = g.q[a] * (g.lig[a] ? g.lam[4 * w] : 1.0f);
+    const float q = window_charge(g, a, g.lam[4 * w]);
     v = make_float4(g.x[o], g.y[o], g.z[o], q * (float)sqrt(kKE));
   }
   if (valid) {
@@ -88,7 +88,41 @@ __device__ __forceinline__ float3 min_img(const BoxW& B, float dx, float dy, flo
 // The 8 i-atoms of a cluster, wave-uniform (held in scalar registers).
 struct ICluster {
   float x[kClus], y[kClus], z[kClus], q[kClus], sig[kClus], eps[kClus], lig[kClus];
+  float xr[kClus], yr[kClus], zr[kClus];   // unshifted coordinates (FP64 energies)
+  int ai[kClus];                            // atom indices (FP64 energies)
 };
+
+// One pair's real-space Coulomb and LJ energies with every term in FP64 (the
+// energy level 2 of the pair kernel): the minimum-image distance from the raw
+// FP32 coordinates as d - L rint(d (1/L)) and d^2 = (dx^2 + dy^2) + dz^2
+// without contraction, the cutoff r < r_c on r = sqrt(d^2), the window's
+// charges of atoms ai, aj in FP64, Lorentz-Berthelot parameters from the packed (sigma/2,
+// 2 sqrt(eps)) and the softcore form at lambda_vdw for pairs touching the
+// ligand.  Out of line: its registers stay out of the force path.
+__device__ __attribute__((noinline)) void pair_energy_fp64(const LegDev& g, const BoxW& B, float xi, float yi,
+                                                           float zi, float xj, float yj, float zj, int ai, int aj,
+                                                           float ligi, float ligj, float hsi, float hsj,
+                                                           float e2i, float e2j, float lam_e, float lam_v,
+                                                           double& ec, double& el) {
+#pragma clang fp contract(off)
+  double dx = (double)xi - (double)xj, dy = (double)yi - (double)yj, dz = (double)zi - (double)zj;
+  dx = dx - B.L[0] * rint(dx * B.invL[0]);
+  dy = dy - B.L[1] * rint(dy * B.invL[1]);
+  dz = dz - B.L[2] * rint(dz * B.invL[2]);
+  const double r2 = (dx * dx + dy * dy) + dz * dz;
+  const double r = sqrt(r2);
+  if (!(r < g.rcd)) return;
+  const bool li = ligi > 0.0f, lj = ligj > 0.0f;
+  const double qa = window_charge_fp64(g, ai, (double)lam_e), qb = window_charge_fp64(g, aj, (double)lam_e);
+  ec += kKE * qa * qb * erfc(g.alphad * r) / r;
+  const double sig = (double)hsi + (double)hsj;
+  const double eps = 0.25 * (double)e2i * (double)e2j;
+  if (eps == 0.0) return;
+  const double lam = (li || lj) ? (double)lam_v : 1.0;
+  const double s2 = sig * sig, s6 = s2 * s2 * s2;
+  const double s = g.sc_alphad * (1.0 - lam) * s6 + r2 * r2 * r2;
+  el += lam * 4.0 * eps * (s6 * s6 / (s * s) - s6 / s);
+}
 
 __device__ __forceinline__ float uniform(float v) {
   return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
@@ -109,11 +143,12 @@ __device__ __forceinline__ BoxF box_f(const BoxW& B) {
 // i-atoms.  SHIFT: the periodic image of j is chosen once against the
 // cluster's first atom (exact when r_c + cluster extent < L/2 on every axis);
 // otherwise every (i, j) takes its own minimum image.
-template <bool ENERGY, bool SHIFT, int HALF>
+template <int ENERGY, bool SHIFT, int HALF>
 __device__ __forceinline__ void sweep(const LegDev& g, const BoxF B, const ICluster& I, gptr<unsigned> ent, int cnt,
                                       gptr<f32x4> xq, gptr<f32x4> pr, int lane,
                                       float lam_v, float a_sc, bool soft_window, float (&fx)[4],
-                                      float (&fy)[4], float (&fz)[4], double& ec, double& el) {
+                                      float (&fy)[4], float (&fz)[4], double& ec, double& el, const BoxW* Bw,
+                                      float lam_e, const int* permw) {
   const float Lx = B.L[0], Ly = B.L[1], Lz = B.L[2];
   const float iLx = B.iL[0], iLy = B.iL[1], iLz = B.iL[2];
   const float rc2 = g.rc2, alpha = g.alpha;
@@ -192,17 +227,36 @@ __device__ __forceinline__ void sweep(const LegDev& g, const BoxF B, const IClus
       fx[k] = fmaf(-fs, dx, fx[k]);
       fy[k] = fmaf(-fs, dy, fy[k]);
       fz[k] = fmaf(-fs, dz, fz[k]);
-      if (ENERGY && in) {
+      if (ENERGY == 1 && in) {
         ec += (double)(qq * (pt * ex) * rinv);
         el += (double)elj;
       }
+      if (ENERGY == 2 && ((e >> k) & 1u))
+        pair_energy_fp64(g, *Bw, I.xr[ii], I.yr[ii], I.zr[ii], xj.x, xj.y, xj.z, I.ai[ii], permw[s], I.lig[ii],
+                         pj.z, I.sig[ii], pj.x, I.eps[ii], pj.y, lam_e, lam_v, ec, el);
     }
   }
 }
 
-template <bool ENERGY>
+// An excluded pair's reciprocal-space removal -KE q_a q_b erf(alpha r)/r in
+// FP64 (its r -> 0 limit -KE q_a q_b 2 alpha / sqrt(pi) below 1e-6 A)
+__device__ __attribute__((noinline)) double excl_energy_fp64(const LegDev& g, const BoxW& B, size_t oa, size_t ob,
+                                                             double qa, double qb) {
+#pragma clang fp contract(off)
+  double dx = (double)g.x[ob] - (double)g.x[oa], dy = (double)g.y[ob] - (double)g.y[oa];
+  double dz = (double)g.z[ob] - (double)g.z[oa];
+  dx = dx - B.L[0] * rint(dx * B.invL[0]);
+  dy = dy - B.L[1] * rint(dy * B.invL[1]);
+  dz = dz - B.L[2] * rint(dz * B.invL[2]);
+  const double r = sqrt((dx * dx + dy * dy) + dz * dz);
+  const double qq = kKE * qa * qb;
+  if (r < 1e-6) return -qq * 2.0 * g.alphad * 0.56418958354775628;
+  return -qq * erf(g.alphad * r) / r;
+}
+
+template <int ENERGY>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_pairs(const LegDev* legs,
-                                                                                      BlockMap map) {
+                                                                                      BlockMap map, int step) {
   const int leg = find_leg(map, blockIdx.x);
   const LegDev& g = legs[leg];
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
@@ -215,7 +269,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
   const BoxF B = box_f(g.box[w]);
   const float lam_v = g.lam[4 * w + 1];
   const float a_sc = g.lam[4 * w + 3];
+  const float lam_e = g.lam[4 * w];
   const bool soft_window = lam_v < 1.0f;
+  const BoxW* Bw = &g.box[w];
+  const int* permw = g.perm + (size_t)w * g.npad;
 
   // i-atoms: images nearest the cluster's first atom (always a real atom:
   // padding only follows the last atom), and the cluster's extent
@@ -233,6 +290,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
         if (c * kClus + ii < g.n) ext[d] = fmaxf(ext[d], fabsf(v[d] - r0[d]));
       }
     }
+    I.xr[ii] = uniform(a.x); I.yr[ii] = uniform(a.y); I.zr[ii] = uniform(a.z);
+    if (ENERGY == 2) I.ai[ii] = __builtin_amdgcn_readfirstlane(g.perm[(size_t)w * g.npad + c * kClus + ii]);
     I.x[ii] = v[0]; I.y[ii] = v[1]; I.z[ii] = v[2];
     I.q[ii] = uniform(a.w);
     I.sig[ii] = uniform(p.x);
@@ -252,11 +311,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
     const gptr<unsigned> eh = ent + half * g.cap;
     const int cnt = g.lcount[2 * item + half];
     if (half == 0) {
-      if (shift) sweep<ENERGY, true, 0>(g, B, I, eh, cnt, xq, pr, lane, lam_v, a_sc, soft_window, fx, fy, fz, ec, el);
-      else sweep<ENERGY, false, 0>(g, B, I, eh, cnt, xq, pr, lane, lam_v, a_sc, soft_window, fx, fy, fz, ec, el);
+      if (shift) sweep<ENERGY, true, 0>(g, B, I, eh, cnt, xq, pr, lane, lam_v, a_sc, soft_window, fx, fy, fz, ec, el, Bw, lam_e, permw);
+      else sweep<ENERGY, false, 0>(g, B, I, eh, cnt, xq, pr, lane, lam_v, a_sc, soft_window, fx, fy, fz, ec, el, Bw, lam_e, permw);
     } else {
-      if (shift) sweep<ENERGY, true, 1>(g, B, I, eh, cnt, xq, pr, lane, lam_v, a_sc, soft_window, fx, fy, fz, ec, el);
-      else sweep<ENERGY, false, 1>(g, B, I, eh, cnt, xq, pr, lane, lam_v, a_sc, soft_window, fx, fy, fz, ec, el);
+      if (shift) sweep<ENERGY, true, 1>(g, B, I, eh, cnt, xq, pr, lane, lam_v, a_sc, soft_window, fx, fy, fz, ec, el, Bw, lam_e, permw);
+      else sweep<ENERGY, false, 1>(g, B, I, eh, cnt, xq, pr, lane, lam_v, a_sc, soft_window, fx, fy, fz, ec, el, Bw, lam_e, permw);
     }
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
@@ -283,7 +342,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
     if (k < ne) {
       const int b = g.excl_idx[e0 + k];
       const float le = g.lam[4 * w];
-      const float qa = g.q[ai] * (g.lig[ai] ? le : 1.f), qb = g.q[b] * (g.lig[b] ? le : 1.f);
+      const float qa = window_charge(g, ai, le), qb = window_charge(g, b, le);
       const size_t oa = (size_t)w * g.n + ai, ob = (size_t)w * g.n + b;
       float3 d = make_float3(g.x[ob] - g.x[oa], g.y[ob] - g.y[oa], g.z[ob] - g.z[oa]);
       d.x = fmaf(-B.L[0], rintf(d.x * B.iL[0]), d.x);
@@ -304,6 +363,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
       }
       cx = -fs * d.x; cy = -fs * d.y; cz = -fs * d.z;      // F_i = fs (r_i - r_j)
       ex = 0.5 * (double)en;
+      if (ENERGY == 2)
+        ex = 0.5 * excl_energy_fp64(g, g.box[w], oa, ob, window_charge_fp64(g, ai, (double)le),
+                                    window_charge_fp64(g, b, (double)le));
     }
   }
   for (int o = 8; o < 64; o <<= 1) {
@@ -317,10 +379,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
     const int a = ai;
     if (a >= 0) {
       const size_t o = (size_t)w * g.n + a;
-      const int where = (w << 20) | a;
-      g.fx[o] = to_fixed((double)ox, kForceScale, g.err, kSitePairs, where, g.leg_index);
-      g.fy[o] = to_fixed((double)oy, kForceScale, g.err, kSitePairs, where, g.leg_index);
-      g.fz[o] = to_fixed((double)oz, kForceScale, g.err, kSitePairs, where, g.leg_index);
+      if (step && g.plain) {
+        // the plain form: FP64 atomics into the leg's FP64 sums
+        const size_t wn = (size_t)g.W * g.n;
+        unsafeAtomicAdd(&g.fd[o], (double)ox);
+        unsafeAtomicAdd(&g.fd[wn + o], (double)oy);
+        unsafeAtomicAdd(&g.fd[2 * wn + o], (double)oz);
+      } else {
+        const int where = (w << 20) | a;
+        g.fx[o] = to_fixed((double)ox, kForceScale, g.err, kSitePairs, where, g.leg_index);
+        g.fy[o] = to_fixed((double)oy, kForceScale, g.err, kSitePairs, where, g.leg_index);
+        g.fz[o] = to_fixed((double)oz, kForceScale, g.err, kSitePairs, where, g.leg_index);
+      }
     }
   }
   if (ENERGY) {
@@ -362,7 +432,7 @@ __global__ __launch_bounds__(256) void k_self(const LegDev* legs, BlockMap map) 
   const double le = (double)g.lam[4 * w];
   double s1 = 0.0, s2 = 0.0;
   for (int a = threadIdx.x; a < g.n; a += blockDim.x) {
-    const double q = (double)g.q[a] * (g.lig[a] ? le : 1.0);
+    const double q = window_charge_fp64(g, a, le);
     s1 += q; s2 += q * q;
   }
   __shared__ double r1[256], r2[256];
@@ -383,14 +453,55 @@ __device__ __forceinline__ float3 vec(const LegDev& g, const BoxW& B, size_t ofr
   return min_img(B, g.x[oto] - g.x[ofrom], g.y[oto] - g.y[ofrom], g.z[oto] - g.z[ofrom]);
 }
 
-// items: window x (bonds + 1): harmonic bonds; the last item of a window is
-// the lambda_restraint-scaled Boresch restraint (section "Restraints").
-template <bool ENERGY>
+// Torsion t's energy in FP64 from the raw coordinates (consistent images
+// relative to its first atom)
+__device__ __attribute__((noinline)) double torsion_energy_at(const LegDev& g, int w, int t) {
+  const BoxW& B = g.box[w];
+  const size_t base = (size_t)w * g.n, o0 = base + g.tors[4 * t];
+  double p[4][3];
+  for (int s = 0; s < 4; ++s) {
+    const size_t os = base + g.tors[4 * t + s];
+    double d[3] = {(double)g.x[os] - (double)g.x[o0], (double)g.y[os] - (double)g.y[o0],
+                   (double)g.z[os] - (double)g.z[o0]};
+    for (int c = 0; c < 3; ++c) p[s][c] = d[c] - B.L[c] * rint(d[c] * B.invL[c]);
+  }
+  return torsion_energy_fp64(p, (double)g.tors_k[t], g.tors_n[t], (double)g.tors_phase[t]);
+}
+
+// items: window x (bonds + torsions + 1): harmonic bonds, lambda_vdw-scaled
+// rotatable torsions (section "Double annihilation protocol"); the last item
+// of a window is the lambda_restraint-scaled Boresch restraint (section
+// "Restraints").
+// A bond's energy (k/2)(r - r0)^2 with r in FP64 from the raw coordinates
+__device__ __attribute__((noinline)) double bond_energy_fp64(const LegDev& g, const BoxW& B, size_t oa, size_t ob,
+                                                             int k) {
+  double d[3] = {(double)g.x[oa] - (double)g.x[ob], (double)g.y[oa] - (double)g.y[ob],
+                 (double)g.z[oa] - (double)g.z[ob]};
+  for (int t = 0; t < 3; ++t) d[t] -= B.L[t] * rint(d[t] * B.invL[t]);
+  const double dr = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]) - (double)g.bond_r0[k];
+  return 0.5 * (double)g.bond_k[k] * dr * dr;
+}
+
+// The unscaled Boresch energy in FP64 (anchor positions relative to P1, minimum image)
+__device__ __attribute__((noinline)) double restraint_energy_fp64(const LegDev& g, int w) {
+  const BoxW& B = g.box[w];
+  const size_t base = (size_t)w * g.n, o1 = base + g.ranch[0];
+  double p[6][3];
+  for (int t = 0; t < 6; ++t) {
+    const size_t ot = base + g.ranch[t];
+    double d[3] = {(double)g.x[ot] - (double)g.x[o1], (double)g.y[ot] - (double)g.y[o1],
+                   (double)g.z[ot] - (double)g.z[o1]};
+    for (int c = 0; c < 3; ++c) p[t][c] = d[c] - B.L[c] * rint(d[c] * B.invL[c]);
+  }
+  return boresch_energy_fp64(p, g.rg0d, g.rkd);
+}
+
+template <int ENERGY>
 __global__ __launch_bounds__(256) void k_bonded(const LegDev* legs, BlockMap map) {
   const int leg = find_leg(map, blockIdx.x);
   const LegDev& g = legs[leg];
   const long long i = (long long)(blockIdx.x - map.start[leg]) * blockDim.x + threadIdx.x;
-  const int per = g.nbonds + 1;
+  const int per = g.nbonds + g.ntors + 1;
   const long long tot = (long long)g.W * per;
   const int lane = threadIdx.x & 63;
   double eb = 0.0, er = 0.0;
@@ -406,7 +517,24 @@ __global__ __launch_bounds__(256) void k_bonded(const LegDev* legs, BlockMap map
       const float fs = -g.bond_k[k] * dr / r;                // F_a = fs (r_a - r_b)
       add_force(g, base + a, fs * d.x, fs * d.y, fs * d.z, kSiteBonded);
       add_force(g, base + b, -fs * d.x, -fs * d.y, -fs * d.z, kSiteBonded);
-      eb = 0.5 * (double)g.bond_k[k] * (double)dr * (double)dr;
+      eb = ENERGY == 2 ? bond_energy_fp64(g, g.box[w], base + a, base + b, k)
+                       : 0.5 * (double)g.bond_k[k] * (double)dr * (double)dr;
+    } else if (k < g.nbonds + g.ntors) {
+      const int t = k - g.nbonds;
+      const float lv = g.lam[4 * w + 1];
+      if (lv != 0.0f) {
+        v3 p[4], F[4];
+        const size_t o0 = base + g.tors[4 * t];
+        for (int s = 0; s < 4; ++s) {
+          const size_t os = base + g.tors[4 * t + s];
+          const float3 d = min_img(g.box[w], g.x[os] - g.x[o0], g.y[os] - g.y[o0], g.z[os] - g.z[o0]);
+          p[s] = mk(d.x, d.y, d.z);
+        }
+        const float e = torsion_eval(p, g.tors_k[t], g.tors_n[t], g.tors_phase[t], F);
+        for (int s = 0; s < 4; ++s)
+          add_force(g, base + g.tors[4 * t + s], lv * F[s].x, lv * F[s].y, lv * F[s].z, kSiteBonded);
+        eb = (double)lv * (ENERGY == 2 ? torsion_energy_at(g, w, t) : (double)e);
+      }
     } else if (g.has_rest && g.lam[4 * w + 2] != 0.0f) {
       const float lr = g.lam[4 * w + 2];
       v3 p[6], F[6];
@@ -417,6 +545,7 @@ __global__ __launch_bounds__(256) void k_bonded(const LegDev* legs, BlockMap map
         p[t] = mk(d.x, d.y, d.z);
       }
       er = (double)lr * boresch_eval(p, g.rg0, g.rk, F);
+      if (ENERGY == 2) er = (double)lr * restraint_energy_fp64(g, w);
       for (int t = 0; t < 6; ++t)
         add_force(g, base + g.ranch[t], lr * F[t].x, lr * F[t].y, lr * F[t].z, kSiteBonded);
     }
@@ -474,12 +603,14 @@ void launch_pack(hipStream_t s, const LegDev* d, const LegHost* h, int nl, bool 
   else hipLaunchKernelGGL(k_pack<false>, dim3(nb), dim3(256), 0, s, d, m);
 }
 
-void launch_pairs(hipStream_t s, const LegDev* d, const LegHost* h, int nl, bool energy) {
+void launch_pairs(hipStream_t s, const LegDev* d, const LegHost* h, int nl, int energy, bool step) {
   BlockMap m;
   const int nb = make_map(m, nl, [&](int i) { return blocks_for((long long)h[i].W * h[i].nclus, 4); });
   if (!nb) return;
-  if (energy) hipLaunchKernelGGL(k_pairs<true>, dim3(nb), dim3(256), 0, s, d, m);
-  else hipLaunchKernelGGL(k_pairs<false>, dim3(nb), dim3(256), 0, s, d, m);
+  const int st = step ? 1 : 0;
+  if (energy == 2) hipLaunchKernelGGL(k_pairs<2>, dim3(nb), dim3(256), 0, s, d, m, 0);
+  else if (energy == 1) hipLaunchKernelGGL(k_pairs<1>, dim3(nb), dim3(256), 0, s, d, m, 0);
+  else hipLaunchKernelGGL(k_pairs<0>, dim3(nb), dim3(256), 0, s, d, m, st);
 }
 
 void launch_corrections(hipStream_t s, const LegDev* d, const LegHost* h, int nl, bool energy) {
@@ -490,12 +621,13 @@ void launch_corrections(hipStream_t s, const LegDev* d, const LegHost* h, int nl
   }
 }
 
-void launch_bonded(hipStream_t s, const LegDev* d, const LegHost* h, int nl, bool energy) {
+void launch_bonded(hipStream_t s, const LegDev* d, const LegHost* h, int nl, int energy) {
   BlockMap m;
-  const int nb = make_map(m, nl, [&](int i) { return blocks_for((long long)h[i].W * (h[i].nbonds + 1), 256); });
+  const int nb = make_map(m, nl, [&](int i) { return blocks_for((long long)h[i].W * (h[i].nbonds + h[i].ntors + 1), 256); });
   if (!nb) return;
-  if (energy) hipLaunchKernelGGL(k_bonded<true>, dim3(nb), dim3(256), 0, s, d, m);
-  else hipLaunchKernelGGL(k_bonded<false>, dim3(nb), dim3(256), 0, s, d, m);
+  if (energy == 2) hipLaunchKernelGGL(k_bonded<2>, dim3(nb), dim3(256), 0, s, d, m);
+  else if (energy == 1) hipLaunchKernelGGL(k_bonded<1>, dim3(nb), dim3(256), 0, s, d, m);
+  else hipLaunchKernelGGL(k_bonded<0>, dim3(nb), dim3(256), 0, s, d, m);
 }
 
 void launch_zero_energy(hipStream_t s, const LegDev* d, const LegHost* h, int nl, int c0, int c1) {

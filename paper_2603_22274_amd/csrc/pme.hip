@@ -24,6 +24,7 @@ namespace felis {
 namespace {
 
 constexpr int kLines = 16;
+constexpr float kInvSqrtKE = 0.054876864878355476f;   // 1 / sqrt(KE): packed charges carry sqrt(KE)
 constexpr int kMaxPlane = 4096;                 // x-y plane points transformed whole in LDS (2 x 32 KB)
 constexpr int kXYThreads = 512;                 // threads per whole-plane workgroup: ~one butterfly each
 
@@ -402,8 +403,7 @@ __global__ __launch_bounds__(256) void k_spread(const LegDev* legs, BlockMap map
   const int wave = tid >> 6, lane = tid & 63;
   const int* cst = g.cellstart + (size_t)w * (g.ncell + 1);
   const float4* __restrict__ gs = g.gsten + (size_t)w * g.npad;
-  const float4* __restrict__ pr = g.prm + (size_t)w * g.npad;
-  const float le = g.lam[4 * w];
+  const float4* __restrict__ xq = g.xyzq + (size_t)w * g.npad;
   __syncthreads();
   for (int cb = 0; cb < ncells; cb += 256) {
     const int ci = cb + tid;
@@ -456,9 +456,9 @@ __global__ __launch_bounds__(256) void k_spread(const LegDev* legs, BlockMap map
           const unsigned my = brick_mask(b1, K[1], P0[1], P1[1]);
           const unsigned mz = brick_mask(b2, K[2], P0[2], P1[2]);
           if (mx && my && mz) {
-            const float4 pa = pr[s];                 // sorted parameters: .z ligand flag, .w charge
+            const float qs = xq[s].w * kInvSqrtKE;   // the window's charge (packed times sqrt(KE))
             const int k = atomicAdd(&s_n, 1);
-            s_q[k] = pa.w * (pa.z > 0.0f ? le : 1.0f);
+            s_q[k] = qs;
             bspline4(fr[0], &s_w[k][0], nullptr);
             bspline4(fr[1], &s_w[k][4], nullptr);
             bspline4(fr[2], &s_w[k][8], nullptr);
@@ -554,8 +554,7 @@ __global__ __launch_bounds__(256) void k_gather(const LegDev* legs, BlockMap map
   const int a = ap >= 0 ? ap : 0;
   const int iz = threadIdx.x & 3;
   const size_t o = (size_t)w * g.n + a;
-  const float4 pa = g.prm[lc];                  // sorted parameters: .z ligand flag, .w charge
-  const float q = pa.w * (pa.z > 0.0f ? g.lam[4 * w] : 1.0f);
+  const float q = g.xyzq[lc].w * kInvSqrtKE;    // the window's charge (packed times sqrt(KE))
   const float4 st = g.gsten[lc];               // stencil offsets and bases (from the pack)
   int bb[3];
   unpack_bases(st.w, bb);
@@ -604,7 +603,13 @@ __global__ __launch_bounds__(256) void k_gather(const LegDev* legs, BlockMap map
     const long long ix = to_fixed((double)fx, kForceScale, g.err, kSiteGather, where, g.leg_index);
     const long long iy = to_fixed((double)fy, kForceScale, g.err, kSiteGather, where, g.leg_index);
     const long long iz = to_fixed((double)fz, kForceScale, g.err, kSiteGather, where, g.leg_index);
-    if (STEP) {
+    if (STEP && g.plain) {
+      // the plain form: FP64 atomics into the leg's FP64 sums
+      const size_t wn = (size_t)g.W * g.n;
+      unsafeAtomicAdd(&g.fd[o], (double)fx);
+      unsafeAtomicAdd(&g.fd[wn + o], (double)fy);
+      unsafeAtomicAdd(&g.fd[2 * wn + o], (double)fz);
+    } else if (STEP) {
       g.frx[o] = ix; g.fry[o] = iy; g.frz[o] = iz;
     } else {
       // one writer per atom; atomics without a return value let the wave

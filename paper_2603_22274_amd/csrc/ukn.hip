@@ -40,7 +40,7 @@ struct UknArgs {
   float asc[kMaxLamV];
 };
 
-constexpr int kNU = 3 + kMaxLamV;    // accumulators per frame: LE, LL, UB, E_sc[KV]
+constexpr int kNU = 3 + kMaxLamV;    // accumulators per frame: LE, LL, UB, UT (slot 3; rest unused)
 
 __device__ __forceinline__ float erfc_fit(float x, float* ex) {
   const float t = __builtin_amdgcn_rcpf(fmaf(FELIS_ERFC_P, x, 1.0f));
@@ -68,19 +68,36 @@ __device__ __forceinline__ float3 min_img(const BoxW& B, float dx, float dy, flo
   return make_float3(dx, dy, dz);
 }
 
+// The alchemical charge set B: the ligand atoms, then the alchemical-water
+// atoms.  A window's charges are a + lambda_elec b: b is the ligand charge
+// (minus the offset on an alchemical water, zero elsewhere) and a the
+// environment charge plus the offset (zero on ligand atoms), so the
+// electrostatic energy is E[a,a] + lambda_elec 2 E[a,b] + lambda_elec^2
+// E[b,b]; E_LE = 2 E[a,b] and E_LL = E[b,b].
+__device__ __forceinline__ int bset_atom(const LegDev& g, int t) {
+  return t < g.nlig ? g.lig_idx[t] : g.aw_idx[t - g.nlig];
+}
+__device__ __forceinline__ float charge_b(const LegDev& g, int a) {
+  return g.lig[a] ? g.q[a] : (g.aoff ? -g.aoff[a] : 0.0f);
+}
+__device__ __forceinline__ float charge_a(const LegDev& g, int a) {
+  return g.lig[a] ? 0.0f : (g.aoff ? g.q[a] + g.aoff[a] : g.q[a]);
+}
+
 __device__ __forceinline__ void acc_add(const LegDev& g, int f, int slot, double e) {
   atomicAdd((unsigned long long*)&g.uacc[(size_t)f * kNU + slot],
             (unsigned long long)to_fixed(e, kEnergyScale, g.err, kSiteUkn, f));
 }
 
-// items: frame x ligand atom, 16 lanes per atom: the ligand's unscaled
-// charges of frame f into int64 grid f
+// items: frame x atom of the alchemical charge set, 16 lanes per atom: the
+// b charges of frame f into int64 grid f
 __global__ __launch_bounds__(256) void k_ukn_spread(const LegDev* legs, UknArgs A) {
   const LegDev& g = legs[0];
+  const int nB = g.nlig + g.naw;
   const long long local = (long long)blockIdx.x * 16 + (threadIdx.x >> 4);
-  if (local >= (long long)A.nf * g.nlig) return;
-  const int f = (int)(local / g.nlig);
-  const int a = g.lig_idx[local - (long long)f * g.nlig];
+  if (local >= (long long)A.nf * nB) return;
+  const int f = (int)(local / nB);
+  const int a = bset_atom(g, (int)(local - (long long)f * nB));
   const int sub = threadIdx.x & 15, iy = sub & 3, iz = sub >> 2;
   const size_t o = (size_t)(A.f0 + f) * A.stride + a;
   float fxr, fyr, fzr, wx[4], wy[4], wz[4];
@@ -95,7 +112,7 @@ __global__ __launch_bounds__(256) void k_ukn_spread(const LegDev* legs, UknArgs 
   // p: frame f takes grid f, or grid 2f (imaginary part left zero) when
   // every frame has a grid of its own
   long long* grid = g.grid64 + (size_t)(A.upk ? 2 * f : f) * g.Ktot + ((size_t)gz * g.K[1] + gy) * g.K[0];
-  const double qyz = (double)(g.q[a] * wy[iy] * wz[iz]);
+  const double qyz = (double)(charge_b(g, a) * wy[iy] * wz[iz]);
 #pragma unroll
   for (int ix = 0; ix < 4; ++ix) {
     int gx = bx - ix; if (gx < 0) gx += g.K[0];
@@ -105,8 +122,8 @@ __global__ __launch_bounds__(256) void k_ukn_spread(const LegDev* legs, UknArgs 
 }
 
 // items: frame x block of 256 atoms, 16 lanes per atom, 16 atoms per pass:
-// phi_L of frame f (part f & 1 of complex grid f / 2) at every atom;
-// E_LE += q phi_L over environment atoms, E_LL += q phi_L / 2 over ligand atoms
+// phi_b of frame f (part f & 1 of complex grid f / 2) at every atom;
+// E_LE += a phi_b, E_LL += b phi_b / 2 over all atoms
 __global__ __launch_bounds__(256) void k_ukn_gather(const LegDev* legs, UknArgs A) {
   const LegDev& g = legs[0];
   const int nb = (g.n + 255) / 256;
@@ -139,9 +156,8 @@ __global__ __launch_bounds__(256) void k_ukn_gather(const LegDev* legs, UknArgs 
     ph *= wy[iy] * wz[iz];
     for (int off = 1; off < 16; off <<= 1) ph += __shfl_xor(ph, off, 64);
     if (sub == 0 && valid) {
-      const double qp = (double)g.q[ac] * (double)ph;
-      if (g.lig[ac]) ll += 0.5 * qp;
-      else le += qp;
+      le += (double)charge_a(g, ac) * (double)ph;
+      ll += 0.5 * (double)charge_b(g, ac) * (double)ph;
     }
   }
   le = wave_sum(le);
@@ -171,7 +187,9 @@ __device__ __forceinline__ void block_flush(const double* s_red, double* out, in
              s_red[3 * (1 + kMaxLamV) + t];
 }
 
-// items: frame x block of 256 atoms: ligand-environment pairs within r_c.
+// items: frame x block of 256 atoms: pairs of the alchemical charge set with
+// environment atoms within r_c (an alchemical water's own atoms: excluded-pair
+// erf correction), softcore LJ for the ligand entries.
 // Each lane keeps its own FP64 sums over the ligand atoms for kGV lambda_vdw
 // values at a time; one block partial per frame, block and slot (slot 0
 // Coulomb, 1 + kv softcore LJ at lamv[kv]), unbounded (a frame evaluated at a
@@ -182,15 +200,21 @@ __global__ __launch_bounds__(256) void k_ukn_pairs(const LegDev* legs, UknArgs A
   const int nb = (g.n + 255) / 256;
   const int f = blockIdx.x / nb;
   const int j = (blockIdx.x - f * nb) * 256 + threadIdx.x;
-  __shared__ float4 s_lx[kMaxLigand];     // x, y, z, q
-  __shared__ float2 s_lp[kMaxLigand];     // sigma/2, eps
+  __shared__ float4 s_lx[kMaxLigand];     // x, y, z, b charge
+  __shared__ float2 s_lp[kMaxLigand];     // sigma/2, eps (ligand entries)
+  __shared__ int3 s_aw[kMaxLigand];       // alchemical-water entries: the atom and its two exclusion partners
   __shared__ double s_red[4 * (1 + kMaxLamV)];
   const size_t fo = (size_t)(A.f0 + f) * A.stride;
   const BoxW& B = g.ubox[f];
-  for (int t = threadIdx.x; t < g.nlig; t += blockDim.x) {
-    const int a = g.lig_idx[t];
-    s_lx[t] = make_float4(A.fx[fo + a], A.fy[fo + a], A.fz[fo + a], g.q[a]);
+  const int nB = g.nlig + g.naw;
+  for (int t = threadIdx.x; t < nB; t += blockDim.x) {
+    const int a = bset_atom(g, t);
+    s_lx[t] = make_float4(A.fx[fo + a], A.fy[fo + a], A.fz[fo + a], charge_b(g, a));
     s_lp[t] = make_float2(0.5f * g.sig[a], g.eps[a]);
+    if (t >= g.nlig) {
+      const int k = t - g.nlig;
+      s_aw[t] = make_int3(a, g.aw_idx[g.naw + 2 * k], g.aw_idx[g.naw + 2 * k + 1]);
+    }
   }
   __syncthreads();
   const bool env = j < g.n && !g.lig[j];
@@ -198,7 +222,7 @@ __global__ __launch_bounds__(256) void k_ukn_pairs(const LegDev* legs, UknArgs A
   double hs = 0.0, epsj = 0.0;
   if (env) {
     xj = A.fx[fo + j]; yj = A.fy[fo + j]; zj = A.fz[fo + j];
-    qj = g.q[j]; hs = 0.5 * (double)g.sig[j]; epsj = (double)g.eps[j];
+    qj = charge_a(g, j); hs = 0.5 * (double)g.sig[j]; epsj = (double)g.eps[j];
   }
   const double Lx = B.L[0], Ly = B.L[1], Lz = B.L[2], iLx = B.invL[0], iLy = B.invL[1], iLz = B.invL[2];
   const float c_ke = (float)kKE;
@@ -207,8 +231,9 @@ __global__ __launch_bounds__(256) void k_ukn_pairs(const LegDev* legs, UknArgs A
     double esc[kGV];
 #pragma unroll
     for (int t = 0; t < kGV; ++t) esc[t] = 0.0;
-    for (int li = 0; li < g.nlig; ++li) {
+    for (int li = 0; li < nB; ++li) {
       const float4 L = s_lx[li];
+      const bool awe = li >= g.nlig;             // uniform: an alchemical-water entry (no softcore)
       // the distance in FP64 (minimum image included): a frame evaluated at a
       // state it was not sampled in can hold r^-12 overlaps of 1e6 kT, where
       // FP32 distances would lose six digits
@@ -217,16 +242,27 @@ __global__ __launch_bounds__(256) void k_ukn_pairs(const LegDev* legs, UknArgs A
       dy = fma(-Ly, rint(dy * iLy), dy);
       dz = fma(-Lz, rint(dz * iLz), dz);
       const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
-      const bool in = env && r2 < g.rc2d;
+      bool in = env && r2 < g.rc2d;
+      bool exc = false;
+      if (awe) {
+        const int3 e3 = s_aw[li];
+        in = in && j != e3.x;                    // never the water's own atom
+        exc = in && (j == e3.y || j == e3.z);    // its own water: excluded pair
+      }
       if (__ballot(in) == 0ull) continue;
       const double r2s = in ? r2 : 1.0;
       if (v0 == 0) {
         const float r2f = (float)r2s;
         const float rinv = __builtin_amdgcn_rsqf(r2f);
-        float ex;
-        const float erfcv = erfc_fit(g.alpha * r2f * rinv, &ex);
-        if (in) ec += (double)(c_ke * L.w * qj * erfcv * rinv);
+        if (exc) {
+          ec -= (double)(c_ke * L.w * qj * erff(g.alpha * r2f * rinv) * rinv);
+        } else {
+          float ex;
+          const float erfcv = erfc_fit(g.alpha * r2f * rinv, &ex);
+          if (in) ec += (double)(c_ke * L.w * qj * erfcv * rinv);
+        }
       }
+      if (awe) continue;                         // an alchemical water keeps its LJ (no lambda dependence)
       const double sg = (double)s_lp[li].x + hs;
       const double s2 = sg * sg;
       const double s6 = s2 * s2 * s2;
@@ -248,14 +284,15 @@ __global__ __launch_bounds__(256) void k_ukn_pairs(const LegDev* legs, UknArgs A
   block_flush(s_red, g.upart + (size_t)blockIdx.x * (1 + kMaxLamV), 1 + A.KV);
 }
 
-// one block per frame: ligand-ligand pairs, excluded-pair corrections and the
-// Boresch energy; one partial row per frame (slot 0 E_LL real space, 1 + kv
+// one block per frame: pairs within the alchemical charge set (Coulomb of the
+// b charges; softcore LJ between ligand atoms), excluded-pair corrections and
+// the Boresch energy; one partial row per frame (slot 0 E_LL real space, 1 + kv
 // softcore LJ), the same per-lane accumulation as k_ukn_pairs
 __global__ __launch_bounds__(256) void k_ukn_ligand(const LegDev* legs, UknArgs A) {
   const LegDev& g = legs[0];
   const int f = blockIdx.x;
   const size_t fo = (size_t)(A.f0 + f) * A.stride;
-  const int nl = g.nlig;
+  const int nl = g.nlig + g.naw;                 // the alchemical charge set
   const int np = nl * (nl - 1) / 2;
   const float c_ke = (float)kKE;
   __shared__ double s_red[4 * (1 + kMaxLamV)];
@@ -273,7 +310,8 @@ __global__ __launch_bounds__(256) void k_ukn_ligand(const LegDev* legs, UknArgs 
         int i = 0, rem = p;
         while (rem >= nl - 1 - i) { rem -= nl - 1 - i; ++i; }
         const int jl = i + 1 + rem;
-        const int a = g.lig_idx[i], b = g.lig_idx[jl];
+        const int a = bset_atom(g, i), b = bset_atom(g, jl);
+        const bool both_lig = i < g.nlig && jl < g.nlig;   // softcore only between ligand atoms
         bool exc = false;
         for (int k = g.excl_ptr[a]; k < g.excl_ptr[a + 1]; ++k) exc |= (g.excl_idx[k] == b);
         const BoxW& B = g.ubox[f];
@@ -285,7 +323,7 @@ __global__ __launch_bounds__(256) void k_ukn_ligand(const LegDev* legs, UknArgs 
         dzd = fma(-B.L[2], rint(dzd * B.invL[2]), dzd);
         const double r2d = fma(dxd, dxd, fma(dyd, dyd, dzd * dzd));
         const float r2 = (float)r2d;
-        const float qq = c_ke * g.q[a] * g.q[b];
+        const float qq = c_ke * charge_b(g, a) * charge_b(g, b);
         if (exc) {
           if (v0 == 0) {
             const float r = sqrtf(r2);
@@ -293,7 +331,7 @@ __global__ __launch_bounds__(256) void k_ukn_ligand(const LegDev* legs, UknArgs 
                                : (double)(qq * 2.0f * g.alpha * 0.56418958354775628f);
           }
         } else if (r2d < g.rc2d) {
-          in = true;
+          in = both_lig;
           r2s = r2d;
           if (v0 == 0) {
             const float rinv = __builtin_amdgcn_rsqf(r2);
@@ -332,29 +370,47 @@ __global__ __launch_bounds__(256) void k_ukn_ligand(const LegDev* legs, UknArgs 
     }
     acc_add(g, f, 2, boresch_eval(p, g.rg0, g.rk, nullptr));
   }
+  if (threadIdx.x == 64 && g.ntors > 0) {
+    // rotatable torsions, unscaled, in FP64 (slot 3)
+    double ut = 0.0;
+    for (int t = 0; t < g.ntors; ++t) {
+      const size_t o0 = fo + g.tors[4 * t];
+      const BoxW& B = g.ubox[f];
+      double p[4][3];
+      for (int s = 0; s < 4; ++s) {
+        const size_t os = fo + g.tors[4 * t + s];
+        double d[3] = {(double)A.fx[os] - (double)A.fx[o0], (double)A.fy[os] - (double)A.fy[o0],
+                       (double)A.fz[os] - (double)A.fz[o0]};
+        for (int c = 0; c < 3; ++c) p[s][c] = d[c] - B.L[c] * rint(d[c] * B.invL[c]);
+      }
+      ut += torsion_energy_fp64(p, (double)g.tors_k[t], g.tors_n[t], (double)g.tors_phase[t]);
+    }
+    acc_add(g, f, 3, ut);
+  }
 }
 
-// one block: lambda-independent constants of E_LE / E_LL that depend only on
-// charges: ligand self term and the two background terms
+// one block: the constants of E_LE / E_LL that depend only on charges: the
+// self terms and the two background terms
 __global__ __launch_bounds__(256) void k_ukn_const(const LegDev* legs, double* out) {
   const LegDev& g = legs[0];
-  double qe = 0.0, ql = 0.0, ql2 = 0.0;
+  double qa = 0.0, qb = 0.0, qb2 = 0.0, qab = 0.0;
   for (int a = threadIdx.x; a < g.n; a += blockDim.x) {
-    const double q = (double)g.q[a];
-    if (g.lig[a]) { ql += q; ql2 += q * q; } else qe += q;
+    const double ca = (double)charge_a(g, a), cb = (double)charge_b(g, a);
+    qa += ca; qb += cb; qb2 += cb * cb; qab += ca * cb;
   }
-  __shared__ double r[3][256];
-  r[0][threadIdx.x] = qe; r[1][threadIdx.x] = ql; r[2][threadIdx.x] = ql2;
+  __shared__ double r[4][256];
+  r[0][threadIdx.x] = qa; r[1][threadIdx.x] = qb; r[2][threadIdx.x] = qb2; r[3][threadIdx.x] = qab;
   __syncthreads();
   for (int s = 128; s > 0; s >>= 1) {
     if (threadIdx.x < s)
-      for (int k = 0; k < 3; ++k) r[k][threadIdx.x] += r[k][threadIdx.x + s];
+      for (int k = 0; k < 4; ++k) r[k][threadIdx.x] += r[k][threadIdx.x + s];
     __syncthreads();
   }
   if (threadIdx.x == 0) {
     out[0] = 2.0 * r[0][0] * r[1][0];             // E_LE background / (-bg_pref)
     out[1] = r[1][0] * r[1][0];                   // E_LL background / (-bg_pref)
-    out[2] = -(double)g.self_pref * r[2][0];      // E_LL self term
+    out[2] = -g.self_pref * r[2][0];              // E_LL self term
+    out[3] = -2.0 * g.self_pref * r[3][0];        // E_LE self term (atoms with both a and b charges)
   }
 }
 
@@ -380,7 +436,7 @@ __global__ __launch_bounds__(256) void k_ukn_combine(const LegDev* legs, UknArgs
   const LegDev& g = legs[0];
   const int f = blockIdx.x;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int nb = g.nlig > 0 ? (g.n + 255) / 256 : 0;     // no ligand: no pair partials
+  const int nb = g.nlig + g.naw > 0 ? (g.n + 255) / 256 : 0;     // no alchemical charges: no pair partials
   __shared__ double s_p[1 + kMaxLamV];
   const double* pp = g.upart + (size_t)f * nb * (1 + kMaxLamV);
   const double* lp = g.lpart + (size_t)f * (1 + kMaxLamV);
@@ -393,17 +449,18 @@ __global__ __launch_bounds__(256) void k_ukn_combine(const LegDev* legs, UknArgs
   __syncthreads();
   const long long* acc = g.uacc + (size_t)f * kNU;
   const double s = 1.0 / kEnergyScale;
-  const bool has_l = g.nlig > 0;
+  const bool has_l = g.nlig + g.naw > 0;
   const double bg = g.ubox[f].bg_pref;
   const double pv = C.pressure * g.ubox[f].vol;
   for (int k = threadIdx.x; k < K; k += blockDim.x) {
     const int kv = C.kv[k];
-    const double ele = (double)acc[0] * s - bg * cst[0] + s_p[0];
+    const double ele = (double)acc[0] * s - bg * cst[0] + s_p[0] + cst[3];
     const double ell = (double)acc[1] * s + cst[2] - bg * cst[1] + (has_l ? lp[0] : 0.0);
     const double ub = (double)acc[2] * s;
+    const double ut = (double)acc[3] * s;
     const double esc = s_p[1 + kv] + (has_l ? lp[1 + kv] : 0.0);
-    const double le = C.le[k], lr = C.lr[k];
-    u[(long long)k * u_stride + A.f0 + f] = beta * (le * ele + le * le * ell + esc + lr * ub + pv);
+    const double le = C.le[k], lr = C.lr[k], lv = (double)A.lamv[kv];
+    u[(long long)k * u_stride + A.f0 + f] = beta * (le * ele + le * le * ell + esc + lr * ub + lv * ut + pv);
   }
 }
 
@@ -414,7 +471,8 @@ int launch_ukn(hipStream_t s, const LegDev* d, const LegHost& h, double sc_alpha
                long long n_frames, const double* frame_box, double pressure, double beta, double* u,
                long long u_stride, long long* uacc, double* cst) {
   if (K < 1 || K > kMaxStates) return FELIS_E_UNSUPPORTED;
-  if (h.nlig > kMaxLigand) return FELIS_E_UNSUPPORTED;
+  const int nB = h.nlig + h.naw;
+  if (nB > kMaxLigand) return FELIS_E_UNSUPPORTED;
   UknArgs A;
   CombineArgs C;
   A.fx = fx; A.fy = fy; A.fz = fz;
@@ -449,8 +507,8 @@ int launch_ukn(hipStream_t s, const LegDev* d, const LegHost& h, double sc_alpha
     A.nf = nf;
     launch_fill_i64(s, uacc, (size_t)nf * kNU);
     hipLaunchKernelGGL(k_ukn_boxes, dim3(1), dim3(256), 0, s, d, A, frame_box);
-    if (h.nlig) {
-      hipLaunchKernelGGL(k_ukn_spread, dim3((unsigned)(((long long)nf * h.nlig + 15) / 16)), dim3(256), 0, s, d, A);
+    if (nB) {
+      hipLaunchKernelGGL(k_ukn_spread, dim3((unsigned)(((long long)nf * nB + 15) / 16)), dim3(256), 0, s, d, A);
       launch_pme_fft(s, d, &h, 1, frame_box ? 2 : 1);
       hipLaunchKernelGGL(k_ukn_gather, dim3((unsigned)(nf * nb)), dim3(256), 0, s, d, A);
       hipLaunchKernelGGL(k_ukn_pairs, dim3((unsigned)(nf * nb)), dim3(256), 0, s, d, A);

@@ -44,6 +44,8 @@ class FelisLeg(C.Structure):
         ('fx', vp), ('fy', vp), ('fz', vp), ('energy', vp),
         ('seed', C.c_uint64), ('step', C.c_int64), ('list_cap', C.c_int32),
         ('pressure_bar', C.c_double), ('barostat_every', C.c_int32),
+        ('n_torsions', C.c_int32), ('torsion_ijkl', vp), ('torsion_k', vp), ('torsion_n', vp),
+        ('torsion_phase', vp), ('alch_offset', vp), ('plain_fp64', C.c_int32),
         ('work', vp), ('work_bytes', C.c_size_t),
     ]
 
@@ -153,7 +155,7 @@ class Leg:
     a synthetic system (``paper_2603_22274_amd.gen.System``)."""
 
     def __init__(self, ctx: Context, sysd, windows=None, seed=1234, device='cuda', list_cap=0, positions=None,
-                 pressure_bar=0.0, barostat_every=25):
+                 pressure_bar=0.0, barostat_every=25, plain_fp64=False):
         self.sys = sysd
         self.ctx = ctx
         lam = sysd.lambdas if windows is None else sysd.lambdas[windows]
@@ -176,6 +178,13 @@ class Leg:
         self.bond_r0 = t(sysd.bond_r0 if nb else np.zeros(1, np.float32), torch.float32)
         nw = len(sysd.waters)
         self.water = t(sysd.waters.reshape(-1, 3) if nw else np.zeros((1, 3), np.int32), torch.int32)
+        nt = 0 if getattr(sysd, 'torsions', None) is None else len(sysd.torsions)
+        self.tors = t(sysd.torsions.reshape(-1, 4) if nt else np.zeros((1, 4), np.int32), torch.int32)
+        self.tors_k = t(sysd.torsion_k if nt else np.zeros(1, np.float32), torch.float32)
+        self.tors_n = t(sysd.torsion_n if nt else np.ones(1, np.int32), torch.int32)
+        self.tors_phase = t(sysd.torsion_phase if nt else np.zeros(1, np.float32), torch.float32)
+        off = getattr(sysd, 'alch_offset', None)
+        self.alch_offset = t(off, torch.float32) if off is not None and np.any(off) else None
         pos = sysd.pos if positions is None else positions
         pos = np.asarray(pos, np.float32)
         if pos.ndim == 2:
@@ -221,6 +230,11 @@ class Leg:
         s.step = 0
         s.list_cap = list_cap
         s.pressure_bar, s.barostat_every = float(pressure_bar), int(barostat_every)
+        s.n_torsions = nt
+        s.torsion_ijkl, s.torsion_k = _ptr(self.tors), _ptr(self.tors_k)
+        s.torsion_n, s.torsion_phase = _ptr(self.tors_n), _ptr(self.tors_phase)
+        s.alch_offset = _ptr(self.alch_offset)
+        s.plain_fp64 = 1 if plain_fp64 else 0
         nbytes = C.c_size_t(0)
         ctx.check(lib().felis_leg_work_size(C.byref(s), C.byref(nbytes)))
         self.work = torch.empty(int(nbytes.value), dtype=torch.uint8, device=dev)
@@ -269,18 +283,20 @@ def leg_footprint(sysd, n_windows=None, list_cap=0, pressure_bar=0.0):
     s.list_cap = list_cap
     s.pressure_bar, s.barostat_every = float(pressure_bar), 25
     s.n_excl, s.n_bonds, s.n_waters = len(sysd.excl), len(sysd.bonds), len(sysd.waters)
+    s.n_torsions = 0 if getattr(sysd, 'torsions', None) is None else len(sysd.torsions)
     # felis_leg_work_size validates but never dereferences the arrays
     fake = C.c_void_p(256)
     for k in ('charge', 'sigma', 'epsilon', 'mass', 'is_ligand', 'excl_ij', 'excl_ptr', 'excl_idx', 'bond_ij',
               'bond_k', 'bond_r0', 'water_ohh', 'lambdas', 'x', 'y', 'z', 'vx', 'vy', 'vz', 'fx', 'fy', 'fz',
-              'energy'):
+              'energy', 'torsion_ijkl', 'torsion_k', 'torsion_n', 'torsion_phase'):
         setattr(s, k, fake)
     nbytes = C.c_size_t(0)
     rc = lib().felis_leg_work_size(C.byref(s), C.byref(nbytes))
     if rc:
         raise FelisError(rc, "leg configuration rejected")
     state = W * N * (6 * 4 + 3 * 8) + W * NE * 8
-    topo = N * 17 + (N + 1) * 4 + len(sysd.excl) * 12 + len(sysd.bonds) * 16 + len(sysd.waters) * 12
+    topo = (N * 17 + (N + 1) * 4 + len(sysd.excl) * 12 + len(sysd.bonds) * 16 + len(sysd.waters) * 12
+            + s.n_torsions * 28)
     return int(nbytes.value) + state + topo
 
 

@@ -73,6 +73,15 @@ class System:
     restraint_g0: np.ndarray | None = None      # (6,) r, thetaA, thetaB, phiA, phiB, phiC
     restraint_k: np.ndarray | None = None       # (6,)
     spline_order: int = 4
+    # rotatable ligand torsions, scaled by lambda_vdw: energy k [1 + cos(n phi - delta)]
+    torsions: np.ndarray | None = None          # (nt, 4) int32 atoms a-b-c-d (rotatable bond b-c)
+    torsion_k: np.ndarray | None = None         # (nt,) float32 kcal/mol
+    torsion_n: np.ndarray | None = None         # (nt,) int32 periodicity
+    torsion_phase: np.ndarray | None = None     # (nt,) float32 rad
+    # alchemical waters (charged ligands): the oxygen of each designated water
+    # carries (1 - lambda_elec) * alch_offset[i] on top of its charge, so that
+    # the system's net charge stays that of the coupled state in every window
+    alch_offset: np.ndarray | None = None       # (N,) float32 e, nonzero only on alchemical-water oxygens
 
     @property
     def n_atoms(self) -> int:
@@ -386,6 +395,78 @@ def config0(seed=BASE_SEED):
     cutoff 9 A, PME grid 20^3, 12 windows."""
     return solvent_leg(config=0, seed=seed, n_waters=216, lattice_n=6, box_edge=18.6, n_lig=20,
                        r_cut=9.0, grid=(20, 20, 20), skin=0.25, sched='cfg0', keep_all_sites=True)
+
+
+def ligand_torsions(sysd, seed=BASE_SEED, config=50):
+    """Give the ligand chain of ``sysd`` rotatable torsions: every consecutive
+    quadruple a-b-c-d of the chain (rotatable bond b-c), with seeded
+    k ~ U[0.5, 3] kcal/mol, periodicity n ~ {1, 2, 3} and phase {0, pi}
+    (synthetic stand-ins for a force field's terms on rotatable bonds)."""
+    lig = np.where(sysd.is_ligand.astype(bool))[0]
+    quads = np.array([lig[i:i + 4] for i in range(len(lig) - 3)], np.int32).reshape(-1, 4)
+    rng = _rng(config, 7, seed)
+    t = len(quads)
+    return dataclasses.replace(sysd, torsions=quads, torsion_k=rng.uniform(0.5, 3.0, t).astype(np.float32),
+                               torsion_n=rng.integers(1, 4, t).astype(np.int32),
+                               torsion_phase=(np.pi * rng.integers(0, 2, t)).astype(np.float32))
+
+
+def torsion_leg(seed=BASE_SEED):
+    """The 12-window small solvent leg (216 waters, 20-atom ligand) whose
+    ligand carries 17 rotatable torsions scaled with lambda_vdw."""
+    return ligand_torsions(config0(seed), seed)
+
+
+AW_MAX_POS, AW_MAX_NEG = 0.6, 0.4      # largest charge one alchemical water takes up (e)
+
+
+def alchemical_water_count(q_ligand):
+    """Fewest alchemical waters that take up a ligand net charge q_ligand with
+    every water's offset within [-0.4, +0.6] e (the count is the same in every
+    window: the decoupled window needs the whole charge)."""
+    if abs(q_ligand) < 1e-12:
+        return 0
+    cap = AW_MAX_POS if q_ligand > 0 else AW_MAX_NEG
+    return int(math.ceil(abs(q_ligand) / cap - 1e-9))
+
+
+def charged_leg(seed=BASE_SEED, q_ligand=1.0, config=51):
+    """The small solvent leg (18.6 A box, 20-atom ligand, cutoff 9 A, PME 20^3,
+    12 windows) with a charged ligand: ligand charges N(0, 0.3) shifted to a
+    net q_ligand, the lattice waters farthest from the ligand replaced by
+    counter-ions (one per unit charge: the coupled state is neutral for an
+    integer q_ligand), rotatable ligand torsions, and
+    the alchemical waters that keep every window neutral -- the waters whose
+    oxygens lie farthest from the ligand's centre."""
+    box = np.array([18.6] * 3)
+    sites = _lattice(6, 3.1)
+    rng_l = _rng(config, 1, seed)
+    center = box / 2 + rng_l.uniform(-0.3, 0.3, 3)
+    lig_xyz = _self_avoiding_walk(rng_l, 20, center, box, obstacles=sites, d_obs=2.1)
+    q, sg, ep = _ligand_params(_rng(config, 4, seed), 20)
+    q = q + q_ligand / 20.0
+    c = lig_xyz.mean(0)
+    dist = np.linalg.norm((sites - c) - box * np.round((sites - c) / box), axis=1)
+    order = np.argsort(-dist, kind='stable')            # farthest first
+    n_ion = int(round(abs(q_ligand)))                    # one counter-ion per unit of ligand charge
+    ion_sites = set(int(k) for k in order[:n_ion])
+    n_aw = alchemical_water_count(q_ligand)
+    wsites = np.array([k for k in range(len(sites)) if k not in ion_sites])
+    wxyz = _orient_waters(_rng(config, 3, seed), sites[wsites], box, fixed_pts=lig_xyz)
+    b = _Builder()
+    b.add_chain(lig_xyz, q, sg, ep, 1)
+    ion = ION_CL if q_ligand > 0 else ION_NA
+    for k in order[:n_ion]:
+        b.add(sites[k][None], ion['q'], ion['sigma'], ion['eps'], ion['mass'], 0)
+    b.add_waters(wxyz)
+    sysd = b.finish(f'charged{config}', box, schedule('cfg0'), 9.0, 0.25, 5e-4, (20, 20, 20))
+    # alchemical waters: the next-farthest sites, as waters
+    aw_sites = [int(k) for k in order[n_ion:]][:n_aw]
+    off = np.zeros(sysd.n_atoms, np.float32)
+    for k in aw_sites:
+        w = int(np.where(wsites == k)[0][0])
+        off[sysd.waters[w, 0]] = q_ligand / n_aw
+    return ligand_torsions(dataclasses.replace(sysd, alch_offset=off), seed, config)
 
 
 def config1(seed=BASE_SEED):

@@ -205,7 +205,7 @@ class FelisEngine:
     """Engine over the C ABI: one context, device-resident legs."""
 
     def __init__(self, ctx, dt=0.002, temperature=300.0, gamma=0.5, list_cap=0, mbar_tol=1e-10,
-                 mbar_max_iter=20000):
+                 mbar_max_iter=20000, keep_frames=False):
         from . import felis
         self.felis = felis
         self.ctx = ctx
@@ -213,6 +213,12 @@ class FelisEngine:
         self.beta = 1.0 / (KB * temperature)
         self.list_cap = list_cap
         self.tol, self.max_iter = mbar_tol, mbar_max_iter
+        # keep_frames: every sample's coordinates and replica -> state map stay
+        # on the device after the leg finishes (frames[rid]: list of (W, N, 3)
+        # tensors; states[rid]: list of numpy arrays), for checking a served
+        # result against another implementation on the same frames
+        self.keep_frames = keep_frames
+        self.frames, self.states = {}, {}
 
     def footprint(self, r):
         """Device bytes a leg holds while active: scratch, state, topology and
@@ -256,6 +262,9 @@ class FelisEngine:
         boxes = f.leg_boxes_device(self.ctx, h.leg, h.boxes) if h.boxes is not None else None
         f.ukn(self.ctx, h.leg, h.leg.lambdas, h.leg.x, h.leg.y, h.leg.z, self.beta, out=col, boxes=boxes)
         r = h.req
+        if self.keep_frames:
+            self.frames.setdefault(r.rid, []).append(h.leg.positions().clone())
+            self.states.setdefault(r.rid, []).append(f.leg_states(self.ctx, h.leg))
         if r.exchange_every and ((h.k + 1) * r.sample_every) % r.exchange_every == 0:
             # replica exchange from this sample's u[state][replica] (no host sync)
             f.hrex(self.ctx, h.leg, col, h.attempts, r.seed, count=False)

@@ -175,3 +175,27 @@ def test_capacity_retry_and_eviction_isolated(F, legs):
     out, stats = _serve(ctx, [_req(0, A, 0.0, 21), _req(1, B, 0.0, 22, cap=8)], max_retries=0)
     assert out[1].status.startswith('evicted') and 'capacity' in out[1].status
     assert out[0].status == 'ok' and out[0].dG == ref_a[0].dG
+
+
+def test_served_dg_matches_oracle_on_its_frames(F, legs):
+    """A served leg's Delta G (GPU u_kn at sample time + GPU MBAR at the end,
+    inside the serving loop, beside another leg) against the oracle's u_kn and
+    MBAR evaluated on the frames that leg produced."""
+    felis, ctx = F
+    from oracle import mbar as ombar, ukn as oukn
+    from paper_2603_22274_amd import serve
+    A, B, _ = legs
+    reqs = [serve.Request(0, 0.0, A, 300, 50, seed=31), serve.Request(1, 0.0, B, 300, 50, seed=32)]
+    eng = serve.FelisEngine(ctx, keep_frames=True, mbar_tol=1e-12)
+    out, _ = serve.Server(eng, hbm_budget=16 << 30, epoch_steps=50).serve(reqs)
+    res = out[0]
+    assert res.status == 'ok', res.status
+    W = A.n_windows
+    frames = torch.cat(eng.frames[0], 0).cpu().numpy().astype(np.float64)     # sample-major, replica order
+    n_samples = len(eng.frames[0])
+    assert frames.shape == (n_samples * W, A.n_atoms, 3)
+    ref_u = oukn.ukn(A, frames, A.lambdas, BETA)
+    f_ref, _ = ombar.mbar(ref_u, np.full(W, n_samples), tol=1e-12, max_iter=2000000)
+    dg_ref = (f_ref[-1] - f_ref[0]) / BETA
+    print('served dG', res.dG, 'oracle', dg_ref)
+    assert abs(res.dG - dg_ref) <= 0.01, (res.dG, dg_ref)
