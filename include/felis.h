@@ -19,12 +19,13 @@
  * Memory: every device buffer is allocated and owned by the caller (e.g. a
  * PyTorch tensor's data pointer).  The library never frees caller memory and
  * allocates device memory only in felis_create (a few KB of tables and an
- * error word).  Per-leg scratch lives in caller memory sized by
+ * error word); felis_mbar_noalloc uses a static 64 MiB device array instead
+ * of a workspace.  Per-leg scratch lives in caller memory sized by
  * felis_leg_work_size.
  * Streams: every call is enqueued on the HIP stream given to felis_create and
  * returns without waiting, except felis_leg_init, felis_check,
- * felis_check_detail, felis_leg_rebuilds, felis_nlist_export_pairs and
- * felis_mbar (they synchronise that stream).
+ * felis_check_detail, felis_leg_rebuilds, felis_nlist_export_pairs,
+ * felis_mbar and felis_mbar_noalloc (they synchronise that stream).
  * Errors: every function returns FELIS_OK (0) or a negative FELIS_E_* code; no
  * exception crosses the ABI and nothing aborts.  Device-side faults (list
  * capacity, fixed-point overflow, non-finite forces) are latched in a device
@@ -396,6 +397,21 @@ int felis_mbar_work_size(int K, int64_t n_total, size_t* bytes);
 int felis_mbar(felis_ctx* ctx, const double* u, const int32_t* N_k, int K, int64_t n_total,
                double rel_tol, int max_iter, double* f_out, int* iters, void* work,
                size_t work_bytes);
+
+/* felis_mbar without a workspace argument, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc): the same solver and result as felis_mbar, with its
+ * scratch in a static device array of 64 MiB that each device holds from the
+ * first felis_create on it until the process ends.  Allocates nothing (no
+ * hipMalloc, hipFree or allocating library call).  FELIS_E_CAPACITY (with a
+ * message giving the bytes needed) when the input needs more than 64 MiB of
+ * scratch (about (K + 1) n_total + K^2 (n_total / 4096 + 1) doubles; e.g.
+ * 42 states x 84,000 samples fit); other errors as felis_mbar.  The array is
+ * shared by every call on a device and keeps the last call's contents: calls
+ * that overlap on one device (several contexts or threads) race.
+ * Synchronises the context's stream. */
+int felis_mbar_noalloc(felis_ctx* ctx, const double* u, const int32_t* N_k, int K, int64_t n_total,
+                       double rel_tol, int max_iter, double* f_out, int* iters);
 
 #ifdef __cplusplus
 }

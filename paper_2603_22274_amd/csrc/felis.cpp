@@ -404,7 +404,8 @@ int felis_create(felis_ctx** out, int device, void* hip_stream) {
       hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess ||
-      hipMemset(c->d_err, 0, 8 * sizeof(int)) != hipSuccess) {
+      hipMemset(c->d_err, 0, 8 * sizeof(int)) != hipSuccess ||
+      mbar_scratch_setup(device) != FELIS_OK) {
     felis_destroy(c);
     return FELIS_E_DEVICE;
   }
@@ -1073,6 +1074,26 @@ int felis_mbar(felis_ctx* c, const double* u, const int32_t* N_k, int K, int64_t
   if (!c) return FELIS_E_INVAL;
   int rc = launch_mbar(c->stream, u, N_k, K, n_total, rel_tol, max_iter, f_out, iters, work, work_bytes);
   if (rc == FELIS_E_INVAL) return fail(c, rc, "MBAR arguments (K in [2, 512], sum N_k = n_total, work size)");
+  if (rc == FELIS_E_NOCONV) return fail(c, rc, "MBAR did not converge within max_iter");
+  if (rc) return fail(c, rc, "MBAR device error");
+  return launched(c);
+}
+
+int felis_mbar_noalloc(felis_ctx* c, const double* u, const int32_t* N_k, int K, int64_t n_total, double rel_tol,
+                       int max_iter, double* f_out, int* iters) {
+  if (!c) return FELIS_E_INVAL;
+  if (!u || !N_k || !f_out || !(rel_tol > 0) || max_iter < 1)
+    return fail(c, FELIS_E_INVAL, "MBAR arguments (K in [2, 512], sum N_k = n_total)");
+  if (K >= 2 && K <= 512 && n_total >= 1 && mbar_work_bytes(K, n_total) > kMbarStaticBytes) {
+    char msg[200];
+    std::snprintf(msg, sizeof msg,
+                  "K = %d states x %lld samples need %zu bytes of MBAR scratch; the allocation-free entry point "
+                  "holds %zu (use felis_mbar with a workspace)",
+                  K, (long long)n_total, mbar_work_bytes(K, n_total), kMbarStaticBytes);
+    return fail(c, FELIS_E_CAPACITY, msg);
+  }
+  int rc = launch_mbar_noalloc(c->device, c->stream, u, N_k, K, n_total, rel_tol, max_iter, f_out, iters);
+  if (rc == FELIS_E_INVAL) return fail(c, rc, "MBAR arguments (K in [2, 512], sum N_k = n_total)");
   if (rc == FELIS_E_NOCONV) return fail(c, rc, "MBAR did not converge within max_iter");
   if (rc) return fail(c, rc, "MBAR device error");
   return launched(c);

@@ -387,5 +387,10 @@ void launch_baro_accept(hipStream_t s, const LegDev* d, const LegHost* h, int nl
 int launch_mbar(hipStream_t s, const double* u, const int* N_k, int K, long long Ntot, double tol,
                 int max_iter, double* f_out, int* iters, void* work, size_t work_bytes);
 size_t mbar_work_bytes(int K, long long Ntot);
+// allocation-free MBAR: workspace in a static device array of kMbarStaticBytes
+constexpr size_t kMbarStaticBytes = size_t(64) << 20;
+int mbar_scratch_setup(int device);
+int launch_mbar_noalloc(int device, hipStream_t s, const double* u, const int* N_k, int K, long long Ntot,
+                        double tol, int max_iter, double* f_out, int* iters);
 
 }  // namespace felis

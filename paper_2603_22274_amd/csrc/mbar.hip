@@ -18,6 +18,7 @@
 // of the 16x16 tiles of W W^T, and a fixed-order reduction over chunks.  The
 // K x K Newton system is solved on the host.
 #include <cmath>
+#include <mutex>
 #include <vector>
 
 #include "felis_internal.h"
@@ -314,6 +315,47 @@ int launch_mbar(hipStream_t s, const double* u, const int* N_k, int K, long long
   for (int k = 0; k < K; ++k)
     if (!std::isfinite(f_out[k])) return FELIS_E_NOCONV;
   return done ? FELIS_OK : FELIS_E_NOCONV;
+}
+
+// ---- allocation-free MBAR
+//
+// Workspace in a file-scope device array, for callers that cannot allocate
+// device memory.  Host code never passes `scratch` itself to a kernel (in
+// host code the name is a stand-in, not a device address): its device
+// address is looked up once per device with hipGetSymbolAddress at context
+// creation and kept in g_scratch[device].  Every region of the workspace is
+// written by a kernel before any kernel reads it, so nothing needs clearing
+// between calls; calls that overlap on one device share the array and race.
+
+static __device__ __align__(256) unsigned char scratch[kMbarStaticBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch[kMaxDevices] = {};
+}  // namespace
+
+int mbar_scratch_setup(int device) {
+  if (device < 0 || device >= kMaxDevices) return FELIS_E_INVAL;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch[device]) return FELIS_OK;
+  void* p = nullptr;
+  if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return FELIS_E_DEVICE;
+  g_scratch[device] = p;
+  return FELIS_OK;
+}
+
+int launch_mbar_noalloc(int device, hipStream_t s, const double* u, const int* N_k, int K, long long N, double tol,
+                        int max_iter, double* f_out, int* iters) {
+  if (K < 2 || K > 512 || N < 1) return FELIS_E_INVAL;
+  if (mbar_work_bytes(K, N) > kMbarStaticBytes) return FELIS_E_CAPACITY;
+  void* p = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (device >= 0 && device < kMaxDevices) p = g_scratch[device];
+  }
+  if (!p) return FELIS_E_DEVICE;
+  return launch_mbar(s, u, N_k, K, N, tol, max_iter, f_out, iters, p, kMbarStaticBytes);
 }
 
 }  // namespace felis

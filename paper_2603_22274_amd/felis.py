@@ -101,6 +101,7 @@ def lib():
         'felis_mbar_work_size': (C.c_int, [C.c_int, C.c_int64, P(C.c_size_t)]),
         'felis_mbar': (C.c_int, [vp, vp, vp, C.c_int, C.c_int64, C.c_double, C.c_int, vp, P(C.c_int), vp,
                                  C.c_size_t]),
+        'felis_mbar_noalloc': (C.c_int, [vp, vp, vp, C.c_int, C.c_int64, C.c_double, C.c_int, vp, P(C.c_int)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -507,6 +508,20 @@ def mbar(ctx, u, N_k, tol=1e-10, max_iter=100000):
     it = C.c_int(0)
     ctx.check(lib().felis_mbar(ctx.h, _ptr(u), nk.ctypes.data_as(C.c_void_p), K, N, tol, max_iter,
                                f.ctypes.data_as(C.c_void_p), C.byref(it), _ptr(work), nbytes.value))
+    return f, it.value
+
+
+def mbar_noalloc(ctx, u, N_k, tol=1e-10, max_iter=100000):
+    """As ``mbar`` through the allocation-free entry point (scratch in the
+    library's static device array; ``u`` must already be contiguous)."""
+    if not u.is_contiguous():
+        raise ValueError('u must be contiguous (no copy is made here)')
+    K, N = u.shape
+    nk = np.ascontiguousarray(N_k, np.int32)
+    f = np.zeros(K, np.float64)
+    it = C.c_int(0)
+    ctx.check(lib().felis_mbar_noalloc(ctx.h, _ptr(u), nk.ctypes.data_as(C.c_void_p), K, N, tol, max_iter,
+                                       f.ctypes.data_as(C.c_void_p), C.byref(it)))
     return f, it.value
 
 
