@@ -11,8 +11,9 @@
 // E_rec = 1/2 sum_i q~_i phi(r_i); F_i = -q~_i grad(spline weights) . phi.
 //
 // FFT: Stockham autosort, radices 4/2/3/5.  Grids whose x-y planes fit in
-// LDS (<= 4096 points) are transformed by whole planes (x then y in one
-// workgroup), otherwise one kernel per axis with 16 lines per workgroup
+// LDS twice (gfx950: 160 KB per workgroup, so up to ~100 x 100 points) are
+// transformed by whole planes (x then y in one workgroup), otherwise one
+// kernel per axis with 16 lines per workgroup
 // ([element][line] layout, coalesced loads for every axis).  The inverse
 // transform is conj(DFT(conj(.))).  The z pass fuses forward transform,
 // multiplication by G and inverse transform.
@@ -25,8 +26,13 @@ namespace {
 
 constexpr int kLines = 16;
 constexpr float kInvSqrtKE = 0.054876864878355476f;   // 1 / sqrt(KE): packed charges carry sqrt(KE)
-constexpr int kMaxPlane = 4096;                 // x-y plane points transformed whole in LDS (2 x 32 KB)
-constexpr int kXYThreads = 512;                 // threads per whole-plane workgroup: ~one butterfly each
+#ifndef FELIS_FFT_XY_THREADS
+#define FELIS_FFT_XY_THREADS 512
+#endif
+#ifndef FELIS_FFT_XY_LDS_CAP
+#define FELIS_FFT_XY_LDS_CAP (1 << 30)
+#endif
+constexpr int kXYThreads = FELIS_FFT_XY_THREADS;  // threads per whole-plane workgroup: ~one butterfly each
 
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
   return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
@@ -270,7 +276,10 @@ __device__ __forceinline__ float2* fft_lines_nl(float2* src, float2* dst, int n,
 // One workgroup per (window pair, z plane): 2D transform of the Kx x Ky
 // plane in LDS -- x lines, transpose, y lines -- so a forward (or inverse)
 // transform over x and y reads and writes the grid once.  INVERSE uses
-// conj(DFT(conj(.))).
+// conj(DFT(conj(.))).  The line-interleaved buffers carry one extra (zero)
+// line, Ky + 1 for the x lines and Kx + 1 for the y lines: with an even line
+// count the scatter into line order and the transpose hit one LDS bank with
+// every lane (96 lines: a stride of 192 dwords).
 template <bool INVERSE>
 __global__ __launch_bounds__(kXYThreads) void k_fft_xy(const LegDev* legs, BlockMap map) {
   const int leg = find_leg(map, blockIdx.x);
@@ -279,33 +288,38 @@ __global__ __launch_bounds__(kXYThreads) void k_fft_xy(const LegDev* legs, Block
   const int bl = blockIdx.x - map.start[leg];
   const int p = bl / Kz, z = bl - p * Kz;
   if (p >= g.npair) return;
-  extern __shared__ float2 smem[];                // A, B: one plane each; then the x and y twiddles
+  extern __shared__ float2 smem[];                // A, B: one padded plane each; then the x and y twiddles
   const int np = Kx * Ky;
+  const int nlx = Ky + 1, nly = Kx + 1;
+  const int nbuf = np + max(Kx, Ky);
   float2* A = smem;
-  float2* B = smem + np;
-  float2* twx = B + np;
+  float2* B = smem + nbuf;
+  float2* twx = B + nbuf;
   float2* twy = twx + Kx;
   float2* cg = g.cgrid + (size_t)p * g.Ktot + (size_t)z * np;
-  const FastDiv dKx(Kx), dKy(Ky);
+  const FastDiv dKx(Kx), dKy(Ky), dlx(nlx), dly(nly);
   for (int e = threadIdx.x; e < Kx; e += blockDim.x) twx[e] = g.tw[0][e];
   for (int e = threadIdx.x; e < Ky; e += blockDim.x) twy[e] = g.tw[1][e];
+  for (int x = threadIdx.x; x < Kx; x += blockDim.x) A[x * nlx + Ky] = make_float2(0.f, 0.f);
   for (int idx = threadIdx.x; idx < np; idx += blockDim.x) {       // [x][y]: lines along x
     const int y = dKx.div(idx), x = idx - y * Kx;
     float2 v = cg[idx];
     if (INVERSE) v = conj2(v);
-    A[x * Ky + y] = v;
+    A[x * nlx + y] = v;
   }
   __syncthreads();
-  float2* r = fft_lines_nl(A, B, Kx, dKy, g.rad[0], g.nrad[0], twx);
+  float2* r = fft_lines_nl(A, B, Kx, dlx, g.rad[0], g.nrad[0], twx);
   float2* o = (r == A) ? B : A;
+  for (int y = threadIdx.x; y < Ky; y += blockDim.x) o[y * nly + Kx] = make_float2(0.f, 0.f);
   for (int idx = threadIdx.x; idx < np; idx += blockDim.x) {       // -> [y][x]: lines along y
     const int x = dKy.div(idx), y = idx - x * Ky;
-    o[y * Kx + x] = r[idx];
+    o[y * nly + x] = r[x * nlx + y];
   }
   __syncthreads();
-  r = fft_lines_nl(o, r, Ky, dKx, g.rad[1], g.nrad[1], twy);
+  r = fft_lines_nl(o, r, Ky, dly, g.rad[1], g.nrad[1], twy);
   for (int idx = threadIdx.x; idx < np; idx += blockDim.x) {
-    float2 v = r[idx];                                              // [y][x] = grid order
+    const int y = dKx.div(idx), x = idx - y * Kx;
+    float2 v = r[y * nly + x];                                      // [y][x] = grid order
     if (INVERSE) v = conj2(v);
     cg[idx] = v;
   }
@@ -326,7 +340,26 @@ __device__ __forceinline__ void bspline4(float f, float* w, float* dw) {
 }
 
 
-constexpr int kBrick = 8;                      // brick edge in grid points
+// spreading brick edges in grid points (x fastest).  16 x 8 x 8: against
+// 8 x 8 x 8 the halo a brick must scan (3 grid spacings and the cell margin
+// on every side) weighs less per owned point; reciprocal space alone on the
+// 96^3 grid of 42 windows 1.73 -> 1.61 ms
+#ifndef FELIS_SPREAD_BX
+#define FELIS_SPREAD_BX 16
+#endif
+#ifndef FELIS_SPREAD_BY
+#define FELIS_SPREAD_BY 8
+#endif
+#ifndef FELIS_SPREAD_BZ
+#define FELIS_SPREAD_BZ 8
+#endif
+constexpr int kBX = FELIS_SPREAD_BX, kBY = FELIS_SPREAD_BY, kBZ = FELIS_SPREAD_BZ;
+constexpr int kBrickPts = kBX * kBY * kBZ;
+// spreading tile: int32 fixed point, 2^26 units per e.  A grid point's charge
+// stays far inside +-32 e (an atom adds at most |q| (2/3)^3), so the integer
+// sum modulo 2^32 is exact and independent of the order of the adds; one
+// unit (1.5e-8 e) is far below the FP32 FFT's own rounding
+constexpr float kTileScale = 67108864.0f;
 constexpr int kSpreadCellOf = 1024;            // candidates per table window in spreading
 constexpr int kSpreadChunk = 128;              // atoms per compact task list in spreading
 
@@ -344,14 +377,14 @@ __device__ __forceinline__ unsigned brick_mask(int b, int K, int P0, int P1) {
   return m;
 }
 
-// One block per (window, 8x8x8 brick of grid points): the block owns its
+// One block per (window, brick of grid points, kBX x kBY x kBZ): the block owns its
 // window's component of the brick (the real part of the pair's complex grid
 // for the even window, the imaginary part for the odd one).  Candidate atoms
 // come from the fine cells of the window's last list build that can hold an
 // atom whose stencil reaches the brick (the brick's extent plus 3 grid
 // spacings on the upper side, widened by skin/2 for the drift since that
 // build); each contributing atom adds its stencil points inside the brick to
-// an int64 fixed-point tile in LDS (integer sums: the tile does not depend on
+// an int32 fixed-point tile in LDS (integer sums: the tile does not depend on
 // the order of the adds), and the block writes its component of the brick
 // once, with plain stores.
 __global__ __launch_bounds__(256) void k_spread(const LegDev* legs, BlockMap map) {
@@ -361,8 +394,8 @@ __global__ __launch_bounds__(256) void k_spread(const LegDev* legs, BlockMap map
   const int K[3] = {__builtin_amdgcn_readfirstlane(g.K[0]), __builtin_amdgcn_readfirstlane(g.K[1]),
                     __builtin_amdgcn_readfirstlane(g.K[2])};
   const int tid = threadIdx.x;
-  const int nbx = (K[0] + kBrick - 1) / kBrick, nby = (K[1] + kBrick - 1) / kBrick;
-  const int nbz = (K[2] + kBrick - 1) / kBrick;
+  const int nbx = (K[0] + kBX - 1) / kBX, nby = (K[1] + kBY - 1) / kBY;
+  const int nbz = (K[2] + kBZ - 1) / kBZ;
   const int bl = blockIdx.x - map.start[leg];
   const int per = nbx * nby * nbz;
   const int w = bl / per;
@@ -370,10 +403,10 @@ __global__ __launch_bounds__(256) void k_spread(const LegDev* legs, BlockMap map
   const int bz = r / (nbx * nby);
   r -= bz * nbx * nby;
   const int by = r / nbx, bx = r - by * nbx;
-  const int P0[3] = {bx * kBrick, by * kBrick, bz * kBrick};
-  const int P1[3] = {min(P0[0] + kBrick, K[0]), min(P0[1] + kBrick, K[1]), min(P0[2] + kBrick, K[2])};
+  const int P0[3] = {bx * kBX, by * kBY, bz * kBZ};
+  const int P1[3] = {min(P0[0] + kBX, K[0]), min(P0[1] + kBY, K[1]), min(P0[2] + kBZ, K[2])};
 
-  __shared__ long long tile[kBrick * kBrick * kBrick];
+  __shared__ int tile[kBrickPts];
   __shared__ int s_start[256], s_pre[256], s_wsum[4];
   __shared__ unsigned char s_cellof[kSpreadCellOf];   // candidate -> cell of the round
   __shared__ int s_n;
@@ -382,7 +415,7 @@ __global__ __launch_bounds__(256) void k_spread(const LegDev* legs, BlockMap map
   __shared__ unsigned s_m[256];
   __shared__ unsigned short s_task[16 * kSpreadChunk];  // (atom << 4 | ix << 2 | iy) of the chunk
   __shared__ int s_tw[4];
-  for (int e = tid; e < kBrick * kBrick * kBrick; e += 256) tile[e] = 0;
+  for (int e = tid; e < kBrickPts; e += 256) tile[e] = 0;
   if (tid == 0) s_n = 0;
 
   // candidate fine cells per axis
@@ -500,14 +533,14 @@ __global__ __launch_bounds__(256) void k_spread(const LegDev* legs, BlockMap map
             unpack_bases(__int_as_float(s_b[k]), bb);
             int px = bb[0] - ix; if (px < 0) px += K[0];
             int py = bb[1] - iy; if (py < 0) py += K[1];
-            const double qxy = (double)(s_q[k] * s_w[k][ix] * s_w[k][4 + iy]);
-            const int row = ((py - P0[1]) * kBrick + (px - P0[0]));
+            const float qxy = s_q[k] * s_w[k][ix] * s_w[k][4 + iy] * kTileScale;
+            const int row = ((py - P0[1]) * kBX + (px - P0[0]));
 #pragma unroll
             for (int iz = 0; iz < 4; ++iz) {
               if (!((m >> (8 + iz)) & 1u)) continue;
               int pz = bb[2] - iz; if (pz < 0) pz += K[2];
-              const long long v = __double2ll_rn(qxy * (double)s_w[k][8 + iz] * kGridScale);
-              atomicAdd((unsigned long long*)&tile[(pz - P0[2]) * kBrick * kBrick + row], (unsigned long long)v);
+              const int v = (int)rintf(qxy * s_w[k][8 + iz]);
+              atomicAdd(&tile[(pz - P0[2]) * (kBX * kBY) + row], v);
             }
           }
           __syncthreads();                          // s_task and s_tw are rewritten next
@@ -524,12 +557,12 @@ __global__ __launch_bounds__(256) void k_spread(const LegDev* legs, BlockMap map
   float* cg = reinterpret_cast<float*>(g.cgrid + (size_t)(g.pack ? w >> 1 : w) * g.Ktot);
   const int comp = g.pack ? (w & 1) : 0;
   const bool clear_im = comp == 0 && (!g.pack || w + 1 >= g.W);
-  for (int e = tid; e < kBrick * kBrick * kBrick; e += 256) {
-    const int lx = e % kBrick, ly = (e / kBrick) % kBrick, lz = e / (kBrick * kBrick);
+  for (int e = tid; e < kBrickPts; e += 256) {
+    const int lx = e % kBX, ly = (e / kBX) % kBY, lz = e / (kBX * kBY);
     const int x = P0[0] + lx, y = P0[1] + ly, z = P0[2] + lz;
     if (x >= P1[0] || y >= P1[1] || z >= P1[2]) continue;
     const size_t off = ((size_t)z * K[1] + y) * K[0] + x;
-    cg[2 * off + comp] = (float)((double)tile[e] * (1.0 / kGridScale));
+    cg[2 * off + comp] = (float)tile[e] * (1.0f / kTileScale);
     if (clear_im) cg[2 * off + 1] = 0.f;
   }
 }
@@ -654,17 +687,40 @@ void fft_pass(hipStream_t s, const LegDev* d, const LegHost* h, int nl, int ukn)
 
 }  // namespace
 
+// Largest dynamic LDS a whole-plane workgroup may take on this device (gfx950:
+// 160 KB per workgroup), with the kernels opted in above 64 KB; 0 when the
+// device or the runtime refuses.
+size_t plane_lds_limit() {
+  static size_t limit = [] {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0)
+      return (size_t)0;
+    const size_t lim = (size_t)v;
+    if (lim > 65536 &&
+        (hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fft_xy<false>),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lim) != hipSuccess ||
+         hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fft_xy<true>),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lim) != hipSuccess)) {
+      (void)hipGetLastError();
+      return (size_t)65536;
+    }
+    return lim;
+  }();
+  return limit;
+}
+
 void launch_pme_fft(hipStream_t s, const LegDev* d, const LegHost* h, int nl, int ukn_mode) {
   const bool from_int64 = ukn_mode != 0;
   int plane = 0, kxy = 0;
   for (int i = 0; i < nl; ++i) {
-    plane = std::max(plane, h[i].K[0] * h[i].K[1]);
+    plane = std::max(plane, h[i].K[0] * h[i].K[1] + std::max(h[i].K[0], h[i].K[1]));   // one padded buffer
     kxy = std::max(kxy, h[i].K[0] + h[i].K[1]);
   }
-  if (!from_int64 && plane <= kMaxPlane) {           // whole x-y planes in LDS
+  const size_t lds = (2 * (size_t)plane + kxy) * sizeof(float2);
+  if (!from_int64 && lds <= std::min(plane_lds_limit(), (size_t)FELIS_FFT_XY_LDS_CAP)) {   // whole x-y planes in LDS
     BlockMap m;
     const int nb = make_map(m, nl, [&](int i) { return h[i].npair * h[i].K[2]; });
-    const size_t lds = (2 * (size_t)plane + kxy) * sizeof(float2);
     if (nb) hipLaunchKernelGGL(k_fft_xy<false>, dim3(nb), dim3(kXYThreads), lds, s, d, m);
     fft_pass<2, 3>(s, d, h, nl, ukn_mode);
     if (nb) hipLaunchKernelGGL(k_fft_xy<true>, dim3(nb), dim3(kXYThreads), lds, s, d, m);
@@ -681,8 +737,7 @@ void launch_pme_fft(hipStream_t s, const LegDev* d, const LegHost* h, int nl, in
 void launch_pme(hipStream_t s, const LegDev* d, const LegHost* h, int nl, bool energy, bool step_forces) {
   BlockMap m;
   int nb = make_map(m, nl, [&](int i) {
-    const int nbr = ((h[i].K[0] + kBrick - 1) / kBrick) * ((h[i].K[1] + kBrick - 1) / kBrick) *
-                    ((h[i].K[2] + kBrick - 1) / kBrick);
+    const int nbr = ((h[i].K[0] + kBX - 1) / kBX) * ((h[i].K[1] + kBY - 1) / kBY) * ((h[i].K[2] + kBZ - 1) / kBZ);
     return h[i].W * nbr;
   });
   if (!nb) return;
