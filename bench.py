@@ -182,6 +182,80 @@ def cpu_baseline(sysd, lam_index, nproc, n_atoms_sample):
                       f"{wall_step:.1f} s on {nproc + 1} cores"}
 
 
+def ukn_at_scale(ctx, felis, leg, sysd, beta, n_per_window, chunk_per_window, n_oracle, seg, nproc):
+    """u_kn of every state over n_per_window frames per window (seeded
+    Gaussian perturbations, 0.02 A, of each window's current frame, made on
+    the device chunk by chunk: the coordinates are input, the u_kn calls are
+    timed), MBAR on the whole K x (K n_per_window) matrix, and the oracle on a
+    seeded subset: n_oracle frames from the windows of ``seg``, every state
+    element by element and Delta G over the segment."""
+    import torch
+    from oracle import mbar as ombar
+    W, N = leg.n_windows, leg.n_atoms
+    nf = W * n_per_window
+    u = torch.empty((W, nf), dtype=torch.float64, device='cuda')
+    base = leg.positions()                               # (W, N, 3)
+    gen_t = torch.Generator(device='cuda')
+    gen_t.manual_seed(22274)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t_ukn = 0.0
+    nch = chunk_per_window * W
+    for c0 in range(0, n_per_window, chunk_per_window):
+        m = min(chunk_per_window, n_per_window - c0)
+        fr = base.repeat(m, 1, 1)                         # frame k of the chunk: window k % W
+        fr += torch.randn(fr.shape, generator=gen_t, device='cuda') * 0.02
+        xs, ys, zs = fr[..., 0].contiguous(), fr[..., 1].contiguous(), fr[..., 2].contiguous()
+        del fr
+        ev0.record()
+        felis.ukn(ctx, leg, sysd.lambdas, xs, ys, zs, beta, out=u[:, c0 * W:(c0 + m) * W])
+        ev1.record()
+        torch.cuda.synchronize()
+        t_ukn += ev0.elapsed_time(ev1) / 1000.0
+        if c0 == 0:
+            first = (xs[:nch].clone(), ys[:nch].clone(), zs[:nch].clone())
+        del xs, ys, zs
+    ctx.device_check()
+    N_k = np.full(W, n_per_window)
+    ev0.record()
+    f, iters = felis.mbar(ctx, u, N_k, tol=1e-10, max_iter=20000)
+    ev1.record()
+    torch.cuda.synchronize()
+    mbar_ms = ev0.elapsed_time(ev1)
+    dg_full = felis.delta_g(f, 300.0)
+    # oracle subset: frames of the first chunk from the segment's windows
+    rng = np.random.default_rng(22274)
+    cand = np.array([k for k in range(nch) if (k % W) in seg])
+    pick = np.sort(rng.choice(cand, size=min(n_oracle, len(cand)), replace=False))
+    fx, fy, fz = (t[torch.as_tensor(pick, device='cuda')].cpu().numpy() for t in first)
+    frames = np.stack([fx, fy, fz], -1)
+    t0 = time.perf_counter()
+    with _pool(sysd, nproc) as p:
+        ref = np.stack(p.map(_ukn_task, [(fr, sysd.lambdas, beta) for fr in frames], chunksize=1), 1)
+    t_or = time.perf_counter() - t0
+    cols = torch.as_tensor(pick, device='cuda')             # first chunk: frame k is column k
+    ug = u[:, cols].cpu().numpy()
+    du = (ug - ug[0]) - (ref - ref[0])
+    states = pick % W
+    ss = np.array(seg)
+    Nk_s = np.array([(states == s).sum() for s in ss])
+    f_g, _ = felis.mbar(ctx, torch.as_tensor(np.ascontiguousarray(ug[ss])).cuda(), Nk_s, tol=1e-12, max_iter=20000)
+    f_o, it_o = ombar.mbar(ref[ss], Nk_s, tol=1e-12, max_iter=2000000)
+    dg_g, dg_o = felis.delta_g(f_g, 300.0), felis.delta_g(f_o, 300.0)
+    bytes_per_frame = N * 12
+    return {"frames": int(nf), "states": int(W), "frames_per_window": int(n_per_window),
+            "ukn_s": round(t_ukn, 3), "frames_per_s": nf / t_ukn,
+            "coordinate_stream_gb_per_s": nf * bytes_per_frame / t_ukn / 1e9,
+            "coordinate_stream_frac_of_hbm": nf * bytes_per_frame / t_ukn / 8e12,
+            "mbar_ms": mbar_ms, "mbar_iterations": int(iters), "dG_kcal_per_mol": dg_full,
+            "oracle_subset": {"frames": int(len(pick)), "windows": [int(s) for s in seg],
+                              "max_abs_du_kT_all_states": float(np.abs(du).max()),
+                              "dG_gpu": dg_g, "dG_oracle": dg_o, "abs_ddG": abs(dg_g - dg_o),
+                              "passed": bool(abs(dg_g - dg_o) <= DDG_TOL), "oracle_s": round(t_or, 1),
+                              "oracle_mbar_iterations": int(it_o)},
+            "frames_from": "seeded Gaussian perturbations (0.02 A) of each window's frame after the timed run, "
+                           "generated on the device in chunks (untimed)"}
+
+
 def served_stream(ctx, systems, specs, n_steps, sample_every, rate):
     """The served form: a seeded Poisson stream of uneven legs, admitted by
     device memory and stepped together with continuous batching; latency is
@@ -223,6 +297,9 @@ def main():
                          "73 solvent windows)")
     ap.add_argument('--npt', action='store_true',
                     help='also measure the leg in NPT (Monte Carlo barostat, a volume move every 25 steps)')
+    ap.add_argument('--ukn-frames', type=int, default=2000,
+                    help='frames per window of the u_kn + MBAR measurement at scale (0: skip)')
+    ap.add_argument('--ukn-oracle-frames', type=int, default=210, help='frames of its oracle subset')
     ap.add_argument('--copy-calibration', action='store_true',
                     help='run a plain 256 MiB device copy first (reference for traffic counters)')
     args = ap.parse_args()
@@ -375,29 +452,44 @@ def main():
     del frames
     value = rate if (ddg is None or ddg['passed']) else 0.0
 
+    ukn_scale = None
+    if args.ukn_frames > 0 and seg:
+        ukn_scale = ukn_at_scale(ctx, felis, leg, sysd, beta, args.ukn_frames, 50, args.ukn_oracle_frames, seg,
+                                 nproc)
+        print(f"# u_kn at scale: {ukn_scale['frames']} frames in {ukn_scale['ukn_s']} s; oracle subset "
+              f"|ddG| {ukn_scale['oracle_subset']['abs_ddG']:.2e}", file=sys.stderr, flush=True)
+        torch.cuda.empty_cache()
+
     per_window = None
     if not args.no_per_window:
-        # the same leg as one-window legs, each launched on its own
+        # the same leg as one-window legs, each launched on its own: the plain
+        # form (FP32 pairs, FP64 atomic force sums) and the default kernels
         wins = list(range(W))
-        legs1 = [felis.Leg(ctx, sysd, windows=[w], seed=22274, positions=leg.positions()[w].cpu().numpy())
-                 for w in wins]
-        for l in legs1:
-            felis.build_nlist(ctx, [l], force=True)
+        pos0 = leg.positions().cpu().numpy()
         nrep = 10
-        for l in legs1:
-            felis.step(ctx, [l], 5, DT, 300.0, 0.5)
-        torch.cuda.synchronize()
-        ta = time.perf_counter()
-        for l in legs1:
-            felis.step(ctx, [l], nrep, DT, 300.0, 0.5)
-        torch.cuda.synchronize()
-        tb = time.perf_counter()
-        ctx.device_check()
-        per_window = {"value": nrep * DT * len(wins) / 1000.0 / ((tb - ta) / 86400.0), "unit": "ns·windows/day",
-                      "form": "one window per leg and launch chain (same kernels), MD only",
+        forms = {}
+        for name, plain in (("plain", True), ("unbatched_same_kernels", False)):
+            legs1 = [felis.Leg(ctx, sysd, windows=[w], seed=22274, positions=pos0[w], plain_fp64=plain)
+                     for w in wins]
+            for l in legs1:
+                felis.build_nlist(ctx, [l], force=True)
+            for l in legs1:
+                felis.step(ctx, [l], 5, DT, 300.0, 0.5)
+            torch.cuda.synchronize()
+            ta = time.perf_counter()
+            for l in legs1:
+                felis.step(ctx, [l], nrep, DT, 300.0, 0.5)
+            torch.cuda.synchronize()
+            tb = time.perf_counter()
+            ctx.device_check()
+            forms[name] = nrep * DT * len(wins) / 1000.0 / ((tb - ta) / 86400.0)
+            del legs1
+            torch.cuda.empty_cache()
+        per_window = {"value": forms["plain"], "unit": "ns·windows/day",
+                      "form": "plain: one window per leg and launch chain, FP32 pair and reciprocal forces summed "
+                              "with FP64 atomics, MD only",
+                      "unbatched_same_kernels": forms["unbatched_same_kernels"],
                       "md_steps_per_window": nrep, "windows": len(wins)}
-        del legs1
-        torch.cuda.empty_cache()
 
     npt = None
     if args.npt:
@@ -468,6 +560,7 @@ def main():
                      "launches_timed_of": args.steps * args.md},
         "cpu_baseline": cpu,
         "per_window_form": per_window,
+        "ukn_cfg3": ukn_scale,
         "npt": npt,
         "stage_ms_per_md_step": {k: v[0] / max(v[1], 1) for k, v in stages.items()},
         "ukn_ms_per_call": prof['ukn'][0] / max(prof['ukn'][1], 1),

@@ -5,7 +5,14 @@
     python -m paper_2603_22274_amd.profiling counters <pmc_dir> <kernel-substring> ...
     python -m paper_2603_22274_amd.profiling profiles <gpurun_out> <profiles_dir>
 
+    python -m paper_2603_22274_amd.profiling steps <trace_dir> [min_pair_us]
+    python -m paper_2603_22274_amd.profiling timeline <trace_dir>
+
 ``stats`` prints per-kernel call counts, average and total durations.
+``steps`` splits a kernel trace at the pair kernel's launches (one per MD
+step) into device time per kernel, busy and idle time per step; ``timeline``
+measures the idle device time of a whole run (queue packets between launches
+and host time between calls) per MD step.
 ``profiles`` writes the committed summaries of the pair kernel's HBM traffic
 (JSON with the digest of the kernel's sources, read by bench.py) and of the
 VALU counters of the main kernels from the four counter passes
@@ -44,6 +51,99 @@ def kernel_stats(trace_dir, top=25):
     for name, n, tot, avg, pct in rows[:top]:      # the view reports microseconds
         out.append(f"{short(name)[:44]:44s} {n:7d} {avg:10.2f} {tot / 1e3:10.3f} {pct:6.1f}")
     return "\n".join(out)
+
+
+def _kernel_rows(trace_dir):
+    con = _db(trace_dir)
+    return con.execute("select name, start, end from kernels order by start").fetchall()
+
+
+def _union(iv):
+    """Total length covered by the intervals ``iv`` [(start, end)]."""
+    tot, cur_s, cur_e = 0, None, None
+    for a, b in sorted(iv):
+        if cur_e is None or a > cur_e:
+            if cur_e is not None:
+                tot += cur_e - cur_s
+            cur_s, cur_e = a, b
+        else:
+            cur_e = max(cur_e, b)
+    if cur_e is not None:
+        tot += cur_e - cur_s
+    return tot
+
+
+def step_breakdown(trace_dir, min_pair_us=0.0, max_step_us=20000.0):
+    """Device time per MD step between consecutive launches of the pair kernel
+    (one per MD step): per kernel, the sum over kernels, the wall time, the
+    time at least one kernel ran (busy) and the rest (idle queue).  Pair
+    launches shorter than ``min_pair_us`` (other legs or passes) do not
+    delimit steps; intervals longer than ``max_step_us`` (host work between
+    calls) are skipped."""
+    import collections
+    import re
+    rows = _kernel_rows(trace_dir)
+
+    def nm(n):
+        m = re.search(r'(k_\w+(<[^>(]*>)?)', n)
+        return m.group(1) if m else short(n)[:40]
+    p = [i for i, r in enumerate(rows) if 'k_pairs' in r[0] and (r[2] - r[1]) >= min_pair_us * 1e3]
+    acc, cnt = collections.defaultdict(float), collections.Counter()
+    steps, wall, busy = 0, 0.0, 0.0
+    for a, b in zip(p, p[1:]):
+        t0, t1 = rows[a][1], rows[b][1]
+        if t1 - t0 > max_step_us * 1e3:
+            continue
+        steps += 1
+        wall += t1 - t0
+        iv = []
+        for r in rows[max(0, a - 64):b]:
+            s0, s1 = max(r[1], t0), min(r[2], t1)
+            if s1 > s0:
+                iv.append((s0, s1))
+        busy += _union(iv)
+        for r in rows[a:b]:
+            acc[nm(r[0])] += r[2] - r[1]
+            cnt[nm(r[0])] += 1
+    if not steps:
+        return {"steps": 0}
+    per = {k: {"us_per_step": v / steps / 1e3, "launches_per_step": cnt[k] / steps}
+           for k, v in sorted(acc.items(), key=lambda kv: -kv[1])}
+    return {"steps": steps, "wall_us_per_step": wall / steps / 1e3, "busy_us_per_step": busy / steps / 1e3,
+            "idle_us_per_step": (wall - busy) / steps / 1e3,
+            "kernel_sum_us_per_step": sum(v for v in acc.values()) / steps / 1e3, "kernels": per}
+
+
+def timeline(trace_dir, host_gap_us=100.0):
+    """Idle device time over a whole run, from the first to the last pair
+    launch: gaps between kernels shorter than ``host_gap_us`` (queue packets
+    between launches inside a call) and longer ones (the host between calls),
+    per MD step (pair launches)."""
+    rows = _kernel_rows(trace_dir)
+    p = [i for i, r in enumerate(rows) if 'k_pairs' in r[0]]
+    if len(p) < 2:
+        return {"md_steps": len(p)}
+    t0, t1 = rows[p[0]][1], rows[p[-1]][2]
+    iv = sorted((max(r[1], t0), min(r[2], t1)) for r in rows if r[2] > t0 and r[1] < t1)
+    busy = _union(iv)
+    short_gap = long_gap = 0
+    n_long = 0
+    cur_e = None
+    for a, b in iv:
+        if cur_e is not None and a > cur_e:
+            g = a - cur_e
+            if g < host_gap_us * 1e3:
+                short_gap += g
+            else:
+                long_gap += g
+                n_long += 1
+        cur_e = b if cur_e is None else max(cur_e, b)
+    n = len(p)
+    return {"md_steps": n, "span_ms": (t1 - t0) / 1e6, "busy_ms": busy / 1e6,
+            "idle_fraction": 1.0 - busy / (t1 - t0),
+            "queue_gaps_us_per_md_step": short_gap / n / 1e3,
+            "host_gaps_us_per_md_step": long_gap / n / 1e3, "host_gaps": n_long,
+            "busy_us_per_md_step": busy / n / 1e3}
 
 
 def _counter(con, kernel_sub):
@@ -166,6 +266,10 @@ def write_profiles(out_dir, prof_dir, kernel='k_pairs<false>'):
 if __name__ == '__main__':
     if sys.argv[1] == 'stats':
         print(kernel_stats(sys.argv[2], int(sys.argv[3]) if len(sys.argv) > 3 else 25))
+    elif sys.argv[1] == 'steps':
+        print(json.dumps(step_breakdown(sys.argv[2], float(sys.argv[3]) if len(sys.argv) > 3 else 0.0), indent=1))
+    elif sys.argv[1] == 'timeline':
+        print(json.dumps(timeline(sys.argv[2]), indent=1))
     elif sys.argv[1] == 'profiles':
         print(json.dumps(write_profiles(sys.argv[2], sys.argv[3]), indent=1))
     elif sys.argv[1] == 'counters':

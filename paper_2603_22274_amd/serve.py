@@ -359,3 +359,47 @@ def run_sequential_per_window(ctx, requests, dt=0.002, temperature=300.0, gamma=
     wall = clock() - t0
     return {'wall_s': wall, 'ns_windows_per_day': nsw / (wall / 86400.0),
             'latency_p50_s': percentile(lat, 50), 'latency_p99_s': percentile(lat, 99)}
+
+
+def main(argv=None):
+    """Serve a seeded stream of uneven legs on device 0 and print its
+    statistics as one JSON line (atoms ~ U[lo, hi], windows ~ {12, 20, 42},
+    Poisson arrivals)."""
+    import argparse
+    import json
+    import multiprocessing as mp
+
+    ap = argparse.ArgumentParser(prog='python -m paper_2603_22274_amd.serve')
+    ap.add_argument('--legs', type=int, default=16)
+    ap.add_argument('--atoms', type=str, default='5000:80000', help='lo:hi atoms per leg')
+    ap.add_argument('--steps', type=int, default=400, help='MD steps per window')
+    ap.add_argument('--sample-every', type=int, default=50)
+    ap.add_argument('--rate', type=float, default=2.0, help='mean arrivals per second')
+    ap.add_argument('--epoch', type=int, default=50, help='MD steps per batched felis_step call')
+    ap.add_argument('--hbm-gib', type=float, default=200.0)
+    ap.add_argument('--seed', type=int, default=22274)
+    ap.add_argument('--procs', type=int, default=8, help='processes generating the legs')
+    a = ap.parse_args(argv)
+    lo, hi = (int(v) for v in a.atoms.split(':'))
+    rng = np.random.default_rng([a.seed, 4])
+    specs = [(int(rng.integers(lo, hi + 1)), int(rng.choice([12, 20, 42])), a.seed + i) for i in range(a.legs)]
+    from . import gen
+    with mp.get_context('spawn').Pool(max(1, a.procs)) as p:
+        systems = p.starmap(gen.sized_leg, specs, chunksize=1)
+    from . import felis
+    ctx = felis.Context(0)
+    for s in systems:
+        relax_start(ctx, s)
+    reqs = poisson_requests(a.legs, a.rate, a.seed, lambda i: systems[i], a.steps, a.sample_every)
+    srv = Server(FelisEngine(ctx, mbar_max_iter=5000), hbm_budget=int(a.hbm_gib * (1 << 30)),
+                 epoch_steps=a.epoch)
+    out, stats = srv.serve(reqs)
+    stats["legs_ok"] = sum(1 for r in out if r.status == 'ok')
+    stats["atoms"] = [s.n_atoms for s in systems]
+    stats["windows"] = [s.n_windows for s in systems]
+    print(json.dumps(stats), flush=True)
+    ctx.close()
+
+
+if __name__ == '__main__':
+    main()
