@@ -271,6 +271,7 @@ def served_stream(ctx, systems, specs, n_steps, sample_every, rate):
                          f"{sample_every}, Poisson arrivals at {rate} legs/s, HBM budget 200 GiB, starts relaxed by "
                          f"400 high-friction steps of the coupled state")
     stats["mbar_converged"] = sum(1 for r in out if r.status == 'ok')
+    stats["not_ok"] = [{"leg": r.rid, "status": str(r.status)[:200]} for r in out if r.status != 'ok']
     stats["latencies_s"] = [round(r.latency, 3) for r in out]
     return stats
 

@@ -7,10 +7,13 @@
 //   H_ij = delta_ij N_i sum_n W_in - N_i N_j sum_n W_in W_jn,
 // W_in = exp(f_i - u_in - logden_n).  Newton steps on the sampled states
 // (gauge: the first sampled state is held fixed), with a backtracking line
-// search on F while steps are large, and a self-consistent step
+// search on F while steps are large (a change of F below its rounding level
+// counts as no increase), and a self-consistent step
 // f_i <- f_i - ln sum_n W_in when the Newton system is singular.  Unsampled
-// states follow from the converged denominators.  Converged when
-// max|step| <= tol * max(1, max|f|); final gauge f_0 = 0.
+// states follow from the converged denominators.  Converged when the
+// self-consistent update at the current iterate (the fixed-point iteration's
+// own change, relative to the gauge state) or a full Newton step is within
+// tol * max(1, max|f|); final gauge f_0 = 0.
 //
 // Device work per evaluation (FP64, fixed summation order, so the result is
 // independent of launch timing): logden per sample with per-block objective
@@ -246,6 +249,21 @@ int launch_mbar(hipStream_t s, const double* u, const int* N_k, int K, long long
     int rc = evaluate(s, u, w, K, N, f, Nk, true, ev);
     if (rc) return rc;
     ++it;
+    // the self-consistent update at this iterate, -ln(sum_n W_in) relative
+    // to the gauge state: the change of f the fixed-point iteration would
+    // make, which is the stopping rule's quantity
+    double fscale = 1.0;
+    for (int k = 0; k < K; ++k) fscale = std::fmax(fscale, std::fabs(f[k]));
+    if (ev.G[ref] > 0.0) {
+      double sc = 0.0;
+      bool finite = true;
+      for (int r = 0; r < m; ++r) {
+        const double d = std::log(ev.G[idx[r]]) - std::log(ev.G[ref]);
+        finite = finite && std::isfinite(d);
+        sc = std::fmax(sc, std::fabs(d));
+      }
+      if (finite && sc <= tol * fscale) { done = true; break; }
+    }
     // gradient of F on the free states and the Newton system H d = -g
     std::vector<double> A((size_t)m * m), b(m);
     for (int r = 0; r < m; ++r) {
@@ -276,12 +294,17 @@ int launch_mbar(hipStream_t s, const double* u, const int* N_k, int K, long long
     }
     double t = 1.0;
     if (newton && smax > 1e-3) {         // backtracking on F while the step is large
+      // F is a sum over every sample: a change below its rounding level
+      // (far from the optimum's curvature along flat directions) is no increase
+      double fabs_sum = std::fabs(ev.F);
+      for (int k = 0; k < K; ++k) fabs_sum += Nk[k] * std::fabs(f[k]);
+      const double f_round = 1e-12 * fabs_sum;
       bool ok = false;
       for (int ls = 0; ls < 30 && !ok; ++ls) {
         for (int k = 0; k < K; ++k) ftry[k] = f[k] + t * step[k];
         rc = evaluate(s, u, w, K, N, ftry, Nk, false, trial);
         if (rc) return rc;
-        ok = trial.F <= ev.F + 1e-4 * t * slope;
+        ok = trial.F <= ev.F + 1e-4 * t * slope + f_round;
         if (!ok) t *= 0.5;
       }
       if (!ok) {                         // no decrease found: self-consistent step instead
@@ -300,9 +323,9 @@ int launch_mbar(hipStream_t s, const double* u, const int* N_k, int K, long long
       f[k] += t * step[k];
       fmaxv = std::fmax(fmaxv, std::fabs(f[k]));
     }
-    // converged only when the full (undamped) step is within the tolerance:
-    // a step the line search cut short says nothing about the distance left
-    if (smax <= tol * std::fmax(1.0, fmaxv)) { done = true; break; }
+    // or converged when the full (undamped) step is within the tolerance: a
+    // step the line search cut short says nothing about the distance left
+    if (t == 1.0 && smax <= tol * std::fmax(1.0, fmaxv)) { done = true; break; }
   }
   // unsampled states from the final denominators, then the gauge f_0 = 0
   int rc = evaluate(s, u, w, K, N, f, Nk, true, ev);

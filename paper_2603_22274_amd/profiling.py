@@ -3,10 +3,10 @@
     python -m paper_2603_22274_amd.profiling stats <trace_dir> [n]
     python -m paper_2603_22274_amd.profiling traffic <fetch_dir> <write_dir> <kernel-substring>
     python -m paper_2603_22274_amd.profiling counters <pmc_dir> <kernel-substring> ...
-    python -m paper_2603_22274_amd.profiling profiles <gpurun_out> <profiles_dir>
+    python -m paper_2603_22274_amd.profiling profiles <gpurun_out> <profiles_dir> [workload]
 
     python -m paper_2603_22274_amd.profiling steps <trace_dir> [min_pair_us]
-    python -m paper_2603_22274_amd.profiling timeline <trace_dir>
+    python -m paper_2603_22274_amd.profiling timeline <trace_dir> [after_gap_ms]
 
 ``stats`` prints per-kernel call counts, average and total durations.
 ``steps`` splits a kernel trace at the pair kernel's launches (one per MD
@@ -16,7 +16,7 @@ and host time between calls) per MD step.
 ``profiles`` writes the committed summaries of the pair kernel's HBM traffic
 (JSON with the digest of the kernel's sources, read by bench.py) and of the
 VALU counters of the main kernels from the four counter passes
-(pmc_A, pmc_B, pmc_FETCH_SIZE, pmc_WRITE_SIZE under <gpurun_out>).
+(pmc_<workload>_A, _B, _FETCH_SIZE, _WRITE_SIZE under <gpurun_out>).
 ``traffic`` scales the FETCH_SIZE / WRITE_SIZE counters (KiB per dispatch)
 of one kernel by what the same counters read for the largest plain device
 copy in the run (bytes actually moved / bytes counted), and prints the
@@ -114,12 +114,21 @@ def step_breakdown(trace_dir, min_pair_us=0.0, max_step_us=20000.0):
             "kernel_sum_us_per_step": sum(v for v in acc.values()) / steps / 1e3, "kernels": per}
 
 
-def timeline(trace_dir, host_gap_us=100.0):
+def timeline(trace_dir, host_gap_us=100.0, after_gap_ms=0.0):
     """Idle device time over a whole run, from the first to the last pair
     launch: gaps between kernels shorter than ``host_gap_us`` (queue packets
     between launches inside a call) and longer ones (the host between calls),
-    per MD step (pair launches)."""
+    per MD step (pair launches).  ``after_gap_ms`` > 0: only the part after
+    the first idle gap of at least that length (a pause the program makes
+    between its preparation and the measured phase)."""
     rows = _kernel_rows(trace_dir)
+    if after_gap_ms > 0:
+        end = None
+        for i, r in enumerate(rows):
+            if end is not None and r[1] - end >= after_gap_ms * 1e6:
+                rows = rows[i:]
+                break
+            end = r[2] if end is None else max(end, r[2])
     p = [i for i, r in enumerate(rows) if 'k_pairs' in r[0]]
     if len(p) < 2:
         return {"md_steps": len(p)}
@@ -191,8 +200,16 @@ def counters(pmc_dir, kernels):
 
 _CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), 'csrc')
 PAIR_SOURCES = ('nonbonded.hip', 'erfc_coeffs.h', 'felis_internal.h')
-_BENCH = ("python -u <repo>/bench.py --steps 2 --warmup 0 --md 10 --equil 20 --no-cpu-baseline "
-          "--no-per-window --serve-legs 0 --no-npt --copy-calibration")
+WORKLOADS = {
+    'complex42': ("42-window complex leg (70527 atoms, 96^3 grid)",
+                  "python -u <repo>/bench.py --workload complex42 --steps 2 --warmup 0 --md 10 --equil 20 "
+                  "--no-cpu-baseline --no-per-window --serve-legs 0 --ukn-frames 0 --ddg-segment '' "
+                  "--copy-calibration", 'k_pairs<0>', 42 * 70527 * 3 * 8),
+    'solvent20': ("20-window solvent leg (7540 atoms, 48^3 grid)",
+                  "python -u <repo>/bench.py --workload solvent20 --steps 2 --warmup 0 --md 10 --equil 20 "
+                  "--no-cpu-baseline --no-per-window --serve-legs 0 --ukn-frames 0 --ddg-segment '' "
+                  "--copy-calibration", 'k_pairs<0>', 20 * 7540 * 3 * 8),
+}
 _PASSES = {
     'A': 'SQ_WAVES SQ_WAVE_CYCLES SQ_BUSY_CYCLES SQ_WAIT_ANY SQ_WAIT_INST_ANY SQ_ACTIVE_INST_VALU '
          'SQ_ACTIVE_INST_LDS SQ_ACTIVE_INST_VMEM',
@@ -211,40 +228,44 @@ def src_digest():
     return h.hexdigest()[:16]
 
 
-def _cmd(name):
+def _cmd(name, workload):
     return (f"cd /tmp && TMPDIR=/tmp timeout -s KILL 120 rocprofv3 --pmc {_PASSES[name]} "
-            f"-d <repo>/gpurun_out/pmc_{name} -o run -- {_BENCH}")
+            f"-d <repo>/gpurun_out/pmc_{workload}_{name} -o run -- {WORKLOADS[workload][1]}")
 
 
-def write_profiles(out_dir, prof_dir, kernel='k_pairs<false>'):
-    t = traffic(os.path.join(out_dir, 'pmc_FETCH_SIZE'), os.path.join(out_dir, 'pmc_WRITE_SIZE'), kernel)
+def write_profiles(out_dir, prof_dir, workload='complex42'):
+    """Committed summaries from the four counter passes of ``workload``
+    (pmc_<workload>_{A,B,FETCH_SIZE,WRITE_SIZE} under ``out_dir``)."""
+    desc, _, kernel, force_bytes = WORKLOADS[workload]
+    pre = os.path.join(out_dir, f'pmc_{workload}_')
+    t = traffic(pre + 'FETCH_SIZE', pre + 'WRITE_SIZE', kernel)
     t['kernel_digest'] = src_digest()
-    t['commands'] = [_cmd('FETCH_SIZE'), _cmd('WRITE_SIZE'),
-                     f"python -m paper_2603_22274_amd.profiling profiles gpurun_out profiles"]
-    with open(os.path.join(prof_dir, 'pairs_traffic_solvent20.json'), 'w') as fh:
+    t['commands'] = [_cmd('FETCH_SIZE', workload), _cmd('WRITE_SIZE', workload),
+                     f"python -m paper_2603_22274_amd.profiling profiles gpurun_out profiles {workload}"]
+    with open(os.path.join(prof_dir, f'pairs_traffic_{workload}.json'), 'w') as fh:
         json.dump(t, fh, indent=1)
     f, w, c = t['fetch_bytes_per_launch'] / 1e6, t['write_bytes_per_launch'] / 1e6, t['copy_reference']
-    txt = [f"HBM traffic of the real-space pair kernel {kernel}, 20-window solvent leg (7540 atoms), MI355X.",
+    txt = [f"HBM traffic of the real-space pair kernel {kernel}, {desc}, MI355X.",
            "Two rocprofv3 --pmc passes (FETCH_SIZE, then WRITE_SIZE) of bench.py with a 256 MiB device copy at start.",
            f"Copy reference: FETCH_SIZE {c['fetch_kib']:.0f} KiB and WRITE_SIZE {c['write_kib']:.0f} KiB for 262144 KiB "
            f"read + 262144 KiB written -> scale {c['fetch_scale']:.3f} (fetch), {c['write_scale']:.3f} (write).",
            f"{kernel}: FETCH_SIZE {t['fetch_kib_per_dispatch']:.1f} KiB/dispatch, WRITE_SIZE "
            f"{t['write_kib_per_dispatch']:.1f} KiB/dispatch",
            f"  -> {f:.1f} MB read + {w:.1f} MB written = {f + w:.1f} MB per launch ({t['dispatches'][0]} dispatches)",
-           "  (the half-cluster lists are read once; forces 20 x 7540 x 3 x 8 B = 3.6 MB are written once;",
-           "   the rest is partner coordinates and parameters re-read through L2)",
+           f"  (forces of every atom-window, {force_bytes / 1e6:.1f} MB, are written once; the half-cluster lists",
+           "   are read once; the rest is partner coordinates and parameters re-read through L2)",
            f"kernel source digest: {t['kernel_digest']}", "Commands:"] + t['commands']
-    with open(os.path.join(prof_dir, 'pairs_traffic_solvent20.txt'), 'w') as fh:
+    with open(os.path.join(prof_dir, f'pairs_traffic_{workload}.txt'), 'w') as fh:
         fh.write("\n".join(txt) + "\n")
-    ks = ['k_pairs<false>', 'k_build', 'k_spread', 'k_gather<false>', 'k_fft_xy<false>', 'k_fft<2, 3>',
-          'k_fft_xy<true>', 'k_integrate']
-    A = counters(os.path.join(out_dir, 'pmc_A'), ks)
-    B = counters(os.path.join(out_dir, 'pmc_B'), ks)
-    lines = ["VALU counters per dispatch, bench.py workload (20-window solvent leg, 7540 atoms), MI355X.",
+    ks = [kernel, 'k_build', 'k_spread', 'k_gather<false, true>', 'k_fft_xy<false>', 'k_fft<2, 3>',
+          'k_fft_xy<true>', 'k_integrate', 'k_pack<true>']
+    A = counters(pre + 'A', ks)
+    B = counters(pre + 'B', ks)
+    lines = [f"VALU counters per dispatch, bench.py workload ({desc}), MI355X.",
              "issue_util = SQ_INSTS_VALU / (1024 SIMDs x GRBM_GUI_ACTIVE/8 cycles / 4 cycles per wave64 instruction);",
              "FP32 flops = SQ_INSTS_VALU_FLOPS_FP32 x 64 lanes; duration = GRBM_GUI_ACTIVE/8 at 2.4 GHz (under "
-             "counter collection).", "",
-             f"{'kernel':18s} {'us':>7s} {'VALU instr':>11s} {'issue_util':>10s} {'FP32 Gflop':>10s} {'TFLOP/s':>8s} "
+             "counter collection, kernels serialised).", "",
+             f"{'kernel':22s} {'us':>8s} {'VALU instr':>11s} {'issue_util':>10s} {'FP32 Gflop':>10s} {'TFLOP/s':>8s} "
              f"{'LDS instr':>10s} {'VMEM rd':>9s} {'wait/wave-cyc':>13s}"]
     for k in ks:
         a, b = A.get(k, {}), B.get(k, {})
@@ -253,12 +274,12 @@ def write_profiles(out_dir, prof_dir, kernel='k_pairs<false>'):
         cyc = b['GRBM_GUI_ACTIVE'] / 8
         us = cyc / 2400
         fl = b['SQ_INSTS_VALU_FLOPS_FP32'] * 64
-        lines.append(f"{k:18s} {us:7.1f} {b['SQ_INSTS_VALU']:11.3g} {b['SQ_INSTS_VALU'] / (1024 * cyc / 4):10.2f} "
+        lines.append(f"{k:22s} {us:8.1f} {b['SQ_INSTS_VALU']:11.3g} {b['SQ_INSTS_VALU'] / (1024 * cyc / 4):10.2f} "
                      f"{fl / 1e9:10.2f} {fl / us / 1e6:8.1f} {b['SQ_INSTS_LDS']:10.3g} {b['SQ_INSTS_VMEM_RD']:9.3g} "
                      f"{a.get('SQ_WAIT_ANY', 0) / max(a.get('SQ_WAVE_CYCLES', 1), 1):13.2f}")
-    lines += ["", "Commands (one pass each):", _cmd('A'), _cmd('B'),
-              "python -m paper_2603_22274_amd.profiling profiles gpurun_out profiles"]
-    with open(os.path.join(prof_dir, 'valu_counters_solvent20.txt'), 'w') as fh:
+    lines += ["", "Commands (one pass each):", _cmd('A', workload), _cmd('B', workload),
+              f"python -m paper_2603_22274_amd.profiling profiles gpurun_out profiles {workload}"]
+    with open(os.path.join(prof_dir, f'valu_counters_{workload}.txt'), 'w') as fh:
         fh.write("\n".join(lines) + "\n")
     return t
 
@@ -269,9 +290,11 @@ if __name__ == '__main__':
     elif sys.argv[1] == 'steps':
         print(json.dumps(step_breakdown(sys.argv[2], float(sys.argv[3]) if len(sys.argv) > 3 else 0.0), indent=1))
     elif sys.argv[1] == 'timeline':
-        print(json.dumps(timeline(sys.argv[2]), indent=1))
+        print(json.dumps(timeline(sys.argv[2], after_gap_ms=float(sys.argv[3]) if len(sys.argv) > 3 else 0.0),
+                         indent=1))
     elif sys.argv[1] == 'profiles':
-        print(json.dumps(write_profiles(sys.argv[2], sys.argv[3]), indent=1))
+        print(json.dumps(write_profiles(sys.argv[2], sys.argv[3], sys.argv[4] if len(sys.argv) > 4 else 'complex42'),
+                         indent=1))
     elif sys.argv[1] == 'counters':
         print(json.dumps(counters(sys.argv[2], sys.argv[3:]), indent=1))
     elif sys.argv[1] == 'traffic':

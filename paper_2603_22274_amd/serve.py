@@ -378,23 +378,37 @@ def main(argv=None):
     ap.add_argument('--epoch', type=int, default=50, help='MD steps per batched felis_step call')
     ap.add_argument('--hbm-gib', type=float, default=200.0)
     ap.add_argument('--seed', type=int, default=22274)
-    ap.add_argument('--procs', type=int, default=8, help='processes generating the legs')
+    ap.add_argument('--pause-s', type=float, default=0.0,
+                    help='host idle time between the relaxation and the stream (marks the boundary in a '
+                         'kernel trace)')
+    ap.add_argument('--procs', type=int, default=8,
+                    help='processes generating the legs (1: in this process, e.g. under a profiler)')
     a = ap.parse_args(argv)
     lo, hi = (int(v) for v in a.atoms.split(':'))
     rng = np.random.default_rng([a.seed, 4])
     specs = [(int(rng.integers(lo, hi + 1)), int(rng.choice([12, 20, 42])), a.seed + i) for i in range(a.legs)]
     from . import gen
-    with mp.get_context('spawn').Pool(max(1, a.procs)) as p:
-        systems = p.starmap(gen.sized_leg, specs, chunksize=1)
+    if a.procs > 1:
+        with mp.get_context('spawn').Pool(a.procs) as p:
+            systems = p.starmap(gen.sized_leg, specs, chunksize=1)
+    else:
+        systems = [gen.sized_leg(*sp) for sp in specs]
     from . import felis
     ctx = felis.Context(0)
     for s in systems:
         relax_start(ctx, s)
     reqs = poisson_requests(a.legs, a.rate, a.seed, lambda i: systems[i], a.steps, a.sample_every)
+    if a.pause_s > 0:
+        import torch
+        torch.cuda.synchronize()
+        time.sleep(a.pause_s)
     srv = Server(FelisEngine(ctx, mbar_max_iter=5000), hbm_budget=int(a.hbm_gib * (1 << 30)),
                  epoch_steps=a.epoch)
     out, stats = srv.serve(reqs)
     stats["legs_ok"] = sum(1 for r in out if r.status == 'ok')
+    stats["not_ok"] = [{"leg": r.rid, "atoms": r.atoms, "windows": r.windows, "status": str(r.status)[:300]}
+                       for r in out if r.status != 'ok']
+    stats["events"] = [e for e in srv.log if e.get('event') in ('retry', 'evict')]
     stats["atoms"] = [s.n_atoms for s in systems]
     stats["windows"] = [s.n_windows for s in systems]
     print(json.dumps(stats), flush=True)
