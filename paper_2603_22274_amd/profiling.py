@@ -156,9 +156,15 @@ def timeline(trace_dir, host_gap_us=100.0, after_gap_ms=0.0):
 
 
 def _counter(con, kernel_sub):
-    vals = [v for (n, v) in con.execute("select kernel_name, value from counters_collection")
+    """Mean per dispatch over the kernel's largest launches (the workload's
+    own: a run also launches the kernel for smaller preparation legs)."""
+    rows = [(g, v) for (n, g, v) in con.execute("select kernel_name, grid_size, value from counters_collection")
             if kernel_sub in n]
-    return sum(vals) / len(vals) if vals else None, len(vals)
+    if not rows:
+        return None, 0
+    gmax = max(g for g, _ in rows)
+    vals = [v for g, v in rows if g == gmax]
+    return sum(vals) / len(vals), len(vals)
 
 
 def _copy_reference(con):
@@ -189,11 +195,16 @@ def counters(pmc_dir, kernels):
     """Per-dispatch averages of every counter collected in ``pmc_dir`` for the
     kernels whose names contain one of ``kernels``."""
     con = _db(pmc_dir)
-    rows = con.execute("select kernel_name, counter_name, value from counters_collection").fetchall()
-    out = {}
-    for name, cname, v in rows:
+    rows = con.execute("select kernel_name, grid_size, counter_name, value from counters_collection").fetchall()
+    gmax = {}
+    for name, g, cname, v in rows:
         for k in kernels:
             if k in name:
+                gmax[k] = max(gmax.get(k, 0), g)
+    out = {}
+    for name, g, cname, v in rows:
+        for k in kernels:
+            if k in name and g == gmax[k]:       # the workload's own launches
                 out.setdefault(k, {}).setdefault(cname, []).append(v)
     return {k: {c: sum(v) / len(v) for c, v in d.items()} for k, d in out.items()}
 

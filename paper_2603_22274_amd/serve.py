@@ -295,12 +295,19 @@ class FelisEngine:
 
 def relax_start(ctx, sysd, steps=400, seed=7, dt=0.002, temperature=300.0):
     """Replace ``sysd.pos`` with coordinates relaxed by high-friction Langevin
-    dynamics of the fully coupled state (first window): a synthetic lattice
-    start releases enough potential energy to heat a leg far above the target
-    temperature under the production friction.  Input preparation, done before
-    a leg is submitted."""
+    dynamics of the fully coupled state with the Boresch restraint (if any)
+    at full strength -- the fully coupled window with the largest
+    lambda_restraint: a synthetic lattice start releases enough potential
+    energy to heat a leg far above the target temperature under the
+    production friction, and relaxing without the restraint lets the anchors
+    drift from the restraint's reference geometry, which then strains every
+    restrained window from the first step.  Input preparation, done before a
+    leg is submitted."""
     from . import felis
-    leg = felis.Leg(ctx, sysd, windows=[0], seed=seed)
+    lam = np.asarray(sysd.lambdas, np.float64)
+    coupled = np.where((lam[:, 0] == 1.0) & (lam[:, 1] == 1.0))[0]
+    w = int(coupled[np.argmax(lam[coupled, 2])]) if len(coupled) else 0
+    leg = felis.Leg(ctx, sysd, windows=[w], seed=seed)
     felis.step(ctx, [leg], steps // 2, dt, temperature, 20.0)
     felis.step(ctx, [leg], steps - steps // 2, dt, temperature, 5.0)
     ctx.device_check()
