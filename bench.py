@@ -256,7 +256,7 @@ def ukn_at_scale(ctx, felis, leg, sysd, beta, n_per_window, chunk_per_window, n_
                            "generated on the device in chunks (untimed)"}
 
 
-def served_stream(ctx, systems, specs, n_steps, sample_every, rate):
+def served_stream(ctx, systems, specs, n_steps, sample_every, rate, compare=True):
     """The served form: a seeded Poisson stream of uneven legs, admitted by
     device memory and stepped together with continuous batching; latency is
     arrival -> Delta G of each leg."""
@@ -271,6 +271,12 @@ def served_stream(ctx, systems, specs, n_steps, sample_every, rate):
                          f"{sample_every}, Poisson arrivals at {rate} legs/s, HBM budget 200 GiB, starts relaxed by "
                          f"400 high-friction steps of the coupled state")
     stats["mbar_converged"] = sum(1 for r in out if r.status == 'ok')
+    if compare:
+        # the same legs and arrivals, one leg and one window at a time in the
+        # plain form (FP32 forces summed with FP64 atomics)
+        reqs = serve.poisson_requests(len(systems), rate, 22274, lambda i: systems[i], n_steps, sample_every)
+        seq = serve.run_sequential_per_window(ctx, reqs, plain=True)
+        stats["plain_sequential"] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in seq.items()}
     stats["not_ok"] = [{"leg": r.rid, "status": str(r.status)[:200]} for r in out if r.status != 'ok']
     stats["latencies_s"] = [round(r.latency, 3) for r in out]
     return stats
@@ -293,6 +299,8 @@ def main():
                     help='MD steps between replica-exchange attempts among the windows (0: none); 5 ps as in the paper')
     ap.add_argument('--serve-legs', type=int, default=16, help='legs in the served stream (0: skip)')
     ap.add_argument('--serve-steps', type=int, default=400, help='MD steps per window of a served leg')
+    ap.add_argument('--no-serve-compare', action='store_true',
+                    help='skip the same stream run one leg and one window at a time in the plain form')
     ap.add_argument('--schedule', choices=('bench', 'paper'), default='bench',
                     help="'paper': the production schedule of appendix B on the same system (80 complex or "
                          "73 solvent windows)")
@@ -530,7 +538,8 @@ def main():
         torch.cuda.empty_cache()
         for s in served_systems:                # relaxed starting coordinates (input preparation, untimed)
             serve.relax_start(ctx, s)
-        served = served_stream(ctx, served_systems, specs, args.serve_steps, 50, 2.0)
+        served = served_stream(ctx, served_systems, specs, args.serve_steps, 50, 2.0,
+                               compare=not args.no_serve_compare)
         print(f"# served {served['completed']}/{served['legs']} legs in {served['wall_s']} s", file=sys.stderr,
               flush=True)
 

@@ -332,10 +332,11 @@ def served_workload(n_legs=12, rate=2.0, seed=22274, atoms=(5000, 16000), n_step
 
 
 def run_sequential_per_window(ctx, requests, dt=0.002, temperature=300.0, gamma=0.5, mbar_max_iter=5000,
-                              clock=time.perf_counter):
-    """The same legs one at a time, each window on its own launch chain (the
-    unbatched form): FIFO, a leg starts when it has arrived and the previous
-    one is done."""
+                              clock=time.perf_counter, plain=True):
+    """The same legs one at a time, each window on its own launch chain: FIFO,
+    a leg starts when it has arrived and the previous one is done.  plain:
+    the plain form (FP32 forces summed with FP64 atomics), else the default
+    kernels unbatched."""
     import torch
     from . import felis
     beta = 1.0 / (KB * temperature)
@@ -346,7 +347,7 @@ def run_sequential_per_window(ctx, requests, dt=0.002, temperature=300.0, gamma=
             time.sleep(min(0.01, r.arrival - (clock() - t0)))
         s = r.sysd
         W = s.n_windows
-        legs = [felis.Leg(ctx, s, windows=[w], seed=r.seed) for w in range(W)]
+        legs = [felis.Leg(ctx, s, windows=[w], seed=r.seed, plain_fp64=plain) for w in range(W)]
         for l in legs:
             felis.build_nlist(ctx, [l], force=True)
         nsamp = r.n_steps // r.sample_every
@@ -363,8 +364,11 @@ def run_sequential_per_window(ctx, requests, dt=0.002, temperature=300.0, gamma=
         ctx.device_check()
         lat.append(clock() - t0 - r.arrival)
         nsw += W * r.n_steps * dt * 1e-3
+        del legs, u
+        torch.cuda.empty_cache()
     wall = clock() - t0
-    return {'wall_s': wall, 'ns_windows_per_day': nsw / (wall / 86400.0),
+    return {'form': 'plain, one leg and one window at a time' if plain else 'default kernels, one leg and one '
+                    'window at a time', 'wall_s': wall, 'ns_windows_per_day': nsw / (wall / 86400.0),
             'latency_p50_s': percentile(lat, 50), 'latency_p99_s': percentile(lat, 99)}
 
 
