@@ -221,6 +221,7 @@ WORKLOADS = {
                   "--no-cpu-baseline --no-per-window --serve-legs 0 --ukn-frames 0 --ddg-segment '' "
                   "--copy-calibration", 'k_pairs<0>', 20 * 7540 * 3 * 8),
 }
+WORKLOADS_SIZE = {'complex42': (42, 70527, 96 ** 3), 'solvent20': (20, 7540, 48 ** 3)}
 _PASSES = {
     'A': 'SQ_WAVES SQ_WAVE_CYCLES SQ_BUSY_CYCLES SQ_WAIT_ANY SQ_WAIT_INST_ANY SQ_ACTIVE_INST_VALU '
          'SQ_ACTIVE_INST_LDS SQ_ACTIVE_INST_VMEM',
@@ -266,6 +267,31 @@ def write_profiles(out_dir, prof_dir, workload='complex42'):
            f"  (forces of every atom-window, {force_bytes / 1e6:.1f} MB, are written once; the half-cluster lists",
            "   are read once; the rest is partner coordinates and parameters re-read through L2)",
            f"kernel source digest: {t['kernel_digest']}", "Commands:"] + t['commands']
+    # every main kernel of the step: HBM bytes per launch against its
+    # algorithmic bytes (read once / written once; none for the list build,
+    # whose work depends on the windows due)
+    W, N, K3 = WORKLOADS_SIZE[workload]
+    npair = (W + 1) // 2
+    alg = {kernel: 56 * W * N,
+           'k_spread': W * (32 * N + 4 * K3),                 # stencils + charges in, own grid component out
+           'k_fft_xy<false>': npair * K3 * 16, 'k_fft<2, 3>': npair * K3 * 16, 'k_fft_xy<true>': npair * K3 * 16,
+           'k_gather<false, true>': W * (4 * K3 + 56 * N),    # own grid component, stencils + charges, forces
+           'k_integrate': W * N * 76, 'k_pack<true>': W * N * 48, 'k_build': None}
+    txt += ["", "Every main kernel of the MD step (same two passes, same scaling; MB per launch):",
+            f"{'kernel':24s} {'launches':>8s} {'read':>9s} {'written':>9s} {'algorithmic':>11s} {'ratio':>7s}"]
+    cf, cw = _db(pre + 'FETCH_SIZE'), _db(pre + 'WRITE_SIZE')
+    fs, ws = c['fetch_scale'], c['write_scale']
+    for k, a in alg.items():
+        fk, nk = _counter(cf, k)
+        wk, _ = _counter(cw, k)
+        if fk is None:
+            continue
+        rd, wr = fk * 1024 * fs / 1e6, wk * 1024 * ws / 1e6
+        txt.append(f"{k:24s} {nk:8d} {rd:9.1f} {wr:9.1f} " +
+                   (f"{a / 1e6:11.1f} {(rd + wr) / (a / 1e6):7.2f}" if a else f"{'-':>11s} {'-':>7s}"))
+    txt += ["algorithmic: pairs 56 B per atom-window; spreading 32 B per atom-window + 4 B per grid point per",
+            "window; an FFT pass 16 B per complex point of each pair grid; gather 4 B per grid point + 56 B per",
+            "atom-window; integrator 76 B and pack 48 B per atom-window."]
     with open(os.path.join(prof_dir, f'pairs_traffic_{workload}.txt'), 'w') as fh:
         fh.write("\n".join(txt) + "\n")
     ks = [kernel, 'k_build', 'k_spread', 'k_gather<false, true>', 'k_fft_xy<false>', 'k_fft<2, 3>',
