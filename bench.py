@@ -425,6 +425,17 @@ def main():
     torch.cuda.synchronize()
     felis.profile(ctx, False)
     stages = {name: felis.profile_read(ctx, i) for i, name in enumerate(('pairs', 'pme', 'nlist', 'integrate'))}
+    # the same pair kernel alone (felis_nonbonded: no reciprocal space beside
+    # it), every launch bracketed
+    felis.profile(ctx, True, stages=(felis.PROF_PAIRS,), every=1)
+    for which in range(felis.PROF_BARO + 1):
+        felis.profile_read(ctx, which)
+    for k in range(6):
+        felis.nonbonded(ctx, [leg], False)
+    torch.cuda.synchronize()
+    felis.profile(ctx, False)
+    iso_ms, iso_n = felis.profile_read(ctx, felis.PROF_PAIRS)
+    iso_s = iso_ms / max(iso_n, 1) / 1000.0
     wall = t1 - t0
     md_steps = args.steps * args.md
     ns_windows = md_steps * DT * W / 1000.0
@@ -567,6 +578,13 @@ def main():
                      "kernel": f"k_pairs (real-space pair kernel, all {W} windows per launch)",
                      "pairs_in_cutoff_per_launch": int(npairs_cut), "flop_per_pair": FLOP_PER_PAIR,
                      "avg_launch_ms": avg_pairs_s * 1000.0, "launches": pairs_n,
+                     "alone": {"avg_launch_ms": iso_s * 1000.0, "launches": iso_n,
+                               "achieved": npairs_cut * FLOP_PER_PAIR / iso_s / 1e12,
+                               "frac": npairs_cut * FLOP_PER_PAIR / iso_s / 1e12 / PEAK_FP32,
+                               "frac_of_nonpacked_peak": npairs_cut * FLOP_PER_PAIR / iso_s / 1e12 / ISSUE_FP32,
+                               "note": "the same kernel launched by felis_nonbonded after the timed region, "
+                                       "with nothing beside it; the timed figures above include the "
+                                       "reciprocal-space kernels sharing the compute units"},
                      "launches_timed_of": args.steps * args.md},
         "cpu_baseline": cpu,
         "per_window_form": per_window,

@@ -353,10 +353,11 @@ int felis_binding_dg(const double* dg_solvent_segments, int n_solvent, const dou
                      int n_complex, const double* g0, const double* k, double temperature, double* dg_bind);
 
 /* Kernel timing with HIP events recorded on the context's stream around the
- * launches of one stage inside felis_step / felis_ukn (the events bracket
- * exactly the stage's kernels, so their elapsed time is the stage's device
- * time).  felis_profile(ctx, 1) starts recording every stage, felis_profile(ctx,
- * FELIS_PROF_MASK | m) only the stages whose bit (1 << FELIS_PROF_x) is set in
+ * launches of one stage inside felis_step / felis_ukn, and around the pair
+ * kernel of felis_nonbonded (the events bracket exactly the stage's kernels,
+ * so their elapsed time is the stage's device time).  felis_profile(ctx, 1)
+ * starts recording every stage, felis_profile(ctx, FELIS_PROF_MASK | m) only
+ * the stages whose bit (1 << FELIS_PROF_x) is set in
  * m (each recorded event adds a queue packet between two kernels), 0 stops;
  * felis_profile_read synchronises, returns the summed milliseconds and the
  * number of bracketed launches for stage `which` since the last read, and

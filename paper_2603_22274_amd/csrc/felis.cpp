@@ -743,7 +743,9 @@ int felis_nonbonded(felis_ctx* c, felis_leg* legs, int n_legs, int flags) {
   const bool en = flags & FELIS_ENERGY;
   if (en) launch_zero_energy(c->stream, c->d_legs, hs.data(), n_legs, FELIS_E_COUL_REAL, FELIS_E_SELF + 1);
   launch_pack(c->stream, c->d_legs, hs.data(), n_legs, false);
+  mark(c, FELIS_PROF_PAIRS, false);
   launch_pairs(c->stream, c->d_legs, hs.data(), n_legs, en ? 2 : 0);
+  mark(c, FELIS_PROF_PAIRS, true);
   launch_corrections(c->stream, c->d_legs, hs.data(), n_legs, en);
   if (en) launch_finish_energy(c->stream, c->d_legs, hs.data(), n_legs, FELIS_E_COUL_REAL, FELIS_E_SELF + 1);
   return launched(c);

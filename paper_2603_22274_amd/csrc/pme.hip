@@ -19,6 +19,8 @@
 // multiplication by G and inverse transform.
 #include <algorithm>
 
+#include <climits>
+
 #include "felis_internal.h"
 
 namespace felis {
@@ -29,8 +31,14 @@ constexpr float kInvSqrtKE = 0.054876864878355476f;   // 1 / sqrt(KE): packed ch
 #ifndef FELIS_FFT_XY_THREADS
 #define FELIS_FFT_XY_THREADS 512
 #endif
+// Largest LDS a whole-plane x-y workgroup may take; larger planes use one
+// pass per axis.  Inside an MD step the transform runs beside the pair
+// kernel, which holds most wave slots: a plane workgroup needing most of a
+// CU's LDS is then starved, while the per-axis passes (25 KB per workgroup
+// on a 96^3 grid) run beside it (42-window complex leg: 5.54 -> 5.41 ms per
+// MD step; planes up to 64 KB, e.g. 48^2, keep the whole-plane form)
 #ifndef FELIS_FFT_XY_LDS_CAP
-#define FELIS_FFT_XY_LDS_CAP (1 << 30)
+#define FELIS_FFT_XY_LDS_CAP 65536
 #endif
 constexpr int kXYThreads = FELIS_FFT_XY_THREADS;  // threads per whole-plane workgroup: ~one butterfly each
 
@@ -567,6 +575,15 @@ __global__ __launch_bounds__(256) void k_spread(const LegDev* legs, BlockMap map
   }
 }
 
+// 1: each gather block stages its 64 atoms' stencil region of the grid in
+// LDS (rows read contiguously) instead of 64 scattered reads per atom; the
+// forces are bitwise the same (42-window complex leg: 5.40 -> 5.34 ms per MD
+// step)
+#ifndef FELIS_GATHER_STAGED
+#define FELIS_GATHER_STAGED 1
+#endif
+constexpr int kGatherTile = 4096;              // grid points staged per block (16 KB)
+
 // STEP: store the force in frx/fry/frz (the integrator adds it to the
 // real-space force) instead of adding it to fx/fy/fz
 template <bool ENERGY, bool STEP>
@@ -578,12 +595,25 @@ __global__ __launch_bounds__(256) void k_gather(const LegDev* legs, BlockMap map
                     __builtin_amdgcn_readfirstlane(g.K[2])};
   // atoms in the neighbour-list sort order (spatially coherent); 4 lanes per
   // atom, lane iz sums the 16 stencil points of plane z = bz - iz
+#if FELIS_GATHER_STAGED
+  // blocks never straddle two windows: the block's 64 atoms share one grid
+  const int bpw = (g.npad + 63) >> 6;
+  const int blk = blockIdx.x - map.start[leg];
+  const int w = blk / bpw;
+  const int s0 = (blk - w * bpw) * 64;
+  if (s0 >= g.n) return;                        // padding only (uniform over the block)
+  const int slot = s0 + (threadIdx.x >> 2);
+  const int lc = w * g.npad + min(slot, g.npad - 1);
+  const int ap = g.perm[lc];
+  const bool valid = slot < g.npad && ap >= 0;
+#else
   const int local = (blockIdx.x - map.start[leg]) * 64 + (threadIdx.x >> 2);   // W N_pad < 2^31
   const int tot = g.W * g.npad;
   const int lc = local < tot ? local : tot - 1;
   const int w = lc / g.npad;
   const int ap = g.perm[lc];
   const bool valid = local < tot && ap >= 0;
+#endif
   const int a = ap >= 0 ? ap : 0;
   const int iz = threadIdx.x & 3;
   const size_t o = (size_t)w * g.n + a;
@@ -591,33 +621,112 @@ __global__ __launch_bounds__(256) void k_gather(const LegDev* legs, BlockMap map
   const float4 st = g.gsten[lc];               // stencil offsets and bases (from the pack)
   int bb[3];
   unpack_bases(st.w, bb);
-  const int bx = bb[0], by = bb[1], bz = bb[2];
+  int bx = bb[0], by = bb[1], bz = bb[2];
   float wx[4], wy[4], wz[4], dx[4], dy[4], dz[4];
   bspline4(st.x, wx, dx);
   bspline4(st.y, wy, dy);
   bspline4(st.z, wz, dz);
-  int gz = bz - iz; if (gz < 0) gz += K[2];
-  int gxv[4];
-#pragma unroll
-  for (int ix = 0; ix < 4; ++ix) { gxv[ix] = bx - ix; if (gxv[ix] < 0) gxv[ix] += K[0]; }
-  const float2* plane = g.cgrid + (size_t)(g.pack ? w >> 1 : w) * g.Ktot + (size_t)gz * K[1] * K[0];
   const bool im = g.pack && (w & 1);
   float p0 = 0.f, px = 0.f, py = 0.f;          // sum w phi, sum dwx phi, sum dwy phi over the plane
-#pragma unroll
-  for (int iy = 0; iy < 4; ++iy) {
-    int gy = by - iy; if (gy < 0) gy += K[1];
-    const float2* row = plane + (size_t)gy * K[0];
-    float s0 = 0.f, s1 = 0.f;
-#pragma unroll
-    for (int ix = 0; ix < 4; ++ix) {
-      const float2 c = row[gxv[ix]];
-      const float phi = im ? c.y : c.x;
-      s0 = fmaf(wx[ix], phi, s0);
-      s1 = fmaf(dx[ix], phi, s1);
+#if FELIS_GATHER_STAGED
+  // Stage the block's stencil region of the window's grid component in LDS
+  // (rows read contiguously), then interpolate from LDS.  Bases are unwrapped
+  // to the periodic image nearest the block's first atom's; a region larger
+  // than the tile (atoms spread over the box) reads the grid directly.
+  __shared__ float s_tile[kGatherTile];
+  __shared__ int s_red[4][6];
+  __shared__ int s_ref[3];
+  if (threadIdx.x == 0) {
+    int r[3];
+    unpack_bases(g.gsten[(size_t)w * g.npad + s0].w, r);
+    s_ref[0] = r[0]; s_ref[1] = r[1]; s_ref[2] = r[2];
+  }
+  __syncthreads();
+  {
+    const int ref[3] = {s_ref[0], s_ref[1], s_ref[2]};
+    int* bp[3] = {&bx, &by, &bz};
+    for (int d = 0; d < 3; ++d) {
+      const int df = *bp[d] - ref[d];
+      if (2 * df > K[d]) *bp[d] -= K[d];
+      else if (2 * df < -K[d]) *bp[d] += K[d];
     }
-    p0 = fmaf(wy[iy], s0, p0);
-    px = fmaf(wy[iy], s1, px);
-    py = fmaf(dy[iy], s0, py);
+  }
+  int mn[3] = {valid ? bx : INT_MAX, valid ? by : INT_MAX, valid ? bz : INT_MAX};
+  int mx[3] = {valid ? bx : INT_MIN, valid ? by : INT_MIN, valid ? bz : INT_MIN};
+  for (int off = 1; off < 64; off <<= 1)
+    for (int d = 0; d < 3; ++d) {
+      mn[d] = min(mn[d], __shfl_xor(mn[d], off, 64));
+      mx[d] = max(mx[d], __shfl_xor(mx[d], off, 64));
+    }
+  const int wave = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0)
+    for (int d = 0; d < 3; ++d) { s_red[wave][d] = mn[d]; s_red[wave][3 + d] = mx[d]; }
+  __syncthreads();
+  int lo[3], nd[3];
+  for (int d = 0; d < 3; ++d) {
+    int a0 = s_red[0][d], a1 = s_red[0][3 + d];
+    for (int k = 1; k < 4; ++k) { a0 = min(a0, s_red[k][d]); a1 = max(a1, s_red[k][3 + d]); }
+    lo[d] = a0 - 3;
+    nd[d] = a1 - lo[d] + 1;
+  }
+  const int vol = nd[0] * nd[1] * nd[2];     // block-uniform (the first atom is valid)
+  if (!valid) { bx = lo[0] + 3; by = lo[1] + 3; bz = lo[2] + 3; }   // in-tile reads, results unused
+  const float* comp = reinterpret_cast<const float*>(g.cgrid + (size_t)(g.pack ? w >> 1 : w) * g.Ktot) + (im ? 1 : 0);
+  if (vol <= kGatherTile) {
+    for (int e = threadIdx.x; e < vol; e += 256) {
+      const int x = e % nd[0], yz = e / nd[0];
+      const int y = yz % nd[1], z = yz / nd[1];
+      int gx = lo[0] + x, gy = lo[1] + y, gz = lo[2] + z;
+      gx += gx < 0 ? K[0] : (gx >= K[0] ? -K[0] : 0);
+      gy += gy < 0 ? K[1] : (gy >= K[1] ? -K[1] : 0);
+      gz += gz < 0 ? K[2] : (gz >= K[2] ? -K[2] : 0);
+      s_tile[e] = comp[2 * (((size_t)gz * K[1] + gy) * K[0] + gx)];
+    }
+    __syncthreads();
+    const int zb = (bz - iz - lo[2]) * nd[1];
+#pragma unroll
+    for (int iy = 0; iy < 4; ++iy) {
+      const float* row = s_tile + (zb + by - iy - lo[1]) * nd[0] + (bx - lo[0]);
+      float s0v = 0.f, s1 = 0.f;
+#pragma unroll
+      for (int ix = 0; ix < 4; ++ix) {
+        const float phi = row[-ix];
+        s0v = fmaf(wx[ix], phi, s0v);
+        s1 = fmaf(dx[ix], phi, s1);
+      }
+      p0 = fmaf(wy[iy], s0v, p0);
+      px = fmaf(wy[iy], s1, px);
+      py = fmaf(dy[iy], s0v, py);
+    }
+  } else {
+    // wrap the unwrapped bases back into the grid and read it directly
+    bx += bx < 0 ? K[0] : (bx >= K[0] ? -K[0] : 0);
+    by += by < 0 ? K[1] : (by >= K[1] ? -K[1] : 0);
+    bz += bz < 0 ? K[2] : (bz >= K[2] ? -K[2] : 0);
+#else
+  {
+#endif
+    int gz = bz - iz; if (gz < 0) gz += K[2];
+    int gxv[4];
+#pragma unroll
+    for (int ix = 0; ix < 4; ++ix) { gxv[ix] = bx - ix; if (gxv[ix] < 0) gxv[ix] += K[0]; }
+    const float2* plane = g.cgrid + (size_t)(g.pack ? w >> 1 : w) * g.Ktot + (size_t)gz * K[1] * K[0];
+#pragma unroll
+    for (int iy = 0; iy < 4; ++iy) {
+      int gy = by - iy; if (gy < 0) gy += K[1];
+      const float2* row = plane + (size_t)gy * K[0];
+      float s0v = 0.f, s1 = 0.f;
+#pragma unroll
+      for (int ix = 0; ix < 4; ++ix) {
+        const float2 c = row[gxv[ix]];
+        const float phi = im ? c.y : c.x;
+        s0v = fmaf(wx[ix], phi, s0v);
+        s1 = fmaf(dx[ix], phi, s1);
+      }
+      p0 = fmaf(wy[iy], s0v, p0);
+      px = fmaf(wy[iy], s1, px);
+      py = fmaf(dy[iy], s0v, py);
+    }
   }
   float pot = p0 * wz[iz], gxs = px * wz[iz], gys = py * wz[iz], gzs = p0 * dz[iz];
   for (int off = 1; off < 4; off <<= 1) {
@@ -743,7 +852,11 @@ void launch_pme(hipStream_t s, const LegDev* d, const LegHost* h, int nl, bool e
   if (!nb) return;
   hipLaunchKernelGGL(k_spread, dim3(nb), dim3(256), 0, s, d, m);
   launch_pme_fft(s, d, h, nl, 0);
+#if FELIS_GATHER_STAGED
+  nb = make_map(m, nl, [&](int i) { return h[i].W * blocks_for((long long)h[i].npad, 64); });
+#else
   nb = make_map(m, nl, [&](int i) { return blocks_for((long long)h[i].W * h[i].npad, 64); });
+#endif
   if (energy && step_forces) hipLaunchKernelGGL((k_gather<true, true>), dim3(nb), dim3(256), 0, s, d, m);
   else if (energy) hipLaunchKernelGGL((k_gather<true, false>), dim3(nb), dim3(256), 0, s, d, m);
   else if (step_forces) hipLaunchKernelGGL((k_gather<false, true>), dim3(nb), dim3(256), 0, s, d, m);

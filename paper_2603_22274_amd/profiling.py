@@ -274,7 +274,9 @@ def write_profiles(out_dir, prof_dir, workload='complex42'):
     npair = (W + 1) // 2
     alg = {kernel: 56 * W * N,
            'k_spread': W * (32 * N + 4 * K3),                 # stencils + charges in, own grid component out
-           'k_fft_xy<false>': npair * K3 * 16, 'k_fft<2, 3>': npair * K3 * 16, 'k_fft_xy<true>': npair * K3 * 16,
+           'k_fft_xy<false>': npair * K3 * 16, 'k_fft<0, 0>': npair * K3 * 16, 'k_fft<1, 0>': npair * K3 * 16,
+           'k_fft<2, 3>': npair * K3 * 16, 'k_fft<1, 1>': npair * K3 * 16, 'k_fft<0, 1>': npair * K3 * 16,
+           'k_fft_xy<true>': npair * K3 * 16,
            'k_gather<false, true>': W * (4 * K3 + 56 * N),    # own grid component, stencils + charges, forces
            'k_integrate': W * N * 76, 'k_pack<true>': W * N * 48, 'k_build': None}
     txt += ["", "Every main kernel of the MD step (same two passes, same scaling; MB per launch):",
@@ -294,14 +296,16 @@ def write_profiles(out_dir, prof_dir, workload='complex42'):
             "atom-window; integrator 76 B and pack 48 B per atom-window."]
     with open(os.path.join(prof_dir, f'pairs_traffic_{workload}.txt'), 'w') as fh:
         fh.write("\n".join(txt) + "\n")
-    ks = [kernel, 'k_build', 'k_spread', 'k_gather<false, true>', 'k_fft_xy<false>', 'k_fft<2, 3>',
-          'k_fft_xy<true>', 'k_integrate', 'k_pack<true>']
+    ks = [kernel, 'k_build', 'k_spread', 'k_gather<false, true>', 'k_fft_xy<false>', 'k_fft<0, 0>', 'k_fft<1, 0>',
+          'k_fft<2, 3>', 'k_fft<1, 1>', 'k_fft<0, 1>', 'k_fft_xy<true>', 'k_integrate', 'k_pack<true>']
     A = counters(pre + 'A', ks)
     B = counters(pre + 'B', ks)
     lines = [f"VALU counters per dispatch, bench.py workload ({desc}), MI355X.",
-             "issue_util = SQ_INSTS_VALU / (1024 SIMDs x GRBM_GUI_ACTIVE/8 cycles / 4 cycles per wave64 instruction);",
-             "FP32 flops = SQ_INSTS_VALU_FLOPS_FP32 x 64 lanes; duration = GRBM_GUI_ACTIVE/8 at 2.4 GHz (under "
-             "counter collection, kernels serialised).", "",
+             "issue_util = SQ_INSTS_VALU / (1024 SIMDs x GRBM_GUI_ACTIVE/8 cycles / 4 cycles per wave64 instruction):",
+             "a relative VALU issue rate (1.0 = one wave64 instruction per SIMD every 4 cycles);",
+             "FP32 flops = SQ_INSTS_VALU_FLOPS_FP32 x 64 lanes; duration = GRBM_GUI_ACTIVE/8 cycles at a nominal 2.4 GHz "
+             "(under counter collection, kernels serialised; HIP events time the pair kernel alone at ~6 % longer, "
+             "i.e. the clock runs below 2.4 GHz under this load).", "",
              f"{'kernel':22s} {'us':>8s} {'VALU instr':>11s} {'issue_util':>10s} {'FP32 Gflop':>10s} {'TFLOP/s':>8s} "
              f"{'LDS instr':>10s} {'VMEM rd':>9s} {'wait/wave-cyc':>13s}"]
     for k in ks:
