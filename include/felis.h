@@ -251,7 +251,9 @@ int felis_step(felis_ctx* ctx, felis_leg* legs, int n_legs, int n_steps, double 
  * [n_frames][3] edges in A, or NULL: every frame in the leg's `box`) gives
  * each frame's periodic box (NPT frames).  lambdas (host) [K][3].  Uses the
  * leg's scratch (call felis_leg_init first); at most 64 distinct lambda_vdw
- * values and 256 ligand atoms. */
+ * values and 256 ligand atoms.  n_frames = 0 is a no-op (the frame and u
+ * pointers are then not read); FELIS_E_INVAL for K < 1, lambdas outside
+ * [0, 1], frame_stride < n_atoms or u_stride < n_frames. */
 int felis_ukn(felis_ctx* ctx, felis_leg* leg, const double* lambdas, int K, const float* fx,
               const float* fy, const float* fz, int64_t frame_stride, int64_t n_frames,
               const double* frame_box, double beta, double* u, int64_t u_stride);

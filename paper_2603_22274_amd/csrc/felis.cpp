@@ -980,12 +980,13 @@ int felis_ukn(felis_ctx* c, felis_leg* leg, const double* lambdas, int K, const 
   std::vector<LegHost> hs;
   int rc = prepare(c, leg, 1, hs);
   if (rc) return rc;
-  if (!lambdas || !fx || !fy || !fz || !u || K < 1 || n_frames < 0 || frame_stride < leg->n_atoms ||
-      u_stride < n_frames)
-    return fail(c, FELIS_E_INVAL, "u_kn arguments");
+  if (!lambdas || K < 1 || n_frames < 0) return fail(c, FELIS_E_INVAL, "u_kn arguments");
   for (int k = 0; k < K; ++k)
     for (int t = 0; t < 3; ++t)
       if (!(lambdas[3 * k + t] >= 0 && lambdas[3 * k + t] <= 1)) return fail(c, FELIS_E_INVAL, "lambdas in [0, 1]");
+  if (n_frames == 0) return FELIS_OK;                 // nothing to read or write
+  if (!fx || !fy || !fz || !u || frame_stride < leg->n_atoms || u_stride < n_frames)
+    return fail(c, FELIS_E_INVAL, "u_kn arguments");
   Plan p;
   make_plan(c, leg, p);
   char* w = (char*)leg->work;

@@ -26,7 +26,13 @@
 namespace felis {
 namespace {
 
-constexpr int kLines = 16;
+// lines per workgroup of a per-axis FFT pass: 32 reads and writes 256-byte
+// runs on the y and z passes (complex leg 5.36 -> 5.33 ms per MD step
+// against 16; 8 was slower)
+#ifndef FELIS_FFT_LINES
+#define FELIS_FFT_LINES 32
+#endif
+constexpr int kLines = FELIS_FFT_LINES;          // lines per workgroup of a per-axis FFT pass
 constexpr float kInvSqrtKE = 0.054876864878355476f;   // 1 / sqrt(KE): packed charges carry sqrt(KE)
 #ifndef FELIS_FFT_XY_THREADS
 #define FELIS_FFT_XY_THREADS 512
@@ -791,6 +797,14 @@ void fft_pass(hipStream_t s, const LegDev* d, const LegHost* h, int nl, int ukn)
     return h[i].npair * outer * ((inner + kLines - 1) / kLines);
   });
   const size_t lds = (2 * (size_t)nmax * kLines + nmax) * sizeof(float2);
+  if (lds > 65536) {
+    // above 64 KB a kernel must opt in (128-point lines of 32: 66.5 KB);
+    // once per instantiation, within the device's per-workgroup limit
+    static const bool opted = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fft<AXIS, MODE>),
+                                                  hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                  (int)(2 * 128 * kLines + 128) * (int)sizeof(float2)) == hipSuccess;
+    if (!opted) (void)hipGetLastError();
+  }
   if (nb) hipLaunchKernelGGL((k_fft<AXIS, MODE>), dim3(nb), dim3(256), lds, s, d, m, ukn);
 }
 

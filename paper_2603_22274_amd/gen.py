@@ -583,34 +583,37 @@ def _choose_anchors(P, L):
     L2/L3 its chain neighbours, P1 among the 20 protein atoms nearest L1,
     P2/P3 its chain neighbours; angles P1-L1-L2 and L1-P1-P2 within
     45-135 deg, triples' own angles within 30-150 deg, preferring both
-    angles near 90 deg, ties broken by atom index."""
+    angles near 90 deg, ties broken by atom index.  When no set around the
+    nearest ligand atom satisfies the angles, the next-nearest ligand atoms
+    (up to the fifth) are tried as L1 in turn."""
     dPL = np.linalg.norm(P[:, None] - L[None], axis=2)
-    l1 = int(np.argmin(dPL.min(0)))
     nl = len(L)
-    ldirs = [(l1 + 1, l1 + 2), (l1 - 1, l1 - 2)]
-    best = None
-    near = np.argsort(dPL[:, l1], kind='stable')[:20]
-    for p1 in near:
-        for l2, l3 in ldirs:
-            if not (0 <= l3 < nl and 0 <= l2 < nl):
-                continue
-            for p2, p3 in ((p1 + 1, p1 + 2), (p1 - 1, p1 - 2)):
-                if not (0 <= p3 < len(P) and 0 <= p2 < len(P)):
+    for l1 in np.argsort(dPL.min(0), kind='stable')[:5]:
+        l1 = int(l1)
+        ldirs = [(l1 + 1, l1 + 2), (l1 - 1, l1 - 2)]
+        best = None
+        near = np.argsort(dPL[:, l1], kind='stable')[:20]
+        for p1 in near:
+            for l2, l3 in ldirs:
+                if not (0 <= l3 < nl and 0 <= l2 < nl):
                     continue
-                ta = math.degrees(_angle(P[p1], L[l1], L[l2]))
-                tb = math.degrees(_angle(L[l1], P[p1], P[p2]))
-                if not (45 <= ta <= 135 and 45 <= tb <= 135):
-                    continue
-                if not (30 <= math.degrees(_angle(L[l1], L[l2], L[l3])) <= 150):
-                    continue
-                if not (30 <= math.degrees(_angle(P[p1], P[p2], P[p3])) <= 150):
-                    continue
-                score = (abs(ta - 90) + abs(tb - 90), int(p1), int(p2), int(l2))
-                if best is None or score < best[0]:
-                    best = (score, (int(p1), int(p2), int(p3), l1, l2, l3))
-    if best is None:
-        raise RuntimeError("no anchor set satisfies the angle rule")
-    return best[1]
+                for p2, p3 in ((p1 + 1, p1 + 2), (p1 - 1, p1 - 2)):
+                    if not (0 <= p3 < len(P) and 0 <= p2 < len(P)):
+                        continue
+                    ta = math.degrees(_angle(P[p1], L[l1], L[l2]))
+                    tb = math.degrees(_angle(L[l1], P[p1], P[p2]))
+                    if not (45 <= ta <= 135 and 45 <= tb <= 135):
+                        continue
+                    if not (30 <= math.degrees(_angle(L[l1], L[l2], L[l3])) <= 150):
+                        continue
+                    if not (30 <= math.degrees(_angle(P[p1], P[p2], P[p3])) <= 150):
+                        continue
+                    score = (abs(ta - 90) + abs(tb - 90), int(p1), int(p2), int(l2))
+                    if best is None or score < best[0]:
+                        best = (score, (int(p1), int(p2), int(p3), l1, l2, l3))
+        if best is not None:
+            return best[1]
+    raise RuntimeError("no anchor set satisfies the angle rule")
 
 
 def complex_leg(config=2, seed=BASE_SEED, n_prot=5000, n_lig=50, box_edge=88.0, lattice_n=29,
