@@ -26,13 +26,6 @@
 namespace felis {
 namespace {
 
-// lines per workgroup of a per-axis FFT pass: 32 reads and writes 256-byte
-// runs on the y and z passes (complex leg 5.36 -> 5.33 ms per MD step
-// against 16; 8 was slower)
-#ifndef FELIS_FFT_LINES
-#define FELIS_FFT_LINES 32
-#endif
-constexpr int kLines = FELIS_FFT_LINES;          // lines per workgroup of a per-axis FFT pass
 constexpr float kInvSqrtKE = 0.054876864878355476f;   // 1 / sqrt(KE): packed charges carry sqrt(KE)
 #ifndef FELIS_FFT_XY_THREADS
 #define FELIS_FFT_XY_THREADS 512
@@ -105,16 +98,16 @@ __device__ __forceinline__ void dft(float2* v) {
   }
 }
 
-// One Stockham stage of radix R over kLines lines (buf[e * kLines + b]).
-template <int R>
+// One Stockham stage of radix R over LINES lines (buf[e * LINES + b]).
+template <int R, int LINES>
 __device__ __forceinline__ void stage(const float2* src, float2* dst, int n, int Ns, const float2* tw) {
   const int nR = n / R;
   const int step = n / (Ns * R);
-  const int s_in = nR * kLines, s_out = Ns * kLines;
+  const int s_in = nR * LINES, s_out = Ns * LINES;
   const FastDiv dNs(Ns);
-  for (int t = threadIdx.x; t < nR * kLines; t += blockDim.x) {
-    // element j = t / kLines of line b = t % kLines; j = jq Ns + k
-    const int j = t / kLines;
+  for (int t = threadIdx.x; t < nR * LINES; t += blockDim.x) {
+    // element j = t / LINES of line b = t % LINES; j = jq Ns + k
+    const int j = t / LINES;
     const int jq = dNs.div(j);
     const int k = j - (int)__umul24((unsigned)jq, (unsigned)Ns);
     const int tk = (int)__umul24((unsigned)k, (unsigned)step);
@@ -131,17 +124,18 @@ __device__ __forceinline__ void stage(const float2* src, float2* dst, int n, int
   }
 }
 
-// Forward transform of kLines lines of length n held in src[e * kLines + b];
+// Forward transform of LINES lines of length n held in src[e * LINES + b];
 // returns the buffer that holds the result.
+template <int LINES>
 __device__ __forceinline__ float2* fft_lines(float2* src, float2* dst, int n, const int* rad, int nrad, const float2* tw) {
   int Ns = 1;
   for (int st = 0; st < nrad; ++st) {
     const int R = rad[st];
     switch (R) {
-      case 2: stage<2>(src, dst, n, Ns, tw); break;
-      case 3: stage<3>(src, dst, n, Ns, tw); break;
-      case 4: stage<4>(src, dst, n, Ns, tw); break;
-      default: stage<5>(src, dst, n, Ns, tw); break;
+      case 2: stage<2, LINES>(src, dst, n, Ns, tw); break;
+      case 3: stage<3, LINES>(src, dst, n, Ns, tw); break;
+      case 4: stage<4, LINES>(src, dst, n, Ns, tw); break;
+      default: stage<5, LINES>(src, dst, n, Ns, tw); break;
     }
     __syncthreads();
     float2* t = src; src = dst; dst = t;
@@ -152,7 +146,7 @@ __device__ __forceinline__ float2* fft_lines(float2* src, float2* dst, int n, co
 
 // MODE: 0 forward, 1 inverse, 2 forward from the int64 grids (x axis),
 //       3 forward * G * inverse (z axis)
-template <int AXIS, int MODE>
+template <int AXIS, int MODE, int LINES>
 __global__ __launch_bounds__(256) void k_fft(const LegDev* legs, BlockMap map, int ukn) {
   const int leg = find_leg(map, blockIdx.x);
   const LegDev& g = legs[leg];
@@ -161,30 +155,30 @@ __global__ __launch_bounds__(256) void k_fft(const LegDev* legs, BlockMap map, i
   // lines: x axis -> (z, y-chunk); y axis -> (z, x-chunk); z axis -> (y, x-chunk)
   const int inner = (AXIS == 0) ? Ky : Kx;
   const int outer = (AXIS == 2) ? Ky : Kz;
-  const int nch = (inner + kLines - 1) / kLines;
+  const int nch = (inner + LINES - 1) / LINES;
   const int bl = blockIdx.x - map.start[leg];
   const int p = bl / (outer * nch);
   const int rem = bl - p * outer * nch;
   const int o = rem / nch, ch = rem - (rem / nch) * nch;
   if (p >= g.npair) return;
-  extern __shared__ float2 smem[];               // two buffers of n * kLines, then n twiddles
+  extern __shared__ float2 smem[];               // two buffers of n * LINES, then n twiddles
   float2* bufA = smem;
-  float2* bufB = smem + (size_t)n * kLines;
-  float2* tw = bufB + (size_t)n * kLines;
+  float2* bufB = smem + (size_t)n * LINES;
+  float2* tw = bufB + (size_t)n * LINES;
   for (int e = threadIdx.x; e < n; e += blockDim.x) tw[e] = g.tw[AXIS][e];
   const FastDiv dn(n);
   float2* cg = g.cgrid + (size_t)p * g.Ktot;
   const int KxKy = Kx * Ky;
   auto offs = [&](int e, int b) -> long long {
-    const int li = ch * kLines + b;
+    const int li = ch * LINES + b;
     if (li >= inner) return -1;
     if (AXIS == 0) return (long long)o * KxKy + (long long)li * Kx + e;
     if (AXIS == 1) return (long long)o * KxKy + (long long)e * Kx + li;
     return (long long)e * KxKy + (long long)o * Kx + li;
   };
-  for (int idx = threadIdx.x; idx < n * kLines; idx += blockDim.x) {
+  for (int idx = threadIdx.x; idx < n * LINES; idx += blockDim.x) {
     int e, b;
-    if (AXIS == 0) { b = dn.div(idx); e = idx - b * n; } else { e = idx / kLines; b = idx - e * kLines; }
+    if (AXIS == 0) { b = dn.div(idx); e = idx - b * n; } else { e = idx / LINES; b = idx - e * LINES; }
     const long long off = offs(e, b);
     float2 v = make_float2(0.f, 0.f);
     if (off >= 0) {
@@ -201,18 +195,18 @@ __global__ __launch_bounds__(256) void k_fft(const LegDev* legs, BlockMap map, i
         if (MODE == 1) v = conj2(v);
       }
     }
-    bufA[e * kLines + b] = v;
+    bufA[e * LINES + b] = v;
   }
   __syncthreads();
-  float2* res = fft_lines(bufA, bufB, n, g.rad[AXIS], g.nrad[AXIS], tw);
+  float2* res = fft_lines<LINES>(bufA, bufB, n, g.rad[AXIS], g.nrad[AXIS], tw);
   if (MODE == 3) {
-    // multiply by G(kx, ky, kz): element e = kz of line (ky = o, kx = ch*kLines + b),
+    // multiply by G(kx, ky, kz): element e = kz of line (ky = o, kx = ch*LINES + b),
     // in the box of the grid's window (u_kn: of its frame)
     const BoxW& B = ukn ? g.ubox[ukn == 1 ? 2 * p : p] : g.box[g.pack ? 2 * p : p];
     const float a2 = g.alpha * g.alpha;
-    for (int idx = threadIdx.x; idx < n * kLines; idx += blockDim.x) {
-      const int e = idx / kLines, b = idx - e * kLines;
-      const int kx = ch * kLines + b, ky = o, kz = e;
+    for (int idx = threadIdx.x; idx < n * LINES; idx += blockDim.x) {
+      const int e = idx / LINES, b = idx - e * LINES;
+      const int kx = ch * LINES + b, ky = o, kz = e;
       float G = 0.f;
       if (kx < Kx) {
         const float mx = (float)(kx <= Kx / 2 ? kx : kx - Kx) * B.invLf[0];
@@ -228,14 +222,14 @@ __global__ __launch_bounds__(256) void k_fft(const LegDev* legs, BlockMap map, i
     }
     __syncthreads();
     float2* other = (res == bufA) ? bufB : bufA;
-    res = fft_lines(res, other, n, g.rad[AXIS], g.nrad[AXIS], tw);
+    res = fft_lines<LINES>(res, other, n, g.rad[AXIS], g.nrad[AXIS], tw);
   }
-  for (int idx = threadIdx.x; idx < n * kLines; idx += blockDim.x) {
+  for (int idx = threadIdx.x; idx < n * LINES; idx += blockDim.x) {
     int e, b;
-    if (AXIS == 0) { b = dn.div(idx); e = idx - b * n; } else { e = idx / kLines; b = idx - e * kLines; }
+    if (AXIS == 0) { b = dn.div(idx); e = idx - b * n; } else { e = idx / LINES; b = idx - e * LINES; }
     const long long off = offs(e, b);
     if (off < 0) continue;
-    float2 v = res[e * kLines + b];
+    float2 v = res[e * LINES + b];
     if (MODE == 1 || MODE == 3) v = conj2(v);
     cg[off] = v;
   }
@@ -786,26 +780,46 @@ __global__ __launch_bounds__(256) void k_gather(const LegDev* legs, BlockMap map
 
 inline int blocks_for(long long items, int per) { return (int)((items + per - 1) / per); }
 
-template <int AXIS, int MODE>
-void fft_pass(hipStream_t s, const LegDev* d, const LegHost* h, int nl, int ukn) {
+template <int AXIS, int MODE, int LINES>
+void fft_launch(hipStream_t s, const LegDev* d, const LegHost* h, int nl, int ukn) {
   BlockMap m;
   int nmax = 0;
   const int nb = make_map(m, nl, [&](int i) {
     const int inner = (AXIS == 0) ? h[i].K[1] : h[i].K[0];
     const int outer = (AXIS == 2) ? h[i].K[1] : h[i].K[2];
     nmax = std::max(nmax, h[i].K[AXIS]);
-    return h[i].npair * outer * ((inner + kLines - 1) / kLines);
+    return h[i].npair * outer * ((inner + LINES - 1) / LINES);
   });
-  const size_t lds = (2 * (size_t)nmax * kLines + nmax) * sizeof(float2);
+  const size_t lds = (2 * (size_t)nmax * LINES + nmax) * sizeof(float2);
   if (lds > 65536) {
     // above 64 KB a kernel must opt in (128-point lines of 32: 66.5 KB);
     // once per instantiation, within the device's per-workgroup limit
-    static const bool opted = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fft<AXIS, MODE>),
+    static const bool opted = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fft<AXIS, MODE, LINES>),
                                                   hipFuncAttributeMaxDynamicSharedMemorySize,
-                                                  (int)(2 * 128 * kLines + 128) * (int)sizeof(float2)) == hipSuccess;
+                                                  (int)(2 * 128 * LINES + 128) * (int)sizeof(float2)) == hipSuccess;
     if (!opted) (void)hipGetLastError();
   }
-  if (nb) hipLaunchKernelGGL((k_fft<AXIS, MODE>), dim3(nb), dim3(256), lds, s, d, m, ukn);
+  if (nb) hipLaunchKernelGGL((k_fft<AXIS, MODE, LINES>), dim3(nb), dim3(256), lds, s, d, m, ukn);
+}
+
+// 32 lines per workgroup read and write 256-byte runs on the y and z passes
+// (42-window complex leg: 5.36 -> 5.33 ms per MD step against 16) but take
+// 50 KB of LDS and halve the workgroups: launches that would have fewer than
+// kFftWideBlocks workgroups at 32 lines (a single window) and the u_kn
+// transforms, which run alone, keep 16 (one-window legs 637 vs 594
+// ns*windows/day, u_kn 26,800 vs 23,900 frames/s with 32)
+constexpr long long kFftWideBlocks = 4096;
+
+template <int AXIS, int MODE>
+void fft_pass(hipStream_t s, const LegDev* d, const LegHost* h, int nl, int ukn, bool allow_wide) {
+  long long wide = 0;
+  for (int i = 0; i < nl; ++i) {
+    const int inner = (AXIS == 0) ? h[i].K[1] : h[i].K[0];
+    const int outer = (AXIS == 2) ? h[i].K[1] : h[i].K[2];
+    wide += (long long)h[i].npair * outer * ((inner + 31) / 32);
+  }
+  if (allow_wide && wide >= kFftWideBlocks) fft_launch<AXIS, MODE, 32>(s, d, h, nl, ukn);
+  else fft_launch<AXIS, MODE, 16>(s, d, h, nl, ukn);
 }
 
 }  // namespace
@@ -834,6 +848,7 @@ size_t plane_lds_limit() {
 }
 
 void launch_pme_fft(hipStream_t s, const LegDev* d, const LegHost* h, int nl, int ukn_mode) {
+  const bool wide = ukn_mode == 0;              // MD and force passes; u_kn keeps 16 lines
   const bool from_int64 = ukn_mode != 0;
   int plane = 0, kxy = 0;
   for (int i = 0; i < nl; ++i) {
@@ -845,16 +860,16 @@ void launch_pme_fft(hipStream_t s, const LegDev* d, const LegHost* h, int nl, in
     BlockMap m;
     const int nb = make_map(m, nl, [&](int i) { return h[i].npair * h[i].K[2]; });
     if (nb) hipLaunchKernelGGL(k_fft_xy<false>, dim3(nb), dim3(kXYThreads), lds, s, d, m);
-    fft_pass<2, 3>(s, d, h, nl, ukn_mode);
+    fft_pass<2, 3>(s, d, h, nl, ukn_mode, wide);
     if (nb) hipLaunchKernelGGL(k_fft_xy<true>, dim3(nb), dim3(kXYThreads), lds, s, d, m);
     return;
   }
-  if (from_int64) fft_pass<0, 2>(s, d, h, nl, 0);
-  else fft_pass<0, 0>(s, d, h, nl, 0);
-  fft_pass<1, 0>(s, d, h, nl, 0);
-  fft_pass<2, 3>(s, d, h, nl, ukn_mode);
-  fft_pass<1, 1>(s, d, h, nl, 0);
-  fft_pass<0, 1>(s, d, h, nl, 0);
+  if (from_int64) fft_pass<0, 2>(s, d, h, nl, 0, wide);
+  else fft_pass<0, 0>(s, d, h, nl, 0, wide);
+  fft_pass<1, 0>(s, d, h, nl, 0, wide);
+  fft_pass<2, 3>(s, d, h, nl, ukn_mode, wide);
+  fft_pass<1, 1>(s, d, h, nl, 0, wide);
+  fft_pass<0, 1>(s, d, h, nl, 0, wide);
 }
 
 void launch_pme(hipStream_t s, const LegDev* d, const LegHost* h, int nl, bool energy, bool step_forces) {
