@@ -24,6 +24,7 @@ from __future__ import annotations
 
 import dataclasses
 import math
+import sys
 import time
 import types
 from typing import List
@@ -96,7 +97,7 @@ class Server:
     """
 
     def __init__(self, engine, hbm_budget, epoch_steps=50, max_legs=64, dt=0.002, max_retries=1,
-                 clock=time.perf_counter, sleep=time.sleep):
+                 clock=time.perf_counter, sleep=time.sleep, on_event=None):
         self.engine = engine
         self.budget = hbm_budget
         self.epoch = epoch_steps
@@ -105,7 +106,13 @@ class Server:
         self.max_retries = max_retries
         self.clock = clock
         self.sleep = sleep
+        self.on_event = on_event          # called with each log entry as it happens
         self.log: List[dict] = []
+
+    def _note(self, entry):
+        self.log.append(entry)
+        if self.on_event is not None:
+            self.on_event(entry)
 
     def serve(self, requests):
         for r in requests:
@@ -131,11 +138,11 @@ class Server:
                 # retry with twice that length
                 cap = (2 * int(exc.needed_cap) + 7) // 8 * 8
                 waiting.insert(0, dataclasses.replace(r, list_cap=cap))
-                self.log.append({'t': now(), 'event': 'retry', 'rid': r.rid, 'list_cap': cap})
+                self._note({'t': now(), 'event': 'retry', 'rid': r.rid, 'list_cap': cap})
             else:
                 res.status = f'evicted: {exc}'
                 res.finished = now()
-                self.log.append({'t': now(), 'event': 'evict', 'rid': r.rid})
+                self._note({'t': now(), 'event': 'evict', 'rid': r.rid})
 
         while pending or waiting or active:
             t = now()
@@ -157,12 +164,14 @@ class Server:
                 state['used'] += need
                 if math.isnan(results[r.rid].admitted):
                     results[r.rid].admitted = now()
-                self.log.append({'t': now(), 'event': 'admit', 'rid': r.rid, 'used': state['used']})
+                self._note({'t': now(), 'event': 'admit', 'rid': r.rid, 'used': state['used']})
             if not active:
                 if pending:
                     self.sleep(max(0.0, pending[0].arrival - now()))
                 continue
             failed = self.engine.run_epoch([a[1] for a in active], self.epoch)
+            if self.on_event is not None:
+                self.on_event({'t': now(), 'event': 'epoch', 'rid': None, 'active': len(active)})
             keep = []
             for a in active:
                 r, h, done, need = a
@@ -186,7 +195,7 @@ class Server:
                     res.dG, res.mbar_iters, res.steps = dG, iters, done
                     res.status = 'ok' if ok else 'ok (MBAR not converged)'
                     res.finished = now()
-                    self.log.append({'t': now(), 'event': 'finish', 'rid': r.rid})
+                    self._note({'t': now(), 'event': 'finish', 'rid': r.rid})
                     continue
                 keep.append(a)
             active = keep
@@ -394,7 +403,14 @@ def main(argv=None):
                          'kernel trace)')
     ap.add_argument('--procs', type=int, default=8,
                     help='processes generating the legs (1: in this process, e.g. under a profiler)')
+    ap.add_argument('--progress', action='store_true',
+                    help='print a line to stderr as the legs are built and as each leg finishes')
     a = ap.parse_args(argv)
+
+    def say(msg):
+        if a.progress:
+            print(msg, file=sys.stderr, flush=True)
+
     lo, hi = (int(v) for v in a.atoms.split(':'))
     rng = np.random.default_rng([a.seed, 4])
     specs = [(int(rng.integers(lo, hi + 1)), int(rng.choice([12, 20, 42])), a.seed + i) for i in range(a.legs)]
@@ -404,17 +420,29 @@ def main(argv=None):
             systems = p.starmap(gen.sized_leg, specs, chunksize=1)
     else:
         systems = [gen.sized_leg(*sp) for sp in specs]
+    say(f'built {len(systems)} legs')
     from . import felis
     ctx = felis.Context(0)
-    for s in systems:
+    for i, s in enumerate(systems):
         relax_start(ctx, s)
+        say(f'relaxed leg {i}: {s.n_atoms} atoms, {s.n_windows} windows')
     reqs = poisson_requests(a.legs, a.rate, a.seed, lambda i: systems[i], a.steps, a.sample_every)
     if a.pause_s > 0:
         import torch
         torch.cuda.synchronize()
         time.sleep(a.pause_s)
+    last = [0.0]
+
+    def event(e):
+        if e['event'] == 'epoch':                   # at most one line every 30 s
+            if e['t'] - last[0] >= 30.0:
+                last[0] = e['t']
+                say(f"{e['t']:.1f} s: {e['active']} legs stepping")
+        elif e['event'] != 'admit':
+            say(f"{e['t']:.1f} s: {e['event']} leg {e['rid']}")
+
     srv = Server(FelisEngine(ctx, mbar_max_iter=5000), hbm_budget=int(a.hbm_gib * (1 << 30)),
-                 epoch_steps=a.epoch)
+                 epoch_steps=a.epoch, on_event=event)
     out, stats = srv.serve(reqs)
     stats["legs_ok"] = sum(1 for r in out if r.status == 'ok')
     stats["not_ok"] = [{"leg": r.rid, "atoms": r.atoms, "windows": r.windows, "status": str(r.status)[:300]}
