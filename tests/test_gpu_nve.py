@@ -2,10 +2,14 @@
 solvent leg (7,540 atoms, PME 48^3): FP32 forces summed in int64 fixed point,
 SETTLE and the rigid-water velocity projection.  After equilibration under
 friction, three windows run 1,000 steps (2 ps) of Langevin-middle dynamics
-without friction; the total energy (FP64 potential plus the kinetic energy
-of the stored velocities) has no drift above 1e-4 kcal/mol/ps per degree of
-freedom (measured: a few 1e-6) and fluctuates by under 2e-3 per degree of
-freedom (measured: ~4e-4), and the kinetic temperature stays near 300 K."""
+without friction, sampled every 25 steps.  The total energy (FP64 potential
+plus the kinetic energy of the stored velocities) fluctuates by ~4e-4
+kcal/mol per degree of freedom from sample to sample, so a straight-line fit
+over 41 samples resolves a drift only to ~1e-4 kcal/mol/ps per degree of
+freedom (measured slopes over 4 ps: -8e-5 to 3e-5, of either sign, with both
+orders of the list entries); the bar is 5e-4, about five standard errors.  A
+broken constraint or a wrong force drifts by far more.  The fluctuation stays
+under 2e-3 per degree of freedom and the kinetic temperature near 300 K."""
 import numpy as np
 import pytest
 import torch
@@ -57,6 +61,6 @@ def test_nve_drift_solvent_leg(F):
         spread = float(np.std(tot)) / dof
         temp = 2 * A[:, nw + k].mean() / (dof * KB)
         print('window', windows[k], 'drift per dof', slope, 'std per dof', spread, 'T', temp)
-        assert abs(slope) < 1e-4, (windows[k], slope)
+        assert abs(slope) < 5e-4, (windows[k], slope)
         assert spread < 2e-3, (windows[k], spread)
         assert 270.0 < temp < 330.0, (windows[k], temp)
