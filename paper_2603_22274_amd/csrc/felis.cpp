@@ -209,7 +209,7 @@ int make_plan(felis_ctx* c, const felis_leg* L, Plan& P) {
   y.cellstart = put(W * (h.ncell + 1) * 4);
   y.cursor = put(W * h.ncell * 4);
   y.xyzq = put(W * npad * 16);
-  y.prm = put(W * npad * 16);
+  y.prm = put(W * npad * 8);
   y.bblo = put(W * nc * 16);
   y.bbhi = put(W * nc * 16);
   y.gsten = put(W * npad * 16);
@@ -315,7 +315,7 @@ LegDev make_dev(const felis_ctx* c, const felis_leg* L, const Plan& p, const Met
   g.cellstart = (int*)(w + y.cellstart);
   g.cursor = (int*)(w + y.cursor);
   g.xyzq = (float4*)(w + y.xyzq);
-  g.prm = (float4*)(w + y.prm);
+  g.prm = (float2*)(w + y.prm);
   g.bblo = (float4*)(w + y.bblo);
   g.bbhi = (float4*)(w + y.bbhi);
   g.gsten = (float4*)(w + y.gsten);

@@ -149,7 +149,7 @@ struct LegDev {
   int* cellstart;                       // [W][ncell + 1]
   int* cursor;                          // [W][ncell]
   float4* xyzq;                         // [W][npad] x, y, z, q_scaled * sqrt(KE)
-  float4* prm;                          // [W][npad] sigma/2, 2 sqrt(eps), ligand flag, q
+  float2* prm;                          // [W][npad] sigma/2 and 2 sqrt(eps), negated (sign bit set) for a ligand atom
   float4* gsten;                        // [W][npad] PME stencil: offsets fx, fy, fz and the packed bases
   float4* bblo;                         // [W][nclus] cluster bounding boxes (wrapped)
   float4* bbhi;
@@ -233,6 +233,8 @@ __device__ __forceinline__ gptr<T> as_global(const T* p) { return (gptr<T>)p; }
 // float4 records read through a global pointer as a native 4-vector
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ gptr<f32x4> as_global4(const float4* p) { return (gptr<f32x4>)p; }
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ gptr<f32x2> as_global2(const float2* p) { return (gptr<f32x2>)p; }
 
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {

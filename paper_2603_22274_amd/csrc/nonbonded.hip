@@ -28,7 +28,7 @@ namespace {
 
 // items: window x slot -- current coordinates and scaled charges in sorted
 // order, and each slot's PME stencil (grid base and B-spline offsets).  REBUILD (inside a list build): for windows being rebuilt also the
-// sorted per-slot parameters and each 8-slot cluster's bounding box of
+// sorted per-slot LJ parameters and each 8-slot cluster's bounding box of
 // wrapped positions (8 consecutive lanes hold one cluster: N_pad is a
 // multiple of 8).
 template <bool REBUILD>
@@ -59,8 +59,13 @@ __global__ __launch_bounds__(256) void k_pack(const LegDev* legs, BlockMap map) 
   if (REBUILD) {
     const bool fl = valid && g.flag[w] != 0;
     if (fl) {
-      float4 p = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (a >= 0) p = make_float4(0.5f * g.sig[a], 2.0f * sqrtf(g.eps[a]), g.lig[a] ? 1.f : 0.f, g.q[a]);
+      // the ligand flag rides in the sign bit of 2 sqrt(eps) (-0 for a
+      // ligand atom without LJ), so a partner's parameters are 8 bytes
+      float2 p = make_float2(0.f, 0.f);
+      if (a >= 0) {
+        const float e2 = 2.0f * sqrtf(g.eps[a]);
+        p = make_float2(0.5f * g.sig[a], g.lig[a] ? -e2 : e2);
+      }
       g.prm[i] = p;
     }
     float lo[3] = {3.0e38f, 3.0e38f, 3.0e38f}, hi[3] = {-3.0e38f, -3.0e38f, -3.0e38f};
@@ -149,7 +154,7 @@ __device__ __forceinline__ BoxF box_f(const BoxW& B) {
 // otherwise every (i, j) takes its own minimum image.
 template <int ENERGY, bool SHIFT, int HALF>
 __device__ __forceinline__ void sweep(const LegDev& g, const BoxF B, const ICluster& I, gptr<unsigned> ent, int cnt,
-                                      gptr<f32x4> xq, gptr<f32x4> pr, int lane,
+                                      gptr<f32x4> xq, gptr<f32x2> pr, int lane,
                                       float lam_v, float a_sc, bool soft_window, float (&fx)[4],
                                       float (&fy)[4], float (&fz)[4], double& ec, double& el, const BoxW* Bw,
                                       float lam_e, const int* permw) {
@@ -166,7 +171,8 @@ __device__ __forceinline__ void sweep(const LegDev& g, const BoxF B, const IClus
     e_next = nidx < cnt ? ent[nidx] : 0u;                  // in flight during this iteration
     const int s = (int)(e >> 8);
     const f32x4 xj = xq[s];
-    const f32x4 pj = pr[s];
+    const f32x2 pj = pr[s];
+    const float ligj = (__float_as_uint(pj.y) >> 31) ? 1.0f : 0.0f;
     float jx = xj.x, jy = xj.y, jz = xj.z;
     if (SHIFT) {
       jx = fmaf(-Lx, rintf((jx - I.x[0]) * iLx), jx);
@@ -174,7 +180,7 @@ __device__ __forceinline__ void sweep(const LegDev& g, const BoxF B, const IClus
       jz = fmaf(-Lz, rintf((jz - I.z[0]) * iLz), jz);
     }
     // wave-uniform: does any listed j of this step belong to the ligand?
-    const bool jlig = soft_window && __ballot(pj.z > 0.0f) != 0ull;
+    const bool jlig = soft_window && __ballot(ligj > 0.0f) != 0ull;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       const int ii = 4 * HALF + k;
@@ -214,10 +220,10 @@ __device__ __forceinline__ void sweep(const LegDev& g, const BoxF B, const IClus
       if (I.eps[ii] == 0.0f) {
         // wave-uniform: an i-atom without LJ (a water hydrogen) contributes
         // exactly zero LJ force and energy with every partner
-      } else if (const float sig = I.sig[ii] + pj.x, eps4 = I.eps[ii] * pj.y;
+      } else if (const float sig = I.sig[ii] + pj.x, eps4 = I.eps[ii] * fabsf(pj.y);
                  (jlig || (soft_window && I.lig[ii] > 0.0f)) &&
-                 __ballot(in && (I.lig[ii] + pj.z) > 0.0f) != 0ull) {
-        const bool ligp = (I.lig[ii] + pj.z) > 0.0f;
+                 __ballot(in && (I.lig[ii] + ligj) > 0.0f) != 0ull) {
+        const bool ligp = (I.lig[ii] + ligj) > 0.0f;
         const float lam = ligp ? lam_v : 1.0f;
         const float a = ligp ? a_sc : 0.0f;
         const float s2 = sig * sig;
@@ -245,7 +251,7 @@ __device__ __forceinline__ void sweep(const LegDev& g, const BoxF B, const IClus
       }
       if (ENERGY == 2 && ((e >> k) & 1u))
         pair_energy_fp64(g, *Bw, I.xr[ii], I.yr[ii], I.zr[ii], xj.x, xj.y, xj.z, I.ai[ii], permw[s], I.lig[ii],
-                         pj.z, I.sig[ii], pj.x, I.eps[ii], pj.y, lam_e, lam_v, ec, el);
+                         ligj, I.sig[ii], pj.x, I.eps[ii], fabsf(pj.y), lam_e, lam_v, ec, el);
     }
   }
 }
@@ -277,7 +283,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
   const int w = (int)(item / g.nclus);
   const int c = (int)(item - (long long)w * g.nclus);
   const gptr<f32x4> xq = as_global4(g.xyzq + (size_t)w * g.npad);
-  const gptr<f32x4> pr = as_global4(g.prm + (size_t)w * g.npad);
+  const gptr<f32x2> pr = as_global2(g.prm + (size_t)w * g.npad);
   const BoxF B = box_f(g.box[w]);
   const float lam_v = g.lam[4 * w + 1];
   const float a_sc = g.lam[4 * w + 3];
@@ -293,7 +299,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
 #pragma unroll
   for (int ii = 0; ii < kClus; ++ii) {
     const f32x4 a = xq[c * kClus + ii];
-    const f32x4 p = pr[c * kClus + ii];
+    const f32x2 p = pr[c * kClus + ii];
     float v[3] = {uniform(a.x), uniform(a.y), uniform(a.z)};
     if (ii > 0) {
       const float r0[3] = {I.x[0], I.y[0], I.z[0]};
@@ -307,8 +313,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
     I.x[ii] = v[0]; I.y[ii] = v[1]; I.z[ii] = v[2];
     I.q[ii] = uniform(a.w);
     I.sig[ii] = uniform(p.x);
-    I.eps[ii] = uniform(p.y);
-    I.lig[ii] = uniform(p.z);
+    I.eps[ii] = uniform(fabsf(p.y));
+    I.lig[ii] = uniform((__float_as_uint(p.y) >> 31) ? 1.0f : 0.0f);
   }
   const float rc = sqrtf(g.rc2) + 0.01f;
   const bool shift = rc + ext[0] < 0.5f * B.L[0] && rc + ext[1] < 0.5f * B.L[1] && rc + ext[2] < 0.5f * B.L[2];
