@@ -164,14 +164,22 @@ __device__ __forceinline__ void sweep(const LegDev& g, const BoxF B, const IClus
   const float c2a = 2.0f * alpha * 0.56418958354775628f;   // 2 alpha / sqrt(pi)
   const float pa = FELIS_ERFC_P * alpha;                    // fit variable t = 1 / (1 + P alpha r)
   const float kx2 = -alpha * alpha * 1.4426950408889634f;   // exp(-alpha^2 r^2) = 2^(kx2 r^2)
+  // software pipeline: the entries two steps ahead and the partner data one
+  // step ahead are in flight while a step computes
   unsigned e_next = lane < cnt ? ent[lane] : 0u;          // slot 0 with an empty mask
+  unsigned e_next2 = 64 + lane < cnt ? ent[64 + lane] : 0u;
+  f32x4 xj_next = xq[(int)(e_next >> 8)];
+  f32x2 pj_next = pr[(int)(e_next >> 8)];
   for (int it = 0; it < cnt; it += 64) {
     const unsigned e = e_next;
-    const int nidx = it + 64 + lane;
-    e_next = nidx < cnt ? ent[nidx] : 0u;                  // in flight during this iteration
+    const f32x4 xj = xj_next;
+    const f32x2 pj = pj_next;
     const int s = (int)(e >> 8);
-    const f32x4 xj = xq[s];
-    const f32x2 pj = pr[s];
+    e_next = e_next2;
+    const int nidx = it + 128 + lane;
+    e_next2 = nidx < cnt ? ent[nidx] : 0u;
+    xj_next = xq[(int)(e_next >> 8)];
+    pj_next = pr[(int)(e_next >> 8)];
     const float ligj = (__float_as_uint(pj.y) >> 31) ? 1.0f : 0.0f;
     float jx = xj.x, jy = xj.y, jz = xj.z;
     if (SHIFT) {
