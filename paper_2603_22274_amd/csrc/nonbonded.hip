@@ -199,7 +199,10 @@ __device__ __forceinline__ void sweep(const LegDev& g, const BoxF B, const IClus
         dz = fmaf(-Lz, rintf(dz * iLz), dz);
       }
       const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-      const bool in = ((e >> k) & 1u) && (r2 < rc2);
+      // r^2 of a listed pair, 3e38 for an unlisted one (excluded, the atom
+      // itself or beyond r_list): one compare gives the in-range mask
+      const float r2m = ((e >> k) & 1u) ? r2 : 3.0e38f;
+      const bool in = r2m < rc2;
 #if FELIS_PAIR_WAVE_SKIP
       // wave-uniform: no lane's partner lies within r_c of this i-atom (the
       // list's entries are consecutive in the Hilbert order, so a wave's

@@ -274,8 +274,8 @@ def write_profiles(out_dir, prof_dir, workload='complex42'):
     npair = (W + 1) // 2
     alg = {kernel: 56 * W * N,
            'k_spread': W * (32 * N + 4 * K3),                 # stencils + charges in, own grid component out
-           'k_fft_xy<false>': npair * K3 * 16, 'k_fft<0, 0': npair * K3 * 16, 'k_fft<1, 0': npair * K3 * 16,
-           'k_fft<2, 3': npair * K3 * 16, 'k_fft<1, 1': npair * K3 * 16, 'k_fft<0, 1': npair * K3 * 16,
+           'k_fft_xy<false>': npair * K3 * 16, 'k_fft<0, 0, 32>': npair * K3 * 16, 'k_fft<1, 0, 32>': npair * K3 * 16,
+           'k_fft<2, 3, 32>': npair * K3 * 16, 'k_fft<1, 1, 32>': npair * K3 * 16, 'k_fft<0, 1, 32>': npair * K3 * 16,
            'k_fft_xy<true>': npair * K3 * 16,
            'k_gather<false, true>': W * (4 * K3 + 56 * N),    # own grid component, stencils + charges, forces
            'k_integrate': W * N * 76, 'k_pack<true>': W * N * 48, 'k_build': None}
@@ -296,9 +296,11 @@ def write_profiles(out_dir, prof_dir, workload='complex42'):
             "atom-window; integrator 76 B and pack 48 B per atom-window."]
     with open(os.path.join(prof_dir, f'pairs_traffic_{workload}.txt'), 'w') as fh:
         fh.write("\n".join(txt) + "\n")
-    # per-axis FFT passes by prefix (the line count per workgroup is a third template argument)
-    ks = [kernel, 'k_build', 'k_spread', 'k_gather<false, true>', 'k_fft_xy<false>', 'k_fft<0, 0', 'k_fft<1, 0',
-          'k_fft<2, 3', 'k_fft<1, 1', 'k_fft<0, 1', 'k_fft_xy<true>', 'k_integrate', 'k_pack<true>']
+    # per-axis FFT passes of the step: 32 lines per workgroup (the u_kn passes,
+    # with 16 lines and a larger grid, are other launches)
+    ks = [kernel, 'k_build', 'k_spread', 'k_gather<false, true>', 'k_fft_xy<false>', 'k_fft<0, 0, 32>',
+          'k_fft<1, 0, 32>', 'k_fft<2, 3, 32>', 'k_fft<1, 1, 32>', 'k_fft<0, 1, 32>', 'k_fft_xy<true>', 'k_integrate',
+          'k_pack<true>']
     A = counters(pre + 'A', ks)
     B = counters(pre + 'B', ks)
     lines = [f"VALU counters per dispatch, bench.py workload ({desc}), MI355X.",
