@@ -14,10 +14,6 @@
 
 #include "felis_internal.h"
 
-#ifndef FELIS_STEP_ORDER
-#define FELIS_STEP_ORDER 0
-#endif
-
 using namespace felis;
 
 namespace {
@@ -854,7 +850,6 @@ int felis_step(felis_ctx* c, felis_leg* legs, int n_legs, int n_steps, double dt
     // reciprocal space needs only the cell sort and the packed coordinates
     // and parameters: it runs on the side stream beside the list build, the
     // pair kernel and the bonded terms, and stores its forces apart (frx..)
-#if FELIS_STEP_ORDER == 0
     (void)hipEventRecord(c->ev_fork, c->stream);
     (void)hipStreamWaitEvent(c->side, c->ev_fork, 0);
     mark(c, FELIS_PROF_PME, false, c->side);
@@ -868,26 +863,6 @@ int felis_step(felis_ctx* c, felis_leg* legs, int n_legs, int n_steps, double dt
     mark(c, FELIS_PROF_PAIRS, true);
     // bonded and restraint forces are summed by the integrator itself
     (void)hipStreamWaitEvent(c->stream, c->ev_join, 0);
-#elif FELIS_STEP_ORDER == 1
-    launch_pme(c->stream, c->d_legs, hs.data(), n_legs, false, true);
-    launch_lists(c->stream, c->d_legs, hs.data(), n_legs);
-    mark(c, FELIS_PROF_NLIST, true);
-    launch_pairs(c->stream, c->d_legs, hs.data(), n_legs, 0, true);
-#elif FELIS_STEP_ORDER == 2
-    launch_lists(c->stream, c->d_legs, hs.data(), n_legs);
-    mark(c, FELIS_PROF_NLIST, true);
-    launch_pairs(c->stream, c->d_legs, hs.data(), n_legs, 0, true);
-    launch_pme(c->stream, c->d_legs, hs.data(), n_legs, false, true);
-#else
-    (void)hipEventRecord(c->ev_fork, c->stream);
-    (void)hipStreamWaitEvent(c->side, c->ev_fork, 0);
-    launch_pme(c->side, c->d_legs, hs.data(), n_legs, false, true);
-    (void)hipEventRecord(c->ev_join, c->side);
-    launch_lists(c->stream, c->d_legs, hs.data(), n_legs);
-    mark(c, FELIS_PROF_NLIST, true);
-    (void)hipStreamWaitEvent(c->stream, c->ev_join, 0);
-    launch_pairs(c->stream, c->d_legs, hs.data(), n_legs, 0, true);
-#endif
     mark(c, FELIS_PROF_INTEGRATE, false);
     launch_integrate(c->stream, c->d_legs, hs.data(), n_legs, step.data(), seed.data(), (float)dt,
                      (float)temperature, (float)gamma);

@@ -17,9 +17,6 @@
 // point.
 #include "felis_internal.h"
 
-#ifndef FELIS_PAIR_WAVE_SKIP
-#define FELIS_PAIR_WAVE_SKIP 1
-#endif
 #include "erfc_coeffs.h"
 #include "restraint.h"
 
@@ -203,14 +200,12 @@ __device__ __forceinline__ void sweep(const LegDev& g, const BoxF B, const IClus
       // itself or beyond r_list): one compare gives the in-range mask
       const float r2m = ((e >> k) & 1u) ? r2 : 3.0e38f;
       const bool in = r2m < rc2;
-#if FELIS_PAIR_WAVE_SKIP
       // wave-uniform: no lane's partner lies within r_c of this i-atom (the
       // list's entries are consecutive in the Hilbert order, so a wave's
       // partners are near one another and often all beyond r_c of one side
       // of the half-cluster); a skipped lane adds nothing, exactly as the
       // select below would.  The FP64 energy form decides its own cutoff.
       if (ENERGY < 2 && __ballot(in) == 0ull) continue;
-#endif
       // lanes outside (in == false) may compute inf or NaN below: every
       // result they feed is dropped by the selects on `in`
       const float r2s = r2;

@@ -27,19 +27,14 @@ namespace felis {
 namespace {
 
 constexpr float kInvSqrtKE = 0.054876864878355476f;   // 1 / sqrt(KE): packed charges carry sqrt(KE)
-#ifndef FELIS_FFT_XY_THREADS
-#define FELIS_FFT_XY_THREADS 512
-#endif
 // Largest LDS a whole-plane x-y workgroup may take; larger planes use one
 // pass per axis.  Inside an MD step the transform runs beside the pair
 // kernel, which holds most wave slots: a plane workgroup needing most of a
 // CU's LDS is then starved, while the per-axis passes (25 KB per workgroup
 // on a 96^3 grid) run beside it (42-window complex leg: 5.54 -> 5.41 ms per
 // MD step; planes up to 64 KB, e.g. 48^2, keep the whole-plane form)
-#ifndef FELIS_FFT_XY_LDS_CAP
-#define FELIS_FFT_XY_LDS_CAP 65536
-#endif
-constexpr int kXYThreads = FELIS_FFT_XY_THREADS;  // threads per whole-plane workgroup: ~one butterfly each
+constexpr size_t kXYLdsCap = 65536;
+constexpr int kXYThreads = 512;               // threads per whole-plane workgroup: ~one butterfly each
 
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
   return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
@@ -352,16 +347,7 @@ __device__ __forceinline__ void bspline4(float f, float* w, float* dw) {
 // 8 x 8 x 8 the halo a brick must scan (3 grid spacings and the cell margin
 // on every side) weighs less per owned point; reciprocal space alone on the
 // 96^3 grid of 42 windows 1.73 -> 1.61 ms
-#ifndef FELIS_SPREAD_BX
-#define FELIS_SPREAD_BX 16
-#endif
-#ifndef FELIS_SPREAD_BY
-#define FELIS_SPREAD_BY 8
-#endif
-#ifndef FELIS_SPREAD_BZ
-#define FELIS_SPREAD_BZ 8
-#endif
-constexpr int kBX = FELIS_SPREAD_BX, kBY = FELIS_SPREAD_BY, kBZ = FELIS_SPREAD_BZ;
+constexpr int kBX = 16, kBY = 8, kBZ = 8;
 constexpr int kBrickPts = kBX * kBY * kBZ;
 // spreading tile: int32 fixed point, 2^26 units per e.  A grid point's charge
 // stays far inside +-32 e (an atom adds at most |q| (2/3)^3), so the integer
@@ -575,13 +561,9 @@ __global__ __launch_bounds__(256) void k_spread(const LegDev* legs, BlockMap map
   }
 }
 
-// 1: each gather block stages its 64 atoms' stencil region of the grid in
-// LDS (rows read contiguously) instead of 64 scattered reads per atom; the
-// forces are bitwise the same (42-window complex leg: 5.40 -> 5.34 ms per MD
-// step)
-#ifndef FELIS_GATHER_STAGED
-#define FELIS_GATHER_STAGED 1
-#endif
+// Each gather block stages its 64 atoms' stencil region of the grid in LDS
+// (rows read contiguously) instead of 64 scattered reads per atom; the forces
+// are bitwise the same (42-window complex leg: 5.40 -> 5.34 ms per MD step)
 constexpr int kGatherTile = 4096;              // grid points staged per block (16 KB)
 
 // STEP: store the force in frx/fry/frz (the integrator adds it to the
@@ -595,7 +577,6 @@ __global__ __launch_bounds__(256) void k_gather(const LegDev* legs, BlockMap map
                     __builtin_amdgcn_readfirstlane(g.K[2])};
   // atoms in the neighbour-list sort order (spatially coherent); 4 lanes per
   // atom, lane iz sums the 16 stencil points of plane z = bz - iz
-#if FELIS_GATHER_STAGED
   // blocks never straddle two windows: the block's 64 atoms share one grid
   const int bpw = (g.npad + 63) >> 6;
   const int blk = blockIdx.x - map.start[leg];
@@ -606,14 +587,6 @@ __global__ __launch_bounds__(256) void k_gather(const LegDev* legs, BlockMap map
   const int lc = w * g.npad + min(slot, g.npad - 1);
   const int ap = g.perm[lc];
   const bool valid = slot < g.npad && ap >= 0;
-#else
-  const int local = (blockIdx.x - map.start[leg]) * 64 + (threadIdx.x >> 2);   // W N_pad < 2^31
-  const int tot = g.W * g.npad;
-  const int lc = local < tot ? local : tot - 1;
-  const int w = lc / g.npad;
-  const int ap = g.perm[lc];
-  const bool valid = local < tot && ap >= 0;
-#endif
   const int a = ap >= 0 ? ap : 0;
   const int iz = threadIdx.x & 3;
   const size_t o = (size_t)w * g.n + a;
@@ -628,7 +601,6 @@ __global__ __launch_bounds__(256) void k_gather(const LegDev* legs, BlockMap map
   bspline4(st.z, wz, dz);
   const bool im = g.pack && (w & 1);
   float p0 = 0.f, px = 0.f, py = 0.f;          // sum w phi, sum dwx phi, sum dwy phi over the plane
-#if FELIS_GATHER_STAGED
   // Stage the block's stencil region of the window's grid component in LDS
   // (rows read contiguously), then interpolate from LDS.  Bases are unwrapped
   // to the periodic image nearest the block's first atom's; a region larger
@@ -703,9 +675,6 @@ __global__ __launch_bounds__(256) void k_gather(const LegDev* legs, BlockMap map
     bx += bx < 0 ? K[0] : (bx >= K[0] ? -K[0] : 0);
     by += by < 0 ? K[1] : (by >= K[1] ? -K[1] : 0);
     bz += bz < 0 ? K[2] : (bz >= K[2] ? -K[2] : 0);
-#else
-  {
-#endif
     int gz = bz - iz; if (gz < 0) gz += K[2];
     int gxv[4];
 #pragma unroll
@@ -856,7 +825,7 @@ void launch_pme_fft(hipStream_t s, const LegDev* d, const LegHost* h, int nl, in
     kxy = std::max(kxy, h[i].K[0] + h[i].K[1]);
   }
   const size_t lds = (2 * (size_t)plane + kxy) * sizeof(float2);
-  if (!from_int64 && lds <= std::min(plane_lds_limit(), (size_t)FELIS_FFT_XY_LDS_CAP)) {   // whole x-y planes in LDS
+  if (!from_int64 && lds <= std::min(plane_lds_limit(), kXYLdsCap)) {   // whole x-y planes in LDS
     BlockMap m;
     const int nb = make_map(m, nl, [&](int i) { return h[i].npair * h[i].K[2]; });
     if (nb) hipLaunchKernelGGL(k_fft_xy<false>, dim3(nb), dim3(kXYThreads), lds, s, d, m);
@@ -881,11 +850,7 @@ void launch_pme(hipStream_t s, const LegDev* d, const LegHost* h, int nl, bool e
   if (!nb) return;
   hipLaunchKernelGGL(k_spread, dim3(nb), dim3(256), 0, s, d, m);
   launch_pme_fft(s, d, h, nl, 0);
-#if FELIS_GATHER_STAGED
   nb = make_map(m, nl, [&](int i) { return h[i].W * blocks_for((long long)h[i].npad, 64); });
-#else
-  nb = make_map(m, nl, [&](int i) { return blocks_for((long long)h[i].W * h[i].npad, 64); });
-#endif
   if (energy && step_forces) hipLaunchKernelGGL((k_gather<true, true>), dim3(nb), dim3(256), 0, s, d, m);
   else if (energy) hipLaunchKernelGGL((k_gather<true, false>), dim3(nb), dim3(256), 0, s, d, m);
   else if (step_forces) hipLaunchKernelGGL((k_gather<false, true>), dim3(nb), dim3(256), 0, s, d, m);
