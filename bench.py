@@ -48,8 +48,8 @@ DT = 0.002                      # ps
 PEAK_FP32 = 157.3               # TFLOP/s, MI355X FP32 vector (published; counts packed FP32)
 ISSUE_FP32 = 78.6               # TFLOP/s, non-packed FP32 issue: 256 CU x 4 SIMD x 16 lanes x 2 x 2.4 GHz
 FLOP_PER_PAIR = 60              # FP32 flops per unique in-cutoff pair (FMA = 2)
-PAIR_BYTES_PER_ATOM = 56        # algorithmic HBM bytes per atom-window of one pair launch:
-                                # coordinates + charge (16) and parameters (16) read, 3 int64 forces written
+PAIR_BYTES_PER_ATOM = 48        # algorithmic HBM bytes per atom-window of one pair launch: coordinates +
+                                # charge (16) and LJ parameters with the ligand flag (8) read, 3 int64 forces written
 PAIR_SAMPLE = 5                 # the timed region brackets every 5th pair-kernel launch with HIP events
 DDG_TOL = 0.01                  # kcal/mol
 TRAFFIC_FILES = {'complex42': os.path.join(ROOT, 'profiles', 'pairs_traffic_complex42.json'),

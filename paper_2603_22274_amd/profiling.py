@@ -272,7 +272,7 @@ def write_profiles(out_dir, prof_dir, workload='complex42'):
     # whose work depends on the windows due)
     W, N, K3 = WORKLOADS_SIZE[workload]
     npair = (W + 1) // 2
-    alg = {kernel: 56 * W * N,
+    alg = {kernel: 48 * W * N,
            'k_spread': W * (32 * N + 4 * K3),                 # stencils + charges in, own grid component out
            'k_fft_xy<false>': npair * K3 * 16, 'k_fft<0, 0, 32>': npair * K3 * 16, 'k_fft<1, 0, 32>': npair * K3 * 16,
            'k_fft<2, 3, 32>': npair * K3 * 16, 'k_fft<1, 1, 32>': npair * K3 * 16, 'k_fft<0, 1, 32>': npair * K3 * 16,
@@ -291,7 +291,7 @@ def write_profiles(out_dir, prof_dir, workload='complex42'):
         rd, wr = fk * 1024 * fs / 1e6, wk * 1024 * ws / 1e6
         txt.append(f"{k:24s} {nk:8d} {rd:9.1f} {wr:9.1f} " +
                    (f"{a / 1e6:11.1f} {(rd + wr) / (a / 1e6):7.2f}" if a else f"{'-':>11s} {'-':>7s}"))
-    txt += ["algorithmic: pairs 56 B per atom-window; spreading 32 B per atom-window + 4 B per grid point per",
+    txt += ["algorithmic: pairs 48 B per atom-window; spreading 32 B per atom-window + 4 B per grid point per",
             "window; an FFT pass 16 B per complex point of each pair grid; gather 4 B per grid point + 56 B per",
             "atom-window; integrator 76 B and pack 48 B per atom-window."]
     with open(os.path.join(prof_dir, f'pairs_traffic_{workload}.txt'), 'w') as fh:
