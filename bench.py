@@ -314,7 +314,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get('WORLD_SIZE', '1')) > 1:
         print("bench.py measures one GPU: the path needs no collective and nothing here runs on a second GPU; "
-              "legs and window segments shard across GPUs without exchange (see DESIGN.md).", file=sys.stderr)
+              "legs and window segments shard across GPUs without exchange.", file=sys.stderr)
         sys.exit(2)
 
     from paper_2603_22274_amd import gen

@@ -3,7 +3,7 @@
     python -m paper_2603_22274_amd.profiling stats <trace_dir> [n]
     python -m paper_2603_22274_amd.profiling traffic <fetch_dir> <write_dir> <kernel-substring>
     python -m paper_2603_22274_amd.profiling counters <pmc_dir> <kernel-substring> ...
-    python -m paper_2603_22274_amd.profiling profiles <gpurun_out> <profiles_dir> [workload]
+    python -m paper_2603_22274_amd.profiling profiles <run_dir> <profiles_dir> [workload]
 
     python -m paper_2603_22274_amd.profiling steps <trace_dir> [min_pair_us]
     python -m paper_2603_22274_amd.profiling timeline <trace_dir> [after_gap_ms]
@@ -16,7 +16,7 @@ and host time between calls) per MD step.
 ``profiles`` writes the committed summaries of the pair kernel's HBM traffic
 (JSON with the digest of the kernel's sources, read by bench.py) and of the
 VALU counters of the main kernels from the four counter passes
-(pmc_<workload>_A, _B, _FETCH_SIZE, _WRITE_SIZE under <gpurun_out>).
+(pmc_<workload>_A, _B, _FETCH_SIZE, _WRITE_SIZE under <run_dir>).
 ``traffic`` scales the FETCH_SIZE / WRITE_SIZE counters (KiB per dispatch)
 of one kernel by what the same counters read for the largest plain device
 copy in the run (bytes actually moved / bytes counted), and prints the
@@ -242,7 +242,7 @@ def src_digest():
 
 def _cmd(name, workload):
     return (f"cd /tmp && TMPDIR=/tmp timeout -s KILL 120 rocprofv3 --pmc {_PASSES[name]} "
-            f"-d <repo>/gpurun_out/pmc_{workload}_{name} -o run -- {WORKLOADS[workload][1]}")
+            f"-d <run_dir>/pmc_{workload}_{name} -o run -- {WORKLOADS[workload][1]}")
 
 
 def write_profiles(out_dir, prof_dir, workload='complex42'):
@@ -253,7 +253,7 @@ def write_profiles(out_dir, prof_dir, workload='complex42'):
     t = traffic(pre + 'FETCH_SIZE', pre + 'WRITE_SIZE', kernel)
     t['kernel_digest'] = src_digest()
     t['commands'] = [_cmd('FETCH_SIZE', workload), _cmd('WRITE_SIZE', workload),
-                     f"python -m paper_2603_22274_amd.profiling profiles gpurun_out profiles {workload}"]
+                     f"python -m paper_2603_22274_amd.profiling profiles <run_dir> profiles {workload}"]
     with open(os.path.join(prof_dir, f'pairs_traffic_{workload}.json'), 'w') as fh:
         json.dump(t, fh, indent=1)
     f, w, c = t['fetch_bytes_per_launch'] / 1e6, t['write_bytes_per_launch'] / 1e6, t['copy_reference']
@@ -322,7 +322,7 @@ def write_profiles(out_dir, prof_dir, workload='complex42'):
                      f"{fl / 1e9:10.2f} {fl / us / 1e6:8.1f} {b['SQ_INSTS_LDS']:10.3g} {b['SQ_INSTS_VMEM_RD']:9.3g} "
                      f"{a.get('SQ_WAIT_ANY', 0) / max(a.get('SQ_WAVE_CYCLES', 1), 1):13.2f}")
     lines += ["", "Commands (one pass each):", _cmd('A', workload), _cmd('B', workload),
-              f"python -m paper_2603_22274_amd.profiling profiles gpurun_out profiles {workload}"]
+              f"python -m paper_2603_22274_amd.profiling profiles <run_dir> profiles {workload}"]
     with open(os.path.join(prof_dir, f'valu_counters_{workload}.txt'), 'w') as fh:
         fh.write("\n".join(lines) + "\n")
     return t
