@@ -111,7 +111,11 @@ __global__ __launch_bounds__(256) void k_cells_count(const LegDev* legs, BlockMa
   g.xr[i] = x; g.yr[i] = y; g.zr[i] = z;
 }
 
-// one block per window: exclusive scan of the counts into cellstart; reset cursor
+// one block per window: exclusive scan of the counts into cellstart; reset
+// cursor.  The cells go through LDS 4,096 at a time, read and written with
+// consecutive lanes on consecutive cells; each thread scans four neighbouring
+// counts, the block scans the threads' sums (wave shuffles, then the 16 wave
+// totals), and a running total carries across the pieces.
 __global__ __launch_bounds__(1024) void k_cells_scan(const LegDev* legs, BlockMap map) {
   const int leg = find_leg(map, blockIdx.x);
   const LegDev& g = legs[leg];
@@ -119,28 +123,54 @@ __global__ __launch_bounds__(1024) void k_cells_scan(const LegDev* legs, BlockMa
   if (!g.flag[w]) return;
   int* cnt = g.cursor + (size_t)w * g.ncell;
   int* st = g.cellstart + (size_t)w * (g.ncell + 1);
-  const int T = blockDim.x;
-  const int per = (g.ncell + T - 1) / T;
-  const int b0 = threadIdx.x * per;
-  const int b1 = min(g.ncell, b0 + per);
-  int sum = 0;
-  for (int c = b0; c < b1; ++c) sum += cnt[c];
-  __shared__ int part[1024];
-  part[threadIdx.x] = sum;
-  __syncthreads();
-  for (int o = 1; o < T; o <<= 1) {          // Hillis-Steele inclusive scan
-    int v = threadIdx.x >= o ? part[threadIdx.x - o] : 0;
+  constexpr int T = 1024, E = 4, TILE = T * E, NW = T / 64;
+  __shared__ int s_v[TILE];
+  __shared__ int s_wt[NW];
+  __shared__ int s_tile;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int nc = g.ncell;
+  int carry = 0;                                  // counts before this piece (same in every thread)
+  for (int t0 = 0; t0 < nc; t0 += TILE) {
+#pragma unroll
+    for (int k = 0; k < E; ++k) {
+      const int c = t0 + k * T + tid;
+      s_v[k * T + tid] = c < nc ? cnt[c] : 0;
+    }
     __syncthreads();
-    part[threadIdx.x] += v;
+    int v[E], sum = 0;
+#pragma unroll
+    for (int k = 0; k < E; ++k) { v[k] = s_v[tid * E + k]; sum += v[k]; }
+    int inc = sum;                                // inclusive scan over the wave
+    for (int o = 1; o < 64; o <<= 1) {
+      const int u = __shfl_up(inc, o, 64);
+      if (lane >= o) inc += u;
+    }
+    if (lane == 63) s_wt[wave] = inc;
     __syncthreads();
+    if (wave == 0) {                              // exclusive scan of the wave totals; the piece's total
+      const int t = lane < NW ? s_wt[lane] : 0;
+      int ti = t;
+      for (int o = 1; o < NW; o <<= 1) {
+        const int u = __shfl_up(ti, o, 64);
+        if (lane >= o) ti += u;
+      }
+      if (lane < NW) s_wt[lane] = ti - t;
+      if (lane == NW - 1) s_tile = ti;
+    }
+    __syncthreads();
+    int run = carry + s_wt[wave] + inc - sum;
+#pragma unroll
+    for (int k = 0; k < E; ++k) { s_v[tid * E + k] = run; run += v[k]; }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < E; ++k) {
+      const int c = t0 + k * T + tid;
+      if (c < nc) { st[c] = s_v[k * T + tid]; cnt[c] = 0; }
+    }
+    carry += s_tile;
+    __syncthreads();                              // s_v, s_wt and s_tile are rewritten next
   }
-  int run = part[threadIdx.x] - sum;
-  for (int c = b0; c < b1; ++c) {
-    st[c] = run;
-    run += cnt[c];
-    cnt[c] = 0;
-  }
-  if (threadIdx.x == T - 1) st[g.ncell] = part[T - 1];
+  if (tid == 0) st[nc] = carry;
 }
 
 // items: window x atom -- place each atom in its cell's range
