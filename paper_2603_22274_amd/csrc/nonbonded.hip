@@ -23,8 +23,8 @@
 namespace felis {
 namespace {
 
-// items: window x slot -- current coordinates and scaled charges in sorted
-// order, and each slot's PME stencil (grid base and B-spline offsets).  REBUILD (inside a list build): for windows being rebuilt also the
+// items: window x slot -- current coordinates (wrapped into the box) and
+// scaled charges in sorted order, and each slot's PME stencil (grid base and B-spline offsets).  REBUILD (inside a list build): for windows being rebuilt also the
 // sorted per-slot LJ parameters and each 8-slot cluster's bounding box of
 // wrapped positions (8 consecutive lanes hold one cluster: N_pad is a
 // multiple of 8).
@@ -39,9 +39,13 @@ __global__ __launch_bounds__(256) void k_pack(const LegDev* legs, BlockMap map) 
   const int a = valid ? g.perm[ic] : -1;
   float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
   if (a >= 0) {
+    // coordinates wrapped into the window's box [0, L): the pair kernel
+    // needs no periodic shift for a cluster lying r_c inside every face
     const size_t o = (size_t)w * g.n + a;
     const float q = window_charge(g, a, g.lam[4 * w]);
-    v = make_float4(g.x[o], g.y[o], g.z[o], q * (float)sqrt(kKE));
+    const BoxW& Bp = g.box[w];
+    v = make_float4(wrapf(g.x[o], Bp.Lf[0], Bp.invLf[0]), wrapf(g.y[o], Bp.Lf[1], Bp.invLf[1]),
+                    wrapf(g.z[o], Bp.Lf[2], Bp.invLf[2]), q * (float)sqrt(kKE));
   }
   if (valid) {
     g.xyzq[i] = v;
@@ -94,24 +98,24 @@ __device__ __forceinline__ float3 min_img(const BoxW& B, float dx, float dy, flo
 // The 8 i-atoms of a cluster, wave-uniform (held in scalar registers).
 struct ICluster {
   float x[kClus], y[kClus], z[kClus], q[kClus], sig[kClus], eps[kClus], lig[kClus];
-  float xr[kClus], yr[kClus], zr[kClus];   // unshifted coordinates (FP64 energies)
   int ai[kClus];                            // atom indices (FP64 energies)
 };
 
 // One pair's real-space Coulomb and LJ energies with every term in FP64 (the
-// energy level 2 of the pair kernel): the minimum-image distance from the raw
-// FP32 coordinates as d - L rint(d (1/L)) and d^2 = (dx^2 + dy^2) + dz^2
+// energy level 2 of the pair kernel): the minimum-image distance from the
+// raw (unwrapped) FP32 coordinates of atoms ai, aj as d - L rint(d (1/L)) and d^2 = (dx^2 + dy^2) + dz^2
 // without contraction, the cutoff r < r_c on r = sqrt(d^2), the window's
 // charges of atoms ai, aj in FP64, Lorentz-Berthelot parameters from the packed (sigma/2,
 // 2 sqrt(eps)) and the softcore form at lambda_vdw for pairs touching the
 // ligand.  Out of line: its registers stay out of the force path.
-__device__ __attribute__((noinline)) void pair_energy_fp64(const LegDev& g, const BoxW& B, float xi, float yi,
-                                                           float zi, float xj, float yj, float zj, int ai, int aj,
-                                                           float ligi, float ligj, float hsi, float hsj,
+__device__ __attribute__((noinline)) void pair_energy_fp64(const LegDev& g, const BoxW& B, size_t base, int ai,
+                                                           int aj, float ligi, float ligj, float hsi, float hsj,
                                                            float e2i, float e2j, float lam_e, float lam_v,
                                                            double& ec, double& el) {
 #pragma clang fp contract(off)
-  double dx = (double)xi - (double)xj, dy = (double)yi - (double)yj, dz = (double)zi - (double)zj;
+  const size_t oi = base + ai, oj = base + aj;
+  double dx = (double)g.x[oi] - (double)g.x[oj], dy = (double)g.y[oi] - (double)g.y[oj];
+  double dz = (double)g.z[oi] - (double)g.z[oj];
   dx = dx - B.L[0] * rint(dx * B.invL[0]);
   dy = dy - B.L[1] * rint(dy * B.invL[1]);
   dz = dz - B.L[2] * rint(dz * B.invL[2]);
@@ -146,15 +150,18 @@ __device__ __forceinline__ BoxF box_f(const BoxW& B) {
 }
 
 // Sweep a cluster's j-list: lane = listed j, unrolled loop over the cluster's
-// i-atoms.  SHIFT: the periodic image of j is chosen once against the
+// i-atoms.  IMG 1: the periodic image of j is chosen once against the
 // cluster's first atom (exact when r_c + cluster extent < L/2 on every axis);
-// otherwise every (i, j) takes its own minimum image.
-template <int ENERGY, bool SHIFT, int HALF>
+// IMG 2: none (the cluster lies r_c inside every face of the box, so every
+// partner within r_c has its wrapped coordinates as its nearest image, and
+// any other image only lengthens the separation); IMG 0: every (i, j) takes
+// its own minimum image.
+template <int ENERGY, int IMG, int HALF>
 __device__ __forceinline__ void sweep(const LegDev& g, const BoxF B, const ICluster& I, gptr<unsigned> ent, int cnt,
                                       gptr<f32x4> xq, gptr<f32x2> pr, int lane,
                                       float lam_v, float a_sc, bool soft_window, float (&fx)[4],
                                       float (&fy)[4], float (&fz)[4], double& ec, double& el, const BoxW* Bw,
-                                      float lam_e, const int* permw) {
+                                      float lam_e, const int* permw, size_t base) {
   const float Lx = B.L[0], Ly = B.L[1], Lz = B.L[2];
   const float iLx = B.iL[0], iLy = B.iL[1], iLz = B.iL[2];
   const float rc2 = g.rc2, alpha = g.alpha;
@@ -179,7 +186,7 @@ __device__ __forceinline__ void sweep(const LegDev& g, const BoxF B, const IClus
     pj_next = pr[(int)(e_next >> 8)];
     const float ligj = (__float_as_uint(pj.y) >> 31) ? 1.0f : 0.0f;
     float jx = xj.x, jy = xj.y, jz = xj.z;
-    if (SHIFT) {
+    if (IMG == 1) {
       jx = fmaf(-Lx, rintf((jx - I.x[0]) * iLx), jx);
       jy = fmaf(-Ly, rintf((jy - I.y[0]) * iLy), jy);
       jz = fmaf(-Lz, rintf((jz - I.z[0]) * iLz), jz);
@@ -190,7 +197,7 @@ __device__ __forceinline__ void sweep(const LegDev& g, const BoxF B, const IClus
     for (int k = 0; k < 4; ++k) {
       const int ii = 4 * HALF + k;
       float dx = jx - I.x[ii], dy = jy - I.y[ii], dz = jz - I.z[ii];
-      if (!SHIFT) {
+      if (IMG == 0) {
         dx = fmaf(-Lx, rintf(dx * iLx), dx);
         dy = fmaf(-Ly, rintf(dy * iLy), dy);
         dz = fmaf(-Lz, rintf(dz * iLz), dz);
@@ -256,8 +263,8 @@ __device__ __forceinline__ void sweep(const LegDev& g, const BoxF B, const IClus
         el += (double)elj;
       }
       if (ENERGY == 2 && ((e >> k) & 1u))
-        pair_energy_fp64(g, *Bw, I.xr[ii], I.yr[ii], I.zr[ii], xj.x, xj.y, xj.z, I.ai[ii], permw[s], I.lig[ii],
-                         ligj, I.sig[ii], pj.x, I.eps[ii], fabsf(pj.y), lam_e, lam_v, ec, el);
+        pair_energy_fp64(g, *Bw, base, I.ai[ii], permw[s], I.lig[ii], ligj, I.sig[ii], pj.x, I.eps[ii],
+                         fabsf(pj.y), lam_e, lam_v, ec, el);
     }
   }
 }
@@ -314,7 +321,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
         if (c * kClus + ii < g.n) ext[d] = fmaxf(ext[d], fabsf(v[d] - r0[d]));
       }
     }
-    I.xr[ii] = uniform(a.x); I.yr[ii] = uniform(a.y); I.zr[ii] = uniform(a.z);
     if (ENERGY == 2) I.ai[ii] = __builtin_amdgcn_readfirstlane(g.perm[(size_t)w * g.npad + c * kClus + ii]);
     I.x[ii] = v[0]; I.y[ii] = v[1]; I.z[ii] = v[2];
     I.q[ii] = uniform(a.w);
@@ -324,6 +330,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
   }
   const float rc = sqrtf(g.rc2) + 0.01f;
   const bool shift = rc + ext[0] < 0.5f * B.L[0] && rc + ext[1] < 0.5f * B.L[1] && rc + ext[2] < 0.5f * B.L[2];
+  bool inside = shift;
+  for (int d = 0; d < 3; ++d) {
+    const float x0 = d == 0 ? I.x[0] : (d == 1 ? I.y[0] : I.z[0]);
+    inside = inside && x0 - ext[d] - rc >= 0.0f && x0 + ext[d] + rc < B.L[d];
+  }
+  const int img = inside ? 2 : (shift ? 1 : 0);
+  const size_t base = (size_t)w * g.n;
   // the two half-cluster lists (partners of atoms 0-3, then of atoms 4-7);
   // each half's forces are reduced over the wave before the next half
   const gptr<unsigned> ent = as_global(g.lent + (size_t)item * 2 * g.cap);
@@ -334,13 +347,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
     float fx[4] = {0.f, 0.f, 0.f, 0.f}, fy[4] = {0.f, 0.f, 0.f, 0.f}, fz[4] = {0.f, 0.f, 0.f, 0.f};
     const gptr<unsigned> eh = ent + half * g.cap;
     const int cnt = g.lcount[2 * item + half];
+#define FELIS_SWEEP(M, H) sweep<ENERGY, M, H>(g, B, I, eh, cnt, xq, pr, lane, lam_v, a_sc, soft_window, fx, fy, fz, ec, el, Bw, lam_e, permw, base)
     if (half == 0) {
-      if (shift) sweep<ENERGY, true, 0>(g, B, I, eh, cnt, xq, pr, lane, lam_v, a_sc, soft_window, fx, fy, fz, ec, el, Bw, lam_e, permw);
-      else sweep<ENERGY, false, 0>(g, B, I, eh, cnt, xq, pr, lane, lam_v, a_sc, soft_window, fx, fy, fz, ec, el, Bw, lam_e, permw);
+      if (img == 2) FELIS_SWEEP(2, 0);
+      else if (img == 1) FELIS_SWEEP(1, 0);
+      else FELIS_SWEEP(0, 0);
     } else {
-      if (shift) sweep<ENERGY, true, 1>(g, B, I, eh, cnt, xq, pr, lane, lam_v, a_sc, soft_window, fx, fy, fz, ec, el, Bw, lam_e, permw);
-      else sweep<ENERGY, false, 1>(g, B, I, eh, cnt, xq, pr, lane, lam_v, a_sc, soft_window, fx, fy, fz, ec, el, Bw, lam_e, permw);
+      if (img == 2) FELIS_SWEEP(2, 1);
+      else if (img == 1) FELIS_SWEEP(1, 1);
+      else FELIS_SWEEP(0, 1);
     }
+#undef FELIS_SWEEP
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       const float sx = wave_sum(fx[k]), sy = wave_sum(fy[k]), sz = wave_sum(fz[k]);
