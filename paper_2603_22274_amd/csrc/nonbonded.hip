@@ -8,13 +8,15 @@
 // (appendix B).  Real-space Coulomb is the Ewald direct term erfc(a r)/r.
 //
 // Pair kernel layout (gfx950, wave64): one wave per 8-atom i-cluster; the
-// cluster's i-atoms are wave-uniform and each lane takes one listed j-atom per
-// iteration and interacts it with all 8 i-atoms, so a j entry is loaded,
-// decoded and imaged once for 8 pairs.  Each cluster lists all its partners
-// (both directions), so every atom's pair force is summed by one wave in a
-// fixed order and written once: no atomics and no cross-wave ordering.  FP32
-// arithmetic; energies summed in FP64 per lane and combined in int64 fixed
-// point.
+// cluster's i-atoms are wave-uniform (scalar registers).  The cluster's two
+// half-lists (partners of atoms 0-3, then of atoms 4-7) are swept in turn:
+// each lane takes one listed j-atom per step and interacts it with the half's
+// 4 i-atoms, so a j entry is loaded, decoded and imaged once for 4 pairs, and
+// the next steps' entries and partner data are already in flight.  Each
+// cluster lists all its partners (both directions), so every atom's pair force
+// is summed by one wave in a fixed order and written once: no atomics and no
+// cross-wave ordering.  FP32 arithmetic; energies summed in FP64 per lane and
+// combined in int64 fixed point.
 #include "felis_internal.h"
 
 #include "erfc_coeffs.h"
@@ -24,10 +26,11 @@ namespace felis {
 namespace {
 
 // items: window x slot -- current coordinates (wrapped into the box) and
-// scaled charges in sorted order, and each slot's PME stencil (grid base and B-spline offsets).  REBUILD (inside a list build): for windows being rebuilt also the
-// sorted per-slot LJ parameters and each 8-slot cluster's bounding box of
-// wrapped positions (8 consecutive lanes hold one cluster: N_pad is a
-// multiple of 8).
+// scaled charges in sorted order, and each slot's PME stencil (grid base and
+// B-spline offsets).  REBUILD (inside a list build): for windows being
+// rebuilt also the sorted per-slot LJ parameters and each 8-slot cluster's
+// bounding box of wrapped positions (8 consecutive lanes hold one cluster:
+// N_pad is a multiple of 8).
 template <bool REBUILD>
 __global__ __launch_bounds__(256) void k_pack(const LegDev* legs, BlockMap map) {
   const int leg = find_leg(map, blockIdx.x);
