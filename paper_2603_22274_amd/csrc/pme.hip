@@ -10,7 +10,7 @@
 // exp(-pi^2 |m|^2/alpha^2)/|m|^2 |b1 b2 b3|^2, G(0) = 0;
 // E_rec = 1/2 sum_i q~_i phi(r_i); F_i = -q~_i grad(spline weights) . phi.
 //
-// FFT: Stockham autosort, radices 4/2/3/5.  Grids whose x-y planes fit in
+// FFT: Stockham autosort, radices 8/4/2/3/5.  Grids whose x-y planes fit in
 // LDS twice (gfx950: 160 KB per workgroup, so up to ~100 x 100 points) are
 // transformed by whole planes (x then y in one workgroup), otherwise one
 // kernel per axis with 16 lines per workgroup
@@ -77,6 +77,20 @@ __device__ __forceinline__ void dft(float2* v) {
     const float2 m = make_float2(a.x - 0.5f * s.x, a.y - 0.5f * s.y);
     const float2 t = mul_mi(make_float2(h * d.x, h * d.y));
     v[0] = cadd(a, s); v[1] = cadd(m, t); v[2] = csub(m, t);
+  } else if (R == 8) {
+    // two 4-point transforms of the even and odd elements, then the odd ones
+    // turned by w^k, w = exp(-2 pi i / 8)
+    float2 e[4] = {v[0], v[2], v[4], v[6]}, o[4] = {v[1], v[3], v[5], v[7]};
+    dft<4>(e);
+    dft<4>(o);
+    const float h = 0.70710678118654752f;               // 1 / sqrt(2)
+    const float2 t1 = make_float2(h * (o[1].x + o[1].y), h * (o[1].y - o[1].x));   // w o1
+    const float2 t2 = mul_mi(o[2]);                                                // w^2 o2 = -i o2
+    const float2 t3 = make_float2(h * (o[3].y - o[3].x), -h * (o[3].x + o[3].y));  // w^3 o3
+    v[0] = cadd(e[0], o[0]); v[4] = csub(e[0], o[0]);
+    v[1] = cadd(e[1], t1);   v[5] = csub(e[1], t1);
+    v[2] = cadd(e[2], t2);   v[6] = csub(e[2], t2);
+    v[3] = cadd(e[3], t3);   v[7] = csub(e[3], t3);
   } else {  // R == 5
     const float c1 = 0.30901699437494742f, c2 = -0.80901699437494742f;   // cos(2pi/5), cos(4pi/5)
     const float s1 = 0.95105651629515357f, s2 = 0.58778525229247313f;    // sin(2pi/5), sin(4pi/5)
@@ -130,6 +144,7 @@ __device__ __forceinline__ float2* fft_lines(float2* src, float2* dst, int n, co
       case 2: stage<2, LINES>(src, dst, n, Ns, tw); break;
       case 3: stage<3, LINES>(src, dst, n, Ns, tw); break;
       case 4: stage<4, LINES>(src, dst, n, Ns, tw); break;
+      case 8: stage<8, LINES>(src, dst, n, Ns, tw); break;
       default: stage<5, LINES>(src, dst, n, Ns, tw); break;
     }
     __syncthreads();
@@ -267,6 +282,7 @@ __device__ __forceinline__ float2* fft_lines_nl(float2* src, float2* dst, int n,
       case 2: stage_nl<2>(src, dst, n, Ns, dnl, tw); break;
       case 3: stage_nl<3>(src, dst, n, Ns, dnl, tw); break;
       case 4: stage_nl<4>(src, dst, n, Ns, dnl, tw); break;
+      case 8: stage_nl<8>(src, dst, n, Ns, dnl, tw); break;
       default: stage_nl<5>(src, dst, n, Ns, dnl, tw); break;
     }
     __syncthreads();
