@@ -78,6 +78,7 @@ size_t al(size_t v) { return (v + 255) & ~size_t(255); }
 bool factor_plan(int K, int* rad, int* nrad) {
   int m = K, n = 0;
   while (m % 8 == 0 && n < kMaxRadix) { rad[n++] = 8; m /= 8; }
+  while (m % 12 == 0 && n < kMaxRadix) { rad[n++] = 12; m /= 12; }
   while (m % 4 == 0 && n < kMaxRadix) { rad[n++] = 4; m /= 4; }
   while (m % 2 == 0 && n < kMaxRadix) { rad[n++] = 2; m /= 2; }
   while (m % 3 == 0 && n < kMaxRadix) { rad[n++] = 3; m /= 3; }

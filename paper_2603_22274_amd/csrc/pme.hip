@@ -10,7 +10,7 @@
 // exp(-pi^2 |m|^2/alpha^2)/|m|^2 |b1 b2 b3|^2, G(0) = 0;
 // E_rec = 1/2 sum_i q~_i phi(r_i); F_i = -q~_i grad(spline weights) . phi.
 //
-// FFT: Stockham autosort, radices 8/4/2/3/5.  Grids whose x-y planes fit in
+// FFT: Stockham autosort, radices 8/12/4/2/3/5.  Grids whose x-y planes fit in
 // LDS twice (gfx950: 160 KB per workgroup, so up to ~100 x 100 points) are
 // transformed by whole planes (x then y in one workgroup), otherwise one
 // kernel per axis with 16 lines per workgroup
@@ -77,6 +77,24 @@ __device__ __forceinline__ void dft(float2* v) {
     const float2 m = make_float2(a.x - 0.5f * s.x, a.y - 0.5f * s.y);
     const float2 t = mul_mi(make_float2(h * d.x, h * d.y));
     v[0] = cadd(a, s); v[1] = cadd(m, t); v[2] = csub(m, t);
+  } else if (R == 12) {
+    // prime-factor form 12 = 3 x 4: inputs j = (4 j1 + 3 j2) mod 12, 3-point
+    // transforms over j1, then 4-point transforms over j2, outputs
+    // k = (4 k1 + 9 k2) mod 12 (no twiddles between the two)
+    float2 a[4][3];
+#pragma unroll
+    for (int j2 = 0; j2 < 4; ++j2) {
+#pragma unroll
+      for (int j1 = 0; j1 < 3; ++j1) a[j2][j1] = v[(4 * j1 + 3 * j2) % 12];
+      dft<3>(a[j2]);
+    }
+#pragma unroll
+    for (int k1 = 0; k1 < 3; ++k1) {
+      float2 b[4] = {a[0][k1], a[1][k1], a[2][k1], a[3][k1]};
+      dft<4>(b);
+#pragma unroll
+      for (int k2 = 0; k2 < 4; ++k2) v[(4 * k1 + 9 * k2) % 12] = b[k2];
+    }
   } else if (R == 8) {
     // two 4-point transforms of the even and odd elements, then the odd ones
     // turned by w^k, w = exp(-2 pi i / 8)
@@ -145,6 +163,7 @@ __device__ __forceinline__ float2* fft_lines(float2* src, float2* dst, int n, co
       case 3: stage<3, LINES>(src, dst, n, Ns, tw); break;
       case 4: stage<4, LINES>(src, dst, n, Ns, tw); break;
       case 8: stage<8, LINES>(src, dst, n, Ns, tw); break;
+      case 12: stage<12, LINES>(src, dst, n, Ns, tw); break;
       default: stage<5, LINES>(src, dst, n, Ns, tw); break;
     }
     __syncthreads();
@@ -283,6 +302,7 @@ __device__ __forceinline__ float2* fft_lines_nl(float2* src, float2* dst, int n,
       case 3: stage_nl<3>(src, dst, n, Ns, dnl, tw); break;
       case 4: stage_nl<4>(src, dst, n, Ns, dnl, tw); break;
       case 8: stage_nl<8>(src, dst, n, Ns, dnl, tw); break;
+      case 12: stage_nl<12>(src, dst, n, Ns, dnl, tw); break;
       default: stage_nl<5>(src, dst, n, Ns, dnl, tw); break;
     }
     __syncthreads();
