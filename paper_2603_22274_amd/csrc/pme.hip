@@ -151,12 +151,38 @@ __device__ __forceinline__ void stage(const float2* src, float2* dst, int n, int
   }
 }
 
-// Forward transform of LINES lines of length n held in src[e * LINES + b];
+// The first Stockham stage (Ns = 1, so no twiddles) reading its inputs
+// straight from the grid: element e of line b at offs(e, b) (< 0: a line past
+// the grid's edge, read as zero), conjugated for an inverse transform.  Used
+// for the y and z passes, whose lines are consecutive in x, so consecutive
+// threads read consecutive grid points.
+template <int R, int LINES, bool CONJ, typename Off>
+__device__ __forceinline__ void stage_first_global(const float2* __restrict__ cg, const Off& offs, float2* dst, int n) {
+  const int nR = n / R;
+  for (int t = threadIdx.x; t < nR * LINES; t += blockDim.x) {
+    const int j = t / LINES, b = t - j * LINES;
+    float2 v[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const long long off = offs(j + r * nR, b);
+      const float2 c = off >= 0 ? cg[off] : make_float2(0.f, 0.f);
+      v[r] = CONJ ? conj2(c) : c;
+    }
+    dft<R>(v);
+    const int o = t + j * (R - 1) * LINES;
+#pragma unroll
+    for (int r = 0; r < R; ++r) dst[o + r * LINES] = v[r];
+  }
+}
+
+// Forward transform of LINES lines of length n held in src[e * LINES + b],
+// from stage st0 on (Ns0: the product of the radices of the stages done);
 // returns the buffer that holds the result.
 template <int LINES>
-__device__ __forceinline__ float2* fft_lines(float2* src, float2* dst, int n, const int* rad, int nrad, const float2* tw) {
-  int Ns = 1;
-  for (int st = 0; st < nrad; ++st) {
+__device__ __forceinline__ float2* fft_lines(float2* src, float2* dst, int n, const int* rad, int nrad, const float2* tw,
+                                             int st0 = 0, int Ns0 = 1) {
+  int Ns = Ns0;
+  for (int st = st0; st < nrad; ++st) {
     const int R = rad[st];
     switch (R) {
       case 2: stage<2, LINES>(src, dst, n, Ns, tw); break;
@@ -205,6 +231,21 @@ __global__ __launch_bounds__(256) void k_fft(const LegDev* legs, BlockMap map, i
     if (AXIS == 1) return (long long)o * KxKy + (long long)e * Kx + li;
     return (long long)e * KxKy + (long long)o * Kx + li;
   };
+  float2* res;
+  if (AXIS != 0 && MODE != 2) {
+    // the first stage reads the grid itself (no staging pass through LDS)
+    constexpr bool CJ = MODE == 1;
+    switch (g.rad[AXIS][0]) {
+      case 2: stage_first_global<2, LINES, CJ>(cg, offs, bufA, n); break;
+      case 3: stage_first_global<3, LINES, CJ>(cg, offs, bufA, n); break;
+      case 4: stage_first_global<4, LINES, CJ>(cg, offs, bufA, n); break;
+      case 8: stage_first_global<8, LINES, CJ>(cg, offs, bufA, n); break;
+      case 12: stage_first_global<12, LINES, CJ>(cg, offs, bufA, n); break;
+      default: stage_first_global<5, LINES, CJ>(cg, offs, bufA, n); break;
+    }
+    __syncthreads();
+    res = fft_lines<LINES>(bufA, bufB, n, g.rad[AXIS], g.nrad[AXIS], tw, 1, g.rad[AXIS][0]);
+  } else {
   for (int idx = threadIdx.x; idx < n * LINES; idx += blockDim.x) {
     int e, b;
     if (AXIS == 0) { b = dn.div(idx); e = idx - b * n; } else { e = idx / LINES; b = idx - e * LINES; }
@@ -227,7 +268,8 @@ __global__ __launch_bounds__(256) void k_fft(const LegDev* legs, BlockMap map, i
     bufA[e * LINES + b] = v;
   }
   __syncthreads();
-  float2* res = fft_lines<LINES>(bufA, bufB, n, g.rad[AXIS], g.nrad[AXIS], tw);
+  res = fft_lines<LINES>(bufA, bufB, n, g.rad[AXIS], g.nrad[AXIS], tw);
+  }
   if (MODE == 3) {
     // multiply by G(kx, ky, kz): element e = kz of line (ky = o, kx = ch*LINES + b),
     // in the box of the grid's window (u_kn: of its frame)
