@@ -175,14 +175,47 @@ __device__ __forceinline__ void stage_first_global(const float2* __restrict__ cg
   }
 }
 
+// The last Stockham stage of a line set (Ns: the product of the earlier
+// radices) writing its outputs straight to the grid: output element
+// jq Ns R + k + r Ns of line b goes to offs(e, b) (skipped when < 0),
+// conjugated after an inverse transform.
+template <int R, int LINES, bool CONJ, typename Off>
+__device__ __forceinline__ void stage_last_global(const float2* src, float2* __restrict__ cg, const Off& offs, int n,
+                                                  int Ns, const float2* tw) {
+  const int nR = n / R;
+  const int step = n / (Ns * R);
+  const int s_in = nR * LINES;
+  const FastDiv dNs(Ns);
+  for (int t = threadIdx.x; t < nR * LINES; t += blockDim.x) {
+    const int j = t / LINES, b = t - j * LINES;
+    const int jq = dNs.div(j);
+    const int k = j - (int)__umul24((unsigned)jq, (unsigned)Ns);
+    const int tk = (int)__umul24((unsigned)k, (unsigned)step);
+    float2 v[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      v[r] = src[t + r * s_in];
+      if (r) v[r] = cmul(v[r], tw[r * tk]);
+    }
+    dft<R>(v);
+    const int e0 = jq * Ns * R + k;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const long long off = offs(e0 + r * Ns, b);
+      if (off >= 0) cg[off] = CONJ ? conj2(v[r]) : v[r];
+    }
+  }
+}
+
 // Forward transform of LINES lines of length n held in src[e * LINES + b],
-// from stage st0 on (Ns0: the product of the radices of the stages done);
+// stages st0 .. st1 - 1 (Ns0: the product of the radices of the stages done);
 // returns the buffer that holds the result.
 template <int LINES>
 __device__ __forceinline__ float2* fft_lines(float2* src, float2* dst, int n, const int* rad, int nrad, const float2* tw,
-                                             int st0 = 0, int Ns0 = 1) {
+                                             int st0 = 0, int Ns0 = 1, int st1 = -1) {
   int Ns = Ns0;
-  for (int st = st0; st < nrad; ++st) {
+  if (st1 < 0) st1 = nrad;
+  for (int st = st0; st < st1; ++st) {
     const int R = rad[st];
     switch (R) {
       case 2: stage<2, LINES>(src, dst, n, Ns, tw); break;
@@ -244,7 +277,24 @@ __global__ __launch_bounds__(256) void k_fft(const LegDev* legs, BlockMap map, i
       default: stage_first_global<5, LINES, CJ>(cg, offs, bufA, n); break;
     }
     __syncthreads();
-    res = fft_lines<LINES>(bufA, bufB, n, g.rad[AXIS], g.nrad[AXIS], tw, 1, g.rad[AXIS][0]);
+    const int nrad = g.nrad[AXIS];
+    if (MODE != 3 && nrad >= 2) {
+      // the middle stages in LDS, the last one straight to the grid
+      res = fft_lines<LINES>(bufA, bufB, n, g.rad[AXIS], nrad, tw, 1, g.rad[AXIS][0], nrad - 1);
+      int Ns = 1;
+      for (int st = 0; st < nrad - 1; ++st) Ns *= g.rad[AXIS][st];
+      constexpr bool CO = MODE == 1;
+      switch (g.rad[AXIS][nrad - 1]) {
+        case 2: stage_last_global<2, LINES, CO>(res, cg, offs, n, Ns, tw); break;
+        case 3: stage_last_global<3, LINES, CO>(res, cg, offs, n, Ns, tw); break;
+        case 4: stage_last_global<4, LINES, CO>(res, cg, offs, n, Ns, tw); break;
+        case 8: stage_last_global<8, LINES, CO>(res, cg, offs, n, Ns, tw); break;
+        case 12: stage_last_global<12, LINES, CO>(res, cg, offs, n, Ns, tw); break;
+        default: stage_last_global<5, LINES, CO>(res, cg, offs, n, Ns, tw); break;
+      }
+      return;
+    }
+    res = fft_lines<LINES>(bufA, bufB, n, g.rad[AXIS], nrad, tw, 1, g.rad[AXIS][0]);
   } else {
   for (int idx = threadIdx.x; idx < n * LINES; idx += blockDim.x) {
     int e, b;
@@ -293,7 +343,23 @@ __global__ __launch_bounds__(256) void k_fft(const LegDev* legs, BlockMap map, i
     }
     __syncthreads();
     float2* other = (res == bufA) ? bufB : bufA;
-    res = fft_lines<LINES>(res, other, n, g.rad[AXIS], g.nrad[AXIS], tw);
+    const int nrad = g.nrad[AXIS];
+    if (AXIS != 0) {
+      // the inverse transform's last stage straight to the grid
+      res = fft_lines<LINES>(res, other, n, g.rad[AXIS], nrad, tw, 0, 1, nrad - 1);
+      int Ns = 1;
+      for (int st = 0; st < nrad - 1; ++st) Ns *= g.rad[AXIS][st];
+      switch (g.rad[AXIS][nrad - 1]) {
+        case 2: stage_last_global<2, LINES, true>(res, cg, offs, n, Ns, tw); break;
+        case 3: stage_last_global<3, LINES, true>(res, cg, offs, n, Ns, tw); break;
+        case 4: stage_last_global<4, LINES, true>(res, cg, offs, n, Ns, tw); break;
+        case 8: stage_last_global<8, LINES, true>(res, cg, offs, n, Ns, tw); break;
+        case 12: stage_last_global<12, LINES, true>(res, cg, offs, n, Ns, tw); break;
+        default: stage_last_global<5, LINES, true>(res, cg, offs, n, Ns, tw); break;
+      }
+      return;
+    }
+    res = fft_lines<LINES>(res, other, n, g.rad[AXIS], nrad, tw);
   }
   for (int idx = threadIdx.x; idx < n * LINES; idx += blockDim.x) {
     int e, b;
