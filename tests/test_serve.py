@@ -181,3 +181,20 @@ def test_capacity_failure_evicted_when_retries_spent():
     srv = Server(eng, 10 ** 9, epoch_steps=50, max_retries=0, clock=clk, sleep=clk.sleep)
     out, stats = srv.serve(reqs)
     assert out[0].status == 'ok' and out[1].status.startswith('evicted')
+
+
+def test_events_reported_as_they_happen():
+    # the on_event hook sees every log entry when it is made, plus one
+    # 'epoch' entry per batched epoch (with the number of legs stepping)
+    clk = Clock()
+    eng = BookEngine(clk, 10 ** 9, fail={0: (1, 'overflow')})
+    seen = []
+    srv = Server(eng, 10 ** 9, epoch_steps=50, clock=clk, sleep=clk.sleep, on_event=seen.append)
+    out, stats = srv.serve([req(0, 0.0, 1000, 10), req(1, 0.05, 1000, 10), req(2, 0.1, 1000, 10)])
+    logged = [e for e in seen if e['event'] != 'epoch']
+    assert logged == srv.log
+    epochs = [e for e in seen if e['event'] == 'epoch']
+    assert len(epochs) == len(eng.batches)
+    assert [e['active'] for e in epochs] == [len(b) for b in eng.batches]
+    assert [e['t'] for e in seen] == sorted(e['t'] for e in seen)
+    assert {e['event'] for e in logged} == {'admit', 'finish', 'evict'}
