@@ -1,6 +1,7 @@
 """Host logic of the kernel-trace summaries on a hand-built trace database:
 per-step device time, busy and idle time, and the whole-run queue and host
-gaps (no GPU, no profiler)."""
+gaps, and the per-dispatch counter averages of a kernel's workload launches
+(no GPU, no profiler)."""
 import sqlite3
 
 import pytest
@@ -62,3 +63,27 @@ def test_timeline_splits_queue_and_host_gaps(tmp_path):
     assert tl['queue_gaps_us_per_md_step'] == pytest.approx((3 * 5.0 + 2 * 5.0) / 4)
     whole = profiling.timeline(d)
     assert whole['md_steps'] == 4                                 # k_prep comes before the first pair launch
+
+
+def test_counters_take_the_workload_launches(tmp_path):
+    # per-dispatch counter averages over a kernel's largest-grid launches only,
+    # and the FFT passes of the step told apart from the u_kn ones by their
+    # line count (the third template argument)
+    d = tmp_path / 'pmc'
+    d.mkdir()
+    con = sqlite3.connect(str(d / 'run_results.db'))
+    con.execute("create table counters_collection (kernel_name text, grid_size integer, counter_name text, "
+                "value real)")
+    rows = [("void felis::k_fft<1, 0, 32>(...)", 6048, "SQ_INSTS_VALU", 100.0),
+            ("void felis::k_fft<1, 0, 32>(...)", 6048, "SQ_INSTS_VALU", 120.0),
+            ("void felis::k_fft<1, 0, 32>(...)", 288, "SQ_INSTS_VALU", 5.0),       # a one-window launch
+            ("void felis::k_fft<1, 0, 16>(...)", 24192, "SQ_INSTS_VALU", 900.0),   # u_kn, more workgroups
+            ("void felis::k_pairs<0>(...)", 92568, "SQ_INSTS_VALU", 7.0)]
+    con.executemany("insert into counters_collection values (?, ?, ?, ?)", rows)
+    con.commit()
+    con.close()
+    c = profiling.counters(str(d), ['k_fft<1, 0, 32>', 'k_pairs<0>'])
+    assert c['k_fft<1, 0, 32>']['SQ_INSTS_VALU'] == pytest.approx(110.0)
+    assert c['k_pairs<0>']['SQ_INSTS_VALU'] == pytest.approx(7.0)
+    # a prefix without the line count would have picked the u_kn launches
+    assert profiling.counters(str(d), ['k_fft<1, 0'])['k_fft<1, 0']['SQ_INSTS_VALU'] == pytest.approx(900.0)
