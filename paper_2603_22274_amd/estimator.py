@@ -13,8 +13,6 @@ adds the analytic restraint term (``felis_restraint_dg``):
 """
 from __future__ import annotations
 
-import numpy as np
-
 from . import felis
 
 
